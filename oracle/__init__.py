@@ -1,0 +1,214 @@
+"""Plain FP64 CPU oracle (ctypes wrapper around tm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only code allowed to import this package.  It shares
+nothing with the GPU library (no code, no headers, no tables); both sides only
+receive the same seeded inputs.
+
+Arrays are numpy complex128 in the canonical layout:
+  spinor  [V][4][3]           (site lexicographic, t slowest, x fastest)
+  links   [V][4][3][3]        (direction mu: 0 = t, 1 = x, 2 = y, 3 = z)
+  clover  [V][12][12]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tm_oracle.c")
+_LIB = os.environ.get("TM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no SIMD intrinsics)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Op(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int * 4),
+        ("antiperiodic_t", ctypes.c_int),
+        ("U", ctypes.c_void_p),
+        ("clov", ctypes.c_void_p),
+        ("m", ctypes.c_double),
+        ("mu", ctypes.c_double),
+    ]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("true_rel_res", ctypes.c_double),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        vp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)
+        lib.or_volume.restype = ctypes.c_long
+        lib.or_volume.argtypes = [ip]
+        lib.or_gamma.argtypes = [ctypes.c_int, vp]
+        lib.or_clover.argtypes = [ip, vp, ctypes.c_double, vp]
+        lib.or_dirac.argtypes = [ctypes.POINTER(_Op), vp, vp]
+        lib.or_dirac_blockdiag.argtypes = [ctypes.POINTER(_Op), ip, vp, vp]
+        lib.or_block_colour.argtypes = [ip, ip, ctypes.c_long]
+        lib.or_block_colour.restype = ctypes.c_int
+        lib.or_mr_block.argtypes = [ctypes.POINTER(_Op), ip, ip, vp, vp, ctypes.c_int]
+        lib.or_sap.argtypes = [ctypes.POINTER(_Op), ip, ctypes.c_int, ctypes.c_int, vp, vp]
+        lib.or_sap.restype = ctypes.c_int
+        lib.or_fgmres.argtypes = [
+            ctypes.POINTER(_Op), vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip,
+            ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Report),
+        ]
+        lib.or_fgmres.restype = ctypes.c_int
+        lib.or_num_threads.restype = ctypes.c_int
+        lib.or_set_num_threads.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _i4(v):
+    return (ctypes.c_int * 4)(*[int(a) for a in v])
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def kappa_to_m(kappa: float) -> float:
+    """Hopping-parameter relation m + 4 = 1 / (2 kappa)."""
+    return 1.0 / (2.0 * kappa) - 4.0
+
+
+def volume(dims) -> int:
+    return int(np.prod(dims))
+
+
+def gamma(mu: int) -> np.ndarray:
+    g = np.zeros(16, np.complex128)
+    _load().or_gamma(mu, g.ctypes.data)
+    return g.reshape(4, 4)
+
+
+def clover(dims, U, csw: float) -> np.ndarray:
+    U = _c128(U)
+    V = volume(dims)
+    out = np.zeros((V, 12, 12), np.complex128)
+    _load().or_clover(_i4(dims), U.ctypes.data, float(csw), out.ctypes.data)
+    return out
+
+
+class Operator:
+    """D(mu) = (m+4) + clover - 1/2 hops + i mu Gamma5 on a periodic lattice."""
+
+    def __init__(self, dims, U, m: float, mu: float, csw: float = 0.0, antiperiodic_t: bool = False,
+                 clov: np.ndarray | None = None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = volume(self.dims)
+        self.U = _c128(U).reshape(self.V, 4, 3, 3)
+        self.m, self.mu, self.csw = float(m), float(mu), float(csw)
+        self.antiperiodic_t = bool(antiperiodic_t)
+        if clov is not None:
+            self.clov = _c128(clov)
+        elif self.csw != 0.0:
+            self.clov = clover(self.dims, self.U, self.csw)
+        else:
+            self.clov = None
+        self._op = _Op(_i4(self.dims), int(self.antiperiodic_t), self.U.ctypes.data,
+                       self.clov.ctypes.data if self.clov is not None else None, self.m, self.mu)
+
+    def with_mu(self, mu: float) -> "Operator":
+        return Operator(self.dims, self.U, self.m, mu, self.csw, self.antiperiodic_t, self.clov)
+
+    def _vec(self, v):
+        v = _c128(v)
+        assert v.size == self.V * 12, (v.shape, self.V)
+        return v
+
+    def apply(self, psi) -> np.ndarray:
+        psi = self._vec(psi)
+        out = np.empty_like(psi)
+        _load().or_dirac(ctypes.byref(self._op), psi.ctypes.data, out.ctypes.data)
+        return out
+
+    def apply_blockdiag(self, psi, bdims) -> np.ndarray:
+        psi = self._vec(psi)
+        out = np.empty_like(psi)
+        _load().or_dirac_blockdiag(ctypes.byref(self._op), _i4(bdims), psi.ctypes.data, out.ctypes.data)
+        return out
+
+    def block_colour(self, bdims, site: int) -> int:
+        return _load().or_block_colour(_i4(self.dims), _i4(bdims), int(site))
+
+    def mr_block(self, bdims, B, r, iters: int) -> np.ndarray:
+        r = self._vec(r)
+        e = np.zeros_like(r)
+        _load().or_mr_block(ctypes.byref(self._op), _i4(bdims), _i4(B), r.ctypes.data, e.ctypes.data, int(iters))
+        return e
+
+    def sap(self, b, bdims, n_cycles: int, mr_iters: int, x0=None) -> np.ndarray:
+        b = self._vec(b)
+        x = np.zeros_like(b) if x0 is None else self._vec(x0).copy()
+        rc = _load().or_sap(ctypes.byref(self._op), _i4(bdims), int(n_cycles), int(mr_iters), b.ctypes.data,
+                            x.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"or_sap rejected block shape {bdims} (code {rc})")
+        return x
+
+    def fgmres(self, b, tol: float, restart: int = 20, max_iters: int = 2000, precond: bool = True,
+               bdims=(2, 2, 2, 2), n_cycles: int = 3, mr_iters: int = 4, x0=None):
+        b = self._vec(b)
+        x = np.zeros_like(b) if x0 is None else self._vec(x0).copy()
+        rep = _Report()
+        _load().or_fgmres(ctypes.byref(self._op), b.ctypes.data, x.ctypes.data, float(tol), int(restart),
+                          int(max_iters), int(bool(precond)), _i4(bdims), int(n_cycles), int(mr_iters),
+                          ctypes.byref(rep))
+        return x, {"iters": rep.iters, "restarts": rep.restarts, "converged": bool(rep.converged),
+                   "true_rel_res": rep.true_rel_res}
+
+    def dense(self) -> np.ndarray:
+        """Dense matrix of D (12V x 12V), built column by column; tiny lattices only."""
+        n = self.V * 12
+        M = np.zeros((n, n), np.complex128)
+        e = np.zeros(n, np.complex128)
+        for j in range(n):
+            e[j] = 1.0
+            M[:, j] = self.apply(e)
+            e[j] = 0.0
+        return M
+
+    def dense_blockdiag(self, bdims) -> np.ndarray:
+        n = self.V * 12
+        M = np.zeros((n, n), np.complex128)
+        e = np.zeros(n, np.complex128)
+        for j in range(n):
+            e[j] = 1.0
+            M[:, j] = self.apply_blockdiag(e, bdims)
+            e[j] = 0.0
+        return M
+
+
+def num_threads() -> int:
+    return _load().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().or_set_num_threads(int(n))

@@ -1,0 +1,666 @@
+/*
+ * Plain FP64 CPU oracle (see tm_oracle.h for conventions).
+ *
+ * TEST INFRASTRUCTURE ONLY: never linked into, called by or sharing code with
+ * the GPU library.  Loops follow the paper's definitions term by term; there
+ * is no blocking, fusion or reordering beyond what the definitions state.
+ * OpenMP only splits independent sites / blocks across threads so that the
+ * benchmark can time the oracle on the host cores.
+ *
+ * Pins (checked by the CPU test suite, independent of this code's formulas):
+ *   or_gamma        Clifford relation, Hermiticity, gamma5 = diag(1,1,-1,-1).
+ *   or_clover       zero on the free field; Hermitian; commutes with gamma5;
+ *                   gauge covariant; closed form on a constant abelian
+ *                   field strength.
+ *   or_dirac        plane-wave closed form on the free field (with and
+ *                   without constant abelian phases); Gamma5-hermiticity;
+ *                   D(mu)^+ D(mu) = D(0)^+ D(0) + mu^2; smallest singular
+ *                   value >= |mu|; conjugate spectra of +-mu; gauge
+ *                   covariance.
+ *   or_dirac_blockdiag  equals the full D with all inter-block link
+ *                   products removed (dense check against projector algebra);
+ *                   blocks of one colour do not couple.
+ *   or_mr_block     residual norms non-increasing; converges to the dense LU
+ *                   block solve; optimal step length (perturbing alpha never
+ *                   lowers the residual).
+ *   or_sap          with exact block solves, the closed form
+ *                   x_n = (I - E^n) D^-1 b + E^n x_0, E = (I-B1 D)(I-B0 D);
+ *                   residual vanishes on the colour just swept;
+ *                   1-homogeneity; block-order independence.
+ *   or_fgmres       solution against dense LU (numpy); identity-
+ *                   preconditioned GMRES(N) exact termination.
+ */
+#include "tm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NS 4
+#define NC 3
+#define NSC 12
+
+/* ---------------------------------------------------------------- lattice */
+
+long or_volume(const int dims[4]) {
+    return (long)dims[0] * dims[1] * dims[2] * dims[3];
+}
+
+/* Array axis of direction mu: t is axis 0, x axis 3, y axis 2, z axis 1. */
+static int axis_of(int mu) {
+    static const int ax[4] = {0, 3, 2, 1};
+    return ax[mu];
+}
+
+static void site_coords(const int dims[4], long s, int c[4]) {
+    for (int a = 3; a >= 0; --a) {
+        c[a] = (int)(s % dims[a]);
+        s /= dims[a];
+    }
+}
+
+static long coords_site(const int dims[4], const int c[4]) {
+    long s = 0;
+    for (int a = 0; a < 4; ++a) s = s * dims[a] + c[a];
+    return s;
+}
+
+/* Neighbour of s one step along direction mu (dir = +1 or -1), periodic.
+ * *wrapped is set to 1 when the step crosses the lattice boundary. */
+static long neighbour(const int dims[4], long s, int mu, int dir, int* wrapped) {
+    int c[4];
+    site_coords(dims, s, c);
+    int a = axis_of(mu);
+    int v = c[a] + dir;
+    *wrapped = 0;
+    if (v < 0) { v += dims[a]; *wrapped = 1; }
+    if (v >= dims[a]) { v -= dims[a]; *wrapped = 1; }
+    c[a] = v;
+    return coords_site(dims, c);
+}
+
+static const or_cplx* link(const or_cplx* U, long s, int mu) {
+    return U + ((size_t)s * 4 + mu) * 9;
+}
+
+/* ------------------------------------------------------------- small algebra */
+
+/* c = a b (3x3) */
+static void mm(const or_cplx* a, const or_cplx* b, or_cplx* c) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            or_cplx t = 0;
+            for (int k = 0; k < 3; ++k) t += a[3 * i + k] * b[3 * k + j];
+            c[3 * i + j] = t;
+        }
+}
+
+/* c = a^dagger (3x3) */
+static void dag(const or_cplx* a, or_cplx* c) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) c[3 * i + j] = conj(a[3 * j + i]);
+}
+
+/* product of four 3x3 matrices */
+static void mm4(const or_cplx* a, const or_cplx* b, const or_cplx* c, const or_cplx* d, or_cplx* out) {
+    or_cplx t1[9], t2[9];
+    mm(a, b, t1);
+    mm(t1, c, t2);
+    mm(t2, d, out);
+}
+
+/* -------------------------------------------------------------- gammas */
+
+static void gamma_basic(int mu, or_cplx g[16]) {
+    /* Chiral basis: gamma0 = [[0,-1],[-1,0]], gamma_k = [[0,-i sigma_k],[i sigma_k,0]]. */
+    const or_cplx ii = _Complex_I;
+    or_cplx sig[4][4]; /* sig[k] as 2x2 row-major, k = 1..3 */
+    or_cplx s1[4] = {0, 1, 1, 0};
+    or_cplx s2[4] = {0, -ii, ii, 0};
+    or_cplx s3[4] = {1, 0, 0, -1};
+    memcpy(sig[1], s1, sizeof s1);
+    memcpy(sig[2], s2, sizeof s2);
+    memcpy(sig[3], s3, sizeof s3);
+    for (int i = 0; i < 16; ++i) g[i] = 0;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            or_cplx up, lo; /* upper-right block, lower-left block */
+            if (mu == 0) {
+                up = (r == c) ? -1.0 : 0.0;
+                lo = (r == c) ? -1.0 : 0.0;
+            } else {
+                up = -ii * sig[mu][2 * r + c];
+                lo = ii * sig[mu][2 * r + c];
+            }
+            g[4 * r + (c + 2)] = up;
+            g[4 * (r + 2) + c] = lo;
+        }
+}
+
+void or_gamma(int mu, or_cplx g[16]) {
+    if (mu < 4) {
+        gamma_basic(mu, g);
+        return;
+    }
+    /* gamma5 = gamma0 gamma1 gamma2 gamma3, formed by multiplication. */
+    or_cplx acc[16], gm[16], tmp[16];
+    gamma_basic(0, acc);
+    for (int nu = 1; nu < 4; ++nu) {
+        gamma_basic(nu, gm);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                or_cplx t = 0;
+                for (int k = 0; k < 4; ++k) t += acc[4 * i + k] * gm[4 * k + j];
+                tmp[4 * i + j] = t;
+            }
+        memcpy(acc, tmp, sizeof acc);
+    }
+    memcpy(g, acc, sizeof acc);
+}
+
+/* -------------------------------------------------------------- clover */
+
+/* Q_munu(x): sum of the four plaquette leaves exactly as the paper writes them. */
+static void clover_leaf_sum(const int dims[4], const or_cplx* U, long x, int mu, int nu, or_cplx* Q) {
+    int w;
+    long xpm = neighbour(dims, x, mu, +1, &w);
+    long xpn = neighbour(dims, x, nu, +1, &w);
+    long xmm = neighbour(dims, x, mu, -1, &w);
+    long xmn = neighbour(dims, x, nu, -1, &w);
+    long xmm_pn = neighbour(dims, xmm, nu, +1, &w);
+    long xmm_mn = neighbour(dims, xmm, nu, -1, &w);
+    long xmn_pm = neighbour(dims, xmn, mu, +1, &w);
+
+    or_cplx d1[9], d2[9], d3[9], leaf[9];
+    for (int i = 0; i < 9; ++i) Q[i] = 0;
+
+    /* U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ */
+    dag(link(U, xpn, mu), d1);
+    dag(link(U, x, nu), d2);
+    mm4(link(U, x, mu), link(U, xpm, nu), d1, d2, leaf);
+    for (int i = 0; i < 9; ++i) Q[i] += leaf[i];
+
+    /* U_nu(x) U_mu(x-mu+nu)^+ U_nu(x-mu)^+ U_mu(x-mu) */
+    dag(link(U, xmm_pn, mu), d1);
+    dag(link(U, xmm, nu), d2);
+    mm4(link(U, x, nu), d1, d2, link(U, xmm, mu), leaf);
+    for (int i = 0; i < 9; ++i) Q[i] += leaf[i];
+
+    /* U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu) */
+    dag(link(U, xmm, mu), d1);
+    dag(link(U, xmm_mn, nu), d2);
+    mm4(d1, d2, link(U, xmm_mn, mu), link(U, xmn, nu), leaf);
+    for (int i = 0; i < 9; ++i) Q[i] += leaf[i];
+
+    /* U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+ */
+    dag(link(U, xmn, nu), d1);
+    dag(link(U, x, mu), d3);
+    mm4(d1, link(U, xmn, mu), link(U, xmn_pm, nu), d3, leaf);
+    for (int i = 0; i < 9; ++i) Q[i] += leaf[i];
+}
+
+void or_clover(const int dims[4], const or_cplx* U, double csw, or_cplx* clov) {
+    long V = or_volume(dims);
+    or_cplx g[4][16];
+    for (int mu = 0; mu < 4; ++mu) or_gamma(mu, g[mu]);
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        or_cplx* C = clov + (size_t)x * 144;
+        for (int i = 0; i < 144; ++i) C[i] = 0;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = 0; nu < 4; ++nu) {
+                or_cplx Qmn[9], Qnm[9], gg[16];
+                clover_leaf_sum(dims, U, x, mu, nu, Qmn);
+                clover_leaf_sum(dims, U, x, nu, mu, Qnm);
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        or_cplx t = 0;
+                        for (int k = 0; k < 4; ++k) t += g[mu][4 * i + k] * g[nu][4 * k + j];
+                        gg[4 * i + j] = t;
+                    }
+                for (int s = 0; s < 4; ++s)
+                    for (int sp = 0; sp < 4; ++sp)
+                        for (int c = 0; c < 3; ++c)
+                            for (int cp = 0; cp < 3; ++cp)
+                                C[(3 * s + c) * 12 + 3 * sp + cp] +=
+                                    -(csw / 32.0) * gg[4 * s + sp] * (Qmn[3 * c + cp] - Qnm[3 * c + cp]);
+            }
+    }
+}
+
+/* -------------------------------------------------------------- operator */
+
+/* Contribution of one hop: out += -1/2 (I + sgn*gamma_mu) (x) W  psi_n, with
+ * sgn = -1 for the forward hop (W = U_mu(x)) and +1 for the backward hop
+ * (W = U_mu(x-mu)^+); phase is -1 across an antiperiodic t boundary. */
+static void add_hop(const or_cplx* gmu, double sgn, const or_cplx* W, const or_cplx* psi_n, double phase,
+                    or_cplx* out) {
+    for (int s = 0; s < 4; ++s)
+        for (int c = 0; c < 3; ++c) {
+            or_cplx acc = 0;
+            for (int sp = 0; sp < 4; ++sp) {
+                or_cplx proj = (s == sp ? 1.0 : 0.0) + sgn * gmu[4 * s + sp];
+                if (proj == 0) continue;
+                or_cplx col = 0;
+                for (int cp = 0; cp < 3; ++cp) col += W[3 * c + cp] * psi_n[3 * sp + cp];
+                acc += proj * col;
+            }
+            out[3 * s + c] += -0.5 * phase * acc;
+        }
+}
+
+/* Diagonal part at one site: (m+4) psi + clov psi + i mu gamma5 psi. */
+static void add_diag(const or_op* op, const or_cplx* g5, long x, const or_cplx* psi, or_cplx* out) {
+    for (int i = 0; i < 12; ++i) out[i] += (op->m + 4.0) * psi[i];
+    if (op->clov) {
+        const or_cplx* C = op->clov + (size_t)x * 144;
+        for (int i = 0; i < 12; ++i) {
+            or_cplx t = 0;
+            for (int j = 0; j < 12; ++j) t += C[12 * i + j] * psi[j];
+            out[i] += t;
+        }
+    }
+    for (int s = 0; s < 4; ++s)
+        for (int sp = 0; sp < 4; ++sp) {
+            if (g5[4 * s + sp] == 0) continue;
+            for (int c = 0; c < 3; ++c) out[3 * s + c] += _Complex_I * op->mu * g5[4 * s + sp] * psi[3 * sp + c];
+        }
+}
+
+/* Block coordinates of site s. */
+static void block_of(const int dims[4], const int bdims[4], long s, int B[4]) {
+    int c[4];
+    site_coords(dims, s, c);
+    for (int a = 0; a < 4; ++a) B[a] = c[a] / bdims[a];
+}
+
+static int same_block(const int dims[4], const int bdims[4], long s1, long s2) {
+    int B1[4], B2[4];
+    block_of(dims, bdims, s1, B1);
+    block_of(dims, bdims, s2, B2);
+    return B1[0] == B2[0] && B1[1] == B2[1] && B1[2] == B2[2] && B1[3] == B2[3];
+}
+
+/* out = D in, restricted to hops allowed by `keep` (NULL bdims: all hops). */
+static void dirac_generic(const or_op* op, const int* bdims, const or_cplx* in, or_cplx* out) {
+    long V = or_volume(op->dims);
+    or_cplx g[4][16], g5[16];
+    for (int mu = 0; mu < 4; ++mu) or_gamma(mu, g[mu]);
+    or_gamma(4, g5);
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        or_cplx acc[12];
+        for (int i = 0; i < 12; ++i) acc[i] = 0;
+        add_diag(op, g5, x, in + (size_t)x * 12, acc);
+        for (int mu = 0; mu < 4; ++mu) {
+            int wf, wb;
+            long xf = neighbour(op->dims, x, mu, +1, &wf);
+            long xb = neighbour(op->dims, x, mu, -1, &wb);
+            double pf = (op->antiperiodic_t && mu == 0 && wf) ? -1.0 : 1.0;
+            double pb = (op->antiperiodic_t && mu == 0 && wb) ? -1.0 : 1.0;
+            if (!bdims || same_block(op->dims, bdims, x, xf))
+                add_hop(g[mu], -1.0, link(op->U, x, mu), in + (size_t)xf * 12, pf, acc);
+            if (!bdims || same_block(op->dims, bdims, x, xb)) {
+                or_cplx Wd[9];
+                dag(link(op->U, xb, mu), Wd);
+                add_hop(g[mu], +1.0, Wd, in + (size_t)xb * 12, pb, acc);
+            }
+        }
+        memcpy(out + (size_t)x * 12, acc, sizeof acc);
+    }
+}
+
+void or_dirac(const or_op* op, const or_cplx* in, or_cplx* out) {
+    dirac_generic(op, NULL, in, out);
+}
+
+void or_dirac_blockdiag(const or_op* op, const int bdims[4], const or_cplx* in, or_cplx* out) {
+    dirac_generic(op, bdims, in, out);
+}
+
+int or_block_colour(const int dims[4], const int bdims[4], long site) {
+    int B[4];
+    block_of(dims, bdims, site, B);
+    return (B[0] + B[1] + B[2] + B[3]) & 1;
+}
+
+/* ------------------------------------------------------------ block solves */
+
+/* Sites of block B in local lexicographic order (t slowest). */
+static void block_sites(const int dims[4], const int bdims[4], const int B[4], long* sites) {
+    long n = 0;
+    int c[4];
+    for (int a0 = 0; a0 < bdims[0]; ++a0)
+        for (int a1 = 0; a1 < bdims[1]; ++a1)
+            for (int a2 = 0; a2 < bdims[2]; ++a2)
+                for (int a3 = 0; a3 < bdims[3]; ++a3) {
+                    c[0] = B[0] * bdims[0] + a0;
+                    c[1] = B[1] * bdims[1] + a1;
+                    c[2] = B[2] * bdims[2] + a2;
+                    c[3] = B[3] * bdims[3] + a3;
+                    sites[n++] = coords_site(dims, c);
+                }
+}
+
+/* Local index of site s in block B, or -1 when s is outside B. */
+static long local_index(const int dims[4], const int bdims[4], const int B[4], long s) {
+    int c[4];
+    site_coords(dims, s, c);
+    long l = 0;
+    for (int a = 0; a < 4; ++a) {
+        int rel = c[a] - B[a] * bdims[a];
+        if (rel < 0 || rel >= bdims[a]) return -1;
+        l = l * bdims[a] + rel;
+    }
+    return l;
+}
+
+/* out = D_BB in for block-local vectors (Vb x 12): diagonal part plus the hops
+ * whose both ends lie in the block. */
+static void dirac_block_local(const or_op* op, const int bdims[4], const int B[4], const long* sites, long Vb,
+                              const or_cplx* in, or_cplx* out) {
+    or_cplx g[4][16], g5[16];
+    for (int mu = 0; mu < 4; ++mu) or_gamma(mu, g[mu]);
+    or_gamma(4, g5);
+    for (long l = 0; l < Vb; ++l) {
+        long x = sites[l];
+        or_cplx acc[12];
+        for (int i = 0; i < 12; ++i) acc[i] = 0;
+        add_diag(op, g5, x, in + l * 12, acc);
+        for (int mu = 0; mu < 4; ++mu) {
+            int wf, wb;
+            long xf = neighbour(op->dims, x, mu, +1, &wf);
+            long xb = neighbour(op->dims, x, mu, -1, &wb);
+            long lf = local_index(op->dims, bdims, B, xf);
+            long lb = local_index(op->dims, bdims, B, xb);
+            double pf = (op->antiperiodic_t && mu == 0 && wf) ? -1.0 : 1.0;
+            double pb = (op->antiperiodic_t && mu == 0 && wb) ? -1.0 : 1.0;
+            if (lf >= 0) add_hop(g[mu], -1.0, link(op->U, x, mu), in + lf * 12, pf, acc);
+            if (lb >= 0) {
+                or_cplx Wd[9];
+                dag(link(op->U, xb, mu), Wd);
+                add_hop(g[mu], +1.0, Wd, in + lb * 12, pb, acc);
+            }
+        }
+        memcpy(out + l * 12, acc, sizeof acc);
+    }
+}
+
+static or_cplx vdot(const or_cplx* a, const or_cplx* b, long n) {
+    or_cplx t = 0;
+    for (long i = 0; i < n; ++i) t += conj(a[i]) * b[i];
+    return t;
+}
+
+/* Minimal residual on one block (Saad): e = 0, rho = r; repeat
+ * q = D_BB rho, alpha = <q,rho>/<q,q>, e += alpha rho, rho -= alpha q. */
+static void mr_local(const or_op* op, const int bdims[4], const int B[4], const long* sites, long Vb,
+                     const or_cplx* r, or_cplx* e, int iters) {
+    long n = Vb * 12;
+    or_cplx* rho = malloc(sizeof(or_cplx) * n);
+    or_cplx* q = malloc(sizeof(or_cplx) * n);
+    memcpy(rho, r, sizeof(or_cplx) * n);
+    for (long i = 0; i < n; ++i) e[i] = 0;
+    for (int k = 0; k < iters; ++k) {
+        dirac_block_local(op, bdims, B, sites, Vb, rho, q);
+        or_cplx qr = vdot(q, rho, n);
+        double qq = creal(vdot(q, q, n));
+        if (qq == 0.0) break;
+        or_cplx alpha = qr / qq;
+        for (long i = 0; i < n; ++i) {
+            e[i] += alpha * rho[i];
+            rho[i] -= alpha * q[i];
+        }
+    }
+    free(rho);
+    free(q);
+}
+
+/* Exact solve D_BB e = r by dense Gaussian elimination with partial pivoting. */
+static void exact_local(const or_op* op, const int bdims[4], const int B[4], const long* sites, long Vb,
+                        const or_cplx* r, or_cplx* e) {
+    long n = Vb * 12;
+    or_cplx* A = malloc(sizeof(or_cplx) * n * n); /* column j = D_BB e_j, stored row-major A[i*n+j] */
+    or_cplx* unit = calloc(n, sizeof(or_cplx));
+    or_cplx* col = malloc(sizeof(or_cplx) * n);
+    or_cplx* rhs = malloc(sizeof(or_cplx) * n);
+    for (long j = 0; j < n; ++j) {
+        unit[j] = 1.0;
+        dirac_block_local(op, bdims, B, sites, Vb, unit, col);
+        unit[j] = 0.0;
+        for (long i = 0; i < n; ++i) A[i * n + j] = col[i];
+    }
+    memcpy(rhs, r, sizeof(or_cplx) * n);
+    for (long k = 0; k < n; ++k) {
+        long p = k;
+        for (long i = k + 1; i < n; ++i)
+            if (cabs(A[i * n + k]) > cabs(A[p * n + k])) p = i;
+        if (p != k) {
+            for (long j = 0; j < n; ++j) {
+                or_cplx t = A[k * n + j];
+                A[k * n + j] = A[p * n + j];
+                A[p * n + j] = t;
+            }
+            or_cplx t = rhs[k];
+            rhs[k] = rhs[p];
+            rhs[p] = t;
+        }
+        for (long i = k + 1; i < n; ++i) {
+            or_cplx f = A[i * n + k] / A[k * n + k];
+            if (f == 0) continue;
+            for (long j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            rhs[i] -= f * rhs[k];
+        }
+    }
+    for (long i = n - 1; i >= 0; --i) {
+        or_cplx t = rhs[i];
+        for (long j = i + 1; j < n; ++j) t -= A[i * n + j] * e[j];
+        e[i] = t / A[i * n + i];
+    }
+    free(A);
+    free(unit);
+    free(col);
+    free(rhs);
+}
+
+void or_mr_block(const or_op* op, const int bdims[4], const int B[4], const or_cplx* r, or_cplx* e, int iters) {
+    long Vb = (long)bdims[0] * bdims[1] * bdims[2] * bdims[3];
+    long* sites = malloc(sizeof(long) * Vb);
+    or_cplx* rl = malloc(sizeof(or_cplx) * Vb * 12);
+    or_cplx* el = malloc(sizeof(or_cplx) * Vb * 12);
+    block_sites(op->dims, bdims, B, sites);
+    for (long l = 0; l < Vb; ++l) memcpy(rl + l * 12, r + (size_t)sites[l] * 12, sizeof(or_cplx) * 12);
+    mr_local(op, bdims, B, sites, Vb, rl, el, iters);
+    for (long l = 0; l < Vb; ++l) memcpy(e + (size_t)sites[l] * 12, el + l * 12, sizeof(or_cplx) * 12);
+    free(sites);
+    free(rl);
+    free(el);
+}
+
+/* ------------------------------------------------------------------- SAP */
+
+int or_sap(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, const or_cplx* b, or_cplx* x) {
+    int nb[4];
+    for (int a = 0; a < 4; ++a) {
+        if (bdims[a] <= 0 || op->dims[a] % bdims[a] != 0) return -2;
+        nb[a] = op->dims[a] / bdims[a];
+        if (nb[a] % 2 != 0) return -3;
+    }
+    long V = or_volume(op->dims);
+    long Vb = (long)bdims[0] * bdims[1] * bdims[2] * bdims[3];
+    long nblocks = (long)nb[0] * nb[1] * nb[2] * nb[3];
+    or_cplx* r = malloc(sizeof(or_cplx) * V * 12);
+
+    for (int cyc = 0; cyc < n_cycles; ++cyc) {
+        for (int colour = 0; colour < 2; ++colour) {
+            /* residual r = b - D x on the whole lattice */
+            or_dirac(op, x, r);
+            for (long i = 0; i < V * 12; ++i) r[i] = b[i] - r[i];
+            /* every block of this colour: e_B ~ D_BB^-1 r_B, x_B += e_B */
+#pragma omp parallel for schedule(dynamic)
+            for (long bi = 0; bi < nblocks; ++bi) {
+                int B[4];
+                long t = bi;
+                for (int a = 3; a >= 0; --a) {
+                    B[a] = (int)(t % nb[a]);
+                    t /= nb[a];
+                }
+                if (((B[0] + B[1] + B[2] + B[3]) & 1) != colour) continue;
+                long* sites = malloc(sizeof(long) * Vb);
+                or_cplx* rl = malloc(sizeof(or_cplx) * Vb * 12);
+                or_cplx* el = malloc(sizeof(or_cplx) * Vb * 12);
+                block_sites(op->dims, bdims, B, sites);
+                for (long l = 0; l < Vb; ++l) memcpy(rl + l * 12, r + (size_t)sites[l] * 12, sizeof(or_cplx) * 12);
+                if (mr_iters >= 0)
+                    mr_local(op, bdims, B, sites, Vb, rl, el, mr_iters);
+                else
+                    exact_local(op, bdims, B, sites, Vb, rl, el);
+                for (long l = 0; l < Vb; ++l)
+                    for (int i = 0; i < 12; ++i) x[(size_t)sites[l] * 12 + i] += el[l * 12 + i];
+                free(sites);
+                free(rl);
+                free(el);
+            }
+        }
+    }
+    free(r);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- FGMRES */
+
+static double vnorm(const or_cplx* a, long n) {
+    double t = 0;
+    for (long i = 0; i < n; ++i) t += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return sqrt(t);
+}
+
+static double true_residual(const or_op* op, const or_cplx* b, const or_cplx* x, or_cplx* r, long n) {
+    or_dirac(op, x, r);
+    for (long i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    return vnorm(r, n);
+}
+
+int or_fgmres(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters, int precond,
+              const int bdims[4], int n_cycles, int mr_iters, or_report* rep) {
+    long n = or_volume(op->dims) * 12;
+    int m = restart;
+    or_cplx* Vv = malloc(sizeof(or_cplx) * n * (m + 1));
+    or_cplx* Z = malloc(sizeof(or_cplx) * n * m);
+    or_cplx* w = malloc(sizeof(or_cplx) * n);
+    or_cplx* r = malloc(sizeof(or_cplx) * n);
+    or_cplx* H = calloc((size_t)(m + 1) * m, sizeof(or_cplx)); /* H[i*m + j] */
+    double* cs = malloc(sizeof(double) * m);
+    or_cplx* sn = malloc(sizeof(or_cplx) * m);
+    or_cplx* g = malloc(sizeof(or_cplx) * (m + 1));
+    or_cplx* y = malloc(sizeof(or_cplx) * m);
+
+    double bnorm = vnorm(b, n);
+    int iters = 0, restarts = 0, converged = 0;
+    double rel = 0.0;
+    if (bnorm == 0.0) {
+        for (long i = 0; i < n; ++i) x[i] = 0;
+        converged = 1;
+        goto done;
+    }
+    rel = true_residual(op, b, x, r, n) / bnorm;
+    while (rel > tol && iters < max_iters) {
+        double beta = vnorm(r, n);
+        for (long i = 0; i < n; ++i) Vv[i] = r[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0;
+        g[0] = beta;
+        int j_done = 0;
+        for (int j = 0; j < m && iters < max_iters; ++j) {
+            or_cplx* vj = Vv + (size_t)j * n;
+            or_cplx* zj = Z + (size_t)j * n;
+            /* z_j = M v_j */
+            if (precond) {
+                for (long i = 0; i < n; ++i) zj[i] = 0;
+                or_sap(op, bdims, n_cycles, mr_iters, vj, zj);
+            } else {
+                memcpy(zj, vj, sizeof(or_cplx) * n);
+            }
+            /* w = D z_j, then modified Gram-Schmidt */
+            or_dirac(op, zj, w);
+            for (int i = 0; i <= j; ++i) {
+                or_cplx h = vdot(Vv + (size_t)i * n, w, n);
+                H[i * m + j] = h;
+                for (long k = 0; k < n; ++k) w[k] -= h * Vv[(size_t)i * n + k];
+            }
+            double hn = vnorm(w, n);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0)
+                for (long k = 0; k < n; ++k) Vv[(size_t)(j + 1) * n + k] = w[k] / hn;
+            /* apply earlier rotations to the new column */
+            for (int i = 0; i < j; ++i) {
+                or_cplx a = H[i * m + j], c2 = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c2;
+                H[(i + 1) * m + j] = -conj(sn[i]) * a + cs[i] * c2;
+            }
+            /* new rotation zeroing H[j+1][j] */
+            or_cplx a = H[j * m + j], c2 = H[(j + 1) * m + j];
+            double t = sqrt(creal(a) * creal(a) + cimag(a) * cimag(a) + creal(c2) * creal(c2) + cimag(c2) * cimag(c2));
+            if (cabs(a) == 0.0) {
+                cs[j] = 0.0;
+                sn[j] = 1.0;
+            } else {
+                cs[j] = cabs(a) / t;
+                sn[j] = (a / cabs(a)) * conj(c2) / t;
+            }
+            H[j * m + j] = cs[j] * a + sn[j] * c2;
+            H[(j + 1) * m + j] = 0;
+            g[j + 1] = -conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            ++iters;
+            j_done = j + 1;
+            if (cabs(g[j + 1]) / bnorm <= tol || hn == 0.0) break;
+        }
+        /* y = H^-1 g (upper triangular), x += Z y */
+        for (int i = j_done - 1; i >= 0; --i) {
+            or_cplx t2 = g[i];
+            for (int k = i + 1; k < j_done; ++k) t2 -= H[i * m + k] * y[k];
+            y[i] = t2 / H[i * m + i];
+        }
+        for (int k = 0; k < j_done; ++k)
+            for (long i = 0; i < n; ++i) x[i] += y[k] * Z[(size_t)k * n + i];
+        ++restarts;
+        rel = true_residual(op, b, x, r, n) / bnorm;
+    }
+    converged = rel <= tol;
+done:
+    if (rep) {
+        rep->iters = iters;
+        rep->restarts = restarts;
+        rep->converged = converged;
+        rep->true_rel_res = rel;
+    }
+    free(Vv);
+    free(Z);
+    free(w);
+    free(r);
+    free(H);
+    free(cs);
+    free(sn);
+    free(g);
+    free(y);
+    return converged ? 0 : 1;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

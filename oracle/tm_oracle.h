@@ -1,0 +1,96 @@
+/*
+ * Plain FP64 CPU oracle for the twisted-mass Wilson-clover operator, the
+ * red-black SAP smoother with minimal-residual block solves, and flexible
+ * GMRES (arXiv:1610.02370).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the independent truth that the
+ * GPU library is checked against.  It shares no code, header, table or
+ * constant with the GPU library and must never be linked into it.  Only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg load it.
+ *
+ * Conventions (the paper fixes gamma5 and the Clifford relation; the rest is
+ * a reading, listed in the design notes):
+ *   dims[4] = (T, Z, Y, X); site index lexicographic, t slowest, x fastest.
+ *   Direction mu: 0 = t (x0), 1 = x (x1), 2 = y (x2), 3 = z (x3).
+ *   Spinor at a site: psi[s][c], s = spin 0..3, c = colour 0..2 (12 complex).
+ *   Links: U[site][mu][row][col], complex, SU(3).
+ *   Clover: clov[site][12][12] complex, index 3*s + c.
+ *   Chiral gamma basis with gamma5 = gamma0 gamma1 gamma2 gamma3 = diag(1,1,-1,-1).
+ *   m = 1/(2 kappa) - 4 is applied by the caller; the oracle takes m.
+ *
+ * Parity status of each function is stated at its definition in tm_oracle.c.
+ */
+#ifndef TM_ORACLE_H
+#define TM_ORACLE_H
+
+#include <complex.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef double _Complex or_cplx;
+
+typedef struct {
+    int dims[4];            /* (T, Z, Y, X) */
+    int antiperiodic_t;     /* 1: spinor hops across the t boundary pick up -1 */
+    const or_cplx* U;       /* [V][4][3][3] */
+    const or_cplx* clov;    /* [V][12][12], may be NULL when csw == 0 */
+    double m;               /* bare mass: D contains (m + 4) */
+    double mu;              /* twisted mass: D contains + i mu Gamma5 */
+} or_op;
+
+typedef struct {
+    int iters;              /* total Arnoldi steps */
+    int restarts;           /* completed restart cycles */
+    int converged;          /* 1 when the true residual met tol */
+    double true_rel_res;    /* ||b - D x|| / ||b|| at exit */
+} or_report;
+
+long or_volume(const int dims[4]);
+/* gamma matrix mu (0..3), or gamma5 for mu == 4; g[4*row + col]. */
+void or_gamma(int mu, or_cplx g[16]);
+
+/* Clover term of the paper's Wilson operator: -(csw/32) sum_{mu,nu}
+ * (gamma_mu gamma_nu) (x) (Q_munu - Q_numu), as a 12x12 matrix per site. */
+void or_clover(const int dims[4], const or_cplx* U, double csw, or_cplx* clov);
+
+/* out = D(mu) in over the whole lattice. */
+void or_dirac(const or_op* op, const or_cplx* in, or_cplx* out);
+
+/* out = block-diagonal part of D(mu) for Schwarz blocks bdims (hops that
+ * leave a block dropped: Dirichlet cuts at block faces). */
+void or_dirac_blockdiag(const or_op* op, const int bdims[4], const or_cplx* in, or_cplx* out);
+
+/* Colour of the Schwarz block that holds site: (sum of block coords) mod 2. */
+int or_block_colour(const int dims[4], const int bdims[4], long site);
+
+/* Minimal-residual approximation of D_BB^{-1} r on one block, block given by
+ * its block coordinates B[4]; r and e are full-lattice vectors, only the
+ * block's sites are read / written (e is overwritten there). */
+void or_mr_block(const or_op* op, const int bdims[4], const int B[4], const or_cplx* r,
+                 or_cplx* e, int iters);
+
+/* Red-black multiplicative SAP: n_cycles cycles, colour 0 then colour 1,
+ * each block solved by mr_iters MR steps (mr_iters < 0: exact block solve by
+ * dense Gaussian elimination, used only by the closed-form pins).
+ * x is in/out. Returns 0, or -3 when a direction has an odd block count. */
+int or_sap(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, const or_cplx* b,
+           or_cplx* x);
+
+/* Flexible GMRES(restart) with right preconditioning (precond: 0 = none,
+ * 1 = SAP with the given parameters), modified Gram-Schmidt, complex Givens
+ * rotations.  x is in/out (initial guess).  Stops when the true relative
+ * residual <= tol or after max_iters Arnoldi steps.  Returns 0 when
+ * converged, 1 otherwise. */
+int or_fgmres(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
+              int precond, const int bdims[4], int n_cycles, int mr_iters, or_report* rep);
+
+/* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
+int or_num_threads(void);
+void or_set_num_threads(int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,57 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake into a copy of the oracle source (on the CPU only),
+builds it into a temporary library and runs the pin tests against it; at least one
+pin must fail.  The shipped oracle itself is untouched.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "tm_oracle.c")
+
+MUTATIONS = {
+    # forward hop with (1 + gamma) instead of (1 - gamma)
+    "projector_sign": ("add_hop(g[mu], -1.0, link(op->U, x, mu)", "add_hop(g[mu], +1.0, link(op->U, x, mu)"),
+    # backward hop uses U_mu(x) instead of U_mu(x - mu)
+    "backward_link_site": ("dag(link(op->U, xb, mu), Wd);\n                add_hop", "dag(link(op->U, x, mu), Wd);\n                add_hop"),
+    # link transposed in the colour product
+    "link_transposed": ("col += W[3 * c + cp] * psi_n[3 * sp + cp];", "col += W[3 * cp + c] * psi_n[3 * sp + cp];"),
+    # twisted mass with the wrong sign
+    "twist_sign": ("out[3 * s + c] += _Complex_I * op->mu", "out[3 * s + c] -= _Complex_I * op->mu"),
+    # one clover leaf dropped
+    "clover_leaf_dropped": ("mm4(d1, d2, link(U, xmm_mn, mu), link(U, xmn, nu), leaf);\n    for (int i = 0; i < 9; ++i) Q[i] += leaf[i];",
+                            "mm4(d1, d2, link(U, xmm_mn, mu), link(U, xmn, nu), leaf);"),
+    # clover normalisation 1/16 instead of 1/32
+    "clover_norm": ("-(csw / 32.0)", "-(csw / 16.0)"),
+    # MR step with conjugated alpha
+    "mr_alpha_conj": ("or_cplx alpha = qr / qq;", "or_cplx alpha = conj(qr) / qq;"),
+    # SAP sweeps colour 1 first
+    "sap_colour_order": ("!= colour) continue;", "!= 1 - colour) continue;"),
+    # Dirichlet cut missing: block operator keeps hops that leave the block
+    "no_dirichlet_cut": ("if (lf >= 0) add_hop", "if (lf >= 0 || 1) add_hop"),
+    # Givens rotation without the conjugate
+    "givens_conj": ("g[j + 1] = -conj(sn[j]) * g[j];", "g[j + 1] = -sn[j] * g[j];"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    mutated = tmp_path / "tm_oracle.c"
+    mutated.write_text(src.replace(old, new))
+    (tmp_path / "tm_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "tm_oracle.h")).read())
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(mutated), "-lm"])
+    env = dict(os.environ, TM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    r = subprocess.run(
+        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+         os.path.join(ROOT, "tests", "test_oracle_operator.py"), os.path.join(ROOT, "tests", "test_oracle_sap.py")],
+        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"planted mistake {name} was not caught:\n{r.stdout[-2000:]}"

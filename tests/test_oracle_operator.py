@@ -1,0 +1,276 @@
+"""Pins of the oracle's operator against what the paper and mathematics fix.
+
+Operator (section 2.1): D(mu) = (m+4) + clover - 1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu)
++ (1+g_mu) U_mu(x-mu)^+ psi(x-mu)] + i mu Gamma5.  Each test computes its expected
+value by a different route than the oracle's site loop (closed forms, invariants,
+library linear algebra), so that a wrong sign, index or transposition fails one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_02370_amd import synth
+
+AXIS = {0: 0, 1: 3, 2: 2, 3: 1}  # direction mu -> array axis of dims (T, Z, Y, X)
+
+
+def coords(dims):
+    """[V][4] coordinates per direction mu (t, x, y, z)."""
+    grid = np.indices(dims).reshape(4, -1).T  # axes (t, z, y, x)
+    return np.stack([grid[:, AXIS[mu]] for mu in range(4)], axis=1)
+
+
+def dir_extent(dims, mu):
+    return dims[AXIS[mu]]
+
+
+def g5_apply(psi):
+    out = psi.reshape(-1, 4, 3).copy()
+    out[:, 2:, :] *= -1
+    return out.reshape(psi.shape)
+
+
+def vdot(a, b):
+    return np.vdot(a.ravel(), b.ravel())
+
+
+# ------------------------------------------------------------------ gammas
+
+def test_gamma_clifford_hermitian_gamma5():
+    g = [oracle.gamma(mu) for mu in range(4)]
+    for a in range(4):
+        assert np.allclose(g[a], g[a].conj().T, atol=0)
+        for b in range(4):
+            anti = g[a] @ g[b] + g[b] @ g[a]
+            assert np.allclose(anti, 2 * np.eye(4) * (a == b), atol=0)
+    g5 = g[0] @ g[1] @ g[2] @ g[3]
+    assert np.array_equal(g5, np.diag([1, 1, -1, -1]).astype(complex))
+    assert np.array_equal(oracle.gamma(4), g5)
+
+
+# ------------------------------------------------------------------ plane waves
+
+def plane_wave_matrix(p, W, m, mu):
+    """12x12 action of D on exp(i p.x) chi when every U_mu(x) equals the constant W[mu]."""
+    M = (m + 4) * np.eye(12, dtype=complex)
+    for d in range(4):
+        g = oracle.gamma(d)
+        fw = np.kron(np.eye(4) - g, W[d]) * np.exp(1j * p[d])
+        bw = np.kron(np.eye(4) + g, W[d].conj().T) * np.exp(-1j * p[d])
+        M -= 0.5 * (fw + bw)
+    M += 1j * mu * np.kron(oracle.gamma(4), np.eye(3))
+    return M
+
+
+def apply_plane_wave(dims, U, p, chi, m, mu, antiperiodic=False):
+    X = coords(dims)
+    phase = np.exp(1j * (X @ np.asarray(p)))
+    psi = phase[:, None] * chi[None, :]
+    op = oracle.Operator(dims, U, m, mu, antiperiodic_t=antiperiodic)
+    return op.apply(psi).reshape(-1, 12), phase
+
+
+@pytest.mark.parametrize("antiperiodic", [False, True])
+def test_free_field_plane_waves(antiperiodic):
+    dims = (4, 6, 4, 8)
+    V = oracle.volume(dims)
+    U = np.broadcast_to(np.eye(3, dtype=complex), (V, 4, 3, 3)).copy()
+    rng = np.random.default_rng(0)
+    m, mu = -0.875, 0.01
+    for n in [(0, 0, 0, 0), (1, 2, 3, 1), (3, 1, 5, 2)]:
+        p = []
+        for d in range(4):
+            L = dir_extent(dims, d)
+            shift = 0.5 if (antiperiodic and d == 0) else 0.0
+            p.append(2 * np.pi * (n[d] + shift) / L)
+        chi = rng.normal(size=12) + 1j * rng.normal(size=12)
+        out, phase = apply_plane_wave(dims, U, p, chi, m, mu, antiperiodic)
+        W = [np.eye(3)] * 4
+        expect = phase[:, None] * (plane_wave_matrix(p, W, m, mu) @ chi)[None, :]
+        assert np.abs(out - expect).max() < 1e-13
+
+
+def test_free_field_eigenvalues_closed_form():
+    # eigenvalues m + sum(1 - cos p) +- i sqrt(sum sin^2 p + mu^2), each 6-fold
+    dims = (4, 2, 2, 4)
+    V = oracle.volume(dims)
+    U = np.broadcast_to(np.eye(3, dtype=complex), (V, 4, 3, 3)).copy()
+    m, mu = -0.875, 0.01
+    ev = np.linalg.eigvals(oracle.Operator(dims, U, m, mu).dense())
+    expect = []
+    for nt in range(dims[0]):
+        for nz in range(dims[1]):
+            for ny in range(dims[2]):
+                for nx in range(dims[3]):
+                    p = 2 * np.pi * np.array([nt / dims[0], nx / dims[3], ny / dims[2], nz / dims[1]])
+                    re = m + np.sum(1 - np.cos(p))
+                    im = np.sqrt(np.sum(np.sin(p) ** 2) + mu ** 2)
+                    expect += [re + 1j * im] * 6 + [re - 1j * im] * 6
+    key = lambda z: (np.round(z.real, 9), np.round(z.imag, 9))
+    a = np.array(sorted(ev, key=key))
+    b = np.array(sorted(expect, key=key))
+    assert np.abs(a - b).max() < 1e-12
+
+
+def test_constant_nonabelian_links_plane_wave():
+    dims = (4, 4, 6, 4)
+    V = oracle.volume(dims)
+    W = [synth.su3_field((1, 1, 1, 1), 2.0, seed=40 + d)[0] for d in range(4)]
+    U = np.empty((V, 4, 3, 3), complex)
+    for d in range(4):
+        U[:, d] = W[d]
+    m, mu = -0.4132, 0.001
+    rng = np.random.default_rng(1)
+    p = [2 * np.pi * k / dir_extent(dims, d) for d, k in enumerate((1, 3, 2, 5))]
+    chi = rng.normal(size=12) + 1j * rng.normal(size=12)
+    out, phase = apply_plane_wave(dims, U, p, chi, m, mu)
+    expect = phase[:, None] * (plane_wave_matrix(p, W, m, mu) @ chi)[None, :]
+    assert np.abs(out - expect).max() < 1e-13
+
+
+# ------------------------------------------------------------------ clover
+
+def abelian_flux_field(dims, mu, nu, n_flux):
+    """Constant field strength in the (mu,nu) plane, colour structure diag(e^{ia}, e^{-ia}, 1):
+    every (mu,nu) plaquette equals diag(e^{i phi}, e^{-i phi}, 1), phi = 2 pi n / (L_mu L_nu)."""
+    V = oracle.volume(dims)
+    X = coords(dims)
+    Lm, Ln = dir_extent(dims, mu), dir_extent(dims, nu)
+    phi = 2 * np.pi * n_flux / (Lm * Ln)
+
+    def su3(a):
+        z = np.zeros((a.size, 3, 3), complex)
+        z[:, 0, 0] = np.exp(1j * a)
+        z[:, 1, 1] = np.exp(-1j * a)
+        z[:, 2, 2] = 1
+        return z
+
+    U = np.broadcast_to(np.eye(3, dtype=complex), (V, 4, 3, 3)).copy()
+    U[:, nu] = su3(phi * X[:, mu])
+    edge = X[:, mu] == Lm - 1
+    U[edge, mu] = su3(-phi * Lm * X[edge, nu])
+    return U, phi
+
+
+@pytest.mark.parametrize("plane", [(1, 2), (0, 3), (2, 0)])
+def test_clover_constant_abelian_field_closed_form(plane):
+    mu, nu = plane
+    dims = (4, 6, 4, 6)
+    U, phi = abelian_flux_field(dims, mu, nu, 1)
+    csw = 1.5
+    C = oracle.clover(dims, U, csw)
+    F = 8j * np.sin(phi) * np.diag([1.0, -1.0, 0.0])
+    expect = -(csw / 16.0) * np.kron(oracle.gamma(mu) @ oracle.gamma(nu), F)
+    assert np.abs(C - expect[None]).max() < 1e-13
+
+
+def test_clover_free_field_hermitian_commutes_gamma5():
+    dims = (4, 4, 4, 4)
+    V = oracle.volume(dims)
+    U1 = np.broadcast_to(np.eye(3, dtype=complex), (V, 4, 3, 3)).copy()
+    assert np.abs(oracle.clover(dims, U1, 1.7)).max() == 0
+    U = synth.gauge_field(dims, 0.6, seed=5)
+    C = oracle.clover(dims, U, 1.5)
+    assert np.abs(C - C.conj().transpose(0, 2, 1)).max() < 1e-14
+    G5 = np.kron(np.diag([1, 1, -1, -1]), np.eye(3))
+    assert np.abs(G5 @ C - C @ G5).max() < 1e-14
+    assert np.abs(C).max() > 1e-2
+
+
+def gauge_transform(dims, U, G):
+    """U^G_mu(x) = G(x) U_mu(x) G(x+mu)^+."""
+    V = oracle.volume(dims)
+    idx = np.arange(V).reshape(dims)
+    out = np.empty_like(U)
+    for mu in range(4):
+        fwd = np.roll(idx, -1, axis=AXIS[mu]).ravel()
+        out[:, mu] = G @ U[:, mu] @ G[fwd].conj().transpose(0, 2, 1)
+    return out
+
+
+def test_clover_gauge_covariance():
+    dims = (4, 4, 6, 4)
+    U = synth.gauge_field(dims, 0.6, seed=6)
+    G = synth.su3_field(dims, 3.0, seed=7)
+    C = oracle.clover(dims, U, 1.5)
+    CG = oracle.clover(dims, gauge_transform(dims, U, G), 1.5)
+    GG = np.einsum("ab,nij->naibj", np.eye(4), G).reshape(-1, 12, 12)
+    assert np.abs(CG - GG @ C @ GG.conj().transpose(0, 2, 1)).max() < 1e-13
+
+
+# ------------------------------------------------------------------ invariants
+
+@pytest.fixture(scope="module")
+def rough():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.6, seed=8)
+    return dims, U
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.5])
+def test_gamma5_hermiticity(rough, csw):
+    dims, U = rough
+    mu = 0.05
+    D = oracle.Operator(dims, U, oracle.kappa_to_m(0.1394), mu, csw)
+    Dm = D.with_mu(-mu)
+    rng = np.random.default_rng(2)
+    phi = rng.normal(size=(D.V, 12)) + 1j * rng.normal(size=(D.V, 12))
+    psi = rng.normal(size=(D.V, 12)) + 1j * rng.normal(size=(D.V, 12))
+    lhs = vdot(phi, D.apply(psi))
+    rhs = vdot(g5_apply(Dm.apply(g5_apply(phi))), psi)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+@pytest.mark.parametrize("csw", [0.0, 1.5])
+def test_normal_operator_identity(rough, csw):
+    # D(mu)^+ D(mu) = D(0)^+ D(0) + mu^2, tested in polarised form <D phi, D psi>
+    dims, U = rough
+    mu = 0.3
+    D = oracle.Operator(dims, U, oracle.kappa_to_m(0.1632), mu, csw)
+    D0 = D.with_mu(0.0)
+    rng = np.random.default_rng(3)
+    phi = rng.normal(size=(D.V, 12)) + 1j * rng.normal(size=(D.V, 12))
+    psi = rng.normal(size=(D.V, 12)) + 1j * rng.normal(size=(D.V, 12))
+    lhs = vdot(D.apply(phi), D.apply(psi))
+    rhs = vdot(D0.apply(phi), D0.apply(psi)) + mu ** 2 * vdot(phi, psi)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_gauge_covariance_of_D(rough):
+    dims, U = rough
+    G = synth.su3_field(dims, 3.0, seed=9)
+    UG = gauge_transform(dims, U, G)
+    m = oracle.kappa_to_m(0.1373)
+    D = oracle.Operator(dims, U, m, 0.0009, 1.5)
+    DG = oracle.Operator(dims, UG, m, 0.0009, 1.5)
+    rng = np.random.default_rng(4)
+    psi = (rng.normal(size=(D.V, 4, 3)) + 1j * rng.normal(size=(D.V, 4, 3)))
+    rot = lambda v: np.einsum("nij,nsj->nsi", G, v.reshape(-1, 4, 3))
+    lhs = DG.apply(rot(psi))
+    rhs = rot(D.apply(psi))
+    assert np.abs(lhs - rhs).max() < 1e-13
+
+
+def test_singular_values_and_conjugate_spectra():
+    # SVD of D(mu): sigma = sqrt(lambda(H_W)^2 + mu^2) with H_W = Gamma5 D_W Hermitian;
+    # spectra of D(+mu) and D(-mu) are complex conjugates.
+    from scipy.optimize import linear_sum_assignment
+
+    dims = (4, 4, 2, 2)
+    U = synth.gauge_field(dims, 0.6, seed=10)
+    mu = 0.2
+    D = oracle.Operator(dims, U, oracle.kappa_to_m(0.1632), mu, 1.5)
+    M = D.dense()
+    MW = D.with_mu(0.0).dense()
+    G5 = np.kron(np.eye(D.V), np.kron(np.diag([1, 1, -1, -1]), np.eye(3)))
+    HW = G5 @ MW
+    assert np.abs(HW - HW.conj().T).max() < 1e-13
+    lam = np.linalg.eigvalsh(HW)
+    sv = np.sort(np.linalg.svd(M, compute_uv=False))
+    assert np.abs(sv - np.sort(np.sqrt(lam ** 2 + mu ** 2))).max() < 1e-12
+    assert sv[0] >= mu - 1e-12
+    ep = np.linalg.eigvals(M)
+    em = np.linalg.eigvals(D.with_mu(-mu).dense())
+    cost = np.abs(ep[:, None] - np.conj(em)[None, :])
+    r, c = linear_sum_assignment(cost)
+    assert cost[r, c].max() < 1e-10

@@ -1,0 +1,187 @@
+"""Pins of the oracle's Schwarz blocks, MR block solves, SAP and FGMRES.
+
+SAP (section 2.4, eqs. for E_SAP and B_rr / B_bb): blocks coloured like a
+checkerboard, colour 0 (the block holding the origin) swept first; block inverses
+approximated by minimal-residual steps.  FGMRES (section 2.5): flexible GMRES with
+right preconditioning.  Expected values come from dense linear algebra (numpy /
+LAPACK), closed forms and invariants, never from the oracle's own loops.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_02370_amd import synth
+
+
+def block_masks(op, bdims):
+    colour = np.array([op.block_colour(bdims, s) for s in range(op.V)])
+    return np.repeat(colour, 12)
+
+
+def block_ids(dims, bdims):
+    grid = np.indices(dims).reshape(4, -1).T
+    B = grid // np.asarray(bdims)
+    nb = np.asarray(dims) // np.asarray(bdims)
+    return np.ravel_multi_index(B.T, nb)
+
+
+@pytest.fixture(scope="module")
+def small():
+    dims = (4, 4, 2, 2)
+    U = synth.gauge_field(dims, 0.5, seed=11)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(0.16), 0.05, csw=1.5)
+    return op, (2, 2, 1, 1)
+
+
+def test_blockdiag_is_restriction(small):
+    op, bd = small
+    bid = np.repeat(block_ids(op.dims, bd), 12)
+    rng = np.random.default_rng(0)
+    psi = rng.normal(size=op.V * 12) + 1j * rng.normal(size=op.V * 12)
+    total = np.zeros_like(psi)
+    for b in np.unique(bid):
+        part = np.where(bid == b, psi, 0)
+        full = op.apply(part)
+        # D_BB psi_B equals D psi_B restricted to block B
+        blk = op.apply_blockdiag(part, bd)
+        assert np.abs(np.where(bid == b, full - blk, blk)).max() < 1e-14
+        total += blk
+    assert np.abs(total - op.apply_blockdiag(psi, bd)).max() < 1e-13
+
+
+def test_same_colour_blocks_do_not_couple(small):
+    op, bd = small
+    col = block_masks(op, bd)
+    bid = np.repeat(block_ids(op.dims, bd), 12)
+    rng = np.random.default_rng(1)
+    for c in (0, 1):
+        for b in np.unique(bid[col == c]):
+            part = np.where(bid == b, rng.normal(size=op.V * 12), 0).astype(complex)
+            out = op.apply(part)
+            other_same = (col == c) & (bid != b)
+            assert np.abs(out[other_same]).max() == 0
+
+
+def test_mr_monotone_optimal_and_converges(small):
+    op, bd = small
+    dims = op.dims
+    bid = np.repeat(block_ids(dims, bd), 12)
+    B = (1, 0, 1, 0)
+    nb = np.asarray(dims) // np.asarray(bd)
+    b_index = np.ravel_multi_index(B, nb)
+    sel = bid == b_index
+    rng = np.random.default_rng(2)
+    r = np.where(sel, rng.normal(size=op.V * 12) + 1j * rng.normal(size=op.V * 12), 0)
+    A = op.dense_blockdiag(bd)[np.ix_(sel, sel)]
+    exact = np.linalg.solve(A, r[sel])
+    res = []
+    for k in range(0, 8):
+        e = op.mr_block(bd, B, r, k)
+        assert np.abs(e[~sel]).max() == 0
+        res.append(np.linalg.norm(r[sel] - A @ e[sel]))
+    assert all(res[i + 1] <= res[i] * (1 + 1e-14) for i in range(len(res) - 1))
+    assert res[1] < res[0]
+    # the last step length minimises the residual along rho
+    e_prev = op.mr_block(bd, B, r, 3)[sel]
+    e_next = op.mr_block(bd, B, r, 4)[sel]
+    rho = r[sel] - A @ e_prev
+    step = e_next - e_prev
+    for pert in (1.01, 0.99, 1 + 0.01j, 1 - 0.01j):
+        assert np.linalg.norm(rho - pert * (A @ step)) >= np.linalg.norm(rho - A @ step)
+    e = op.mr_block(bd, B, r, 200)
+    assert np.linalg.norm(e[sel] - exact) < 1e-12 * np.linalg.norm(exact)
+
+
+def sap_closed_form_operators(op, bd):
+    D = op.dense()
+    BD = op.dense_blockdiag(bd)
+    col = block_masks(op, bd)
+    n = D.shape[0]
+    Bc = []
+    for c in (0, 1):
+        sel = col == c
+        M = np.zeros((n, n), complex)
+        M[np.ix_(sel, sel)] = np.linalg.inv(BD[np.ix_(sel, sel)])
+        Bc.append(M)
+    I = np.eye(n)
+    E = (I - Bc[1] @ D) @ (I - Bc[0] @ D)
+    return D, E, col
+
+
+@pytest.mark.parametrize("dims,bd", [((4, 4, 2, 2), (2, 2, 1, 1)), ((4, 4, 4, 4), (2, 2, 2, 2))])
+def test_sap_exact_blocks_closed_form(dims, bd):
+    U = synth.gauge_field(dims, 0.3, seed=12)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(0.16), 0.01, csw=1.0)
+    D, E, col = sap_closed_form_operators(op, bd)
+    rng = np.random.default_rng(3)
+    n = D.shape[0]
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    x0 = rng.normal(size=n) + 1j * rng.normal(size=n)
+    xs = np.linalg.solve(D, b)
+    for cycles in (1, 2, 3):
+        x = op.sap(b, bd, cycles, -1, x0=x0)
+        En = np.linalg.matrix_power(E, cycles)
+        expect = xs - En @ xs + En @ x0
+        assert np.linalg.norm(x - expect) < 1e-12 * np.linalg.norm(expect)
+    # after a cycle the residual vanishes on the colour swept last
+    x = op.sap(b, bd, 1, -1, x0=x0)
+    r = b - D @ x
+    assert np.abs(r[col == 1]).max() < 1e-12 * np.abs(b).max()
+    assert np.abs(r[col == 0]).max() > 1e-3
+
+
+def test_sap_mr_homogeneous_and_thread_independent(small):
+    op, bd = small
+    rng = np.random.default_rng(4)
+    b = rng.normal(size=op.V * 12) + 1j * rng.normal(size=op.V * 12)
+    lam = 0.7 - 2.1j
+    x1 = op.sap(b, bd, 3, 4)
+    x2 = op.sap(lam * b, bd, 3, 4)
+    assert np.linalg.norm(x2 - lam * x1) < 1e-13 * np.linalg.norm(x2)
+    n0 = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        xa = op.sap(b, bd, 2, 4)
+        oracle.set_num_threads(max(2, n0))
+        xb = op.sap(b, bd, 2, 4)
+    finally:
+        oracle.set_num_threads(n0)
+    assert np.array_equal(xa, xb)
+
+
+def test_sap_rejects_odd_block_counts(small):
+    op, _ = small
+    b = np.zeros(op.V * 12, complex)
+    with pytest.raises(ValueError):
+        op.sap(b, (4, 4, 1, 1), 1, 4)  # one block along t: colouring breaks
+
+
+def test_gmres_identity_preconditioner_terminates():
+    dims = (2, 2, 2, 2)
+    U = synth.gauge_field(dims, 0.6, seed=13)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(0.14), 0.1, csw=1.5)
+    n = op.V * 12
+    rng = np.random.default_rng(5)
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    x, rep = op.fgmres(b, 1e-30, restart=n, max_iters=n, precond=False)
+    xs = np.linalg.solve(op.dense(), b)
+    assert rep["iters"] <= n
+    assert np.linalg.norm(x - xs) < 1e-10 * np.linalg.norm(xs)
+
+
+def test_fgmres_sap_config_4x4x4x4_against_dense_lu():
+    # 4^4 periodic, eps 0.3, kappa 0.16, mu 0.01, csw 0, Gaussian RHS,
+    # SAP 2^4 blocks, 4 MR steps, 3 cycles; dense LU as the reference.
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, seed=1)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(0.16), 0.01, csw=0.0)
+    b = synth.gaussian_spinor(dims, 1, seed=101)[0].ravel()
+    tol = 1e-10
+    x, rep = op.fgmres(b, tol, restart=20, max_iters=500, precond=True, bdims=(2, 2, 2, 2), n_cycles=3,
+                       mr_iters=4)
+    assert rep["converged"] and rep["true_rel_res"] <= tol
+    D = op.dense()
+    xs = np.linalg.solve(D, b)
+    cond = np.linalg.cond(D)
+    assert np.linalg.norm(x - xs) <= cond * tol * np.linalg.norm(xs)
+    assert np.linalg.norm(b - D @ x) <= tol * np.linalg.norm(b) * 1.0001
