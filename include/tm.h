@@ -1,0 +1,206 @@
+/*
+ * tm.h - C ABI of the MI355X library for the twisted-mass Wilson-clover
+ * operator, its red-black Schwarz (SAP) smoother and the SAP-preconditioned
+ * flexible GMRES solve (arXiv:1610.02370).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice  dims = (T, Z, Y, X), V = T*Z*Y*X sites, lexicographic site index
+ *          with t slowest and x fastest (section 2.1, lattice definition).
+ * Direction mu: 0 = t (x0), 1 = x (x1), 2 = y (x2), 3 = z (x3).
+ * Spinor   12 complex per site, index [spin][colour]; spin basis is the chiral
+ *          basis with gamma5 = diag(1, 1, -1, -1) (section 2.1).
+ * Links    U_mu(x) in SU(3), 3x3 complex, index [row][col].  The library
+ *          stores two rows and rebuilds the third, so links must be special
+ *          unitary to 1e-6 (TM_ERR_NOT_SU3 otherwise).
+ * Mass     kappa gives the bare mass through m + 4 = 1 / (2 kappa).
+ * Twist    system k carries the twist + i mu[k] Gamma5 (section 2.1:
+ *          +mu for the u flavour, -mu for the d flavour).
+ *
+ * Canonical layout (io = TM_IO_CANONICAL): complex128 ("double _Complex")
+ *   links  [V][4][3][3]
+ *   spinor [nsys][V][4][3]
+ * Internal layout (io = TM_IO_INTERNAL): opaque device buffers of
+ *   tm_spinor_bytes() bytes, produced only by tm_spinor_import() with the same
+ *   dims, nsys, storage precision and layout block; they let a caller keep
+ *   many systems resident at storage precision (e.g. FP16 at 64^3 x 128).
+ *
+ * Memory ownership: every U / psi / out / b / x pointer is a caller-owned
+ * DEVICE pointer on the current HIP device.  The library never frees caller
+ * memory.  It converts U into its own link copy and clover term.  With
+ * opts.gauge_tag == 0 it rebuilds them on every call (and synchronises once
+ * to validate the links); with a nonzero tag it reuses the copy made for the
+ * same (U pointer, tag, dims, kappa, c_sw, precision, tile), so the caller
+ * must change the tag, or call tm_gauge_release(U), whenever the contents at
+ * U change.  tm_finalize() frees everything the library allocated.
+ *
+ * Streams: all work is enqueued on opts->stream (NULL = the null stream).
+ * tm_dirac_apply and tm_sap_smooth return after enqueueing (the caller
+ * synchronises); tm_fgmres_solve synchronises once per Arnoldi step to read
+ * the Hessenberg column and returns with the result complete.
+ *
+ * Errors: negative return values are errors and leave outputs unspecified;
+ * tm_last_error() returns a thread-local message for the last failure.
+ * Calls are not re-entrant on one stream: two calls that overlap on the same
+ * device share the library's scratch buffers and race.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TM_API __attribute__((visibility("default")))
+#else
+#define TM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define TM_OK 0
+#define TM_NOT_CONVERGED 1   /* solve stopped at max_iters; x holds the best iterate */
+#define TM_ERR_ARG (-1)      /* null pointer or invalid argument value */
+#define TM_ERR_DIMS (-2)     /* dims not positive, or not divisible by the block dims */
+#define TM_ERR_BLOCKS (-3)   /* odd block count in a direction (breaks red-black) or block too large */
+#define TM_ERR_PREC (-4)     /* unsupported precision combination */
+#define TM_ERR_HIP (-5)      /* HIP runtime error */
+#define TM_ERR_NOMEM (-6)    /* device allocation failed */
+#define TM_ERR_NONFINITE (-7)/* NaN or Inf in an input field */
+#define TM_ERR_NOT_SU3 (-8)  /* a link is not special unitary to 1e-6 */
+
+/* ------------------------------------------------------------- precisions */
+typedef enum { TM_F64 = 0, TM_F32 = 1, TM_F16 = 2, TM_BF16 = 3 } tm_prec;
+
+#define TM_IO_CANONICAL 0
+#define TM_IO_INTERNAL 1
+
+#define TM_MAX_SYS 64
+
+typedef struct {
+    int dims[4];          /* (T, Z, Y, X) */
+    int antiperiodic_t;   /* 1: spinor hops across the t boundary get a factor -1 */
+    int nsys;             /* number of systems in psi / b / x (1 .. TM_MAX_SYS) */
+    const double* mu;     /* HOST array [nsys]: twisted mass of each system */
+} tm_geom;
+
+typedef struct {
+    int storage;          /* tm_prec of links and spinors inside the library */
+    int compute;          /* TM_F64 (storage TM_F64 only) or TM_F32 */
+    void* stream;         /* hipStream_t; NULL = null stream */
+    int io;               /* TM_IO_CANONICAL or TM_IO_INTERNAL */
+    int layout_block[4];  /* site tiling of internal buffers; zeros = default
+                             (4^4 where it divides dims, else 2 or 1 per axis);
+                             tm_sap_smooth always tiles by its block_dims */
+    unsigned long long gauge_tag; /* 0: rebuild the gauge copy every call; else cache key (see above) */
+} tm_opts;
+
+/* Fills opts with: storage F64, compute F64, null stream, canonical io, tag 0. */
+TM_API void tm_opts_default(tm_opts* opts);
+
+/* --------------------------------------------------------------- library */
+TM_API int tm_init(void);                 /* optional: creates per-device state */
+TM_API int tm_finalize(void);             /* frees every library allocation */
+TM_API const char* tm_last_error(void);   /* thread-local message of the last error */
+TM_API int tm_gauge_release(const void* U);  /* drops every cached copy derived from U */
+
+/* --------------------------------------------------------- the operator */
+/*
+ * out = D(mu_k) psi_k for every system k (section 2.1, the Wilson-clover
+ * operator with twist):
+ *   D = (m+4) - (c_sw/32) sum_{mu,nu} (gamma_mu gamma_nu) (x) (Q_munu - Q_numu)
+ *       - 1/2 sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)]
+ *       + i mu Gamma5,
+ * with Q_munu the four-leaf clover of plaquettes.  Periodic in every
+ * direction (antiperiodic in t on request).  psi and out must not alias.
+ * Precision: opts->storage / opts->compute; the clover is built in FP64 and
+ * rounded to storage (FP32 for FP16/BF16 storage).
+ */
+TM_API int tm_dirac_apply(const tm_geom* geom, const void* U, const void* psi, void* out, double kappa, double c_sw,
+                   const tm_opts* opts);
+
+/* ------------------------------------------------------------ the smoother */
+/*
+ * Red-black multiplicative SAP (section 2.4, eq. for E_SAP and the block
+ * inverses B_rr, B_bb): the lattice is tiled by blocks block_dims (T,Z,Y,X)
+ * coloured by the parity of the sum of block coordinates.  One cycle sweeps
+ * colour 0 (the block holding the origin) then colour 1; each sweep sets
+ * r = b - D x on the blocks of that colour and adds to x the result of
+ * mr_iters minimal-residual steps on D restricted to the block (hops that
+ * leave the block dropped), started from zero.  x is in/out (initial guess).
+ * Every direction needs an even number (>= 2) of blocks (TM_ERR_BLOCKS), and
+ * a block holds at most 1024 sites.  b and x must not alias.
+ */
+TM_API int tm_sap_smooth(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw,
+                  const int block_dims[4], int n_cycles, int mr_iters, const tm_opts* opts);
+
+/* ---------------------------------------------------------------- solves */
+#define TM_SOLVE_FLEXIBLE 0          /* FP64 FGMRES, SAP at opts->storage */
+#define TM_SOLVE_DEFECT_CORRECTION 1 /* FP64 residual loop around an FP32 FGMRES+SAP solve */
+
+typedef struct {
+    int form;             /* TM_SOLVE_FLEXIBLE or TM_SOLVE_DEFECT_CORRECTION */
+    int restart;          /* FGMRES restart length (outer, or inner for defect correction) */
+    int max_iters;        /* cap on Arnoldi steps (per system, summed over restarts) */
+    int n_cycles;         /* SAP cycles per preconditioner application */
+    int mr_iters;         /* MR steps per block solve */
+    int block_dims[4];    /* SAP blocks; zeros = autotuned (or 4^4 when no tuning is cached) */
+    double inner_tol;     /* defect correction: relative tolerance of each inner solve */
+    int max_outer;        /* defect correction: cap on outer corrections */
+    int group;            /* systems solved together (0 = all nsys) */
+} tm_solver_opts;
+
+/* restart 20, max_iters 2000, 4 cycles, 4 MR steps, 4^4 blocks, flexible form,
+ * inner_tol 1e-6, max_outer 50, group 0. */
+TM_API void tm_solver_opts_default(tm_solver_opts* sopts);
+
+typedef struct {
+    int iters;                          /* Arnoldi steps, max over systems */
+    int outer;                          /* defect-correction corrections (0 for flexible form) */
+    int converged;                      /* systems whose true residual met tol */
+    double true_rel_res[TM_MAX_SYS];    /* ||b - D x|| / ||b|| per system, in FP64 */
+    double t_total;                     /* seconds inside the call */
+    double t_sap;                       /* seconds in SAP kernels (event-timed) */
+    long long sap_cycles;               /* SAP cycles applied (summed over calls, per system batch) */
+} tm_solve_report;
+
+/*
+ * Solves D(mu_k) x_k = b_k for every system to ||b - D x|| <= tol ||b||
+ * (true residual in FP64) with flexible GMRES right-preconditioned by SAP
+ * (section 2.5: the outer method must be flexible because SAP with MR is not
+ * a fixed linear map).  TM_SOLVE_FLEXIBLE keeps the Krylov basis in FP64 and
+ * runs SAP at opts->storage; TM_SOLVE_DEFECT_CORRECTION repeats
+ * r = b - D x (FP64), an FP32 FGMRES+SAP solve of D c = r to inner_tol, and
+ * x += c (the mixed-precision solver of section 3.1).  x is in/out.  Returns
+ * TM_OK when every system converged, TM_NOT_CONVERGED otherwise (report
+ * filled; x holds the last iterate).  report may be NULL.
+ */
+TM_API int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw,
+                    double tol, const tm_solver_opts* sopts, const tm_opts* opts, tm_solve_report* report);
+
+/* ------------------------------------------------------ internal buffers */
+/* Bytes of an internal spinor buffer for geom->nsys systems at opts->storage. */
+TM_API size_t tm_spinor_bytes(const tm_geom* geom, const tm_opts* opts);
+/* canonical complex128 -> internal (opts->storage, opts->layout_block) */
+TM_API int tm_spinor_import(const tm_geom* geom, const void* canon, void* internal, const tm_opts* opts);
+/* internal -> canonical complex128 */
+TM_API int tm_spinor_export(const tm_geom* geom, const void* internal, void* canon, const tm_opts* opts);
+
+/* --------------------------------------------------------------- tuning */
+/*
+ * Times SAP cycles for every candidate block shape (divisors of dims with an
+ * even block count per direction, 16..1024 sites) and picks the fastest per
+ * SAP application; stores the choice in a cache file (path from the
+ * TM_TUNE_CACHE environment variable, default ./tm_tune.json) and writes it
+ * to best_block[4].  The block shape changes the preconditioner, so solves
+ * with a tuned shape converge differently from 4^4.
+ */
+TM_API int tm_autotune_sap(const tm_geom* geom, const void* U, double kappa, double c_sw, int n_cycles, int mr_iters,
+                    const tm_opts* opts, int best_block[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,256 @@
+"""Python binding of libtmsap.so, the MI355X twisted-mass operator / SAP / FGMRES library.
+
+Argument marshalling only: every step runs in the HIP kernels behind the C ABI
+declared in include/tm.h.  PyTorch supplies device memory and the stream.  The
+binding raises if the compiled library is missing; there is no CPU fallback.
+
+Tensors are complex128 on the current GPU in the canonical layout:
+  U    [V, 4, 3, 3]       (or any shape with that many elements)
+  psi  [nsys, V, 4, 3]
+Sites are lexicographic over dims = (T, Z, Y, X), t slowest; direction mu: 0 = t, 1 = x, 2 = y, 3 = z.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtmsap.so")
+
+TM_OK, TM_NOT_CONVERGED = 0, 1
+ERRORS = {-1: "TM_ERR_ARG", -2: "TM_ERR_DIMS", -3: "TM_ERR_BLOCKS", -4: "TM_ERR_PREC", -5: "TM_ERR_HIP",
+          -6: "TM_ERR_NOMEM", -7: "TM_ERR_NONFINITE", -8: "TM_ERR_NOT_SU3"}
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+IO = {"canonical": 0, "internal": 1}
+FORMS = {"flexible": 0, "defect_correction": 1}
+MAX_SYS = 64
+
+# Every entry point declared in include/tm.h.
+EXPORTS = (
+    "tm_opts_default", "tm_init", "tm_finalize", "tm_last_error", "tm_gauge_release", "tm_dirac_apply",
+    "tm_sap_smooth", "tm_solver_opts_default", "tm_fgmres_solve", "tm_spinor_bytes", "tm_spinor_import",
+    "tm_spinor_export", "tm_autotune_sap",
+)
+
+
+class TMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("antiperiodic_t", ctypes.c_int), ("nsys", ctypes.c_int),
+                ("mu", ctypes.POINTER(ctypes.c_double))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int), ("compute", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("io", ctypes.c_int), ("layout_block", ctypes.c_int * 4), ("gauge_tag", ctypes.c_ulonglong)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
+                ("n_cycles", ctypes.c_int), ("mr_iters", ctypes.c_int), ("block_dims", ctypes.c_int * 4),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("group", ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("converged", ctypes.c_int),
+                ("true_rel_res", ctypes.c_double * MAX_SYS), ("t_total", ctypes.c_double),
+                ("t_sap", ctypes.c_double), ("sap_cycles", ctypes.c_longlong)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the library has no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER
+        L.tm_opts_default.argtypes = [P(Opts)]
+        L.tm_opts_default.restype = None
+        L.tm_solver_opts_default.argtypes = [P(SolverOpts)]
+        L.tm_solver_opts_default.restype = None
+        L.tm_init.restype = ctypes.c_int
+        L.tm_finalize.restype = ctypes.c_int
+        L.tm_last_error.restype = ctypes.c_char_p
+        L.tm_gauge_release.argtypes = [vp]
+        L.tm_dirac_apply.argtypes = [P(Geom), vp, vp, vp, ctypes.c_double, ctypes.c_double, P(Opts)]
+        L.tm_sap_smooth.argtypes = [P(Geom), vp, vp, vp, ctypes.c_double, ctypes.c_double, P(ctypes.c_int),
+                                    ctypes.c_int, ctypes.c_int, P(Opts)]
+        L.tm_fgmres_solve.argtypes = [P(Geom), vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      P(SolverOpts), P(Opts), P(Report)]
+        L.tm_spinor_bytes.argtypes = [P(Geom), P(Opts)]
+        L.tm_spinor_bytes.restype = ctypes.c_size_t
+        L.tm_spinor_import.argtypes = [P(Geom), vp, vp, P(Opts)]
+        L.tm_spinor_export.argtypes = [P(Geom), vp, vp, P(Opts)]
+        L.tm_autotune_sap.argtypes = [P(Geom), vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                      P(Opts), P(ctypes.c_int)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, allow_not_converged: bool = False) -> int:
+    if rc == TM_OK or (allow_not_converged and rc == TM_NOT_CONVERGED):
+        return rc
+    raise TMError(rc, lib().tm_last_error().decode())
+
+
+def _stream_handle(stream):
+    """None: torch's current stream; False: the null stream (no torch call)."""
+    if stream is False:
+        return ctypes.c_void_p(None)
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_geom(dims: Sequence[int], mu, antiperiodic_t: bool = False):
+    mus = [float(mu)] if isinstance(mu, (int, float)) else [float(m) for m in mu]
+    arr = (ctypes.c_double * len(mus))(*mus)
+    g = Geom((ctypes.c_int * 4)(*[int(d) for d in dims]), int(bool(antiperiodic_t)), len(mus),
+             ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+    g._keep = arr
+    return g
+
+
+def make_opts(storage: str = "f64", compute: str | None = None, stream=None, io: str = "canonical",
+              layout_block=None, gauge_tag: int = 0):
+    o = Opts()
+    lib().tm_opts_default(ctypes.byref(o))
+    o.storage = PREC[storage]
+    o.compute = PREC[compute] if compute else (PREC["f64"] if storage == "f64" else PREC["f32"])
+    o.stream = _stream_handle(stream)
+    o.io = IO[io]
+    if layout_block is not None:
+        o.layout_block = (ctypes.c_int * 4)(*[int(v) for v in layout_block])
+    o.gauge_tag = int(gauge_tag)
+    return o
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _canon(t, what: str):
+    import torch
+
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{what} must be complex128 in the canonical layout")
+    return _ptr(t)
+
+
+def tm_init() -> None:
+    _check(lib().tm_init())
+
+
+def tm_finalize() -> None:
+    _check(lib().tm_finalize())
+
+
+def tm_gauge_release(U) -> None:
+    _check(lib().tm_gauge_release(ctypes.c_void_p(U.data_ptr())))
+
+
+def tm_dirac_apply(dims, U, psi, kappa: float, mu, c_sw: float, out=None, *, storage: str = "f64",
+                   antiperiodic_t: bool = False, stream=None, io: str = "canonical", layout_block=None,
+                   gauge_tag: int = 0):
+    """out_k = D(mu_k) psi_k for every system k (psi: [nsys, V, 4, 3] complex128, or internal buffers)."""
+    import torch
+
+    g = make_geom(dims, mu, antiperiodic_t)
+    o = make_opts(storage, stream=stream, io=io, layout_block=layout_block, gauge_tag=gauge_tag)
+    if out is None:
+        out = torch.empty_like(psi)
+    pin = _canon(psi, "psi") if io == "canonical" else _ptr(psi)
+    pout = _canon(out, "out") if io == "canonical" else _ptr(out)
+    _check(lib().tm_dirac_apply(ctypes.byref(g), _canon(U, "U"), pin, pout, float(kappa), float(c_sw),
+                                ctypes.byref(o)))
+    return out
+
+
+def tm_sap_smooth(dims, U, b, x, kappa: float, mu, c_sw: float, block_dims, n_cycles: int, mr_iters: int, *,
+                  storage: str = "f64", antiperiodic_t: bool = False, stream=None, io: str = "canonical",
+                  gauge_tag: int = 0):
+    """x <- SAP(b, x): n_cycles red-black cycles, mr_iters MR steps per block (x is in/out)."""
+    g = make_geom(dims, mu, antiperiodic_t)
+    o = make_opts(storage, stream=stream, io=io, layout_block=block_dims, gauge_tag=gauge_tag)
+    bd = (ctypes.c_int * 4)(*[int(v) for v in block_dims])
+    pb = _canon(b, "b") if io == "canonical" else _ptr(b)
+    px = _canon(x, "x") if io == "canonical" else _ptr(x)
+    _check(lib().tm_sap_smooth(ctypes.byref(g), _canon(U, "U"), pb, px, float(kappa), float(c_sw), bd,
+                               int(n_cycles), int(mr_iters), ctypes.byref(o)))
+    return x
+
+
+def solver_opts(form: str = "flexible", restart: int = 20, max_iters: int = 2000, n_cycles: int = 4,
+                mr_iters: int = 4, block_dims=(4, 4, 4, 4), inner_tol: float = 1e-6, max_outer: int = 50,
+                group: int = 0) -> SolverOpts:
+    s = SolverOpts()
+    lib().tm_solver_opts_default(ctypes.byref(s))
+    s.form = FORMS[form]
+    s.restart, s.max_iters, s.n_cycles, s.mr_iters = int(restart), int(max_iters), int(n_cycles), int(mr_iters)
+    s.block_dims = (ctypes.c_int * 4)(*[int(v) for v in (block_dims or (0, 0, 0, 0))])
+    s.inner_tol, s.max_outer, s.group = float(inner_tol), int(max_outer), int(group)
+    return s
+
+
+def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, storage: str = "f32",
+                    antiperiodic_t: bool = False, stream=None, gauge_tag: int = 0, **solver_kw):
+    """Solve D(mu_k) x_k = b_k to a true relative residual tol; returns (status, report dict)."""
+    g = make_geom(dims, mu, antiperiodic_t)
+    o = make_opts(storage, stream=stream, gauge_tag=gauge_tag)
+    s = solver_opts(**solver_kw)
+    rep = Report()
+    rc = _check(lib().tm_fgmres_solve(ctypes.byref(g), _canon(U, "U"), _canon(b, "b"), _canon(x, "x"), float(kappa),
+                                      float(c_sw), float(tol), ctypes.byref(s), ctypes.byref(o), ctypes.byref(rep)),
+                allow_not_converged=True)
+    n = g.nsys
+    return rc, {"iters": rep.iters, "outer": rep.outer, "converged": rep.converged,
+                "true_rel_res": [rep.true_rel_res[k] for k in range(n)], "t_total": rep.t_total,
+                "t_sap": rep.t_sap, "sap_cycles": rep.sap_cycles}
+
+
+def tm_spinor_bytes(dims, nsys: int, storage: str, layout_block=None) -> int:
+    """Bytes of an internal buffer (host-side arithmetic, no GPU call)."""
+    g = make_geom(dims, [0.0] * nsys)
+    o = make_opts(storage, stream=False, io="internal", layout_block=layout_block)
+    return int(lib().tm_spinor_bytes(ctypes.byref(g), ctypes.byref(o)))
+
+
+def tm_spinor_import(dims, canon, internal, *, storage: str, layout_block=None, stream=None):
+    nsys = canon.shape[0]
+    g = make_geom(dims, [0.0] * nsys)
+    o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
+    _check(lib().tm_spinor_import(ctypes.byref(g), _canon(canon, "canon"), _ptr(internal), ctypes.byref(o)))
+    return internal
+
+
+def tm_spinor_export(dims, internal, canon, *, storage: str, layout_block=None, stream=None):
+    nsys = canon.shape[0]
+    g = make_geom(dims, [0.0] * nsys)
+    o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
+    _check(lib().tm_spinor_export(ctypes.byref(g), _ptr(internal), _canon(canon, "canon"), ctypes.byref(o)))
+    return canon
+
+
+def tm_autotune_sap(dims, U, kappa: float, mu, c_sw: float, n_cycles: int, mr_iters: int, *, storage: str = "f32",
+                    stream=None):
+    g = make_geom(dims, mu)
+    o = make_opts(storage, stream=stream)
+    best = (ctypes.c_int * 4)()
+    _check(lib().tm_autotune_sap(ctypes.byref(g), _canon(U, "U"), float(kappa), float(c_sw), int(n_cycles),
+                                 int(mr_iters), ctypes.byref(o), best))
+    return tuple(best)

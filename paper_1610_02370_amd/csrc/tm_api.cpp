@@ -1,0 +1,463 @@
+// C ABI of the library: argument checking, the per-device gauge cache,
+// workspaces, and the entry points declared in include/tm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tm.h"
+#include "tm_api_internal.h"
+
+namespace tmsap {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    if (e == hipErrorOutOfMemory) return fail(TM_ERR_NOMEM, "%s: out of device memory", where);
+    return fail(TM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ state
+
+static std::mutex g_mutex;
+static std::vector<std::unique_ptr<DeviceState>> g_devices;
+
+DeviceState* device_state(int* err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *err = hip_fail(e, "hipGetDevice");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (auto& d : g_devices)
+        if (d->device == dev) {
+            ++d->call_id;
+            return d.get();
+        }
+    g_devices.emplace_back(new DeviceState());
+    g_devices.back()->device = dev;
+    g_devices.back()->call_id = 1;
+    return g_devices.back().get();
+}
+
+DeviceBuffer::~DeviceBuffer() { release(); }
+void DeviceBuffer::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+hipError_t DeviceBuffer::ensure(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return e;
+    }
+    bytes = n;
+    return hipSuccess;
+}
+
+GaugeEntry::~GaugeEntry() {
+    if (dev.links) (void)hipFree(dev.links);
+    if (dev.clover) (void)hipFree(dev.clover);
+}
+
+// ------------------------------------------------------------------ checks
+
+static bool prec_ok(int p) { return p >= TM_F64 && p <= TM_BF16; }
+
+int check_geom(const tm_geom* geom) {
+    if (!geom) return fail(TM_ERR_ARG, "geom is NULL");
+    for (int a = 0; a < 4; ++a)
+        if (geom->dims[a] <= 0) return fail(TM_ERR_DIMS, "dims[%d] = %d is not positive", a, geom->dims[a]);
+    long long V = (long long)geom->dims[0] * geom->dims[1] * geom->dims[2] * geom->dims[3];
+    if (V > (1LL << 31) / 4) return fail(TM_ERR_DIMS, "lattice of %lld sites is too large", V);
+    if (geom->nsys < 1 || geom->nsys > TM_MAX_SYS)
+        return fail(TM_ERR_ARG, "nsys = %d outside 1..%d", geom->nsys, TM_MAX_SYS);
+    if (!geom->mu) return fail(TM_ERR_ARG, "geom->mu is NULL");
+    for (int k = 0; k < geom->nsys; ++k)
+        if (!std::isfinite(geom->mu[k])) return fail(TM_ERR_NONFINITE, "mu[%d] is not finite", k);
+    return TM_OK;
+}
+
+int check_opts(const tm_opts* opts) {
+    if (!opts) return fail(TM_ERR_ARG, "opts is NULL");
+    if (!prec_ok(opts->storage) || !prec_ok(opts->compute)) return fail(TM_ERR_PREC, "unknown precision");
+    if (opts->compute != TM_F64 && opts->compute != TM_F32) return fail(TM_ERR_PREC, "compute must be F64 or F32");
+    if (opts->storage == TM_F64 && opts->compute != TM_F64)
+        return fail(TM_ERR_PREC, "FP64 storage requires FP64 compute");
+    if (opts->storage != TM_F64 && opts->compute != TM_F32)
+        return fail(TM_ERR_PREC, "FP32/FP16/BF16 storage computes in FP32");
+    if (opts->io != TM_IO_CANONICAL && opts->io != TM_IO_INTERNAL) return fail(TM_ERR_ARG, "unknown io mode");
+    return TM_OK;
+}
+
+// Tile for a layout: explicit, else 4 where it divides the axis, else 2, else 1.
+int choose_tile(const tm_geom* geom, const int* req, int tile[4]) {
+    bool given = req && (req[0] | req[1] | req[2] | req[3]);
+    for (int a = 0; a < 4; ++a) {
+        if (given) {
+            tile[a] = req[a];
+            if (tile[a] <= 0 || geom->dims[a] % tile[a] != 0)
+                return fail(TM_ERR_DIMS, "block/tile %d does not divide dims[%d] = %d", tile[a], a, geom->dims[a]);
+        } else {
+            tile[a] = geom->dims[a] % 4 == 0 ? 4 : (geom->dims[a] % 2 == 0 ? 2 : 1);
+        }
+    }
+    if ((long long)tile[0] * tile[1] * tile[2] * tile[3] > 1024) return fail(TM_ERR_BLOCKS, "tile holds more than 1024 sites");
+    return TM_OK;
+}
+
+Geo make_geo(const tm_geom* geom, const int tile[4]) {
+    Geo g;
+    g.V = 1;
+    g.Vb = 1;
+    for (int a = 0; a < 4; ++a) {
+        g.d[a] = geom->dims[a];
+        g.lb[a] = tile[a];
+        g.nb[a] = geom->dims[a] / tile[a];
+        g.V *= geom->dims[a];
+        g.Vb *= tile[a];
+    }
+    g.antiperiodic_t = geom->antiperiodic_t ? 1 : 0;
+    return g;
+}
+
+Prec clover_prec_for(Prec link_p) { return (link_p == P_F16 || link_p == P_BF16) ? P_F32 : link_p; }
+
+// Links + clover derived from U at (link precision, tile).  A nonzero tag
+// reuses a copy made for the same (U, tag, dims, tile, kappa, c_sw,
+// precision); tag 0 rebuilds into a reusable tag-0 slot of matching size.
+static bool same_shape(const GaugeEntry& e, const Geo& g, Prec link_p) {
+    return e.dev.link_prec == link_p && std::memcmp(e.g.d, g.d, sizeof g.d) == 0 &&
+           std::memcmp(e.g.lb, g.lb, sizeof g.lb) == 0;
+}
+
+int get_gauge(DeviceState* ds, const Geo& g, const void* U, double kappa, double csw, Prec link_p,
+              unsigned long long tag, hipStream_t st, const GaugeDev** out) {
+    const Prec cl_p = clover_prec_for(link_p);
+    std::lock_guard<std::mutex> lock(ds->mutex);
+    GaugeEntry* slot = nullptr;
+    for (auto& ep : ds->gauge) {
+        GaugeEntry& e = *ep;
+        if (!same_shape(e, g, link_p)) continue;
+        if (tag != 0 && e.tag == tag && e.U == U && e.kappa == kappa && e.csw == csw) {
+            e.last_call = ds->call_id;
+            *out = &e.dev;
+            return TM_OK;
+        }
+        if (tag == 0 && e.tag == 0 && e.last_call != ds->call_id) {
+            slot = &e;
+            break;
+        }
+    }
+    if (!slot) {
+        // keep the cache small: at most 8 entries per device, evicting the
+        // oldest entry this call has not handed out
+        if (ds->gauge.size() >= 8) {
+            for (auto it = ds->gauge.begin(); it != ds->gauge.end(); ++it)
+                if ((*it)->last_call != ds->call_id) {
+                    ds->gauge.erase(it);
+                    break;
+                }
+        }
+        std::unique_ptr<GaugeEntry> e(new GaugeEntry());
+        e->g = g;
+        e->dev.link_prec = link_p;
+        e->dev.clover_prec = cl_p;
+        size_t lb = (size_t)4 * 3 * g.V * unit_bytes(link_p);
+        size_t cb = (size_t)18 * g.V * unit_bytes(cl_p);
+        hipError_t h = hipMalloc(&e->dev.links, lb);
+        if (h != hipSuccess) return hip_fail(h, "gauge links");
+        h = hipMalloc(&e->dev.clover, cb);
+        if (h != hipSuccess) return hip_fail(h, "clover");
+        ds->gauge.emplace_back(std::move(e));
+        slot = ds->gauge.back().get();
+    }
+    // (re)build: mark the slot unusable until validation passes
+    slot->U = nullptr;
+    slot->tag = 0;
+    hipError_t h = ds->stats.ensure(256);
+    if (h != hipSuccess) return hip_fail(h, "stats");
+    unsigned* stats = (unsigned*)ds->stats.ptr;
+    if ((h = hipMemsetAsync(stats, 0, 2 * sizeof(unsigned), st)) != hipSuccess) return hip_fail(h, "memset");
+    if ((h = launch_link_ingest(g, link_p, U, slot->dev.links, stats, st)) != hipSuccess)
+        return hip_fail(h, "link ingest");
+    const double m4 = 1.0 / (2.0 * kappa);
+    if ((h = launch_clover_build(g, cl_p, U, m4, csw, slot->dev.clover, st)) != hipSuccess)
+        return hip_fail(h, "clover build");
+    unsigned host[2];
+    if ((h = hipMemcpyAsync(host, stats, sizeof host, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(h, "stats copy");
+    if ((h = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(h, "gauge ingest");
+    if (host[1]) return fail(TM_ERR_NONFINITE, "gauge field holds NaN or Inf");
+    float dev;
+    std::memcpy(&dev, &host[0], sizeof dev);
+    if (!(dev <= 1e-6f)) return fail(TM_ERR_NOT_SU3, "links deviate from SU(3) by %g (limit 1e-6)", (double)dev);
+    slot->U = U;
+    slot->tag = tag;
+    slot->last_call = ds->call_id;
+    slot->kappa = kappa;
+    slot->csw = csw;
+    *out = &slot->dev;
+    return TM_OK;
+}
+
+// Internal spinor buffer carved from a workspace or wrapping caller memory.
+SpinorBuf wrap_internal(void* base, const Geo& g, int nsys, Prec p) {
+    SpinorBuf b;
+    b.data = base;
+    b.prec = p;
+    b.nsys = nsys;
+    b.scale = prec_has_scale(p)
+                  ? reinterpret_cast<float*>(static_cast<char*>(base) + align256(spinor_data_bytes(g.V, nsys, p)))
+                  : nullptr;
+    return b;
+}
+
+size_t internal_bytes(const Geo& g, int nsys, Prec p) {
+    return align256(spinor_data_bytes(g.V, nsys, p)) + align256(spinor_scale_bytes(g.V, nsys, p));
+}
+
+void fill_mu(const tm_geom* geom, double* mu) {
+    for (int k = 0; k < kMaxSys; ++k) mu[k] = k < geom->nsys ? geom->mu[k] : 0.0;
+}
+
+int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,
+            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st) {
+    SapArgs a;
+    a.g = g;
+    a.links = G.links;
+    a.clover = G.clover;
+    a.b = b.data;
+    a.b_scale = b.scale;
+    a.x = x.data;
+    a.x_scale = x.scale;
+    a.nsys = nsys;
+    a.sys_tile = sys_tile > 0 ? sys_tile : nsys;
+    a.mr_iters = mr_iters;
+    for (int k = 0; k < kMaxSys; ++k) a.mu[k] = mu[k];
+    const Prec cp = b.prec == P_F64 ? P_F64 : P_F32;
+    for (int cyc = 0; cyc < n_cycles; ++cyc)
+        for (int colour = 0; colour < 2; ++colour) {
+            a.colour = colour;
+            a.x_zero = (x_zero && cyc == 0 && colour == 0) ? 1 : 0;
+            hipError_t h = launch_sap_half(a, b.prec, G.link_prec, G.clover_prec, cp, st);
+            if (h == hipErrorInvalidConfiguration)
+                return fail(TM_ERR_BLOCKS, "block of %d sites needs more LDS than the device has at this precision",
+                            g.Vb);
+            if (h != hipSuccess) return hip_fail(h, "sap half-sweep");
+        }
+    return TM_OK;
+}
+
+int run_dirac(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu, int nsys,
+              Prec compute, hipStream_t st) {
+    DiracArgs a;
+    a.g = g;
+    a.links = G.links;
+    a.clover = G.clover;
+    a.in = in.data;
+    a.in_scale = in.scale;
+    a.out = out.data;
+    a.out_scale = out.scale;
+    a.nsys = nsys;
+    for (int k = 0; k < kMaxSys; ++k) a.mu[k] = mu[k];
+    hipError_t h = launch_dirac(a, in.prec, out.prec, G.link_prec, G.clover_prec, compute, st);
+    if (h == hipErrorInvalidValue) return fail(TM_ERR_PREC, "unsupported precision combination for the operator");
+    if (h != hipSuccess) return hip_fail(h, "dirac");
+    return TM_OK;
+}
+
+int check_sap_blocks(const tm_geom* geom, const int* block_dims, int tile[4]) {
+    if (!block_dims) return fail(TM_ERR_ARG, "block_dims is NULL");
+    for (int a = 0; a < 4; ++a) {
+        if (block_dims[a] <= 0 || geom->dims[a] % block_dims[a] != 0)
+            return fail(TM_ERR_DIMS, "block_dims[%d] = %d does not divide dims[%d] = %d", a, block_dims[a], a,
+                        geom->dims[a]);
+        if ((geom->dims[a] / block_dims[a]) % 2 != 0)
+            return fail(TM_ERR_BLOCKS, "odd number of blocks (%d) along axis %d", geom->dims[a] / block_dims[a], a);
+        tile[a] = block_dims[a];
+    }
+    if ((long long)tile[0] * tile[1] * tile[2] * tile[3] > 1024) return fail(TM_ERR_BLOCKS, "block holds more than 1024 sites");
+    return TM_OK;
+}
+
+}  // namespace tmsap
+
+using namespace tmsap;
+
+extern "C" {
+
+void tm_opts_default(tm_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->storage = TM_F64;
+    o->compute = TM_F64;
+    o->io = TM_IO_CANONICAL;
+}
+
+int tm_init(void) {
+    int err = TM_OK;
+    return device_state(&err) ? TM_OK : err;
+}
+
+int tm_finalize(void) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    g_devices.clear();
+    return TM_OK;
+}
+
+const char* tm_last_error(void) { return g_last_error.c_str(); }
+
+int tm_gauge_release(const void* U) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (auto& d : g_devices) {
+        std::lock_guard<std::mutex> l2(d->mutex);
+        for (size_t i = 0; i < d->gauge.size();) {
+            if (d->gauge[i]->U == U)
+                d->gauge.erase(d->gauge.begin() + i);
+            else
+                ++i;
+        }
+    }
+    return TM_OK;
+}
+
+size_t tm_spinor_bytes(const tm_geom* geom, const tm_opts* opts) {
+    if (check_geom(geom) != TM_OK || check_opts(opts) != TM_OK) return 0;
+    int tile[4];
+    if (choose_tile(geom, opts->layout_block, tile) != TM_OK) return 0;
+    Geo g = make_geo(geom, tile);
+    return internal_bytes(g, geom->nsys, (Prec)opts->storage);
+}
+
+int tm_spinor_import(const tm_geom* geom, const void* canon, void* internal, const tm_opts* opts) {
+    int rc;
+    if ((rc = check_geom(geom)) || (rc = check_opts(opts))) return rc;
+    if (!canon || !internal) return fail(TM_ERR_ARG, "null buffer");
+    int tile[4];
+    if ((rc = choose_tile(geom, opts->layout_block, tile))) return rc;
+    DeviceState* ds = device_state(&rc);
+    if (!ds) return rc;
+    Geo g = make_geo(geom, tile);
+    hipStream_t st = (hipStream_t)opts->stream;
+    hipError_t h = ds->stats.ensure(256);
+    if (h != hipSuccess) return hip_fail(h, "stats");
+    SpinorBuf dst = wrap_internal(internal, g, geom->nsys, (Prec)opts->storage);
+    if ((h = launch_spinor_import(g, dst, canon, (unsigned*)ds->stats.ptr + 2, st)) != hipSuccess)
+        return hip_fail(h, "spinor import");
+    return TM_OK;
+}
+
+int tm_spinor_export(const tm_geom* geom, const void* internal, void* canon, const tm_opts* opts) {
+    int rc;
+    if ((rc = check_geom(geom)) || (rc = check_opts(opts))) return rc;
+    if (!canon || !internal) return fail(TM_ERR_ARG, "null buffer");
+    int tile[4];
+    if ((rc = choose_tile(geom, opts->layout_block, tile))) return rc;
+    Geo g = make_geo(geom, tile);
+    SpinorBuf src = wrap_internal(const_cast<void*>(internal), g, geom->nsys, (Prec)opts->storage);
+    hipError_t h = launch_spinor_export(g, src, canon, (hipStream_t)opts->stream);
+    if (h != hipSuccess) return hip_fail(h, "spinor export");
+    return TM_OK;
+}
+
+int tm_dirac_apply(const tm_geom* geom, const void* U, const void* psi, void* out, double kappa, double c_sw,
+                   const tm_opts* opts) {
+    int rc;
+    if ((rc = check_geom(geom)) || (rc = check_opts(opts))) return rc;
+    if (!U || !psi || !out) return fail(TM_ERR_ARG, "null pointer");
+    if (psi == out) return fail(TM_ERR_ARG, "psi and out alias");
+    if (!(kappa > 0) || !std::isfinite(kappa) || !std::isfinite(c_sw)) return fail(TM_ERR_ARG, "bad kappa or c_sw");
+    int tile[4];
+    if ((rc = choose_tile(geom, opts->layout_block, tile))) return rc;
+    DeviceState* ds = device_state(&rc);
+    if (!ds) return rc;
+    Geo g = make_geo(geom, tile);
+    hipStream_t st = (hipStream_t)opts->stream;
+    const Prec sp = (Prec)opts->storage, cp = (Prec)opts->compute;
+    const GaugeDev* G;
+    if ((rc = get_gauge(ds, g, U, kappa, c_sw, sp, opts->gauge_tag, st, &G))) return rc;
+    double mu[kMaxSys];
+    fill_mu(geom, mu);
+    if (opts->io == TM_IO_INTERNAL) {
+        SpinorBuf in = wrap_internal(const_cast<void*>(psi), g, geom->nsys, sp);
+        SpinorBuf o = wrap_internal(out, g, geom->nsys, sp);
+        return run_dirac(g, *G, in, o, mu, geom->nsys, cp, st);
+    }
+    size_t nb = internal_bytes(g, geom->nsys, sp);
+    hipError_t h = ds->io.ensure(2 * nb);
+    if (h != hipSuccess) return hip_fail(h, "workspace");
+    hipError_t h2 = ds->stats.ensure(256);
+    if (h2 != hipSuccess) return hip_fail(h2, "stats");
+    SpinorBuf in = wrap_internal(ds->io.ptr, g, geom->nsys, sp);
+    SpinorBuf o = wrap_internal(static_cast<char*>(ds->io.ptr) + nb, g, geom->nsys, sp);
+    if ((h = launch_spinor_import(g, in, psi, (unsigned*)ds->stats.ptr + 2, st)) != hipSuccess)
+        return hip_fail(h, "spinor import");
+    if ((rc = run_dirac(g, *G, in, o, mu, geom->nsys, cp, st))) return rc;
+    if ((h = launch_spinor_export(g, o, out, st)) != hipSuccess) return hip_fail(h, "spinor export");
+    return TM_OK;
+}
+
+int tm_sap_smooth(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw,
+                  const int block_dims[4], int n_cycles, int mr_iters, const tm_opts* opts) {
+    int rc;
+    if ((rc = check_geom(geom)) || (rc = check_opts(opts))) return rc;
+    if (!U || !b || !x) return fail(TM_ERR_ARG, "null pointer");
+    if (b == x) return fail(TM_ERR_ARG, "b and x alias");
+    if (n_cycles < 0 || mr_iters < 0) return fail(TM_ERR_ARG, "negative cycle or MR count");
+    if (!(kappa > 0) || !std::isfinite(kappa) || !std::isfinite(c_sw)) return fail(TM_ERR_ARG, "bad kappa or c_sw");
+    int tile[4];
+    if ((rc = check_sap_blocks(geom, block_dims, tile))) return rc;
+    const Prec sp = (Prec)opts->storage;
+    if (!sap_supported(sp, sp, clover_prec_for(sp), (Prec)opts->compute))
+        return fail(TM_ERR_PREC, "unsupported precision combination for SAP");
+    DeviceState* ds = device_state(&rc);
+    if (!ds) return rc;
+    Geo g = make_geo(geom, tile);
+    hipStream_t st = (hipStream_t)opts->stream;
+    const GaugeDev* G;
+    if ((rc = get_gauge(ds, g, U, kappa, c_sw, sp, opts->gauge_tag, st, &G))) return rc;
+    double mu[kMaxSys];
+    fill_mu(geom, mu);
+    if (opts->io == TM_IO_INTERNAL) {
+        SpinorBuf bb = wrap_internal(const_cast<void*>(b), g, geom->nsys, sp);
+        SpinorBuf xx = wrap_internal(x, g, geom->nsys, sp);
+        return run_sap(g, *G, bb, xx, mu, geom->nsys, n_cycles, mr_iters, false, 0, st);
+    }
+    size_t nb = internal_bytes(g, geom->nsys, sp);
+    hipError_t h = ds->io.ensure(2 * nb);
+    if (h != hipSuccess) return hip_fail(h, "workspace");
+    if ((h = ds->stats.ensure(256)) != hipSuccess) return hip_fail(h, "stats");
+    SpinorBuf bb = wrap_internal(ds->io.ptr, g, geom->nsys, sp);
+    SpinorBuf xx = wrap_internal(static_cast<char*>(ds->io.ptr) + nb, g, geom->nsys, sp);
+    if ((h = launch_spinor_import(g, bb, b, (unsigned*)ds->stats.ptr + 2, st)) != hipSuccess)
+        return hip_fail(h, "spinor import");
+    if ((h = launch_spinor_import(g, xx, x, (unsigned*)ds->stats.ptr + 2, st)) != hipSuccess)
+        return hip_fail(h, "spinor import");
+    if ((rc = run_sap(g, *G, bb, xx, mu, geom->nsys, n_cycles, mr_iters, false, 0, st))) return rc;
+    if ((h = launch_spinor_export(g, xx, x, st)) != hipSuccess) return hip_fail(h, "spinor export");
+    return TM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Host-side state shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/tm.h"
+#include "tm_internal.h"
+
+namespace tmsap {
+
+// Grow-only device allocation.
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    ~DeviceBuffer();
+    hipError_t ensure(size_t n);
+    void release();
+};
+
+struct GaugeEntry {
+    const void* U = nullptr;
+    unsigned long long tag = 0;
+    double kappa = 0, csw = 0;
+    Geo g{};
+    GaugeDev dev;
+    unsigned long long last_call = 0;  // call that last used this entry (never evicted by that call)
+    ~GaugeEntry();
+};
+
+struct DeviceState {
+    int device = 0;
+    unsigned long long call_id = 0;  // bumped by every entry point
+    std::mutex mutex;
+    std::vector<std::unique_ptr<GaugeEntry>> gauge;
+    DeviceBuffer stats;   // small flags / reductions
+    DeviceBuffer io;      // canonical <-> internal staging
+    DeviceBuffer solver;  // Krylov bases and solver vectors
+    DeviceBuffer red;     // reduction partials
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* where);
+// Per-device state of the current device; every entry point gets it through
+// this call, which also starts a new call id for the gauge cache.
+DeviceState* device_state(int* err);
+int check_geom(const tm_geom* geom);
+int check_opts(const tm_opts* opts);
+int choose_tile(const tm_geom* geom, const int* req, int tile[4]);
+int check_sap_blocks(const tm_geom* geom, const int* block_dims, int tile[4]);
+Geo make_geo(const tm_geom* geom, const int tile[4]);
+Prec clover_prec_for(Prec link_p);
+int get_gauge(DeviceState* ds, const Geo& g, const void* U, double kappa, double csw, Prec link_p,
+              unsigned long long tag, hipStream_t st, const GaugeDev** out);
+SpinorBuf wrap_internal(void* base, const Geo& g, int nsys, Prec p);
+size_t internal_bytes(const Geo& g, int nsys, Prec p);
+void fill_mu(const tm_geom* geom, double* mu);
+int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,
+            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st);
+int run_dirac(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu, int nsys,
+              Prec compute, hipStream_t st);
+
+}  // namespace tmsap

@@ -1,0 +1,109 @@
+// The twisted-mass Wilson-clover operator on the whole lattice
+// (section 2.1): out = [(m+4) + C + i mu Gamma5] psi
+//   - 1/2 sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)].
+// One thread per site; spin projection to half spinors before the SU(3)
+// products; every field is read structure-of-arrays so a wavefront's loads
+// are contiguous.
+#include "tm_internal.h"
+
+namespace tmsap {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// Neighbour of internal site s along direction mu, dir = +-1; sets *sign to -1
+// when the hop crosses an antiperiodic t boundary.
+__device__ inline long long neighbour(const Geo& g, const int c[4], int mu, int dir, float* sign) {
+    int n[4] = {c[0], c[1], c[2], c[3]};
+    int a = axis_of(mu);
+    n[a] += dir;
+    *sign = 1.f;
+    if (n[a] < 0) {
+        n[a] += g.d[a];
+        if (mu == 0 && g.antiperiodic_t) *sign = -1.f;
+    } else if (n[a] >= g.d[a]) {
+        n[a] -= g.d[a];
+        if (mu == 0 && g.antiperiodic_t) *sign = -1.f;
+    }
+    return coords_site(g, n);
+}
+
+template <class Si, class So, class G, class C, class R>
+__global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
+    const Geo& g = a.g;
+    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    int c[4];
+    site_coords(g, s, c);
+    long long nf[4], nbk[4];
+    float sf[4], sb[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        nf[mu] = neighbour(g, c, mu, +1, &sf[mu]);
+        nbk[mu] = neighbour(g, c, mu, -1, &sb[mu]);
+    }
+    Clover<R> A;
+    load_clover<R, C>(a.clover, g.V, s, A);
+    const size_t in_stride = (size_t)6 * g.V * Unit<Si>::bytes;
+    const size_t out_stride = (size_t)6 * g.V * Unit<So>::bytes;
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        const void* in = reinterpret_cast<const char*>(a.in) + sys * in_stride;
+        const float* isc = a.in_scale ? a.in_scale + (size_t)sys * g.V : nullptr;
+        Spinor<R> acc;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) acc.v[i] = cmk<R>(0, 0);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            Link<R> L;
+            Spinor<R> p;
+            load_link<R, G>(a.links, g.V, s, mu, L);
+            load_spinor<R, Si>(in, isc, g.V, nf[mu], p);
+            hop_forward(mu, L, p, (R)sf[mu], acc);
+            load_link<R, G>(a.links, g.V, nbk[mu], mu, L);
+            load_spinor<R, Si>(in, isc, g.V, nbk[mu], p);
+            hop_backward(mu, L, p, (R)sb[mu], acc);
+        }
+        Spinor<R> self, out;
+        load_spinor<R, Si>(in, isc, g.V, s, self);
+        clover_apply(A, (R)a.mu[sys], self, out);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) out.v[i] = out.v[i] - (R)0.5 * acc.v[i];
+        store_spinor<R, So>(reinterpret_cast<char*>(a.out) + sys * out_stride,
+                            a.out_scale ? a.out_scale + (size_t)sys * g.V : nullptr, g.V, s, out);
+    }
+}
+
+template <class Si, class So, class G, class C, class R>
+hipError_t run(const DiracArgs& a, hipStream_t st) {
+    unsigned grid = (unsigned)((a.g.V + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_dirac<Si, So, G, C, R>), dim3(grid), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Supported combinations (spinor in, spinor out, links, clover, compute):
+//   all FP64; all FP32; FP16/BF16 spinors and links with FP32 clover and
+//   compute; FP32/FP16/BF16 input with FP64 output, links, clover and compute
+//   (the FP64 operator applied to a low-precision preconditioned vector);
+//   FP16/BF16 input with FP32 output, links, clover and compute.
+hipError_t launch_dirac(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_p, Prec clover_p, Prec compute,
+                        hipStream_t st) {
+#define TM_CASE(PI, PO, PL, PC, PR, TI, TO, TL, TC, TR)                                      \
+    if (in_p == PI && out_p == PO && link_p == PL && clover_p == PC && compute == PR) \
+        return run<TI, TO, TL, TC, TR>(a, st);
+    TM_CASE(P_F64, P_F64, P_F64, P_F64, P_F64, double, double, double, double, double)
+    TM_CASE(P_F32, P_F32, P_F32, P_F32, P_F32, float, float, float, float, float)
+    TM_CASE(P_F16, P_F16, P_F16, P_F32, P_F32, f16, f16, f16, float, float)
+    TM_CASE(P_BF16, P_BF16, P_BF16, P_F32, P_F32, bf16, bf16, bf16, float, float)
+    TM_CASE(P_F32, P_F64, P_F64, P_F64, P_F64, float, double, double, double, double)
+    TM_CASE(P_F16, P_F64, P_F64, P_F64, P_F64, f16, double, double, double, double)
+    TM_CASE(P_BF16, P_F64, P_F64, P_F64, P_F64, bf16, double, double, double, double)
+    TM_CASE(P_F16, P_F32, P_F32, P_F32, P_F32, f16, float, float, float, float)
+    TM_CASE(P_BF16, P_F32, P_F32, P_F32, P_F32, bf16, float, float, float, float)
+#undef TM_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tmsap

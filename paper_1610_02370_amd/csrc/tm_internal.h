@@ -1,0 +1,90 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tm_device.h"
+
+namespace tmsap {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+
+constexpr int kMaxSys = 64;
+
+inline int unit_bytes(Prec p) { return p == P_F64 ? 32 : (p == P_F32 ? 16 : 8); }
+inline bool prec_has_scale(Prec p) { return p == P_F16; }
+
+// Internal spinor field: data [nsys][6 units][V], FP16 scales [nsys][V].
+struct SpinorBuf {
+    void* data = nullptr;
+    float* scale = nullptr;
+    Prec prec = P_F64;
+    int nsys = 0;
+};
+
+// Bytes of the data part / scale part of an internal spinor field.
+inline size_t spinor_data_bytes(long long V, int nsys, Prec p) { return (size_t)nsys * 6 * V * unit_bytes(p); }
+inline size_t spinor_scale_bytes(long long V, int nsys, Prec p) {
+    return prec_has_scale(p) ? (size_t)nsys * V * sizeof(float) : 0;
+}
+inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Gauge data on the device at one precision: links [4][3 units][V] and the
+// packed clover [18 units][V] holding (m+4) + clover.
+struct GaugeDev {
+    void* links = nullptr;
+    void* clover = nullptr;
+    Prec link_prec = P_F64;
+    Prec clover_prec = P_F64;
+};
+
+struct DiracArgs {
+    Geo g;
+    const void* links;
+    const void* clover;
+    const void* in;
+    const float* in_scale;
+    void* out;
+    float* out_scale;
+    int nsys;
+    double mu[kMaxSys];
+};
+
+struct SapArgs {
+    Geo g;               // tile = Schwarz block
+    const void* links;
+    const void* clover;
+    const void* b;
+    const float* b_scale;
+    void* x;
+    float* x_scale;
+    int nsys;            // systems in the buffers
+    int sys_tile;        // systems per workgroup (gridDim.y = ceil(nsys / sys_tile))
+    int colour;
+    int mr_iters;
+    int x_zero;          // 1: x is zero on entry (first half-sweep of a zero guess)
+    double mu[kMaxSys];
+};
+
+// ---- layout kernels (tm_layout.hip)
+hipError_t launch_link_ingest(const Geo& g, Prec G, const void* Ucanon, void* links, unsigned* stats, hipStream_t st);
+hipError_t launch_clover_build(const Geo& g, Prec C, const void* Ucanon, double m4, double csw, void* clover,
+                               hipStream_t st);
+hipError_t launch_spinor_import(const Geo& g, const SpinorBuf& dst, const void* canon, unsigned* flag,
+                                hipStream_t st);
+hipError_t launch_spinor_export(const Geo& g, const SpinorBuf& src, void* canon, hipStream_t st);
+hipError_t launch_spinor_convert(const Geo& g, const SpinorBuf& src, const SpinorBuf& dst, hipStream_t st);
+
+// ---- operator (tm_dirac.hip)
+hipError_t launch_dirac(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_p, Prec clover_p, Prec compute,
+                        hipStream_t st);
+
+// ---- smoother (tm_sap.hip)
+hipError_t launch_sap_half(const SapArgs& a, Prec spinor_p, Prec link_p, Prec clover_p, Prec compute,
+                           hipStream_t st);
+bool sap_supported(Prec spinor_p, Prec link_p, Prec clover_p, Prec compute);
+size_t sap_lds_bytes(int Vb, Prec compute);
+
+}  // namespace tmsap

@@ -1,0 +1,110 @@
+"""GPU operator parity: tm_dirac_apply (HIP) against the FP64 CPU oracle.
+
+Tolerances (norm-wise relative error per application):
+  f64  1e-13  rounding of reordered FP64 sums only
+  f32  1e-5   the per-application bound for FP32 storage and compute
+  f16  4e-3   links and spinors rounded to FP16 (2^-11 relative to the site
+              maximum / link entry), about 8 hops' worth of such errors
+  bf16 2.5e-2 same with BF16's 2^-9 unit roundoff
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1610_02370_amd as tm
+from paper_1610_02370_amd import synth
+
+from gpu_util import announce, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-13, "f32": 1e-5, "f16": 4e-3, "bf16": 2.5e-2}
+
+CASES = [
+    # dims, eps, kappa, mus, csw, antiperiodic; dims chosen so tiles are mixed
+    # (4 and 2 per axis) and the last 256-thread group is partly filled
+    ((8, 6, 4, 10), 0.5, 0.1632, [0.003], 1.5, False),
+    ((4, 4, 4, 4), 0.3, 0.16, [0.01, -0.01], 0.0, True),
+    ((6, 4, 8, 4), 0.6, 0.1373, [0.0009, -0.0009, 0.0009], 1.5, False),
+]
+
+
+@pytest.fixture(scope="module")
+def fields():
+    out = []
+    for k, (dims, eps, kappa, mus, csw, ap) in enumerate(CASES):
+        U = synth.gauge_field(dims, eps, seed=20 + k)
+        psi = synth.gaussian_spinor(dims, len(mus), seed=120 + k)
+        op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), 0.0, csw, antiperiodic_t=ap)
+        ref = np.stack([op.with_mu(m).apply(psi[i]).reshape(-1, 4, 3) for i, m in enumerate(mus)])
+        out.append((U, psi, ref))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_dirac_matches_oracle(fields, case, prec):
+    dims, eps, kappa, mus, csw, ap = CASES[case]
+    U, psi, ref = fields[case]
+    announce(f"dirac parity case={case} dims={dims} prec={prec}")
+    out = tm.tm_dirac_apply(dims, dev(U), dev(psi), kappa, mus, csw, storage=prec, antiperiodic_t=ap)
+    got = host(out)
+    for i in range(len(mus)):
+        assert rel_err(got[i], ref[i]) < TOL[prec], (i, rel_err(got[i], ref[i]))
+
+
+def test_dirac_internal_io_roundtrip(fields):
+    import torch
+
+    dims, eps, kappa, mus, csw, ap = CASES[0]
+    U, psi, ref = fields[0]
+    announce("dirac internal-io roundtrip")
+    for prec in ("f64", "f32"):
+        nbytes = tm.tm_spinor_bytes(dims, len(mus), prec)
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        tm.tm_spinor_import(dims, dev(psi), a, storage=prec)
+        tm.tm_dirac_apply(dims, dev(U), a, kappa, mus, csw, b, storage=prec, io="internal")
+        out = torch.empty_like(dev(psi))
+        tm.tm_spinor_export(dims, b, out, storage=prec)
+        assert rel_err(host(out)[0], ref[0]) < TOL[prec]
+        back = torch.empty_like(out)
+        tm.tm_spinor_export(dims, a, back, storage=prec)
+        if prec == "f64":
+            assert np.array_equal(host(back), psi)
+
+
+def test_dirac_gamma5_hermiticity_on_gpu(fields):
+    # <phi, D(mu) psi> = <Gamma5 D(-mu) Gamma5 phi, psi>, both sides from the GPU
+    dims, eps, kappa, mus, csw, ap = CASES[2]
+    U, psi, _ = fields[2]
+    announce("dirac gamma5-hermiticity on GPU")
+    rng = np.random.default_rng(7)
+    phi = rng.normal(size=psi[:1].shape) + 1j * rng.normal(size=psi[:1].shape)
+    g5 = np.array([1, 1, -1, -1])[None, None, :, None]
+    Dpsi = host(tm.tm_dirac_apply(dims, dev(U), dev(psi[:1]), kappa, [0.2], csw))
+    Dphi = host(tm.tm_dirac_apply(dims, dev(U), dev(g5 * phi), kappa, [-0.2], csw))
+    lhs = np.vdot(phi.ravel(), Dpsi.ravel())
+    rhs = np.vdot((g5 * Dphi).ravel(), psi[:1].ravel())
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_dirac_error_paths(fields):
+    dims, eps, kappa, mus, csw, ap = CASES[0]
+    U, psi, _ = fields[0]
+    announce("dirac error paths")
+    with pytest.raises(tm.TMError) as e:
+        tm.tm_dirac_apply(dims, dev(1.1 * U), dev(psi), kappa, mus, csw)
+    assert e.value.code == -8
+    bad = U.copy()
+    bad[3, 1, 0, 0] = np.nan
+    with pytest.raises(tm.TMError) as e:
+        tm.tm_dirac_apply(dims, dev(bad), dev(psi), kappa, mus, csw)
+    assert e.value.code == -7
+    with pytest.raises(tm.TMError) as e:
+        tm.tm_dirac_apply(dims, dev(U), dev(psi), kappa, mus, csw, layout_block=(3, 3, 4, 5))
+    assert e.value.code == -2
+    t = dev(psi)
+    with pytest.raises(tm.TMError) as e:
+        tm.tm_dirac_apply(dims, dev(U), t, kappa, mus, csw, t)
+    assert e.value.code == -1
