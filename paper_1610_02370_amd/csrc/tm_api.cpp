@@ -260,7 +260,10 @@ int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf
     for (int cyc = 0; cyc < n_cycles; ++cyc)
         for (int colour = 0; colour < 2; ++colour) {
             a.colour = colour;
-            a.x_zero = (x_zero && cyc == 0 && colour == 0) ? 1 : 0;
+            // a zero guess: in the first cycle the swept colour's own x is
+            // still zero, and before the first sweep the halo is zero too
+            a.own_zero = (x_zero && cyc == 0) ? 1 : 0;
+            a.halo_zero = (x_zero && cyc == 0 && colour == 0) ? 1 : 0;
             hipError_t h = launch_sap_half(a, b.prec, G.link_prec, G.clover_prec, cp, st);
             if (h == hipErrorInvalidConfiguration)
                 return fail(TM_ERR_BLOCKS, "block of %d sites needs more LDS than the device has at this precision",

@@ -1,0 +1,276 @@
+// Vector kernels of the Krylov solvers on internal spinor fields: fused
+// classical Gram-Schmidt passes (w -= V h followed by the next dot products
+// or the norm in the same sweep), norms, scaling, the solution update
+// x += Z y, residual b - Dx and precision-changing accumulations.  Every
+// inner product accumulates in FP64; per-workgroup partials are summed by a
+// second kernel in a fixed order, so results do not depend on scheduling.
+#include "tm_blas.h"
+
+namespace tmsap {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxVec = 24;  // basis vectors handled by one pass
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <class P>
+__device__ inline void ld(const VecRef& r, int sys, long long V, long long s, Spinor<double>& out) {
+    load_spinor<double, P>(static_cast<const char*>(r.data) + (size_t)sys * r.sys_stride,
+                           r.scale ? r.scale + (size_t)sys * V : nullptr, V, s, out);
+}
+
+template <class P>
+__device__ inline void st(const VecRef& r, int sys, long long V, long long s, const Spinor<double>& v) {
+    store_spinor<double, P>(static_cast<char*>(r.data) + (size_t)sys * r.sys_stride,
+                            r.scale ? r.scale + (size_t)sys * V : nullptr, V, s, v);
+}
+
+// Workgroup reduction of n values per thread into partials[(sys*n + i)*nblk + blockIdx.x].
+__device__ inline void reduce_out(double* vals, int n, double* lds, double* partials, int sys, int nblk) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = 0; i < n; ++i) {
+        double v = wave_sum_d(vals[i]);
+        if (lane == 0) lds[w * 2 * kMaxVec + i] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < n) {
+        double t = 0;
+        for (int k = 0; k < kThreads / 64; ++k) t += lds[k * 2 * kMaxVec + threadIdx.x];
+        partials[((size_t)sys * n + threadIdx.x) * nblk + blockIdx.x] = t;
+    }
+}
+
+// mode 0: partial <v_i, w> for i < nvec (2 doubles each)
+// mode 1: w -= sum_i coef_i v_i, then partial <v_i, w_new> for i < nvec
+// mode 2: w -= sum_i coef_i v_i, then partial ||w_new||^2
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride, int nvec, VecRef w,
+                                                 const double* coef, int mode, double* partials, long long V) {
+    __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
+    const int sys = blockIdx.y;
+    const int nblk = gridDim.x;
+    double acc[2 * kMaxVec];
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxVec; ++i) acc[i] = 0;
+    cplx<double> c[kMaxVec];
+#pragma unroll
+    for (int i = 0; i < kMaxVec; ++i)
+        c[i] = (mode != 0 && i < nvec) ? cmk(coef[((size_t)sys * nvec + i) * 2], coef[((size_t)sys * nvec + i) * 2 + 1])
+                                        : cmk(0.0, 0.0);
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
+        Spinor<double> wv;
+        ld<P>(w, sys, V, s, wv);
+        if (mode != 0) {
+#pragma unroll
+            for (int i = 0; i < kMaxVec; ++i) {
+                if (i >= nvec) break;
+                VecRef vi = basis;
+                vi.data = static_cast<char*>(basis.data) + i * vec_stride;
+                vi.scale = nullptr;
+                Spinor<double> v;
+                ld<P>(vi, sys, V, s, v);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) wv.v[k] = wv.v[k] - c[i] * v.v[k];
+            }
+            st<P>(w, sys, V, s, wv);
+            // the stored (rounded) value is what later passes see
+            ld<P>(w, sys, V, s, wv);
+        }
+        if (mode == 2) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[0] += wv.v[k].re * wv.v[k].re + wv.v[k].im * wv.v[k].im;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kMaxVec; ++i) {
+                if (i >= nvec) break;
+                VecRef vi = basis;
+                vi.data = static_cast<char*>(basis.data) + i * vec_stride;
+                vi.scale = nullptr;
+                Spinor<double> v;
+                ld<P>(vi, sys, V, s, v);
+                double re = 0, im = 0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    re += v.v[k].re * wv.v[k].re + v.v[k].im * wv.v[k].im;
+                    im += v.v[k].re * wv.v[k].im - v.v[k].im * wv.v[k].re;
+                }
+                acc[2 * i] += re;
+                acc[2 * i + 1] += im;
+            }
+        }
+    }
+    reduce_out(acc, mode == 2 ? 1 : 2 * nvec, lds, partials, sys, nblk);
+}
+
+// out[sys*n + i] = sum over blocks (fixed order), optionally added to out.
+__global__ void k_reduce(const double* partials, int nblk, int nval_total, double* out, int accumulate) {
+    __shared__ double lds[kThreads];
+    const int v = blockIdx.x;
+    if (v >= nval_total) return;
+    double t = 0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) t += partials[(size_t)v * nblk + b];
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = accumulate ? out[v] + lds[0] : lds[0];
+}
+
+// y = a[sys] * x  (a real, per system, read from device memory)
+template <class Pi, class Po>
+__global__ void __launch_bounds__(kThreads) k_scale(VecRef x, const double* a, VecRef y, long long V) {
+    const int sys = blockIdx.y;
+    const double f = a[sys];
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)gridDim.x * kThreads) {
+        Spinor<double> v;
+        ld<Pi>(x, sys, V, s, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v.v[k] = f * v.v[k];
+        st<Po>(y, sys, V, s, v);
+    }
+}
+
+// x += sum_i y_i z_i, y complex per (sys, i) from device memory
+template <class Px, class Pz>
+__global__ void __launch_bounds__(kThreads) k_xupdate(VecRef x, VecRef z, size_t zvec_stride, size_t zscale_stride,
+                                                      int nvec, const double* y, long long V) {
+    const int sys = blockIdx.y;
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)gridDim.x * kThreads) {
+        Spinor<double> xv;
+        ld<Px>(x, sys, V, s, xv);
+        for (int i = 0; i < nvec; ++i) {
+            VecRef zi = z;
+            zi.data = static_cast<char*>(z.data) + i * zvec_stride;
+            zi.scale = z.scale ? z.scale + i * zscale_stride : nullptr;
+            Spinor<double> zv;
+            ld<Pz>(zi, sys, V, s, zv);
+            const cplx<double> c = cmk(y[((size_t)sys * nvec + i) * 2], y[((size_t)sys * nvec + i) * 2 + 1]);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) xv.v[k] = cmad(c, zv.v[k], xv.v[k]);
+        }
+        st<Px>(x, sys, V, s, xv);
+    }
+}
+
+// r = b - ax (r may alias ax), partial ||r||^2 and ||b||^2 (2 values per system)
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_residual(VecRef b, VecRef ax, VecRef r, double* partials, long long V) {
+    __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
+    const int sys = blockIdx.y;
+    double acc[2] = {0, 0};
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)gridDim.x * kThreads) {
+        Spinor<double> bv, av;
+        ld<P>(b, sys, V, s, bv);
+        ld<P>(ax, sys, V, s, av);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            av.v[k] = bv.v[k] - av.v[k];
+            acc[0] += av.v[k].re * av.v[k].re + av.v[k].im * av.v[k].im;
+            acc[1] += bv.v[k].re * bv.v[k].re + bv.v[k].im * bv.v[k].im;
+        }
+        st<P>(r, sys, V, s, av);
+    }
+    reduce_out(acc, 2, lds, partials, sys, gridDim.x);
+}
+
+// x (Px) += c (Pc)
+template <class Px, class Pc>
+__global__ void __launch_bounds__(kThreads) k_accumulate(VecRef x, VecRef c, long long V) {
+    const int sys = blockIdx.y;
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)gridDim.x * kThreads) {
+        Spinor<double> xv, cv;
+        ld<Px>(x, sys, V, s, xv);
+        ld<Pc>(c, sys, V, s, cv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) xv.v[k] = xv.v[k] + cv.v[k];
+        st<Px>(x, sys, V, s, xv);
+    }
+}
+
+__global__ void k_zero(void* p, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n16; i += (size_t)gridDim.x * kThreads)
+        reinterpret_cast<float4*>(p)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+}  // namespace
+
+int blas_blocks(long long V) {
+    long long n = (V + kThreads - 1) / kThreads;
+    return (int)(n < 1024 ? n : 1024);
+}
+
+int blas_max_vec() { return kMaxVec; }
+
+#define TM_DISPATCH_VEC(P, T, ...)                           \
+    switch (P) {                                             \
+        case P_F64: { typedef double T; __VA_ARGS__; break; } \
+        case P_F32: { typedef float T; __VA_ARGS__; break; }  \
+        case P_F16: { typedef f16 T; __VA_ARGS__; break; }    \
+        default: { typedef bf16 T; __VA_ARGS__; break; }      \
+    }
+
+hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, const VecRef& w, const double* coef,
+                   int mode, double* partials, double* out, int accumulate, int nsys, long long V, hipStream_t st) {
+    if (nvec > kMaxVec || (p != P_F64 && p != P_F32)) return hipErrorInvalidValue;
+    const int nblk = blas_blocks(V);
+    dim3 grid(nblk, nsys);
+    TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL(k_gs<T>, grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, coef,
+                                             mode, partials, V));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nval = nsys * (mode == 2 ? 1 : 2 * nvec);
+    hipLaunchKernelGGL(k_reduce, dim3(nval), dim3(kThreads), 0, st, partials, nblk, nval, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t blas_scale(Prec pi, Prec po, const VecRef& x, const double* a, const VecRef& y, int nsys, long long V,
+                      hipStream_t st) {
+    dim3 grid(blas_blocks(V), nsys);
+    TM_DISPATCH_VEC(pi, Ti, TM_DISPATCH_VEC(po, To, hipLaunchKernelGGL((k_scale<Ti, To>), grid, dim3(kThreads), 0, st,
+                                                                        x, a, y, V)));
+    return hipGetLastError();
+}
+
+hipError_t blas_xupdate(Prec px, Prec pz, const VecRef& x, const VecRef& z, size_t zvec_stride, size_t zscale_stride,
+                        int nvec, const double* y, int nsys, long long V, hipStream_t st) {
+    dim3 grid(blas_blocks(V), nsys);
+    TM_DISPATCH_VEC(px, Tx, TM_DISPATCH_VEC(pz, Tz, hipLaunchKernelGGL((k_xupdate<Tx, Tz>), grid, dim3(kThreads), 0,
+                                                                        st, x, z, zvec_stride, zscale_stride, nvec, y,
+                                                                        V)));
+    return hipGetLastError();
+}
+
+hipError_t blas_residual(Prec p, const VecRef& b, const VecRef& ax, const VecRef& r, double* partials, double* out,
+                         int nsys, long long V, hipStream_t st) {
+    const int nblk = blas_blocks(V);
+    dim3 grid(nblk, nsys);
+    TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL(k_residual<T>, grid, dim3(kThreads), 0, st, b, ax, r, partials, V));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(2 * nsys), dim3(kThreads), 0, st, partials, nblk, 2 * nsys, out, 0);
+    return hipGetLastError();
+}
+
+hipError_t blas_accumulate(Prec px, Prec pc, const VecRef& x, const VecRef& c, int nsys, long long V, hipStream_t st) {
+    dim3 grid(blas_blocks(V), nsys);
+    TM_DISPATCH_VEC(px, Tx, TM_DISPATCH_VEC(pc, Tc, hipLaunchKernelGGL((k_accumulate<Tx, Tc>), grid, dim3(kThreads),
+                                                                        0, st, x, c, V)));
+    return hipGetLastError();
+}
+
+hipError_t blas_zero(void* p, size_t bytes, hipStream_t st) {
+    const size_t n16 = bytes / 16;
+    const unsigned nb = (unsigned)((n16 + kThreads - 1) / kThreads < 4096 ? (n16 + kThreads - 1) / kThreads : 4096);
+    hipLaunchKernelGGL(k_zero, dim3(nb > 0 ? nb : 1), dim3(kThreads), 0, st, p, n16);
+    return hipGetLastError();
+}
+
+}  // namespace tmsap

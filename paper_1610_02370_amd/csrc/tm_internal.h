@@ -64,7 +64,8 @@ struct SapArgs {
     int sys_tile;        // systems per workgroup (gridDim.y = ceil(nsys / sys_tile))
     int colour;
     int mr_iters;
-    int x_zero;          // 1: x is zero on entry (first half-sweep of a zero guess)
+    int own_zero;        // 1: x is zero on this colour's blocks (skip reading it)
+    int halo_zero;       // 1: x is zero on the other colour's blocks too (then r = b)
     double mu[kMaxSys];
 };
 

@@ -148,15 +148,21 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
         float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
 
         Spinor<R> r, xv;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) xv.v[i] = cmk<R>(0, 0);
         if (active) load_spinor<R, S>(bb, bsc, g.V, s, r);
-        if (!a.x_zero) {
+        if (!(a.own_zero && a.halo_zero)) {
             // r = b - D x on the block: diagonal and in-block hops from LDS,
-            // hops from the neighbouring blocks straight from memory.
-            if (active) {
-                load_spinor<R, S>(xx, xsc, g.V, s, xv);
-                lds_put(sh, nt, l, xv);
+            // hops from the neighbouring blocks straight from memory.  When x
+            // is still zero on this colour only the halo hops remain.
+            const bool own = !a.own_zero;
+            if (own) {
+                if (active) {
+                    load_spinor<R, S>(xx, xsc, g.V, s, xv);
+                    lds_put(sh, nt, l, xv);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             if (active) {
                 Spinor<R> acc, dx;
 #pragma unroll
@@ -165,26 +171,36 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
                 for (int mu = 0; mu < 4; ++mu) {
                     Link<R> Lk;
                     Spinor<R> p;
-                    load_link<R, G>(a.links, g.V, s, mu, Lk);
-                    if (nlf[mu] >= 0)
-                        lds_get(sh, nt, nlf[mu], p);
-                    else
-                        load_spinor<R, S>(xx, xsc, g.V, ngf[mu], p);
-                    hop_forward(mu, Lk, p, sgf[mu], acc);
+                    if (nlf[mu] < 0 || own) {
+                        load_link<R, G>(a.links, g.V, s, mu, Lk);
+                        if (nlf[mu] >= 0)
+                            lds_get(sh, nt, nlf[mu], p);
+                        else
+                            load_spinor<R, S>(xx, xsc, g.V, ngf[mu], p);
+                        hop_forward(mu, Lk, p, sgf[mu], acc);
+                    }
                     if (nlb[mu] >= 0) {
-                        lds_get(sh, nt, nlb[mu], p);
-                        load_link<R, G>(a.links, g.V, s0 + nlb[mu], mu, Lk);
+                        if (own) {
+                            lds_get(sh, nt, nlb[mu], p);
+                            load_link<R, G>(a.links, g.V, s0 + nlb[mu], mu, Lk);
+                            hop_backward(mu, Lk, p, sgb[mu], acc);
+                        }
                     } else {
                         load_spinor<R, S>(xx, xsc, g.V, ngb[mu], p);
                         load_link<R, G>(a.links, g.V, ngb[mu], mu, Lk);
+                        hop_backward(mu, Lk, p, sgb[mu], acc);
                     }
-                    hop_backward(mu, Lk, p, sgb[mu], acc);
                 }
-                clover_apply(A, mu_tw, xv, dx);
+                if (own) {
+                    clover_apply(A, mu_tw, xv, dx);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) dx.v[i] = cmk<R>(0, 0);
+                }
 #pragma unroll
                 for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] - (dx.v[i] - (R)0.5 * acc.v[i]);
             }
-            __syncthreads();
+            if (own) __syncthreads();
         }
 
         // ---- minimal residual on D_BB from e = 0
@@ -236,10 +252,8 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
         }
 
         if (active) {
-            if (!a.x_zero) {
 #pragma unroll
-                for (int i = 0; i < 12; ++i) e.v[i] = e.v[i] + xv.v[i];
-            }
+            for (int i = 0; i < 12; ++i) e.v[i] = e.v[i] + xv.v[i];
             store_spinor<R, S>(xx, xsc, g.V, s, e);
         }
     }

@@ -1,10 +1,375 @@
-// Flexible GMRES preconditioned by SAP, defect correction, and the block-shape tuner.
+// Flexible GMRES right-preconditioned by SAP (section 2.5), the mixed-
+// precision defect-correction form (section 3.1: an FP64 residual loop around
+// FP32 FGMRES solves to a relative 1e-6), and the SAP block-shape tuner.
+//
+// All systems of a group advance together; each keeps its own Hessenberg
+// matrix, Givens rotations and Krylov dimension.  A system whose residual
+// estimate reaches the tolerance is frozen: its next basis vectors are zero,
+// so batched kernels carry it at no effect.  Orthogonalisation is classical
+// Gram-Schmidt applied twice, fused into three passes over the basis; the
+// host reads one Hessenberg column per step and solves the small
+// least-squares problems.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
+#include <vector>
 
 #include "../../include/tm.h"
 #include "tm_api_internal.h"
+#include "tm_blas.h"
+
+namespace tmsap {
+
+namespace {
+
+typedef std::complex<double> zc;
+
+struct Pinned {
+    double* p = nullptr;
+    size_t n = 0;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+    hipError_t ensure(size_t count) {
+        if (count <= n) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipHostMalloc((void**)&p, count * sizeof(double), hipHostMallocDefault);
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+};
+
+// Device scratch of one solve (carved from the device's reduction buffer).
+struct Scratch {
+    double* h1;        // [nsys][kMaxVec][2]
+    double* h2;        // [nsys][kMaxVec][2]
+    double* nrm;       // [nsys]
+    double* inv;       // [nsys]
+    double* ones;      // [nsys]
+    double* y;         // [nsys][kMaxVec][2]
+    double* res;       // [nsys][2]
+    double* partials;  // [nsys * 2 * kMaxVec][blocks]
+};
+
+struct Ctx {
+    DeviceState* ds;
+    hipStream_t st;
+    Geo g;
+    int nsys;
+    double mu[kMaxSys];
+    int n_cycles, mr_iters;
+    const GaugeDev* op;  // operator for w = D z and residuals
+    Prec op_compute;
+    const GaugeDev* sap;  // smoother gauge
+    Prec vp;              // Krylov vectors
+    Prec sp;              // smoother storage (preconditioned vectors z)
+    Scratch sc;
+    Pinned host;      // pinned host memory: [stage | inv | y], one region per transfer purpose
+    double* hstage = nullptr;  // device -> host Hessenberg columns and norms
+    double* hinv = nullptr;    // host -> device 1/beta and 1/||w|| factors
+    double* hy = nullptr;      // host -> device least-squares solutions
+    hipEvent_t ev[2];
+    double t_sap = 0;
+    long long sap_cycles = 0;
+};
+
+int hcheck(hipError_t e, const char* where) { return e == hipSuccess ? TM_OK : hip_fail(e, where); }
+
+// Krylov storage: basis V (m+1 vectors at vp), Z (m at sp), w (vp), vS (sp, when sp != vp).
+struct Krylov {
+    int m;
+    char* V;
+    size_t vstride;
+    char* Z;
+    size_t zstride;
+    SpinorBuf w;
+    SpinorBuf vS;
+    bool convert;
+
+    SpinorBuf Vb(const Ctx& c, int i) const { return wrap_internal(V + i * vstride, c.g, c.nsys, c.vp); }
+    SpinorBuf Zb(const Ctx& c, int i) const { return wrap_internal(Z + i * zstride, c.g, c.nsys, c.sp); }
+};
+
+size_t krylov_bytes(const Geo& g, int nsys, int m, Prec vp, Prec sp) {
+    size_t v = internal_bytes(g, nsys, vp), z = internal_bytes(g, nsys, sp);
+    return (size_t)(m + 2) * v + (size_t)m * z + (sp != vp ? z : 0);
+}
+
+Krylov carve_krylov(char*& p, const Geo& g, int nsys, int m, Prec vp, Prec sp) {
+    Krylov k;
+    k.m = m;
+    k.vstride = internal_bytes(g, nsys, vp);
+    k.zstride = internal_bytes(g, nsys, sp);
+    k.V = p;
+    p += (size_t)(m + 1) * k.vstride;
+    k.Z = p;
+    p += (size_t)m * k.zstride;
+    k.w = wrap_internal(p, g, nsys, vp);
+    p += k.vstride;
+    k.convert = sp != vp;
+    if (k.convert) {
+        k.vS = wrap_internal(p, g, nsys, sp);
+        p += k.zstride;
+    }
+    return k;
+}
+
+// r = rhs - D x (or r = rhs when x is zero); host gets ||r||^2 and ||rhs||^2.
+int residual(Ctx& c, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const SpinorBuf& r, double* rn2,
+             double* bn2) {
+    const long long V = c.g.V;
+    int rc;
+    if (x_zero) {
+        if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(rhs, V), c.sc.ones, vec_ref(r, V), c.nsys, V, c.st), "copy")))
+            return rc;
+        if ((rc = hcheck(blas_gs(c.vp, vec_ref(r, V), 0, 0, vec_ref(r, V), nullptr, 2, c.sc.partials, c.sc.res, 0,
+                                 c.nsys, V, c.st),
+                         "norm")))
+            return rc;
+        if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, c.nsys * sizeof(double), hipMemcpyDeviceToHost, c.st),
+                         "copy")))
+            return rc;
+        if ((rc = hcheck(hipStreamSynchronize(c.st), "residual"))) return rc;
+        for (int k = 0; k < c.nsys; ++k) rn2[k] = bn2[k] = c.hstage[k];
+        return TM_OK;
+    }
+    if ((rc = run_dirac(c.g, *c.op, x, r, c.mu, c.nsys, c.op_compute, c.st))) return rc;
+    if ((rc = hcheck(blas_residual(c.vp, vec_ref(rhs, V), vec_ref(r, V), vec_ref(r, V), c.sc.partials, c.sc.res,
+                                   c.nsys, V, c.st),
+                     "residual")))
+        return rc;
+    if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, 2 * c.nsys * sizeof(double), hipMemcpyDeviceToHost, c.st),
+                     "copy")))
+        return rc;
+    if ((rc = hcheck(hipStreamSynchronize(c.st), "residual"))) return rc;
+    for (int k = 0; k < c.nsys; ++k) {
+        rn2[k] = c.hstage[2 * k];
+        bn2[k] = c.hstage[2 * k + 1];
+    }
+    return TM_OK;
+}
+
+struct CoreResult {
+    int iters[kMaxSys];
+    double rel[kMaxSys];
+    bool conv[kMaxSys];
+};
+
+// FGMRES(m) for D x = rhs, x in/out, all vectors at c.vp.  Stops per system at
+// ||rhs - D x|| <= tol ||rhs|| (residual recomputed at every restart at the
+// operator's precision) or when max_iters Arnoldi steps were taken.
+int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, double tol, int max_iters,
+                CoreResult& out) {
+    const long long V = c.g.V;
+    const int ns = c.nsys, m = K.m;
+    int rc;
+    std::vector<double> rn2(ns), bn2(ns), bnorm(ns);
+    std::vector<zc> H((size_t)ns * (m + 1) * m), sn((size_t)ns * m), gv((size_t)ns * (m + 1));
+    std::vector<double> cs((size_t)ns * m);
+    std::vector<int> kdim(ns);
+    std::vector<char> frozen(ns);
+    for (int k = 0; k < ns; ++k) out.iters[k] = 0;
+    SpinorBuf V0 = K.Vb(c, 0);
+    if ((rc = residual(c, rhs, x, x_zero, V0, rn2.data(), bn2.data()))) return rc;
+    for (int k = 0; k < ns; ++k) bnorm[k] = std::sqrt(bn2[k]);
+    int steps = 0;
+    for (;;) {
+        bool any = false;
+        for (int k = 0; k < ns; ++k) {
+            const double rel = bnorm[k] > 0 ? std::sqrt(rn2[k]) / bnorm[k] : 0.0;
+            out.rel[k] = rel;
+            out.conv[k] = rel <= tol;
+            frozen[k] = out.conv[k];
+            any |= !out.conv[k];
+        }
+        if (!any || steps >= max_iters) break;
+        // v0 = r / beta
+        for (int k = 0; k < ns; ++k) {
+            const double beta = std::sqrt(rn2[k]);
+            c.hinv[k] = frozen[k] ? 0.0 : 1.0 / beta;
+            for (int i = 0; i <= m; ++i) gv[(size_t)k * (m + 1) + i] = 0;
+            gv[(size_t)k * (m + 1)] = frozen[k] ? 0.0 : beta;
+            kdim[k] = 0;
+        }
+        if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st), "copy")))
+            return rc;
+        if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(V0, V), c.sc.inv, vec_ref(V0, V), ns, V, c.st), "scale")))
+            return rc;
+        int jdone = 0;
+        for (int j = 0; j < m && steps < max_iters; ++j) {
+            const SpinorBuf vj = K.Vb(c, j);
+            const SpinorBuf zj = K.Zb(c, j);
+            SpinorBuf src = vj;
+            if (K.convert) {
+                if ((rc = hcheck(launch_spinor_convert(c.g, vj, K.vS, c.st), "convert"))) return rc;
+                src = K.vS;
+            }
+            // z_j = SAP(v_j) from a zero guess; w = D z_j
+            if ((rc = hcheck(hipEventRecord(c.ev[0], c.st), "event"))) return rc;
+            if ((rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, 0, c.st))) return rc;
+            if ((rc = hcheck(hipEventRecord(c.ev[1], c.st), "event"))) return rc;
+            c.sap_cycles += c.n_cycles;
+            if ((rc = run_dirac(c.g, *c.op, zj, K.w, c.mu, ns, c.op_compute, c.st))) return rc;
+            // classical Gram-Schmidt, twice
+            const VecRef basis = vec_ref(K.Vb(c, 0), V), wr = vec_ref(K.w, V);
+            const int nv = j + 1;
+            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, nullptr, 0, c.sc.partials, c.sc.h1, 0, ns, V, c.st),
+                             "gs")))
+                return rc;
+            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h1, 1, c.sc.partials, c.sc.h2, 0, ns, V, c.st),
+                             "gs")))
+                return rc;
+            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h2, 2, c.sc.partials, c.sc.nrm, 0, ns, V, c.st),
+                             "gs")))
+                return rc;
+            const size_t nh = (size_t)ns * nv * 2;
+            if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.h1, nh * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
+                return rc;
+            if ((rc = hcheck(hipMemcpyAsync(c.hstage + nh, c.sc.h2, nh * sizeof(double), hipMemcpyDeviceToHost, c.st),
+                             "copy")))
+                return rc;
+            if ((rc = hcheck(hipMemcpyAsync(c.hstage + 2 * nh, c.sc.nrm, ns * sizeof(double), hipMemcpyDeviceToHost,
+                                            c.st),
+                             "copy")))
+                return rc;
+            if ((rc = hcheck(hipStreamSynchronize(c.st), "arnoldi step"))) return rc;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, c.ev[0], c.ev[1]) == hipSuccess) c.t_sap += ms * 1e-3;
+            ++steps;
+            bool all_frozen = true;
+            std::vector<double> inv(ns, 0.0);
+            for (int k = 0; k < ns; ++k) {
+                if (frozen[k]) continue;
+                ++out.iters[k];
+                zc* Hk = &H[(size_t)k * (m + 1) * m];
+                for (int i = 0; i < nv; ++i) {
+                    const double* a = c.hstage + ((size_t)k * nv + i) * 2;
+                    const double* b2 = c.hstage + nh + ((size_t)k * nv + i) * 2;
+                    Hk[i * m + j] = zc(a[0] + b2[0], a[1] + b2[1]);
+                }
+                const double hn = std::sqrt(std::max(0.0, c.hstage[2 * nh + k]));
+                Hk[(j + 1) * m + j] = hn;
+                double* csk = &cs[(size_t)k * m];
+                zc* snk = &sn[(size_t)k * m];
+                zc* gk = &gv[(size_t)k * (m + 1)];
+                for (int i = 0; i < j; ++i) {
+                    const zc a = Hk[i * m + j], b2 = Hk[(i + 1) * m + j];
+                    Hk[i * m + j] = csk[i] * a + snk[i] * b2;
+                    Hk[(i + 1) * m + j] = -std::conj(snk[i]) * a + csk[i] * b2;
+                }
+                const zc a = Hk[j * m + j], b2 = Hk[(j + 1) * m + j];
+                const double t = std::sqrt(std::norm(a) + std::norm(b2));
+                if (std::abs(a) == 0.0) {
+                    csk[j] = 0.0;
+                    snk[j] = 1.0;
+                } else {
+                    csk[j] = std::abs(a) / t;
+                    snk[j] = (a / std::abs(a)) * std::conj(b2) / t;
+                }
+                Hk[j * m + j] = csk[j] * a + snk[j] * b2;
+                Hk[(j + 1) * m + j] = 0.0;
+                gk[j + 1] = -std::conj(snk[j]) * gk[j];
+                gk[j] = csk[j] * gk[j];
+                kdim[k] = j + 1;
+                const bool done = std::abs(gk[j + 1]) <= tol * bnorm[k] || hn == 0.0;
+                if (done)
+                    frozen[k] = 1;
+                else
+                    inv[k] = 1.0 / hn;
+                all_frozen &= (bool)frozen[k];
+            }
+            jdone = j + 1;
+            for (int k = 0; k < ns; ++k) c.hinv[k] = inv[k];
+            if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st),
+                             "copy")))
+                return rc;
+            const SpinorBuf vn = K.Vb(c, j + 1);
+            if ((rc = hcheck(blas_scale(c.vp, c.vp, wr, c.sc.inv, vec_ref(vn, V), ns, V, c.st), "scale"))) return rc;
+            if (all_frozen) break;
+        }
+        // x += Z y, y = R^-1 g per system (zero beyond its Krylov dimension)
+        std::vector<double> yh((size_t)ns * jdone * 2, 0.0);
+        for (int k = 0; k < ns; ++k) {
+            const zc* Hk = &H[(size_t)k * (m + 1) * m];
+            const zc* gk = &gv[(size_t)k * (m + 1)];
+            std::vector<zc> y(kdim[k]);
+            for (int i = kdim[k] - 1; i >= 0; --i) {
+                zc t = gk[i];
+                for (int q = i + 1; q < kdim[k]; ++q) t -= Hk[i * m + q] * y[q];
+                y[i] = t / Hk[i * m + i];
+            }
+            for (int i = 0; i < kdim[k]; ++i) {
+                yh[((size_t)k * jdone + i) * 2] = y[i].real();
+                yh[((size_t)k * jdone + i) * 2 + 1] = y[i].imag();
+            }
+        }
+        if (jdone > 0) {
+            std::memcpy(c.hy, yh.data(), yh.size() * sizeof(double));
+            if ((rc = hcheck(hipMemcpyAsync(c.sc.y, c.hy, yh.size() * sizeof(double), hipMemcpyHostToDevice, c.st),
+                             "copy")))
+                return rc;
+            const SpinorBuf z0 = K.Zb(c, 0);
+            const size_t zscale_stride = K.zstride / sizeof(float);
+            if ((rc = hcheck(blas_xupdate(c.vp, c.sp, vec_ref(x, V), vec_ref(z0, V), K.zstride, zscale_stride, jdone,
+                                          c.sc.y, ns, V, c.st),
+                             "x update")))
+                return rc;
+        }
+        x_zero = false;
+        if ((rc = residual(c, rhs, x, false, V0, rn2.data(), bn2.data()))) return rc;
+    }
+    return TM_OK;
+}
+
+int carve_scratch(Ctx& c) {
+    const int nblk = blas_blocks(c.g.V);
+    const size_t nvals = (size_t)c.nsys * 2 * blas_max_vec();
+    const size_t doubles = 2 * nvals + 4 * c.nsys + nvals + 2 * c.nsys + nvals * nblk + 64;
+    hipError_t e = c.ds->red.ensure(doubles * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "solver scratch");
+    double* p = (double*)c.ds->red.ptr;
+    c.sc.h1 = p; p += nvals;
+    c.sc.h2 = p; p += nvals;
+    c.sc.nrm = p; p += c.nsys;
+    c.sc.inv = p; p += c.nsys;
+    c.sc.ones = p; p += c.nsys;
+    c.sc.y = p; p += nvals;
+    c.sc.res = p; p += 2 * c.nsys;
+    c.sc.partials = p;
+    const size_t stage = 2 * nvals + c.nsys + 32, hinv = c.nsys + 32, hy = nvals + 32;
+    e = c.host.ensure(stage + hinv + hy);
+    if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
+    c.hstage = c.host.p;
+    c.hinv = c.host.p + stage;
+    c.hy = c.host.p + stage + hinv;
+    for (int k = 0; k < c.nsys; ++k) c.hinv[k] = 1.0;
+    e = hipMemcpyAsync(c.sc.ones, c.hinv, c.nsys * sizeof(double), hipMemcpyHostToDevice, c.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+    return e == hipSuccess ? TM_OK : hip_fail(e, "scratch init");
+}
+
+// Largest group of systems whose workspace fits in free device memory.
+int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed) {
+    int gsz = group > 0 ? std::min(group, nsys) : nsys;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return gsz;
+    const size_t avail = (size_t)((double)(free_b + ds->solver.bytes) * 0.92);
+    while (gsz > 1 && fixed + per_sys * (size_t)gsz > avail) gsz = (gsz + 1) / 2;
+    return gsz;
+}
+
+}  // namespace
+
+}  // namespace tmsap
 
 using namespace tmsap;
 
@@ -24,9 +389,176 @@ void tm_solver_opts_default(tm_solver_opts* s) {
     s->group = 0;
 }
 
-int tm_fgmres_solve(const tm_geom*, const void*, const void*, void*, double, double, double, const tm_solver_opts*,
-                    const tm_opts*, tm_solve_report*) {
-    return fail(TM_ERR_ARG, "tm_fgmres_solve: not built yet");
+int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw, double tol,
+                    const tm_solver_opts* so, const tm_opts* opts, tm_solve_report* report) {
+    const auto t_start = std::chrono::steady_clock::now();
+    int rc;
+    if ((rc = check_geom(geom)) || (rc = check_opts(opts))) return rc;
+    if (!so) return fail(TM_ERR_ARG, "solver options are NULL");
+    if (!U || !b || !x) return fail(TM_ERR_ARG, "null pointer");
+    if (b == x) return fail(TM_ERR_ARG, "b and x alias");
+    if (opts->io != TM_IO_CANONICAL) return fail(TM_ERR_ARG, "tm_fgmres_solve takes canonical buffers");
+    if (!(tol > 0) || !(kappa > 0) || !std::isfinite(c_sw)) return fail(TM_ERR_ARG, "bad tol, kappa or c_sw");
+    if (so->restart < 1 || so->restart > blas_max_vec() - 1)
+        return fail(TM_ERR_ARG, "restart must be in 1..%d", blas_max_vec() - 1);
+    if (so->n_cycles < 1 || so->mr_iters < 0 || so->max_iters < 1) return fail(TM_ERR_ARG, "bad iteration counts");
+    if (so->form != TM_SOLVE_FLEXIBLE && so->form != TM_SOLVE_DEFECT_CORRECTION) return fail(TM_ERR_ARG, "unknown form");
+    const Prec sp = (Prec)opts->storage;
+    const bool dc = so->form == TM_SOLVE_DEFECT_CORRECTION;
+    if (dc && sp == P_F64) return fail(TM_ERR_PREC, "defect correction needs FP32/FP16/BF16 smoother storage");
+    if (dc && !(so->inner_tol > 0 && so->inner_tol < 1)) return fail(TM_ERR_ARG, "inner_tol must be in (0, 1)");
+    int bd[4];
+    const bool bd_given = so->block_dims[0] | so->block_dims[1] | so->block_dims[2] | so->block_dims[3];
+    for (int a = 0; a < 4; ++a) bd[a] = bd_given ? so->block_dims[a] : 4;
+    int tile[4];
+    if ((rc = check_sap_blocks(geom, bd, tile))) return rc;
+    if (!sap_supported(sp, sp, clover_prec_for(sp), sp == P_F64 ? P_F64 : P_F32))
+        return fail(TM_ERR_PREC, "unsupported smoother precision");
+    DeviceState* ds = device_state(&rc);
+    if (!ds) return rc;
+    hipStream_t st = (hipStream_t)opts->stream;
+    Geo g = make_geo(geom, tile);
+    const long long V = g.V;
+
+    const GaugeDev *op64, *op32 = nullptr, *gs;
+    if ((rc = get_gauge(ds, g, U, kappa, c_sw, P_F64, opts->gauge_tag, st, &op64))) return rc;
+    if (dc && (rc = get_gauge(ds, g, U, kappa, c_sw, P_F32, opts->gauge_tag, st, &op32))) return rc;
+    if (sp == P_F64)
+        gs = op64;
+    else if (sp == P_F32 && op32)
+        gs = op32;
+    else if ((rc = get_gauge(ds, g, U, kappa, c_sw, sp, opts->gauge_tag, st, &gs)))
+        return rc;
+
+    const Prec vp = dc ? P_F32 : P_F64;
+    const int m = so->restart;
+    // bytes per system: outer FP64 vectors (b, x, and r for defect correction) + Krylov space (+ r32, c32)
+    const size_t b64 = internal_bytes(g, 1, P_F64);
+    const size_t per_sys = (dc ? 3 : 2) * b64 + krylov_bytes(g, 1, m, vp, sp) +
+                           (dc ? 2 * internal_bytes(g, 1, P_F32) : 0);
+    const int group = fit_group(ds, geom->nsys, so->group, per_sys, 0);
+
+    Ctx c;
+    c.ds = ds;
+    c.st = st;
+    c.g = g;
+    c.n_cycles = so->n_cycles;
+    c.mr_iters = so->mr_iters;
+    c.sap = gs;
+    c.vp = vp;
+    c.sp = sp;
+    if ((rc = hcheck(hipEventCreate(&c.ev[0]), "event")) || (rc = hcheck(hipEventCreate(&c.ev[1]), "event"))) return rc;
+    struct EvGuard {
+        Ctx& c;
+        ~EvGuard() {
+            (void)hipEventDestroy(c.ev[0]);
+            (void)hipEventDestroy(c.ev[1]);
+        }
+    } evguard{c};
+
+    tm_solve_report rep;
+    std::memset(&rep, 0, sizeof rep);
+    int all_conv = 1;
+    const size_t canon_sys = (size_t)V * 12 * 2 * sizeof(double);
+    for (int g0 = 0; g0 < geom->nsys; g0 += group) {
+        const int ns = std::min(group, geom->nsys - g0);
+        c.nsys = ns;
+        for (int k = 0; k < kMaxSys; ++k) c.mu[k] = k < ns ? geom->mu[g0 + k] : 0.0;
+        size_t bytes = (dc ? 3 : 2) * internal_bytes(g, ns, P_F64) + krylov_bytes(g, ns, m, vp, sp) +
+                       (dc ? 2 * internal_bytes(g, ns, P_F32) : 0);
+        hipError_t h = ds->solver.ensure(bytes);
+        if (h != hipSuccess) return hip_fail(h, "solver workspace");
+        if ((rc = carve_scratch(c))) return rc;
+        char* p = (char*)ds->solver.ptr;
+        SpinorBuf bb = wrap_internal(p, g, ns, P_F64);
+        p += internal_bytes(g, ns, P_F64);
+        SpinorBuf xx = wrap_internal(p, g, ns, P_F64);
+        p += internal_bytes(g, ns, P_F64);
+        const char* bcan = (const char*)b + g0 * canon_sys;
+        char* xcan = (char*)x + g0 * canon_sys;
+        if ((h = ds->stats.ensure(256)) != hipSuccess) return hip_fail(h, "stats");
+        unsigned* flag = (unsigned*)ds->stats.ptr + 2;
+        if ((rc = hcheck(hipMemsetAsync(flag, 0, sizeof(unsigned), st), "memset"))) return rc;
+        if ((rc = hcheck(launch_spinor_import(g, bb, bcan, flag, st), "import b"))) return rc;
+        if ((rc = hcheck(launch_spinor_import(g, xx, xcan, flag, st), "import x"))) return rc;
+        unsigned hflag = 0;
+        if ((rc = hcheck(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st), "copy"))) return rc;
+        if ((rc = hcheck(hipStreamSynchronize(st), "import"))) return rc;
+        if (hflag) return fail(TM_ERR_NONFINITE, "b or x holds NaN or Inf");
+
+        CoreResult res;
+        if (!dc) {
+            c.op = op64;
+            c.op_compute = P_F64;
+            Krylov K = carve_krylov(p, g, ns, m, vp, sp);
+            if ((rc = fgmres_core(c, K, bb, xx, false, tol, so->max_iters, res))) return rc;
+            for (int k = 0; k < ns; ++k) {
+                rep.true_rel_res[g0 + k] = res.rel[k];
+                rep.iters = std::max(rep.iters, res.iters[k]);
+                rep.converged += res.conv[k];
+                all_conv &= res.conv[k];
+            }
+        } else {
+            SpinorBuf rr = wrap_internal(p, g, ns, P_F64);
+            p += internal_bytes(g, ns, P_F64);
+            SpinorBuf r32 = wrap_internal(p, g, ns, P_F32);
+            p += internal_bytes(g, ns, P_F32);
+            SpinorBuf c32 = wrap_internal(p, g, ns, P_F32);
+            p += internal_bytes(g, ns, P_F32);
+            Krylov K = carve_krylov(p, g, ns, m, vp, sp);
+            std::vector<double> rn2(ns), bn2(ns);
+            std::vector<int> iters(ns, 0);
+            int outer = 0;
+            bool done = false;
+            for (;;) {
+                // FP64 residual of the current iterate
+                c.vp = P_F64;
+                c.op = op64;
+                c.op_compute = P_F64;
+                if ((rc = residual(c, bb, xx, false, rr, rn2.data(), bn2.data()))) return rc;
+                done = true;
+                for (int k = 0; k < ns; ++k) {
+                    const double rel = bn2[k] > 0 ? std::sqrt(rn2[k] / bn2[k]) : 0.0;
+                    rep.true_rel_res[g0 + k] = rel;
+                    done &= rel <= tol;
+                }
+                int maxit = 0;
+                for (int k = 0; k < ns; ++k) maxit = std::max(maxit, iters[k]);
+                if (done || outer >= so->max_outer || maxit >= so->max_iters) break;
+                // inner FP32 solve of D c = r to inner_tol, then x += c
+                if ((rc = hcheck(launch_spinor_convert(g, rr, r32, st), "convert"))) return rc;
+                c.vp = P_F32;
+                c.op = op32;
+                c.op_compute = P_F32;
+                double itol = so->inner_tol;
+                // never ask the inner solve for more than the outer tolerance needs
+                for (int k = 0; k < ns; ++k)
+                    if (rn2[k] > 0 && bn2[k] > 0) itol = std::max(itol, 0.5 * tol * std::sqrt(bn2[k] / rn2[k]));
+                itol = std::min(itol, 0.5);
+                if ((rc = hcheck(blas_zero(c32.data, internal_bytes(g, ns, P_F32), st), "zero"))) return rc;
+                if ((rc = fgmres_core(c, K, r32, c32, true, itol, so->max_iters - maxit, res))) return rc;
+                for (int k = 0; k < ns; ++k) iters[k] += res.iters[k];
+                if ((rc = hcheck(blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st),
+                                 "accumulate")))
+                    return rc;
+                ++outer;
+            }
+            for (int k = 0; k < ns; ++k) {
+                const bool ok = rep.true_rel_res[g0 + k] <= tol;
+                rep.converged += ok;
+                all_conv &= ok;
+                rep.iters = std::max(rep.iters, iters[k]);
+            }
+            rep.outer = std::max(rep.outer, outer);
+        }
+        if ((rc = hcheck(launch_spinor_export(g, xx, xcan, st), "export x"))) return rc;
+        if ((rc = hcheck(hipStreamSynchronize(st), "export"))) return rc;
+    }
+    rep.t_sap = c.t_sap;
+    rep.sap_cycles = c.sap_cycles;
+    rep.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (report) *report = rep;
+    return all_conv ? TM_OK : TM_NOT_CONVERGED;
 }
 
 int tm_autotune_sap(const tm_geom*, const void*, double, double, int, int, const tm_opts*, int*) {

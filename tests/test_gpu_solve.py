@@ -1,0 +1,145 @@
+"""GPU solve parity: tm_fgmres_solve (HIP) against the FP64 CPU oracle.
+
+The solution of D(mu) x = b is unique, so the check is on x, not on iteration
+counts: the true residual ||b - D x|| / ||b|| is recomputed with the ORACLE's
+operator from the returned x and must meet the tolerance, and since every
+singular value of D(mu) is >= |mu| (section 2.1), ||x - x*|| <= ||b - D x|| / |mu|
+bounds the distance to the exact solution.  On 4^4 the exact solution comes
+from dense LU and is compared directly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1610_02370_amd as tm
+from paper_1610_02370_amd import synth
+
+from gpu_util import announce, dev, host
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+RES_SLACK = 1.05  # FP64 rounding of the oracle's recomputed residual
+
+
+@pytest.fixture(scope="module")
+def cfg_4444():
+    dims, eps, kappa, mu, csw = (4, 4, 4, 4), 0.3, 0.16, 0.01, 0.0
+    U = synth.gauge_field(dims, eps, seed=1)
+    b = synth.gaussian_spinor(dims, 1, seed=101)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), mu, csw)
+    xs = np.linalg.solve(op.dense(), b[0].ravel())
+    return dims, kappa, mu, csw, U, b, op, xs
+
+
+@pytest.mark.parametrize("form,storage", [("flexible", "f64"), ("flexible", "f32"), ("flexible", "f16"),
+                                          ("defect_correction", "f32"), ("defect_correction", "f16"),
+                                          ("defect_correction", "bf16")])
+def test_4x4x4x4_solve_against_dense_lu(cfg_4444, form, storage):
+    dims, kappa, mu, csw, U, b, op, xs = cfg_4444
+    announce(f"solve 4^4 form={form} storage={storage}")
+    x = dev(np.zeros_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, TOL, storage=storage, form=form,
+                                 restart=20, n_cycles=3, mr_iters=4, block_dims=(2, 2, 2, 2))
+    assert rc == 0 and rep["converged"] == 1, rep
+    xg = host(x)[0].ravel()
+    r = b[0].ravel() - op.apply(xg)
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    assert rel <= TOL * RES_SLACK, rel
+    assert abs(rep["true_rel_res"][0] - rel) <= 0.05 * TOL
+    # sigma_min >= |mu| bounds the error; the dense solution confirms it
+    err = np.linalg.norm(xg - xs)
+    assert err <= np.linalg.norm(r) / mu * 1.01
+    assert err / np.linalg.norm(xs) < 1e-8
+
+
+def test_4x4x4x4_oracle_fgmres_agrees(cfg_4444):
+    dims, kappa, mu, csw, U, b, op, xs = cfg_4444
+    announce("solve 4^4 oracle FGMRES vs GPU FGMRES")
+    xo, rep_o = op.fgmres(b[0].ravel(), 1e-12, restart=20, precond=True, bdims=(2, 2, 2, 2), n_cycles=3, mr_iters=4)
+    x = dev(np.zeros_like(b))
+    tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, 1e-12, storage="f64", restart=20, n_cycles=3,
+                       mr_iters=4, block_dims=(2, 2, 2, 2))
+    assert np.linalg.norm(host(x)[0].ravel() - xo) < 1e-9 * np.linalg.norm(xo)
+
+
+@pytest.fixture(scope="module")
+def cfg_8888():
+    dims, eps, kappa, mu, csw = (8, 8, 8, 8), 0.5, 0.1632, 0.003, 1.5
+    U = synth.gauge_field(dims, eps, seed=2)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), 0.0, csw)
+    return dims, kappa, mu, csw, U, op
+
+
+def check_solutions(op, dims, b, x, mus, tol):
+    for k, m in enumerate(mus):
+        r = b[k].ravel() - op.with_mu(m).apply(x[k].ravel())
+        rel = np.linalg.norm(r) / np.linalg.norm(b[k])
+        assert rel <= tol * RES_SLACK, (k, rel)
+
+
+@pytest.mark.parametrize("form,storage", [("flexible", "f64"), ("flexible", "f32"), ("defect_correction", "f32"),
+                                          ("defect_correction", "f16"), ("defect_correction", "bf16")])
+def test_8x8x8x8_point_source_pm_mu(cfg_8888, form, storage):
+    dims, kappa, mu, csw, U, op = cfg_8888
+    announce(f"solve 8^4 +-mu form={form} storage={storage}")
+    b = synth.point_sources(dims, [(0, 0), (0, 0)])
+    mus = [mu, -mu]
+    x = dev(np.zeros_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, mus, csw, TOL, storage=storage, form=form,
+                                 restart=16, n_cycles=4, mr_iters=4, block_dims=(4, 4, 4, 4))
+    assert rc == 0 and rep["converged"] == 2, rep
+    check_solutions(op, dims, b, host(x), mus, TOL)
+
+
+def test_8x8x8x8_twelve_sources_grouped(cfg_8888):
+    # all 12 spin-colour point sources; group=5 forces groups of 5, 5 and 2
+    dims, kappa, mu, csw, U, op = cfg_8888
+    announce("solve 8^4 twelve sources, groups of 5")
+    b = synth.all_point_sources(dims)
+    mus = [mu] * 12
+    x = dev(np.zeros_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, mus, csw, TOL, storage="f32",
+                                 form="defect_correction", restart=12, group=5)
+    assert rc == 0 and rep["converged"] == 12, rep
+    check_solutions(op, dims, b, host(x), mus, TOL)
+
+
+def test_nonzero_initial_guess_and_antiperiodic():
+    dims, kappa, mu, csw = (8, 4, 4, 8), 0.1394, 0.01, 1.5
+    U = synth.gauge_field(dims, 0.6, seed=3)
+    b = synth.gaussian_spinor(dims, 1, seed=103)
+    x0 = synth.gaussian_spinor(dims, 1, seed=203)
+    announce("solve nonzero guess, antiperiodic t")
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), mu, csw, antiperiodic_t=True)
+    x = dev(x0)
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, TOL, storage="f32",
+                                 antiperiodic_t=True, block_dims=(2, 2, 2, 4))
+    assert rc == 0
+    check_solutions(op, dims, b, host(x), [mu], TOL)
+
+
+def test_solver_error_paths(cfg_4444):
+    dims, kappa, mu, csw, U, b, op, xs = cfg_4444
+    announce("solve error paths")
+    x = dev(np.zeros_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, TOL, storage="f64", max_iters=2,
+                                 block_dims=(2, 2, 2, 2))
+    assert rc == 1 and rep["converged"] == 0 and rep["true_rel_res"][0] > TOL
+    bad = b.copy()
+    bad[0, 5, 1, 1] = np.inf
+    with pytest.raises(tm.TMError) as e:
+        tm.tm_fgmres_solve(dims, dev(U), dev(bad), x, kappa, [mu], csw, TOL, block_dims=(2, 2, 2, 2))
+    assert e.value.code == -7
+    with pytest.raises(tm.TMError) as e:
+        tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, TOL, restart=0, block_dims=(2, 2, 2, 2))
+    assert e.value.code == -1
+    with pytest.raises(tm.TMError) as e:
+        tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, TOL, storage="f64", form="defect_correction",
+                           block_dims=(2, 2, 2, 2))
+    assert e.value.code == -4
+    # zero right-hand side: x = 0 immediately
+    x = dev(np.ones_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(np.zeros_like(b)), x, kappa, [mu], csw, TOL,
+                                 block_dims=(2, 2, 2, 2))
+    assert rc == 0
