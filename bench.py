@@ -1,0 +1,368 @@
+#!/usr/bin/env python3
+"""Benchmark: SAP-smoothed twisted-mass solves on one MI355X.
+
+A step is one pass of the whole hot path over one batch: gauge ingest and
+clover build, RHS import, and the mixed-precision solve of every system to a
+true relative residual of 1e-10 (FP64 residual loop around FP32 FGMRES + SAP),
+with inputs resident in HBM when the timed region starts.
+
+Printed on one JSON line:
+  value            SAP-sweep algorithmic bytes moved per second of whole-step
+                   wall time (GB/s)
+  sap_sweep        the SAP half-sweep kernel alone, all systems in one launch,
+                   event-timed on its stream: GB/s, site-updates/s
+  roofline         the dominant kernel (SAP half-sweep) against its binding
+                   peak, with algorithmic bytes / flops per launch
+  solve            time per RHS of the batched mixed-precision solve vs the
+                   plain FP64 single-RHS solve, both to 1e-10
+  cpu_baseline     the FP64 CPU oracle's SAP on a bounded sample of the same
+                   workload, on the host cores
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+METRIC = "SAP sweep GB/s (% HBM peak); 12-rhs mixed vs 1-rhs FP64 time/rhs @1e-10"
+
+WORKLOADS = {
+    # name: dims (T,Z,Y,X), eps, kappa, mu, csw, systems (list of (spin, colour, mu sign)), storage
+    "48^3x96_12rhs_f32": dict(dims=(96, 48, 48, 48), eps=0.6, kappa=0.1373, mu=0.0009, csw=1.5,
+                              sources=[(s, c, 1) for s in range(4) for c in range(3)], storage="f32"),
+    "32^3x64_pm_f32": dict(dims=(64, 32, 32, 32), eps=0.6, kappa=0.1394, mu=0.001, csw=1.5,
+                           sources=[(0, 0, 1), (0, 0, -1)], storage="f32"),
+    "64^3x128_24sys_f16": dict(dims=(128, 64, 64, 64), eps=0.6, kappa=0.1373, mu=0.0009, csw=1.5,
+                               sources=[(s, c, sg) for sg in (1, -1) for s in range(4) for c in range(3)],
+                               storage="f16"),
+    "16^4_1rhs_f32": dict(dims=(16, 16, 16, 16), eps=0.5, kappa=0.1632, mu=0.003, csw=1.5,
+                          sources=[(0, 0, 1)], storage="f32"),
+}
+
+BLOCK = (4, 4, 4, 4)
+N_CYCLES, MR_ITERS = 4, 4
+TOL = 1e-10
+
+# Algorithmic work of one SAP cycle per site (every operand touched once):
+#   links 4 x 12 reals (two rows, third rebuilt) + clover 72 reals, read once;
+#   per system: b read (24 reals), x read (24) and x written (24).
+LINK_REALS, CLOVER_REALS, SPINOR_REALS = 48, 72, 24
+# Flops of one SAP cycle per site and system, 4^4 blocks, 4 MR steps:
+#   residual b - D x: 8 hops x 168 + clover 552 + 48 = 1944
+#   each MR step: D_BB rho with 6 in-block hops on average (6 x 168 + 552 + 24)
+#   + <q,rho>, <q,q>, e += a rho, rho -= a q (336) = 1920
+# where a hop is projection (24) + SU(3) x 2 columns (132) + reconstruction (12)
+HOP_FLOPS = 24 + 132 + 12
+RESID_FLOPS = 8 * HOP_FLOPS + 552 + 48
+MR_FLOPS = 6 * HOP_FLOPS + 552 + 24 + 336
+REAL_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def _real_bytes(storage):
+    rb = REAL_BYTES[storage]
+    cb = 4 if storage in ("f16", "bf16") else rb  # clover kept in FP32 for 16-bit storage
+    sb = 4 if storage == "f16" else 0              # FP16 spinors carry one FP32 scale per site
+    return rb, cb, sb
+
+
+def sap_bytes_per_site_cycle(storage: str, nsys: int) -> float:
+    """Steady-state cycle: links + clover once, per system b read, x read, x written."""
+    rb, cb, sb = _real_bytes(storage)
+    return LINK_REALS * rb + CLOVER_REALS * cb + nsys * 3 * (SPINOR_REALS * rb + sb)
+
+
+def sap_application_model(storage: str, nsys: int, n_cycles: int, mr: int):
+    """Algorithmic bytes and flops per site of one SAP application from a zero guess
+    (the preconditioner): in the first cycle x is not read and the colour-0 sweep
+    has no residual to form (r = b), the colour-1 sweep only the hops from colour 0
+    (2 of 8 hops per site on average for 4^4 blocks)."""
+    rb, cb, sb = _real_bytes(storage)
+    shared = LINK_REALS * rb + CLOVER_REALS * cb
+    spin = SPINOR_REALS * rb + sb
+    first = shared + nsys * 2 * spin               # b read, x written
+    rest = shared + nsys * 3 * spin
+    bytes_app = first + (n_cycles - 1) * rest
+    mr_f = mr * MR_FLOPS
+    first_f = 0.5 * (mr_f) + 0.5 * (2 * HOP_FLOPS + 24 + mr_f)  # two half-sweeps, per site of a cycle
+    rest_f = RESID_FLOPS + mr_f
+    flops_app = nsys * (first_f + (n_cycles - 1) * rest_f)
+    return bytes_app, flops_app
+
+
+def sap_flops_per_site_cycle(nsys: int, mr: int = MR_ITERS) -> float:
+    return nsys * (RESID_FLOPS + mr * MR_FLOPS)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(wl, torch, tm, synth):
+    import numpy as np
+
+    dims = wl["dims"]
+    V = int(np.prod(dims))
+    t0 = time.time()
+    U = synth.gauge_field(dims, wl["eps"], seed=4 if dims == (96, 48, 48, 48) else 3)
+    log(f"gauge field generated in {time.time() - t0:.1f}s ({U.nbytes / 1e9:.1f} GB)")
+    Ud = torch.from_numpy(U).cuda()
+    del U
+    nsys = len(wl["sources"])
+    b = torch.zeros((nsys, V, 4, 3), dtype=torch.complex128, device="cuda")
+    for k, (s, c, _) in enumerate(wl["sources"]):
+        b[k, 0, s, c] = 1.0
+    mus = [sg * wl["mu"] for (_, _, sg) in wl["sources"]]
+    return Ud, b, mus
+
+
+def sap_sweep_phase(wl, Ud, mus, torch, tm, reps):
+    """SAP cycles over all systems in one launch per half-sweep, event-timed on the stream."""
+    dims, storage = wl["dims"], wl["storage"]
+    nsys = len(mus)
+    nbytes = tm.tm_spinor_bytes(dims, nsys, storage, layout_block=BLOCK)
+    bi = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    xi = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    # b: Gaussian-like content through the canonical import (one system at a time keeps memory low)
+    from paper_1610_02370_amd import synth
+
+    V = int(torch.tensor(dims).prod())
+    g = torch.from_numpy(synth.gaussian_spinor(dims, 1, seed=100)).cuda()
+    canon = g.expand(nsys, -1, -1, -1).contiguous()
+    tm.tm_spinor_import(dims, canon, bi, storage=storage, layout_block=BLOCK)
+    del canon, g
+    xi.zero_()
+    stream = torch.cuda.current_stream()
+    # warm-up (gauge ingest happens here, tag 1 keeps the copy)
+    tm.tm_sap_smooth(dims, Ud, bi, xi, wl["kappa"], mus, wl["csw"], BLOCK, 1, MR_ITERS, storage=storage,
+                     io="internal", gauge_tag=1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        tm.tm_sap_smooth(dims, Ud, bi, xi, wl["kappa"], mus, wl["csw"], BLOCK, 1, MR_ITERS, storage=storage,
+                         io="internal", gauge_tag=1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    launches = 2 * reps
+    per_launch_s = ms * 1e-3 / launches
+    bytes_launch = V / 2 * sap_bytes_per_site_cycle(storage, nsys)
+    flops_launch = V / 2 * sap_flops_per_site_cycle(nsys)
+    del bi, xi
+    torch.cuda.empty_cache()
+    return {
+        "launches": launches,
+        "ms_per_launch": per_launch_s * 1e3,
+        "GBps": bytes_launch / per_launch_s / 1e9,
+        "TFLOPs": flops_launch / per_launch_s / 1e12,
+        "site_updates_per_s": V * nsys * reps / (ms * 1e-3),
+        "bytes_per_launch": bytes_launch,
+        "flops_per_launch": flops_launch,
+    }
+
+
+def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group):
+    x.zero_()
+    rc, rep = tm.tm_fgmres_solve(wl["dims"], Ud, b, x, wl["kappa"], mus, wl["csw"], TOL, storage=wl["storage"],
+                                 form="defect_correction", restart=restart, n_cycles=N_CYCLES, mr_iters=MR_ITERS,
+                                 block_dims=BLOCK, group=group, gauge_tag=0)
+    return rc, rep
+
+
+def fp64_baseline(wl, Ud, torch, tm):
+    import numpy as np
+
+    dims = wl["dims"]
+    V = int(np.prod(dims))
+    b = torch.zeros((1, V, 4, 3), dtype=torch.complex128, device="cuda")
+    s, c, sg = wl["sources"][0]
+    b[0, 0, s, c] = 1.0
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, rep = tm.tm_fgmres_solve(dims, Ud, b, x, wl["kappa"], [sg * wl["mu"]], wl["csw"], TOL, storage="f64",
+                                 form="flexible", restart=20, n_cycles=N_CYCLES, mr_iters=MR_ITERS, block_dims=BLOCK,
+                                 gauge_tag=0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del b, x
+    return {"s_per_rhs": dt, "iters": rep["iters"], "true_rel_res": rep["true_rel_res"][0], "status": rc}
+
+
+def cpu_baseline(wl, target_s: float = 12.0):
+    """FP64 CPU oracle SAP cycles (4^4 blocks, 4 MR steps, one system) on a 16^3 x 32
+    sample of the workload (same eps, kappa, mu, c_sw), all host threads."""
+    import numpy as np
+
+    import oracle
+    from paper_1610_02370_amd import synth
+
+    dims = (32, 16, 16, 16)
+    U = synth.gauge_field(dims, wl["eps"], seed=5)
+    b = synth.gaussian_spinor(dims, 1, seed=105)[0].ravel()
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(wl["kappa"]), wl["mu"], wl["csw"])
+    V = int(np.prod(dims))
+    cycles = 0
+    t0 = time.perf_counter()
+    x = np.zeros_like(b)
+    while True:
+        x = op.sap(b, BLOCK, 1, MR_ITERS, x0=x)
+        cycles += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_s:
+            break
+    nsys = len(wl["sources"])
+    per_site_sys = sap_bytes_per_site_cycle(wl["storage"], nsys) / nsys
+    rate = V * cycles / dt  # site-updates per second (one system)
+    return {
+        "value": rate * per_site_sys / 1e9,
+        "unit": "GB/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{cycles} SAP cycle(s), 4^4 blocks, {MR_ITERS} MR steps, 1 system, FP64, on a 16^3x32 lattice "
+                  f"with the workload's eps/kappa/mu/c_sw; bytes per site-update from the same algorithmic model "
+                  f"as the GPU value ({per_site_sys:.0f} B per site and system per cycle)",
+        "site_updates_per_s": rate,
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="48^3x96_12rhs_f32", choices=sorted(WORKLOADS))
+    ap.add_argument("--sap-reps", type=int, default=10)
+    ap.add_argument("--restart", type=int, default=8)
+    ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--sweep", action="store_true", help="also time SAP cycles with every system in one launch")
+    ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep-only", action="store_true", help="only the all-systems SAP sweep (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1610_02370_amd as tm
+    from paper_1610_02370_amd import synth
+
+    wl = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    Ud, b, mus = make_inputs(wl, torch, tm, synth)
+    nsys = len(mus)
+    dims = wl["dims"]
+    V = int(torch.tensor(dims).prod())
+    log(f"workload {args.workload}: V={V} systems={nsys} storage={wl['storage']}")
+
+    sweep = None
+    if args.sweep or args.sweep_only:
+        sweep = sap_sweep_phase(wl, Ud, mus, torch, tm, args.sap_reps)
+        log(f"SAP sweep ({nsys} systems per launch): {sweep['ms_per_launch']:.3f} ms/launch, "
+            f"{sweep['GBps']:.0f} GB/s, {sweep['TFLOPs']:.1f} TFLOP/s")
+        tm.tm_gauge_release(Ud)
+        if args.sweep_only:
+            print(json.dumps({"sap_sweep": sweep}), flush=True)
+            return
+
+    x = torch.zeros_like(b)
+    for w in range(args.warmup):
+        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group)
+        log(f"warmup {w}: status {rc} iters {rep['iters']} outer {rep['outer']} t {rep['t_total']:.2f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for s in range(args.steps):
+        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group)
+        reps.append((rc, rep))
+        log(f"step {s}: status {rc} iters {rep['iters']} outer {rep['outer']} group {rep['group']} "
+            f"sap {rep['t_sap']:.2f}s total {rep['t_total']:.2f}s max res {max(rep['true_rel_res']):.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ok = all(rc == 0 for rc, _ in reps)
+
+    # SAP launches of the timed region: every application is N_CYCLES cycles from a
+    # zero guess over one group of systems; t_sap is event time on the solve's stream.
+    t_sap = sum(r["t_sap"] for _, r in reps)
+    sap_cycles = sum(r["sap_cycles"] for _, r in reps)
+    sys_cycles = sum(r["sap_sys_cycles"] for _, r in reps)
+    group = reps[0][1]["group"]
+    apps = sap_cycles // N_CYCLES
+    b_shared, f_shared = sap_application_model(wl["storage"], 0, N_CYCLES, MR_ITERS)
+    b_one, f_one = sap_application_model(wl["storage"], 1, N_CYCLES, MR_ITERS)
+    sys_apps = sys_cycles / N_CYCLES
+    sap_bytes = V * (b_shared * apps + (b_one - b_shared) * sys_apps)
+    sap_flops = V * (f_one - f_shared) * sys_apps
+    launches = 2 * sap_cycles
+    per_launch_s = t_sap / launches
+    value = sap_bytes / wall / 1e9
+    del x, b
+    torch.cuda.empty_cache()
+
+    fp64 = None if args.no_fp64_baseline else fp64_baseline(wl, Ud, torch, tm)
+    if fp64:
+        log(f"FP64 1-RHS solve: {fp64['s_per_rhs']:.2f}s iters {fp64['iters']} res {fp64['true_rel_res']:.2e}")
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
+    if cpu:
+        log(f"CPU oracle: {cpu['value']:.3f} GB/s-equivalent on {cpu['cores']} threads")
+
+    ms_per_step = wall / args.steps * 1e3
+    t_rhs = wall / args.steps / nsys
+    achieved_gbps = sap_bytes / t_sap / 1e9
+    achieved_tflops = sap_flops / t_sap / 1e12
+    if wl["storage"] != "f64":
+        roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_sap_half_v2", "launches": launches, "avg_launch_ms": per_launch_s * 1e3,
+                "flops_per_launch": sap_flops / launches, "bytes_per_launch": sap_bytes / launches,
+                "hbm_GBps": achieved_gbps, "hbm_frac": achieved_gbps / HBM_PEAK_GBPS}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved_gbps / HBM_PEAK_GBPS, "traffic": None, "kernel": "k_sap_half",
+                "launches": launches, "avg_launch_ms": per_launch_s * 1e3, "bytes_per_launch": sap_bytes / launches}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl["storage"],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims_TZYX": list(dims), "systems": nsys, "block": list(BLOCK),
+                   "n_cycles": N_CYCLES, "mr_iters": MR_ITERS, "tol": TOL, "restart": args.restart,
+                   "group": group, "parallelism": "single GPU"},
+        "converged": ok,
+        "sap": {"GBps": achieved_gbps, "hbm_frac": achieved_gbps / HBM_PEAK_GBPS, "TFLOPs": achieved_tflops,
+                "site_updates_per_s": V * sys_cycles / t_sap, "share_of_step": t_sap / wall},
+        "sap_sweep_all_systems": sweep,
+        "solve": {"s_per_rhs_mixed": t_rhs, "iters": max(r["iters"] for _, r in reps),
+                  "outer": max(r["outer"] for _, r in reps),
+                  "max_true_rel_res": max(max(r["true_rel_res"]) for _, r in reps),
+                  "s_per_rhs_fp64_1rhs": fp64["s_per_rhs"] if fp64 else None,
+                  "fp64_iters": fp64["iters"] if fp64 else None,
+                  "speedup_per_rhs": (fp64["s_per_rhs"] / t_rhs) if fp64 else None},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

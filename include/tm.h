@@ -163,7 +163,9 @@ typedef struct {
     double true_rel_res[TM_MAX_SYS];    /* ||b - D x|| / ||b|| per system, in FP64 */
     double t_total;                     /* seconds inside the call */
     double t_sap;                       /* seconds in SAP kernels (event-timed) */
-    long long sap_cycles;               /* SAP cycles applied (summed over calls, per system batch) */
+    long long sap_cycles;               /* SAP cycles launched (each over a whole group of systems) */
+    long long sap_sys_cycles;           /* SAP cycles times the systems they carried */
+    int group;                          /* systems solved together (after fitting device memory) */
 } tm_solve_report;
 
 /*

@@ -16,7 +16,7 @@ import os
 from typing import Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtmsap.so")
+LIB_PATH = os.environ.get("TMSAP_LIB") or os.path.join(_HERE, "libtmsap.so")
 
 TM_OK, TM_NOT_CONVERGED = 0, 1
 ERRORS = {-1: "TM_ERR_ARG", -2: "TM_ERR_DIMS", -3: "TM_ERR_BLOCKS", -4: "TM_ERR_PREC", -5: "TM_ERR_HIP",
@@ -59,7 +59,8 @@ class SolverOpts(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("converged", ctypes.c_int),
                 ("true_rel_res", ctypes.c_double * MAX_SYS), ("t_total", ctypes.c_double),
-                ("t_sap", ctypes.c_double), ("sap_cycles", ctypes.c_longlong)]
+                ("t_sap", ctypes.c_double), ("sap_cycles", ctypes.c_longlong),
+                ("sap_sys_cycles", ctypes.c_longlong), ("group", ctypes.c_int)]
 
 
 _lib = None
@@ -220,7 +221,8 @@ def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *,
     n = g.nsys
     return rc, {"iters": rep.iters, "outer": rep.outer, "converged": rep.converged,
                 "true_rel_res": [rep.true_rel_res[k] for k in range(n)], "t_total": rep.t_total,
-                "t_sap": rep.t_sap, "sap_cycles": rep.sap_cycles}
+                "t_sap": rep.t_sap, "sap_cycles": rep.sap_cycles, "sap_sys_cycles": rep.sap_sys_cycles,
+                "group": rep.group}
 
 
 def tm_spinor_bytes(dims, nsys: int, storage: str, layout_block=None) -> int:

@@ -289,6 +289,58 @@ __device__ inline void hop_backward(int mu, const Link<R>& L, const Spinor<R>& p
     }
 }
 
+// Split form of the backward hop used when the neighbour computes the product:
+// the site x-mu forms g = U_mu(x-mu)^+ (upper + B lower) of its own spinor ...
+template <class R>
+__device__ inline void backward_product(int mu, const Link<R>& L, const Spinor<R>& p, Half<R>& g) {
+    Half<R> h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<R> b0, b1;
+        apply_B(mu, p.v[6 + c], p.v[9 + c], b0, b1);
+        h.h[0][c] = p.v[c] + b0;
+        h.h[1][c] = p.v[3 + c] + b1;
+    }
+    su3_dag_mul(L, h, g);
+}
+
+// ... and the site x adds it: hu += g, hd += B^+ g.
+template <class R>
+__device__ inline void backward_accumulate(int mu, const Half<R>& g, Spinor<R>& acc) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<R> d0, d1;
+        apply_Bdag(mu, g.h[0][c], g.h[1][c], d0, d1);
+        acc.v[c] = acc.v[c] + g.h[0][c];
+        acc.v[3 + c] = acc.v[3 + c] + g.h[1][c];
+        acc.v[6 + c] = acc.v[6 + c] + d0;
+        acc.v[9 + c] = acc.v[9 + c] + d1;
+    }
+}
+
+// Forward hop without a boundary sign (hops inside a Schwarz block never wrap).
+template <class R>
+__device__ inline void hop_forward_in(int mu, const Link<R>& L, const Spinor<R>& p, Spinor<R>& acc) {
+    Half<R> h, g;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<R> b0, b1;
+        apply_B(mu, p.v[6 + c], p.v[9 + c], b0, b1);
+        h.h[0][c] = p.v[c] - b0;
+        h.h[1][c] = p.v[3 + c] - b1;
+    }
+    su3_mul(L, h, g);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<R> d0, d1;
+        apply_Bdag(mu, g.h[0][c], g.h[1][c], d0, d1);
+        acc.v[c] = acc.v[c] + g.h[0][c];
+        acc.v[3 + c] = acc.v[3 + c] + g.h[1][c];
+        acc.v[6 + c] = acc.v[6 + c] - d0;
+        acc.v[9 + c] = acc.v[9 + c] - d1;
+    }
+}
+
 // ---------------------------------------------------------------- clover
 // Per site: two Hermitian 6x6 blocks (spins {0,1} and {2,3}; index
 // 3*(s mod 2) + c), each packed as 6 real diagonals followed by the 15
@@ -316,6 +368,30 @@ __device__ inline void clover_block_apply(const R* A, R tw, const cplx<R>* v, cp
         }
 #pragma unroll
     for (int i = 0; i < 6; ++i) out[i] = o[i];
+}
+
+// out += (A_blk + i tw) v for one 6x6 block.
+template <class R>
+__device__ inline void clover_block_acc(const R* A, R tw, const cplx<R>* v, cplx<R>* out) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        out[i] = cmk<R>(out[i].re + A[i] * v[i].re - tw * v[i].im, out[i].im + A[i] * v[i].im + tw * v[i].re);
+    int k = 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) {
+            cplx<R> a = cmk<R>(A[k], A[k + 1]);
+            k += 2;
+            out[i] = cmad(a, v[j], out[i]);
+            out[j] = cjmad(a, v[i], out[j]);
+        }
+}
+
+template <class R>
+__device__ inline void clover_acc(const Clover<R>& C, R mu, const Spinor<R>& in, Spinor<R>& out) {
+    clover_block_acc(C.a, mu, in.v, out.v);
+    clover_block_acc(C.a + 36, -mu, in.v + 6, out.v + 6);
 }
 
 template <class R>

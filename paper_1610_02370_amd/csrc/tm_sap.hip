@@ -9,17 +9,48 @@
 // wavefront with cross-lane shuffles and across the workgroup through LDS.
 // Blocks of one colour do not couple, so all workgroups of a launch are
 // independent; the colour-to-colour dependency is the launch boundary.
+#include <cstdlib>
+
 #include "tm_internal.h"
 
 namespace tmsap {
 
 namespace {
 
+// TM_SAP_KERNEL=v1 selects the generic kernel for every precision (A/B tests).
+bool sap_v1_forced() {
+    static int forced = -1;
+    if (forced < 0) {
+        const char* e = getenv("TM_SAP_KERNEL");
+        forced = (e && e[0] == 'v' && e[1] == '1') ? 1 : 0;
+    }
+    return forced == 1;
+}
+
 template <class R>
 __device__ inline R wave_sum(R v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Wavefront sum with DPP row operations (no LDS crossbar): quad and row
+// reductions, then row broadcasts; the total ends in lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
+                                                                   true));
+}
+
+template <>
+__device__ inline float wave_sum<float>(float v) {
+    v += dpp_f<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_f<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_f<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 // Sum of three values over the workgroup; every thread gets the result.
@@ -259,6 +290,356 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32-compute half-sweep for blocks of at most 256 sites.  Everything the MR
+// steps touch stays on chip: each thread keeps its own four links (third row
+// rebuilt once) and its clover block in registers.  The block operator is
+// applied by a push exchange through LDS: every site publishes its spinor
+// (for the forward hops of its -mu neighbours) and, for each +mu neighbour
+// inside the block, the finished backward product U_mu(x)^+ (1 + gamma_mu)
+// psi(x) as a half spinor, so no link is read in the MR loop.
+constexpr int kV2 = 256;
+
+struct V2Shared {
+    float xs[24 * kV2];      // spinor components [24][site]
+    float gb[4 * 12 * kV2];  // backward products [mu][12][site]
+    float red[64];
+};
+
+__device__ inline void v2_put_spinor(float* xs, int l, const Spinor<float>& p) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        xs[(2 * i) * kV2 + l] = p.v[i].re;
+        xs[(2 * i + 1) * kV2 + l] = p.v[i].im;
+    }
+}
+
+__device__ inline void v2_get_spinor(const float* xs, int l, Spinor<float>& p) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) p.v[i] = cmk(xs[(2 * i) * kV2 + l], xs[(2 * i + 1) * kV2 + l]);
+}
+
+__device__ inline void v2_put_half(float* gb, int mu, int l, const Half<float>& g) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gb[(mu * 12 + 6 * s + 2 * c) * kV2 + l] = g.h[s][c].re;
+            gb[(mu * 12 + 6 * s + 2 * c + 1) * kV2 + l] = g.h[s][c].im;
+        }
+}
+
+__device__ inline void v2_get_half(const float* gb, int mu, int l, Half<float>& g) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            g.h[s][c] = cmk(gb[(mu * 12 + 6 * s + 2 * c) * kV2 + l], gb[(mu * 12 + 6 * s + 2 * c + 1) * kV2 + l]);
+}
+
+// A link kept as its first two rows; the third is rebuilt where it is used.
+struct Link2 {
+    cplx<float> u[2][3];
+};
+
+template <class G>
+__device__ inline void load_link2(const void* base, long long V, long long s, int mu, Link2& L) {
+    float u[4];
+    const size_t b = (size_t)mu * 3 * V;
+    Unit<G>::load(base, b + s, u);
+    L.u[0][0] = cmk(u[0], u[1]);
+    L.u[0][1] = cmk(u[2], u[3]);
+    Unit<G>::load(base, b + V + s, u);
+    L.u[0][2] = cmk(u[0], u[1]);
+    L.u[1][0] = cmk(u[2], u[3]);
+    Unit<G>::load(base, b + 2 * V + s, u);
+    L.u[1][1] = cmk(u[0], u[1]);
+    L.u[1][2] = cmk(u[2], u[3]);
+}
+
+__device__ inline void expand_link(const Link2& c, Link<float>& L) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L.u[r][k] = c.u[r][k];
+    complete_su3(L);
+}
+
+// Third row of an SU(3) link, element k: conj(row0 x row1)_k.
+__device__ inline cplx<float> row2(const Link2& c, int k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    return conj(c.u[0][a] * c.u[1][b] - c.u[0][b] * c.u[1][a]);
+}
+
+// g = U h with the third row rebuilt element by element.
+__device__ inline void su3_mul2(const Link2& c, const Half<float>& h, Half<float>& g) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            cplx<float> t = c.u[i][0] * h.h[s][0];
+            t = cmad(c.u[i][1], h.h[s][1], t);
+            g.h[s][i] = cmad(c.u[i][2], h.h[s][2], t);
+        }
+    }
+    const cplx<float> r0 = row2(c, 0), r1 = row2(c, 1), r2 = row2(c, 2);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) g.h[s][2] = cmad(r2, h.h[s][2], cmad(r1, h.h[s][1], r0 * h.h[s][0]));
+}
+
+// g = U^+ h with the third row rebuilt.
+__device__ inline void su3_dag_mul2(const Link2& c, const Half<float>& h, Half<float>& g) {
+    const cplx<float> r0 = row2(c, 0), r1 = row2(c, 1), r2 = row2(c, 2);
+    const cplx<float> r[3] = {r0, r1, r2};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cplx<float> t = cjmad(c.u[0][i], h.h[s][0], cmk(0.f, 0.f));
+            t = cjmad(c.u[1][i], h.h[s][1], t);
+            g.h[s][i] = cjmad(r[i], h.h[s][2], t);
+        }
+}
+
+// h = upper - B_mu lower of the spinor of local site n, read component by
+// component from LDS so the full neighbour spinor is never held in registers.
+__device__ inline cplx<float> lds_c(const float* xs, int idx, int n) {
+    return cmk(xs[(2 * idx) * kV2 + n], xs[(2 * idx + 1) * kV2 + n]);
+}
+
+__device__ inline void project_forward_lds(const float* xs, int mu, int n, Half<float>& h) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cplx<float> u0 = lds_c(xs, c, n), u1 = lds_c(xs, 3 + c, n);
+        const cplx<float> d0 = lds_c(xs, 6 + c, n), d1 = lds_c(xs, 9 + c, n);
+        cplx<float> b0, b1;
+        apply_B(mu, d0, d1, b0, b1);
+        h.h[0][c] = u0 - b0;
+        h.h[1][c] = u1 - b1;
+    }
+}
+
+// acc += (1 - gamma_mu) lift of g: upper += g, lower -= B^+ g.
+__device__ inline void forward_accumulate(int mu, const Half<float>& g, Spinor<float>& acc) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<float> d0, d1;
+        apply_Bdag(mu, g.h[0][c], g.h[1][c], d0, d1);
+        acc.v[c] = acc.v[c] + g.h[0][c];
+        acc.v[3 + c] = acc.v[3 + c] + g.h[1][c];
+        acc.v[6 + c] = acc.v[6 + c] - d0;
+        acc.v[9 + c] = acc.v[9 + c] - d1;
+    }
+}
+
+// Publish v: spinor plus backward products for the in-block +mu neighbours.
+__device__ inline void v2_push(V2Shared& sm, int l, bool active, const bool fin[4], const Link2 Uo[4],
+                               const Spinor<float>& v) {
+    if (!active) return;
+    v2_put_spinor(sm.xs, l, v);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        // keep one direction's operands live at a time
+        __builtin_amdgcn_sched_barrier(0);
+        if (fin[mu]) {
+            Half<float> h, g;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cplx<float> b0, b1;
+                apply_B(mu, v.v[6 + c], v.v[9 + c], b0, b1);
+                h.h[0][c] = v.v[c] + b0;
+                h.h[1][c] = v.v[3 + c] + b1;
+            }
+            su3_dag_mul2(Uo[mu], h, g);
+            v2_put_half(sm.gb, mu, l, g);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// acc += in-block hop terms (unscaled; the operator adds -1/2 acc).
+__device__ inline void v2_pull(const V2Shared& sm, int l, const bool fin[4], const bool bin[4], const int str[4],
+                               const Link2 Uo[4], Spinor<float>& acc) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (fin[mu]) {
+            Half<float> h, g;
+            project_forward_lds(sm.xs, mu, l + str[mu], h);
+            su3_mul2(Uo[mu], h, g);
+            forward_accumulate(mu, g, acc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (bin[mu]) {
+            Half<float> g;
+            v2_get_half(sm.gb, mu, l - str[mu], g);
+            backward_accumulate(mu, g, acc);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <class S, class G, class C>
+__global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
+    __shared__ V2Shared sm;
+    const Geo& g = a.g;
+    const int Vb = g.Vb;
+    const int l = threadIdx.x;
+    const bool active = l < Vb;
+
+    const int half3 = g.nb[3] >> 1;
+    int j = blockIdx.x;
+    const int k3 = j % half3;
+    j /= half3;
+    const int B2 = j % g.nb[2];
+    j /= g.nb[2];
+    const int B1 = j % g.nb[1];
+    const int B0 = j / g.nb[1];
+    const int B3 = 2 * k3 + ((a.colour + B0 + B1 + B2) & 1);
+    const long long blk = (((long long)B0 * g.nb[1] + B1) * g.nb[2] + B2) * g.nb[3] + B3;
+    const long long s = blk * Vb + (active ? l : 0);
+
+    int Lc[4];
+    {
+        int t = active ? l : 0;
+        for (int ax = 3; ax >= 0; --ax) {
+            Lc[ax] = t % g.lb[ax];
+            t /= g.lb[ax];
+        }
+    }
+    bool fin[4], bin[4];
+    int str[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int ax = axis_of(mu);
+        int st = 1;
+        for (int q = ax + 1; q < 4; ++q) st *= g.lb[q];
+        str[mu] = st;
+        fin[mu] = active && Lc[ax] + 1 < g.lb[ax];
+        bin[mu] = active && Lc[ax] > 0;
+    }
+
+    Link2 Uo[4];
+    Clover<float> A;
+    if (active) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) load_link2<G>(a.links, g.V, s, mu, Uo[mu]);
+        load_clover<float, C>(a.clover, g.V, s, A);
+    }
+
+    const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
+    const int sys_begin = blockIdx.y * a.sys_tile;
+    const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
+    const bool own = !a.own_zero;
+    const bool halo = !(a.own_zero && a.halo_zero);
+
+    for (int sys = sys_begin; sys < sys_end; ++sys) {
+        const float mu_tw = (float)a.mu[sys];
+        const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
+        void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
+        const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
+        float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
+
+        // ---- r = b - D x on the block; e starts at x so that x_new = e
+        Spinor<float> r, e, acc;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            e.v[i] = cmk(0.f, 0.f);
+            acc.v[i] = cmk(0.f, 0.f);
+        }
+        if (active) {
+            load_spinor<float, S>(bb, bsc, g.V, s, r);
+            if (own) load_spinor<float, S>(xx, xsc, g.V, s, e);
+        }
+        if (own) {
+            v2_push(sm, l, active, fin, Uo, e);
+            __syncthreads();
+            if (active) v2_pull(sm, l, fin, bin, str, Uo, acc);
+        }
+        if (halo && active) {
+            const int Bc[4] = {B0, B1, B2, B3};
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                const int ax = axis_of(mu);
+                int n[4];
+                for (int q = 0; q < 4; ++q) n[q] = Bc[q] * g.lb[q] + Lc[q];
+                if (!fin[mu]) {
+                    float sg = 1.f;
+                    if (++n[ax] == g.d[ax]) {
+                        n[ax] = 0;
+                        if (mu == 0 && g.antiperiodic_t) sg = -1.f;
+                    }
+                    Spinor<float> p;
+                    load_spinor<float, S>(xx, xsc, g.V, coords_site(g, n), p);
+                    Link<float> L;
+                    expand_link(Uo[mu], L);
+                    hop_forward(mu, L, p, sg, acc);
+                    n[ax] = Bc[ax] * g.lb[ax] + Lc[ax];
+                }
+                if (!bin[mu]) {
+                    float sg = 1.f;
+                    if (--n[ax] < 0) {
+                        n[ax] = g.d[ax] - 1;
+                        if (mu == 0 && g.antiperiodic_t) sg = -1.f;
+                    }
+                    const long long nb = coords_site(g, n);
+                    Spinor<float> p;
+                    Link<float> Lk;
+                    load_spinor<float, S>(xx, xsc, g.V, nb, p);
+                    load_link<float, G>(a.links, g.V, nb, mu, Lk);
+                    hop_backward(mu, Lk, p, sg, acc);
+                }
+            }
+        }
+        if (active) {
+            // r = b - (A x - acc/2)
+#pragma unroll
+            for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] + 0.5f * acc.v[i];
+            if (own) {
+#pragma unroll
+                for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
+                clover_acc(A, mu_tw, e, acc);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] - acc.v[i];
+            }
+        }
+        if (own) __syncthreads();
+
+        // ---- minimal residual on D_BB: e += alpha rho, rho -= alpha D_BB rho
+        Spinor<float>& rho = r;
+        for (int it = 0; it < a.mr_iters; ++it) {
+            v2_push(sm, l, active, fin, Uo, rho);
+            __syncthreads();
+            Spinor<float> q;
+            float qr_re = 0.f, qr_im = 0.f, qq = 0.f;
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < 12; ++i) q.v[i] = cmk(0.f, 0.f);
+                v2_pull(sm, l, fin, bin, str, Uo, q);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) q.v[i] = -0.5f * q.v[i];
+                clover_acc(A, mu_tw, rho, q);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
+                    qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
+                    qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
+                }
+            }
+            block_sum3(sm.red, qr_re, qr_im, qq);
+            if (active && qq > 0.f) {
+                const cplx<float> alpha = cmk(qr_re / qq, qr_im / qq);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    e.v[i] = cmad(alpha, rho.v[i], e.v[i]);
+                    rho.v[i] = rho.v[i] - alpha * q.v[i];
+                }
+            }
+        }
+        if (active) store_spinor<float, S>(xx, xsc, g.V, s, e);
+    }
+}
+
 template <class S, class G, class C, class R>
 hipError_t run(const SapArgs& a, hipStream_t st) {
     const int nt = (a.g.Vb + 63) & ~63;
@@ -275,6 +656,12 @@ hipError_t run(const SapArgs& a, hipStream_t st) {
     if (lds > 65536) {
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (nt <= kV2 && !sap_v1_forced()) {
+            hipLaunchKernelGGL((k_sap_half_v2<S, G, C>), grid, dim3(nt), 0, st, a);
+            return hipGetLastError();
+        }
     }
     if (nt <= 256)
         hipLaunchKernelGGL((k_sap_half<S, G, C, R, 256>), grid, dim3(nt), lds, st, a);

@@ -80,6 +80,7 @@ struct Ctx {
     hipEvent_t ev[2];
     double t_sap = 0;
     long long sap_cycles = 0;
+    long long sap_sys_cycles = 0;
 };
 
 int hcheck(hipError_t e, const char* where) { return e == hipSuccess ? TM_OK : hip_fail(e, where); }
@@ -218,6 +219,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             if ((rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, 0, c.st))) return rc;
             if ((rc = hcheck(hipEventRecord(c.ev[1], c.st), "event"))) return rc;
             c.sap_cycles += c.n_cycles;
+            c.sap_sys_cycles += (long long)c.n_cycles * ns;
             if ((rc = run_dirac(c.g, *c.op, zj, K.w, c.mu, ns, c.op_compute, c.st))) return rc;
             // classical Gram-Schmidt, twice
             const VecRef basis = vec_ref(K.Vb(c, 0), V), wr = vec_ref(K.w, V);
@@ -556,6 +558,8 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     }
     rep.t_sap = c.t_sap;
     rep.sap_cycles = c.sap_cycles;
+    rep.sap_sys_cycles = c.sap_sys_cycles;
+    rep.group = group;
     rep.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     if (report) *report = rep;
     return all_conv ? TM_OK : TM_NOT_CONVERGED;
