@@ -305,6 +305,8 @@ struct V2Shared {
     float gb[4 * 12 * kV2];  // backward products [mu][12][site]
     float red[64];
 };
+// xs and gb together hold the staged halo: [24][kHaloMax] spinor components.
+constexpr int kHaloMax = 3 * kV2;
 
 __device__ inline void v2_put_spinor(float* xs, int l, const Spinor<float>& p) {
 #pragma unroll
@@ -519,6 +521,33 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
         bin[mu] = active && Lc[ax] > 0;
     }
 
+    // Halo faces: f = 2*axis + side (side 0: the layer below the block, 1: above);
+    // entry of a face site = lexicographic index over the other three axes.
+    const int Bc[4] = {B0, B1, B2, B3};
+    int hoff[9];
+    hoff[0] = 0;
+    for (int f = 0; f < 8; ++f) hoff[f + 1] = hoff[f] + Vb / g.lb[f >> 1];
+    const int nhalo = hoff[8];
+    const bool stage_halo = nhalo <= kHaloMax;
+    int hent_f[4], hent_b[4];
+    long long nbk[4];
+    float sgf[4], sgb[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int ax = axis_of(mu);
+        int p = 0;
+        for (int q = 0; q < 4; ++q)
+            if (q != ax) p = p * g.lb[q] + Lc[q];
+        hent_f[mu] = hoff[2 * ax + 1] + p;
+        hent_b[mu] = hoff[2 * ax] + p;
+        int c[4];
+        for (int q = 0; q < 4; ++q) c[q] = Bc[q] * g.lb[q] + Lc[q];
+        sgf[mu] = (mu == 0 && g.antiperiodic_t && c[0] == g.d[0] - 1) ? -1.f : 1.f;
+        sgb[mu] = (mu == 0 && g.antiperiodic_t && c[0] == 0) ? -1.f : 1.f;
+        c[ax] = c[ax] == 0 ? g.d[ax] - 1 : c[ax] - 1;
+        nbk[mu] = coords_site(g, c);
+    }
+
     Link2 Uo[4];
     Clover<float> A;
     if (active) {
@@ -556,13 +585,72 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
             __syncthreads();
             if (active) v2_pull(sm, l, fin, bin, str, Uo, acc);
         }
-        if (halo && active) {
-            const int Bc[4] = {B0, B1, B2, B3};
+        if (halo && stage_halo) {
+            // The other colour's face spinors, staged once per system by the whole
+            // workgroup (one memory latency instead of one per direction); face
+            // lanes fetch the links of their backward halo hops meanwhile.
+            float* hb = sm.xs;  // xs and gb are contiguous: room for kHaloMax entries
+            for (int e2 = l; e2 < nhalo; e2 += blockDim.x) {
+                int f = 0;
+                while (f < 7 && e2 >= hoff[f + 1]) ++f;
+                const int ax = f >> 1;
+                int p = e2 - hoff[f];
+                int c[4];
+                for (int q = 3; q >= 0; --q) {
+                    if (q == ax) continue;
+                    c[q] = p % g.lb[q];
+                    p /= g.lb[q];
+                }
+                c[ax] = (f & 1) ? g.lb[ax] : -1;
+                for (int q = 0; q < 4; ++q) {
+                    c[q] += Bc[q] * g.lb[q];
+                    if (c[q] < 0) c[q] += g.d[q];
+                    if (c[q] >= g.d[q]) c[q] -= g.d[q];
+                }
+                Spinor<float> hv;
+                load_spinor<float, S>(xx, xsc, g.V, coords_site(g, c), hv);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    hb[(2 * i) * kHaloMax + e2] = hv.v[i].re;
+                    hb[(2 * i + 1) * kHaloMax + e2] = hv.v[i].im;
+                }
+            }
+            Link2 Lb[4];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+                if (active && !bin[mu]) load_link2<G>(a.links, g.V, nbk[mu], mu, Lb[mu]);
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu) {
+                    if (!fin[mu]) {
+                        Spinor<float> p;
+#pragma unroll
+                        for (int i = 0; i < 12; ++i)
+                            p.v[i] = cmk(hb[(2 * i) * kHaloMax + hent_f[mu]], hb[(2 * i + 1) * kHaloMax + hent_f[mu]]);
+                        Link<float> L;
+                        expand_link(Uo[mu], L);
+                        hop_forward(mu, L, p, sgf[mu], acc);
+                    }
+                    if (!bin[mu]) {
+                        Spinor<float> p;
+#pragma unroll
+                        for (int i = 0; i < 12; ++i)
+                            p.v[i] = cmk(hb[(2 * i) * kHaloMax + hent_b[mu]], hb[(2 * i + 1) * kHaloMax + hent_b[mu]]);
+                        Link<float> L;
+                        expand_link(Lb[mu], L);
+                        hop_backward(mu, L, p, sgb[mu], acc);
+                    }
+                }
+            }
+            __syncthreads();
+        } else if (halo && active) {
+            const int Bcc[4] = {B0, B1, B2, B3};
 #pragma unroll
             for (int mu = 0; mu < 4; ++mu) {
                 const int ax = axis_of(mu);
                 int n[4];
-                for (int q = 0; q < 4; ++q) n[q] = Bc[q] * g.lb[q] + Lc[q];
+                for (int q = 0; q < 4; ++q) n[q] = Bcc[q] * g.lb[q] + Lc[q];
                 if (!fin[mu]) {
                     float sg = 1.f;
                     if (++n[ax] == g.d[ax]) {
@@ -574,7 +662,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
                     Link<float> L;
                     expand_link(Uo[mu], L);
                     hop_forward(mu, L, p, sg, acc);
-                    n[ax] = Bc[ax] * g.lb[ax] + Lc[ax];
+                    n[ax] = Bcc[ax] * g.lb[ax] + Lc[ax];
                 }
                 if (!bin[mu]) {
                     float sg = 1.f;
