@@ -308,35 +308,41 @@ struct V2Shared {
 // xs and gb together hold the staged halo: [24][kHaloMax] spinor components.
 constexpr int kHaloMax = 3 * kV2;
 
+// LDS layout in 16-byte units: spinor [6][site] float4, backward products
+// [mu][3][site] float4; consecutive lanes touch consecutive 16-byte words.
 __device__ inline void v2_put_spinor(float* xs, int l, const Spinor<float>& p) {
+    float4* x4 = reinterpret_cast<float4*>(xs);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) {
-        xs[(2 * i) * kV2 + l] = p.v[i].re;
-        xs[(2 * i + 1) * kV2 + l] = p.v[i].im;
-    }
+    for (int k = 0; k < 6; ++k)
+        x4[k * kV2 + l] = make_float4(p.v[2 * k].re, p.v[2 * k].im, p.v[2 * k + 1].re, p.v[2 * k + 1].im);
 }
 
 __device__ inline void v2_get_spinor(const float* xs, int l, Spinor<float>& p) {
+    const float4* x4 = reinterpret_cast<const float4*>(xs);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) p.v[i] = cmk(xs[(2 * i) * kV2 + l], xs[(2 * i + 1) * kV2 + l]);
+    for (int k = 0; k < 6; ++k) {
+        const float4 t = x4[k * kV2 + l];
+        p.v[2 * k] = cmk(t.x, t.y);
+        p.v[2 * k + 1] = cmk(t.z, t.w);
+    }
 }
 
 __device__ inline void v2_put_half(float* gb, int mu, int l, const Half<float>& g) {
+    float4* g4 = reinterpret_cast<float4*>(gb);
+    const cplx<float>* v = &g.h[0][0];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            gb[(mu * 12 + 6 * s + 2 * c) * kV2 + l] = g.h[s][c].re;
-            gb[(mu * 12 + 6 * s + 2 * c + 1) * kV2 + l] = g.h[s][c].im;
-        }
+    for (int k = 0; k < 3; ++k) g4[(mu * 3 + k) * kV2 + l] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
 }
 
 __device__ inline void v2_get_half(const float* gb, int mu, int l, Half<float>& g) {
+    const float4* g4 = reinterpret_cast<const float4*>(gb);
+    cplx<float>* v = &g.h[0][0];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            g.h[s][c] = cmk(gb[(mu * 12 + 6 * s + 2 * c) * kV2 + l], gb[(mu * 12 + 6 * s + 2 * c + 1) * kV2 + l]);
+    for (int k = 0; k < 3; ++k) {
+        const float4 t = g4[(mu * 3 + k) * kV2 + l];
+        v[2 * k] = cmk(t.x, t.y);
+        v[2 * k + 1] = cmk(t.z, t.w);
+    }
 }
 
 // A link kept as its first two rows; the third is rebuilt where it is used.
@@ -403,21 +409,16 @@ __device__ inline void su3_dag_mul2(const Link2& c, const Half<float>& h, Half<f
         }
 }
 
-// h = upper - B_mu lower of the spinor of local site n, read component by
-// component from LDS so the full neighbour spinor is never held in registers.
-__device__ inline cplx<float> lds_c(const float* xs, int idx, int n) {
-    return cmk(xs[(2 * idx) * kV2 + n], xs[(2 * idx + 1) * kV2 + n]);
-}
-
+// h = upper - B_mu lower of the spinor of local site n (from LDS).
 __device__ inline void project_forward_lds(const float* xs, int mu, int n, Half<float>& h) {
+    Spinor<float> p;
+    v2_get_spinor(xs, n, p);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const cplx<float> u0 = lds_c(xs, c, n), u1 = lds_c(xs, 3 + c, n);
-        const cplx<float> d0 = lds_c(xs, 6 + c, n), d1 = lds_c(xs, 9 + c, n);
         cplx<float> b0, b1;
-        apply_B(mu, d0, d1, b0, b1);
-        h.h[0][c] = u0 - b0;
-        h.h[1][c] = u1 - b1;
+        apply_B(mu, p.v[6 + c], p.v[9 + c], b0, b1);
+        h.h[0][c] = p.v[c] - b0;
+        h.h[1][c] = p.v[3 + c] - b1;
     }
 }
 
@@ -435,7 +436,7 @@ __device__ inline void forward_accumulate(int mu, const Half<float>& g, Spinor<f
 }
 
 // Publish v: spinor plus backward products for the in-block +mu neighbours.
-__device__ inline void v2_push(V2Shared& sm, int l, bool active, const bool fin[4], const Link2 Uo[4],
+__device__ inline void v2_push(V2Shared& sm, int l, bool active, const bool fin[4], const Link<float> Uo[4],
                                const Spinor<float>& v) {
     if (!active) return;
     v2_put_spinor(sm.xs, l, v);
@@ -452,7 +453,7 @@ __device__ inline void v2_push(V2Shared& sm, int l, bool active, const bool fin[
                 h.h[0][c] = v.v[c] + b0;
                 h.h[1][c] = v.v[3 + c] + b1;
             }
-            su3_dag_mul2(Uo[mu], h, g);
+            su3_dag_mul(Uo[mu], h, g);
             v2_put_half(sm.gb, mu, l, g);
         }
     }
@@ -461,14 +462,14 @@ __device__ inline void v2_push(V2Shared& sm, int l, bool active, const bool fin[
 
 // acc += in-block hop terms (unscaled; the operator adds -1/2 acc).
 __device__ inline void v2_pull(const V2Shared& sm, int l, const bool fin[4], const bool bin[4], const int str[4],
-                               const Link2 Uo[4], Spinor<float>& acc) {
+                               const Link<float> Uo[4], Spinor<float>& acc) {
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         __builtin_amdgcn_sched_barrier(0);
         if (fin[mu]) {
             Half<float> h, g;
             project_forward_lds(sm.xs, mu, l + str[mu], h);
-            su3_mul2(Uo[mu], h, g);
+            su3_mul(Uo[mu], h, g);
             forward_accumulate(mu, g, acc);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -548,12 +549,16 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
         nbk[mu] = coords_site(g, c);
     }
 
-    Link2 Uo[4];
+    // own links with the third row rebuilt once; the clover kept as -2A so that
+    // the MR direction q' = (hops) - 2 A rho = -2 D_BB rho needs no rescaling
+    Link<float> Uo[4];
     Clover<float> A;
     if (active) {
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) load_link2<G>(a.links, g.V, s, mu, Uo[mu]);
+        for (int mu = 0; mu < 4; ++mu) load_link<float, G>(a.links, g.V, s, mu, Uo[mu]);
         load_clover<float, C>(a.clover, g.V, s, A);
+#pragma unroll
+        for (int i = 0; i < 72; ++i) A.a[i] *= -2.f;
     }
 
     const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
@@ -628,9 +633,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
 #pragma unroll
                         for (int i = 0; i < 12; ++i)
                             p.v[i] = cmk(hb[(2 * i) * kHaloMax + hent_f[mu]], hb[(2 * i + 1) * kHaloMax + hent_f[mu]]);
-                        Link<float> L;
-                        expand_link(Uo[mu], L);
-                        hop_forward(mu, L, p, sgf[mu], acc);
+                        hop_forward(mu, Uo[mu], p, sgf[mu], acc);
                     }
                     if (!bin[mu]) {
                         Spinor<float> p;
@@ -659,9 +662,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
                     }
                     Spinor<float> p;
                     load_spinor<float, S>(xx, xsc, g.V, coords_site(g, n), p);
-                    Link<float> L;
-                    expand_link(Uo[mu], L);
-                    hop_forward(mu, L, p, sg, acc);
+                    hop_forward(mu, Uo[mu], p, sg, acc);
                     n[ax] = Bcc[ax] * g.lb[ax] + Lc[ax];
                 }
                 if (!bin[mu]) {
@@ -680,16 +681,10 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
             }
         }
         if (active) {
-            // r = b - (A x - acc/2)
+            // r = b - (A x - acc/2) = b + (acc - 2 A x) / 2
+            if (own) clover_acc(A, -2.f * mu_tw, e, acc);
 #pragma unroll
             for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] + 0.5f * acc.v[i];
-            if (own) {
-#pragma unroll
-                for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
-                clover_acc(A, mu_tw, e, acc);
-#pragma unroll
-                for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] - acc.v[i];
-            }
         }
         if (own) __syncthreads();
 
@@ -704,9 +699,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
 #pragma unroll
                 for (int i = 0; i < 12; ++i) q.v[i] = cmk(0.f, 0.f);
                 v2_pull(sm, l, fin, bin, str, Uo, q);
-#pragma unroll
-                for (int i = 0; i < 12; ++i) q.v[i] = -0.5f * q.v[i];
-                clover_acc(A, mu_tw, rho, q);
+                clover_acc(A, -2.f * mu_tw, rho, q);  // q = -2 D_BB rho
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
                     qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
@@ -716,10 +709,13 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
             }
             block_sum3(sm.red, qr_re, qr_im, qq);
             if (active && qq > 0.f) {
-                const cplx<float> alpha = cmk(qr_re / qq, qr_im / qq);
+                // with q = -2 D_BB rho: rho -= a q and e += -2 a rho, a = <q,rho>/<q,q>
+                const float inv = __builtin_amdgcn_rcpf(qq);
+                const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
+                const cplx<float> beta = cmk(-2.f * alpha.re, -2.f * alpha.im);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
-                    e.v[i] = cmad(alpha, rho.v[i], e.v[i]);
+                    e.v[i] = cmad(beta, rho.v[i], e.v[i]);
                     rho.v[i] = rho.v[i] - alpha * q.v[i];
                 }
             }
