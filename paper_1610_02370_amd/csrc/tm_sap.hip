@@ -9,6 +9,7 @@
 // wavefront with cross-lane shuffles and across the workgroup through LDS.
 // Blocks of one colour do not couple, so all workgroups of a launch are
 // independent; the colour-to-colour dependency is the launch boundary.
+#include <cstddef>
 #include <cstdlib>
 
 #include "tm_internal.h"
@@ -17,12 +18,22 @@ namespace tmsap {
 
 namespace {
 
-// TM_SAP_KERNEL=v1 selects the generic kernel for every precision (A/B tests).
+// TM_SAP_KERNEL=v1 / v2 select the generic kernel or the general-shape FP32
+// kernel instead of the 4^4 one (A/B tests).
 bool sap_v1_forced() {
     static int forced = -1;
     if (forced < 0) {
         const char* e = getenv("TM_SAP_KERNEL");
         forced = (e && e[0] == 'v' && e[1] == '1') ? 1 : 0;
+    }
+    return forced == 1;
+}
+
+bool sap_v2_forced() {
+    static int forced = -1;
+    if (forced < 0) {
+        const char* e = getenv("TM_SAP_KERNEL");
+        forced = (e && e[0] == 'v' && e[1] == '2') ? 1 : 0;
     }
     return forced == 1;
 }
@@ -724,6 +735,217 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 half-sweep specialised to 4^4 blocks (the paper's level-1 Schwarz
+// block).  Each of the four waves owns one axis: at the start of a system it
+// copies the 64 spinors above the block's upper face on that axis into LDS,
+// and forms the 64 backward hop products U_mu(y)^+ (1 + gamma_mu) psi(y) of
+// the sites y below the lower face (link loaded once per launch, mu fixed per
+// wave).  Every site then takes exactly one forward and one backward hop per
+// direction from either the in-block exchange or these halo buffers, so the
+// residual b - D x costs one full stencil with no idle lanes for the faces.
+struct S44Shared {
+    float xs[24 * kV2];      // in-block spinors, [6][site] float4
+    float gb[4 * 12 * kV2];  // in-block backward products, [mu][3][site] float4
+    float hf[24 * kV2];      // upper-face halo spinors, [6][axis*64 + pos] float4
+    float hb[12 * kV2];      // lower-face halo products, [3][axis*64 + pos] float4
+    float red[64];
+};
+static_assert(offsetof(S44Shared, xs) == offsetof(V2Shared, xs) && offsetof(S44Shared, gb) == offsetof(V2Shared, gb),
+              "the exchange helpers address S44Shared through its V2Shared prefix");
+
+template <int MU>
+__device__ inline void s44_stage_backward(const Link<float>& L, const Spinor<float>& p, float sg, float* hb, int j) {
+    Half<float> g;
+    backward_product(MU, L, p, g);
+    float4* h4 = reinterpret_cast<float4*>(hb);
+    const cplx<float>* v = &g.h[0][0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        h4[k * kV2 + j] = make_float4(sg * v[2 * k].re, sg * v[2 * k].im, sg * v[2 * k + 1].re, sg * v[2 * k + 1].im);
+}
+
+template <class S, class G, class C>
+__global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
+    __shared__ S44Shared sm;
+    V2Shared& sx = *reinterpret_cast<V2Shared*>(&sm);
+    const Geo& g = a.g;
+    const int l = threadIdx.x;  // 256 threads, all sites active
+
+    const int half3 = g.nb[3] >> 1;
+    int j = blockIdx.x;
+    const int k3 = j % half3;
+    j /= half3;
+    const int B2 = j % g.nb[2];
+    j /= g.nb[2];
+    const int B1 = j % g.nb[1];
+    const int B0 = j / g.nb[1];
+    const int B3 = 2 * k3 + ((a.colour + B0 + B1 + B2) & 1);
+    const int Bc[4] = {B0, B1, B2, B3};
+    const long long blk = (((long long)B0 * g.nb[1] + B1) * g.nb[2] + B2) * g.nb[3] + B3;
+    const long long s = blk * 256 + l;
+    const int Lc[4] = {l >> 6, (l >> 4) & 3, (l >> 2) & 3, l & 3};
+
+    bool fin[4], bin[4];
+    int str[4], fsrc[4], bsrc[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int ax = axis_of(mu);
+        str[mu] = 1 << (2 * (3 - ax));
+        fin[mu] = Lc[ax] < 3;
+        bin[mu] = Lc[ax] > 0;
+        int p = 0;
+        for (int q = 0; q < 4; ++q)
+            if (q != ax) p = p * 4 + Lc[q];
+        // forward source: in-block neighbour or the upper-face halo entry; backward likewise
+        fsrc[mu] = fin[mu] ? l + str[mu] : ax * 64 + p;
+        bsrc[mu] = bin[mu] ? l - str[mu] : ax * 64 + p;
+    }
+
+    // this thread's halo duties: axis = wave, position = lane
+    const int wax = __builtin_amdgcn_readfirstlane(l >> 6);
+    const int hp = l & 63;
+    int up_site, dn_site;
+    float up_sign = 1.f, dn_sign = 1.f;
+    {
+        int c[4];
+        int p = hp;
+        for (int q = 3; q >= 0; --q) {
+            if (q == wax) continue;
+            c[q] = p & 3;
+            p >>= 2;
+        }
+        for (int q = 0; q < 4; ++q)
+            if (q != wax) c[q] += Bc[q] * 4;
+        c[wax] = Bc[wax] * 4 + 4;
+        bool wrap = false;
+        if (c[wax] >= g.d[wax]) { c[wax] -= g.d[wax]; wrap = true; }
+        up_site = (int)coords_site(g, c);
+        if (wrap && wax == 0 && g.antiperiodic_t) up_sign = -1.f;
+        c[wax] = Bc[wax] * 4 - 1;
+        wrap = false;
+        if (c[wax] < 0) { c[wax] += g.d[wax]; wrap = true; }
+        dn_site = (int)coords_site(g, c);
+        if (wrap && wax == 0 && g.antiperiodic_t) dn_sign = -1.f;
+    }
+    const int wmu = wax == 0 ? 0 : 4 - wax;
+    Link<float> Ldn;  // U_mu(site below the lower face)
+    load_link<float, G>(a.links, g.V, dn_site, wmu, Ldn);
+
+    Link<float> Uo[4];
+    Clover<float> A;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) load_link<float, G>(a.links, g.V, s, mu, Uo[mu]);
+    load_clover<float, C>(a.clover, g.V, s, A);
+#pragma unroll
+    for (int i = 0; i < 72; ++i) A.a[i] *= -2.f;
+
+    const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
+    const int sys_begin = blockIdx.y * a.sys_tile;
+    const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
+    const bool own = !a.own_zero;
+    const bool halo = !(a.own_zero && a.halo_zero);
+
+    for (int sys = sys_begin; sys < sys_end; ++sys) {
+        const float mu_tw = (float)a.mu[sys];
+        const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
+        void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
+        const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
+        float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
+
+        Spinor<float> r, e;
+        load_spinor<float, S>(bb, bsc, g.V, s, r);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) e.v[i] = cmk(0.f, 0.f);
+        if (halo) {
+            // ---- r = b - D x: one full stencil from the in-block exchange and the halo buffers
+            if (own) load_spinor<float, S>(xx, xsc, g.V, s, e);
+            Spinor<float> hu, hd;
+            load_spinor<float, S>(xx, xsc, g.V, up_site, hu);
+            load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
+            v2_push(sx, l, true, fin, Uo, e);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) hu.v[i] = up_sign * hu.v[i];
+            v2_put_spinor(sm.hf, l, hu);
+            switch (wax) {
+                case 0: s44_stage_backward<0>(Ldn, hd, dn_sign, sm.hb, l); break;
+                case 1: s44_stage_backward<3>(Ldn, hd, dn_sign, sm.hb, l); break;
+                case 2: s44_stage_backward<2>(Ldn, hd, dn_sign, sm.hb, l); break;
+                default: s44_stage_backward<1>(Ldn, hd, dn_sign, sm.hb, l); break;
+            }
+            __syncthreads();
+            Spinor<float> acc;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                Half<float> h, gg;
+                {
+                    Spinor<float> p;
+                    v2_get_spinor(fin[mu] ? sm.xs : sm.hf, fsrc[mu], p);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        cplx<float> b0, b1;
+                        apply_B(mu, p.v[6 + c], p.v[9 + c], b0, b1);
+                        h.h[0][c] = p.v[c] - b0;
+                        h.h[1][c] = p.v[3 + c] - b1;
+                    }
+                }
+                su3_mul(Uo[mu], h, gg);
+                forward_accumulate(mu, gg, acc);
+                {
+                    const float4* src = reinterpret_cast<const float4*>(bin[mu] ? sm.gb : sm.hb);
+                    const int base = bin[mu] ? mu * 3 * kV2 : 0;
+                    cplx<float>* v = &gg.h[0][0];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float4 t = src[base + k * kV2 + bsrc[mu]];
+                        v[2 * k] = cmk(t.x, t.y);
+                        v[2 * k + 1] = cmk(t.z, t.w);
+                    }
+                }
+                backward_accumulate(mu, gg, acc);
+            }
+            // r = b + (acc - 2 A x) / 2
+            if (own) clover_acc(A, -2.f * mu_tw, e, acc);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] + 0.5f * acc.v[i];
+            __syncthreads();
+        }
+
+        // ---- minimal residual on D_BB with q = -2 D_BB rho
+        Spinor<float>& rho = r;
+        for (int it = 0; it < a.mr_iters; ++it) {
+            v2_push(sx, l, true, fin, Uo, rho);
+            __syncthreads();
+            Spinor<float> q;
+            float qr_re = 0.f, qr_im = 0.f, qq = 0.f;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) q.v[i] = cmk(0.f, 0.f);
+            v2_pull(sx, l, fin, bin, str, Uo, q);
+            clover_acc(A, -2.f * mu_tw, rho, q);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
+                qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
+                qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
+            }
+            block_sum3(sm.red, qr_re, qr_im, qq);
+            if (qq > 0.f) {
+                const float inv = __builtin_amdgcn_rcpf(qq);
+                const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
+                const cplx<float> beta = cmk(-2.f * alpha.re, -2.f * alpha.im);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    e.v[i] = cmad(beta, rho.v[i], e.v[i]);
+                    rho.v[i] = rho.v[i] - alpha * q.v[i];
+                }
+            }
+        }
+        store_spinor<float, S>(xx, xsc, g.V, s, e);
+    }
+}
+
 template <class S, class G, class C, class R>
 hipError_t run(const SapArgs& a, hipStream_t st) {
     const int nt = (a.g.Vb + 63) & ~63;
@@ -743,7 +965,11 @@ hipError_t run(const SapArgs& a, hipStream_t st) {
     }
     if constexpr (sizeof(R) == 4) {
         if (nt <= kV2 && !sap_v1_forced()) {
-            hipLaunchKernelGGL((k_sap_half_v2<S, G, C>), grid, dim3(nt), 0, st, a);
+            const bool is44 = a.g.lb[0] == 4 && a.g.lb[1] == 4 && a.g.lb[2] == 4 && a.g.lb[3] == 4;
+            if (is44 && !sap_v2_forced())
+                hipLaunchKernelGGL((k_sap_half_44<S, G, C>), grid, dim3(nt), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_sap_half_v2<S, G, C>), grid, dim3(nt), 0, st, a);
             return hipGetLastError();
         }
     }
