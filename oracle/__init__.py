@@ -71,13 +71,21 @@ def _load():
         lib.or_block_colour.argtypes = [ip, ip, ctypes.c_long]
         lib.or_block_colour.restype = ctypes.c_int
         lib.or_mr_block.argtypes = [ctypes.POINTER(_Op), ip, ip, vp, vp, ctypes.c_int]
+        lib.or_mr_block_eo.argtypes = [ctypes.POINTER(_Op), ip, ip, vp, vp, ctypes.c_int]
         lib.or_sap.argtypes = [ctypes.POINTER(_Op), ip, ctypes.c_int, ctypes.c_int, vp, vp]
         lib.or_sap.restype = ctypes.c_int
+        lib.or_sap_eo.argtypes = [ctypes.POINTER(_Op), ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
+        lib.or_sap_eo.restype = ctypes.c_int
         lib.or_fgmres.argtypes = [
             ctypes.POINTER(_Op), vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip,
             ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Report),
         ]
         lib.or_fgmres.restype = ctypes.c_int
+        lib.or_fgmres_eo.argtypes = [
+            ctypes.POINTER(_Op), vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Report),
+        ]
+        lib.or_fgmres_eo.restype = ctypes.c_int
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -164,23 +172,31 @@ class Operator:
         _load().or_mr_block(ctypes.byref(self._op), _i4(bdims), _i4(B), r.ctypes.data, e.ctypes.data, int(iters))
         return e
 
-    def sap(self, b, bdims, n_cycles: int, mr_iters: int, x0=None) -> np.ndarray:
+    def mr_block_eo(self, bdims, B, r, iters: int) -> np.ndarray:
+        """Even-odd preconditioned MR block solve (odd-site Schur complement)."""
+        r = self._vec(r)
+        e = np.zeros_like(r)
+        _load().or_mr_block_eo(ctypes.byref(self._op), _i4(bdims), _i4(B), r.ctypes.data, e.ctypes.data,
+                               int(iters))
+        return e
+
+    def sap(self, b, bdims, n_cycles: int, mr_iters: int, x0=None, eo: bool = False) -> np.ndarray:
         b = self._vec(b)
         x = np.zeros_like(b) if x0 is None else self._vec(x0).copy()
-        rc = _load().or_sap(ctypes.byref(self._op), _i4(bdims), int(n_cycles), int(mr_iters), b.ctypes.data,
-                            x.ctypes.data)
+        rc = _load().or_sap_eo(ctypes.byref(self._op), _i4(bdims), int(n_cycles), int(mr_iters), int(bool(eo)),
+                               b.ctypes.data, x.ctypes.data)
         if rc != 0:
             raise ValueError(f"or_sap rejected block shape {bdims} (code {rc})")
         return x
 
     def fgmres(self, b, tol: float, restart: int = 20, max_iters: int = 2000, precond: bool = True,
-               bdims=(2, 2, 2, 2), n_cycles: int = 3, mr_iters: int = 4, x0=None):
+               bdims=(2, 2, 2, 2), n_cycles: int = 3, mr_iters: int = 4, x0=None, eo: bool = False):
         b = self._vec(b)
         x = np.zeros_like(b) if x0 is None else self._vec(x0).copy()
         rep = _Report()
-        _load().or_fgmres(ctypes.byref(self._op), b.ctypes.data, x.ctypes.data, float(tol), int(restart),
-                          int(max_iters), int(bool(precond)), _i4(bdims), int(n_cycles), int(mr_iters),
-                          ctypes.byref(rep))
+        _load().or_fgmres_eo(ctypes.byref(self._op), b.ctypes.data, x.ctypes.data, float(tol), int(restart),
+                             int(max_iters), int(bool(precond)), _i4(bdims), int(n_cycles), int(mr_iters),
+                             int(bool(eo)), ctypes.byref(rep))
         return x, {"iters": rep.iters, "restarts": rep.restarts, "converged": bool(rep.converged),
                    "true_rel_res": rep.true_rel_res}
 

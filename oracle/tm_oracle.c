@@ -23,6 +23,9 @@
  *   or_mr_block     residual norms non-increasing; converges to the dense LU
  *                   block solve; optimal step length (perturbing alpha never
  *                   lowers the residual).
+ *   or_mr_block_eo  a dense replica (Schur complement of the dense block
+ *                   matrix split by site parity, MR in NumPy); converges to
+ *                   the dense LU block solve.
  *   or_sap          with exact block solves, the closed form
  *                   x_n = (I - E^n) D^-1 b + E^n x_0, E = (I-B1 D)(I-B0 D);
  *                   residual vanishes on the colour just swept;
@@ -466,6 +469,141 @@ static void exact_local(const or_op* op, const int bdims[4], const int B[4], con
     free(rhs);
 }
 
+/* ------------------------------------------- even-odd reduced block solves */
+
+/* Site parity (t + z + y + x) mod 2 of the global coordinates: 0 = even. */
+static int site_parity(const int dims[4], long s) {
+    int c[4];
+    site_coords(dims, s, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+/* out = D_xx^-1 in at one site, D_xx = (m+4) + C(x) + i mu gamma5 the
+ * site-diagonal part of D, by Gaussian elimination on its 12x12 matrix. */
+static void diag_solve(const or_op* op, const or_cplx* g5, long x, const or_cplx* in, or_cplx* out) {
+    or_cplx A[12][12], rhs[12], unit[12], col[12];
+    for (int j = 0; j < 12; ++j) {
+        for (int i = 0; i < 12; ++i) unit[i] = (i == j) ? 1.0 : 0.0, col[i] = 0;
+        add_diag(op, g5, x, unit, col);
+        for (int i = 0; i < 12; ++i) A[i][j] = col[i];
+    }
+    for (int i = 0; i < 12; ++i) rhs[i] = in[i];
+    for (int k = 0; k < 12; ++k) {
+        int p = k;
+        for (int i = k + 1; i < 12; ++i)
+            if (cabs(A[i][k]) > cabs(A[p][k])) p = i;
+        if (p != k) {
+            for (int j = 0; j < 12; ++j) {
+                or_cplx t = A[k][j];
+                A[k][j] = A[p][j];
+                A[p][j] = t;
+            }
+            or_cplx t = rhs[k];
+            rhs[k] = rhs[p];
+            rhs[p] = t;
+        }
+        for (int i = k + 1; i < 12; ++i) {
+            or_cplx f = A[i][k] / A[k][k];
+            for (int j = k; j < 12; ++j) A[i][j] -= f * A[k][j];
+            rhs[i] -= f * rhs[k];
+        }
+    }
+    for (int i = 11; i >= 0; --i) {
+        or_cplx t = rhs[i];
+        for (int j = i + 1; j < 12; ++j) t -= A[i][j] * out[j];
+        out[i] = t / A[i][i];
+    }
+}
+
+/* Keep the sites of parity `par` of a block-local vector, zero the others. */
+static void keep_parity(const int dims[4], const long* sites, long Vb, int par, or_cplx* v) {
+    for (long l = 0; l < Vb; ++l)
+        if (site_parity(dims, sites[l]) != par)
+            for (int i = 0; i < 12; ++i) v[l * 12 + i] = 0;
+}
+
+/* D_ee^-1 applied on the even sites of a block-local vector (odd sites zeroed). */
+static void diag_solve_even(const or_op* op, const long* sites, long Vb, const or_cplx* in, or_cplx* out) {
+    or_cplx g5[16];
+    or_gamma(4, g5);
+    for (long l = 0; l < Vb; ++l) {
+        if (site_parity(op->dims, sites[l]) == 0)
+            diag_solve(op, g5, sites[l], in + l * 12, out + l * 12);
+        else
+            for (int i = 0; i < 12; ++i) out[l * 12 + i] = 0;
+    }
+}
+
+/* q_o = Dhat rho_o with Dhat = D_oo - D_oe D_ee^-1 D_eo, the block operator
+ * reduced to its odd sites (section 2.5).  rho, q: block-local, odd sites
+ * only; u, t, v: scratch. */
+static void dhat_local(const or_op* op, const int bdims[4], const int B[4], const long* sites, long Vb,
+                       const or_cplx* rho, or_cplx* q, or_cplx* u, or_cplx* t, or_cplx* v) {
+    long n = Vb * 12;
+    dirac_block_local(op, bdims, B, sites, Vb, rho, u); /* u_o = D_oo rho_o, u_e = D_eo rho_o */
+    diag_solve_even(op, sites, Vb, u, t);                /* t_e = D_ee^-1 D_eo rho_o */
+    dirac_block_local(op, bdims, B, sites, Vb, t, v);   /* v_o = D_oe t_e */
+    for (long i = 0; i < n; ++i) q[i] = u[i] - v[i];
+    keep_parity(op->dims, sites, Vb, 1, q);
+}
+
+/* Block solve with even-odd preconditioning (section 2.5): reduce r to the
+ * odd sites, rhat_o = r_o - D_oe D_ee^-1 r_e; run `iters` MR steps on
+ * Dhat e_o = rhat_o from e_o = 0; recover e_e = D_ee^-1 (r_e - D_eo e_o). */
+static void mr_local_eo(const or_op* op, const int bdims[4], const int B[4], const long* sites, long Vb,
+                        const or_cplx* r, or_cplx* e, int iters) {
+    long n = Vb * 12;
+    or_cplx* rho = malloc(sizeof(or_cplx) * n);
+    or_cplx* q = malloc(sizeof(or_cplx) * n);
+    or_cplx* u = malloc(sizeof(or_cplx) * n);
+    or_cplx* t = malloc(sizeof(or_cplx) * n);
+    or_cplx* v = malloc(sizeof(or_cplx) * n);
+    /* rhat_o = r_o - D_oe D_ee^-1 r_e */
+    diag_solve_even(op, sites, Vb, r, t);
+    dirac_block_local(op, bdims, B, sites, Vb, t, v);
+    for (long i = 0; i < n; ++i) rho[i] = r[i] - v[i];
+    keep_parity(op->dims, sites, Vb, 1, rho);
+    /* MR on Dhat over the odd sites */
+    for (long i = 0; i < n; ++i) e[i] = 0;
+    for (int k = 0; k < iters; ++k) {
+        dhat_local(op, bdims, B, sites, Vb, rho, q, u, t, v);
+        or_cplx qr = vdot(q, rho, n);
+        double qq = creal(vdot(q, q, n));
+        if (qq == 0.0) break;
+        or_cplx alpha = qr / qq;
+        for (long i = 0; i < n; ++i) {
+            e[i] += alpha * rho[i];
+            rho[i] -= alpha * q[i];
+        }
+    }
+    /* e_e = D_ee^-1 (r_e - D_eo e_o) */
+    dirac_block_local(op, bdims, B, sites, Vb, e, u);
+    for (long i = 0; i < n; ++i) v[i] = r[i] - u[i];
+    diag_solve_even(op, sites, Vb, v, t);
+    for (long l = 0; l < Vb; ++l)
+        if (site_parity(op->dims, sites[l]) == 0)
+            for (int i = 0; i < 12; ++i) e[l * 12 + i] = t[l * 12 + i];
+    free(rho);
+    free(q);
+    free(u);
+    free(t);
+    free(v);
+}
+
+void or_mr_block_eo(const or_op* op, const int bdims[4], const int B[4], const or_cplx* r, or_cplx* e, int iters) {
+    long Vb = (long)bdims[0] * bdims[1] * bdims[2] * bdims[3];
+    long* sites = malloc(sizeof(long) * Vb);
+    or_cplx* rl = malloc(sizeof(or_cplx) * Vb * 12);
+    or_cplx* el = malloc(sizeof(or_cplx) * Vb * 12);
+    block_sites(op->dims, bdims, B, sites);
+    for (long l = 0; l < Vb; ++l) memcpy(rl + l * 12, r + (size_t)sites[l] * 12, sizeof(or_cplx) * 12);
+    mr_local_eo(op, bdims, B, sites, Vb, rl, el, iters);
+    for (long l = 0; l < Vb; ++l) memcpy(e + (size_t)sites[l] * 12, el + l * 12, sizeof(or_cplx) * 12);
+    free(sites);
+    free(rl);
+    free(el);
+}
+
 void or_mr_block(const or_op* op, const int bdims[4], const int B[4], const or_cplx* r, or_cplx* e, int iters) {
     long Vb = (long)bdims[0] * bdims[1] * bdims[2] * bdims[3];
     long* sites = malloc(sizeof(long) * Vb);
@@ -483,6 +621,11 @@ void or_mr_block(const or_op* op, const int bdims[4], const int B[4], const or_c
 /* ------------------------------------------------------------------- SAP */
 
 int or_sap(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, const or_cplx* b, or_cplx* x) {
+    return or_sap_eo(op, bdims, n_cycles, mr_iters, 0, b, x);
+}
+
+int or_sap_eo(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, int eo, const or_cplx* b,
+              or_cplx* x) {
     int nb[4];
     for (int a = 0; a < 4; ++a) {
         if (bdims[a] <= 0 || op->dims[a] % bdims[a] != 0) return -2;
@@ -514,7 +657,9 @@ int or_sap(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, cons
                 or_cplx* el = malloc(sizeof(or_cplx) * Vb * 12);
                 block_sites(op->dims, bdims, B, sites);
                 for (long l = 0; l < Vb; ++l) memcpy(rl + l * 12, r + (size_t)sites[l] * 12, sizeof(or_cplx) * 12);
-                if (mr_iters >= 0)
+                if (mr_iters >= 0 && eo)
+                    mr_local_eo(op, bdims, B, sites, Vb, rl, el, mr_iters);
+                else if (mr_iters >= 0)
                     mr_local(op, bdims, B, sites, Vb, rl, el, mr_iters);
                 else
                     exact_local(op, bdims, B, sites, Vb, rl, el);
@@ -546,6 +691,11 @@ static double true_residual(const or_op* op, const or_cplx* b, const or_cplx* x,
 
 int or_fgmres(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters, int precond,
               const int bdims[4], int n_cycles, int mr_iters, or_report* rep) {
+    return or_fgmres_eo(op, b, x, tol, restart, max_iters, precond, bdims, n_cycles, mr_iters, 0, rep);
+}
+
+int or_fgmres_eo(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
+                 int precond, const int bdims[4], int n_cycles, int mr_iters, int eo, or_report* rep) {
     long n = or_volume(op->dims) * 12;
     int m = restart;
     or_cplx* Vv = malloc(sizeof(or_cplx) * n * (m + 1));
@@ -579,7 +729,7 @@ int or_fgmres(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int res
             /* z_j = M v_j */
             if (precond) {
                 for (long i = 0; i < n; ++i) zj[i] = 0;
-                or_sap(op, bdims, n_cycles, mr_iters, vj, zj);
+                or_sap_eo(op, bdims, n_cycles, mr_iters, eo, vj, zj);
             } else {
                 memcpy(zj, vj, sizeof(or_cplx) * n);
             }

@@ -71,12 +71,22 @@ int or_block_colour(const int dims[4], const int bdims[4], long site);
 void or_mr_block(const or_op* op, const int bdims[4], const int B[4], const or_cplx* r,
                  or_cplx* e, int iters);
 
+/* Block solve with even-odd preconditioning (section 2.5): sites split by the
+ * parity of t+z+y+x (0 = even); MR runs `iters` steps on the odd-site Schur
+ * complement Dhat = D_oo - D_oe D_ee^-1 D_eo of D_BB with right-hand side
+ * r_o - D_oe D_ee^-1 r_e, then e_e = D_ee^-1 (r_e - D_eo e_o). */
+void or_mr_block_eo(const or_op* op, const int bdims[4], const int B[4], const or_cplx* r,
+                    or_cplx* e, int iters);
+
 /* Red-black multiplicative SAP: n_cycles cycles, colour 0 then colour 1,
  * each block solved by mr_iters MR steps (mr_iters < 0: exact block solve by
  * dense Gaussian elimination, used only by the closed-form pins).
  * x is in/out. Returns 0, or -3 when a direction has an odd block count. */
 int or_sap(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, const or_cplx* b,
            or_cplx* x);
+/* As or_sap; eo != 0 solves the blocks with or_mr_block_eo's method. */
+int or_sap_eo(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, int eo,
+              const or_cplx* b, or_cplx* x);
 
 /* Flexible GMRES(restart) with right preconditioning (precond: 0 = none,
  * 1 = SAP with the given parameters), modified Gram-Schmidt, complex Givens
@@ -85,6 +95,9 @@ int or_sap(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, cons
  * converged, 1 otherwise. */
 int or_fgmres(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
               int precond, const int bdims[4], int n_cycles, int mr_iters, or_report* rep);
+/* As or_fgmres; eo != 0 uses SAP with even-odd preconditioned block solves. */
+int or_fgmres_eo(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
+                 int precond, const int bdims[4], int n_cycles, int mr_iters, int eo, or_report* rep);
 
 /* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
 int or_num_threads(void);

@@ -33,6 +33,13 @@ MUTATIONS = {
     "sap_colour_order": ("!= colour) continue;", "!= 1 - colour) continue;"),
     # Dirichlet cut missing: block operator keeps hops that leave the block
     "no_dirichlet_cut": ("if (lf >= 0) add_hop", "if (lf >= 0 || 1) add_hop"),
+    # even-odd: Schur complement with + instead of -
+    "eo_schur_sign": ("for (long i = 0; i < n; ++i) q[i] = u[i] - v[i];", "for (long i = 0; i < n; ++i) q[i] = u[i] + v[i];"),
+    # even-odd: reduced right-hand side without the even-site correction
+    "eo_rhs_uncorrected": ("for (long i = 0; i < n; ++i) rho[i] = r[i] - v[i];", "for (long i = 0; i < n; ++i) rho[i] = r[i];"),
+    # even-odd: even sites taken as the reduced ones (parity flipped in the reconstruction)
+    "eo_parity_flip": ("if (site_parity(op->dims, sites[l]) == 0)\n            for (int i = 0; i < 12; ++i) e[l * 12 + i] = t[l * 12 + i];",
+                       "if (site_parity(op->dims, sites[l]) == 1)\n            for (int i = 0; i < 12; ++i) e[l * 12 + i] = t[l * 12 + i];"),
     # Givens rotation without the conjugate
     "givens_conj": ("g[j + 1] = -conj(sn[j]) * g[j];", "g[j + 1] = -sn[j] * g[j];"),
 }
@@ -41,7 +48,9 @@ MUTATIONS = {
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_pins_catch_planted_mistake(name, tmp_path):
-    old, new = MUTATIONS[name]
+    old, new = MUTATIONS[name][:2]
+    # mistakes in the even-odd block solve only reach the even-odd pins
+    select = ["-k", "eo"] if name.startswith("eo_") else []
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation anchor for {name} not found"
     mutated = tmp_path / "tm_oracle.c"
@@ -51,7 +60,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     subprocess.check_call(["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(mutated), "-lm"])
     env = dict(os.environ, TM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run(
-        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *select,
          os.path.join(ROOT, "tests", "test_oracle_operator.py"), os.path.join(ROOT, "tests", "test_oracle_sap.py")],
         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} was not caught:\n{r.stdout[-2000:]}"
