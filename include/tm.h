@@ -95,6 +95,15 @@ typedef struct {
                              (4^4 where it divides dims, else 2 or 1 per axis);
                              tm_sap_smooth always tiles by its block_dims */
     unsigned long long gauge_tag; /* 0: rebuild the gauge copy every call; else cache key (see above) */
+    int sys_tile;         /* SAP: systems per workgroup (0 = all systems of the call in one workgroup,
+                             so links and clover are read once per half-sweep) */
+    int sap_eo;           /* SAP block solves (section 2.5): 0 = MR on D_BB; 1 = even-odd
+                             preconditioned: MR on the odd-site Schur complement
+                             D_oo - D_oe D_ee^-1 D_eo (parity of t+z+y+x), e_e recovered after.
+                             Needs an even block extent in x (else TM_ERR_BLOCKS) and at most 8
+                             distinct |mu| per call (else TM_ERR_ARG); the site inverses
+                             (A + i mu gamma5)^-1 are built on first use per |mu| and kept with
+                             the gauge copy (288 B per site at FP32, 576 B at FP64) */
 } tm_opts;
 
 /* Fills opts with: storage F64, compute F64, null stream, canonical io, tag 0. */
@@ -192,15 +201,20 @@ TM_API int tm_spinor_export(const tm_geom* geom, const void* internal, void* can
 
 /* --------------------------------------------------------------- tuning */
 /*
- * Times SAP cycles for every candidate block shape (divisors of dims with an
- * even block count per direction, 16..1024 sites) and picks the fastest per
- * SAP application; stores the choice in a cache file (path from the
- * TM_TUNE_CACHE environment variable, default ./tm_tune.json) and writes it
- * to best_block[4].  The block shape changes the preconditioner, so solves
- * with a tuned shape converge differently from 4^4.
+ * Times SAP applications (n_cycles cycles of mr_iters MR steps, geom->nsys
+ * systems, opts->storage) for candidate Schwarz block shapes (divisors of
+ * dims with an even block count per direction, 16..256 sites) and systems-
+ * per-workgroup tiles, and returns the fastest in best_block[4] and
+ * *best_sys_tile.  The choice is stored in a text cache (path from the
+ * TM_TUNE_CACHE environment variable, default ./tm_tune.txt) keyed by
+ * (dims, nsys, storage, n_cycles, mr_iters); tm_fgmres_solve with block_dims
+ * all zero uses a cached shape when one exists, else 4^4.  The objective is
+ * smoother throughput only: the block shape also changes the preconditioner,
+ * so a tuned shape can converge in a different number of iterations.
+ * Allocates its own test vectors; U is read through the gauge cache.
  */
 TM_API int tm_autotune_sap(const tm_geom* geom, const void* U, double kappa, double c_sw, int n_cycles, int mr_iters,
-                    const tm_opts* opts, int best_block[4]);
+                           const tm_opts* opts, int best_block[4], int* best_sys_tile);
 
 #ifdef __cplusplus
 }

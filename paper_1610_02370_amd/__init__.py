@@ -47,7 +47,8 @@ class Geom(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int), ("compute", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("io", ctypes.c_int), ("layout_block", ctypes.c_int * 4), ("gauge_tag", ctypes.c_ulonglong)]
+                ("io", ctypes.c_int), ("layout_block", ctypes.c_int * 4), ("gauge_tag", ctypes.c_ulonglong),
+                ("sys_tile", ctypes.c_int), ("sap_eo", ctypes.c_int)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -93,7 +94,7 @@ def lib():
         L.tm_spinor_import.argtypes = [P(Geom), vp, vp, P(Opts)]
         L.tm_spinor_export.argtypes = [P(Geom), vp, vp, P(Opts)]
         L.tm_autotune_sap.argtypes = [P(Geom), vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                      P(Opts), P(ctypes.c_int)]
+                                      P(Opts), P(ctypes.c_int), P(ctypes.c_int)]
         _lib = L
     return _lib
 
@@ -184,10 +185,14 @@ def tm_dirac_apply(dims, U, psi, kappa: float, mu, c_sw: float, out=None, *, sto
 
 def tm_sap_smooth(dims, U, b, x, kappa: float, mu, c_sw: float, block_dims, n_cycles: int, mr_iters: int, *,
                   storage: str = "f64", antiperiodic_t: bool = False, stream=None, io: str = "canonical",
-                  gauge_tag: int = 0):
-    """x <- SAP(b, x): n_cycles red-black cycles, mr_iters MR steps per block (x is in/out)."""
+                  gauge_tag: int = 0, sys_tile: int = 0, eo: bool = False):
+    """x <- SAP(b, x): n_cycles red-black cycles, mr_iters MR steps per block (x is in/out).
+
+    eo: even-odd preconditioned block solves (MR on the odd-site Schur complement)."""
     g = make_geom(dims, mu, antiperiodic_t)
     o = make_opts(storage, stream=stream, io=io, layout_block=block_dims, gauge_tag=gauge_tag)
+    o.sys_tile = int(sys_tile)
+    o.sap_eo = int(bool(eo))
     bd = (ctypes.c_int * 4)(*[int(v) for v in block_dims])
     pb = _canon(b, "b") if io == "canonical" else _ptr(b)
     px = _canon(x, "x") if io == "canonical" else _ptr(x)
@@ -209,10 +214,13 @@ def solver_opts(form: str = "flexible", restart: int = 20, max_iters: int = 2000
 
 
 def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, storage: str = "f32",
-                    antiperiodic_t: bool = False, stream=None, gauge_tag: int = 0, **solver_kw):
+                    antiperiodic_t: bool = False, stream=None, gauge_tag: int = 0, sys_tile: int = 0,
+                    eo: bool = False, **solver_kw):
     """Solve D(mu_k) x_k = b_k to a true relative residual tol; returns (status, report dict)."""
     g = make_geom(dims, mu, antiperiodic_t)
     o = make_opts(storage, stream=stream, gauge_tag=gauge_tag)
+    o.sys_tile = int(sys_tile)
+    o.sap_eo = int(bool(eo))
     s = solver_opts(**solver_kw)
     rep = Report()
     rc = _check(lib().tm_fgmres_solve(ctypes.byref(g), _canon(U, "U"), _canon(b, "b"), _canon(x, "x"), float(kappa),
@@ -249,10 +257,13 @@ def tm_spinor_export(dims, internal, canon, *, storage: str, layout_block=None, 
 
 
 def tm_autotune_sap(dims, U, kappa: float, mu, c_sw: float, n_cycles: int, mr_iters: int, *, storage: str = "f32",
-                    stream=None):
+                    stream=None, gauge_tag: int = 0, eo: bool = False):
+    """Fastest (block_dims, sys_tile) for SAP applications on this lattice; cached on disk."""
     g = make_geom(dims, mu)
-    o = make_opts(storage, stream=stream)
+    o = make_opts(storage, stream=stream, gauge_tag=gauge_tag)
+    o.sap_eo = int(bool(eo))
     best = (ctypes.c_int * 4)()
+    tile = ctypes.c_int()
     _check(lib().tm_autotune_sap(ctypes.byref(g), _canon(U, "U"), float(kappa), float(c_sw), int(n_cycles),
-                                 int(mr_iters), ctypes.byref(o), best))
-    return tuple(best)
+                                 int(mr_iters), ctypes.byref(o), best, ctypes.byref(tile)))
+    return tuple(best), tile.value

@@ -76,6 +76,12 @@ hipError_t DeviceBuffer::ensure(size_t n) {
     return hipSuccess;
 }
 
+void EoCache::release() {
+    for (int k = 0; k < n; ++k)
+        if (inv[k]) (void)hipFree(inv[k]);
+    n = 0;
+}
+
 GaugeEntry::~GaugeEntry() {
     if (dev.links) (void)hipFree(dev.links);
     if (dev.clover) (void)hipFree(dev.clover);
@@ -108,6 +114,8 @@ int check_opts(const tm_opts* opts) {
     if (opts->storage != TM_F64 && opts->compute != TM_F32)
         return fail(TM_ERR_PREC, "FP32/FP16/BF16 storage computes in FP32");
     if (opts->io != TM_IO_CANONICAL && opts->io != TM_IO_INTERNAL) return fail(TM_ERR_ARG, "unknown io mode");
+    if (opts->sys_tile < 0) return fail(TM_ERR_ARG, "sys_tile must be >= 0");
+    if (opts->sap_eo != 0 && opts->sap_eo != 1) return fail(TM_ERR_ARG, "sap_eo must be 0 or 1");
     return TM_OK;
 }
 
@@ -196,6 +204,8 @@ int get_gauge(DeviceState* ds, const Geo& g, const void* U, double kappa, double
     // (re)build: mark the slot unusable until validation passes
     slot->U = nullptr;
     slot->tag = 0;
+    slot->eo.release();
+    slot->dev.eo = &slot->eo;
     hipError_t h = ds->stats.ensure(256);
     if (h != hipSuccess) return hip_fail(h, "stats");
     unsigned* stats = (unsigned*)ds->stats.ptr;
@@ -242,9 +252,67 @@ void fill_mu(const tm_geom* geom, double* mu) {
     for (int k = 0; k < kMaxSys; ++k) mu[k] = k < geom->nsys ? geom->mu[k] : 0.0;
 }
 
+// Even-odd inverse sets for the systems' |mu| values: built on first use and
+// kept with the gauge entry; sets a.eo_inv / eo_sel / eo_adj.
+static int prepare_eo(const Geo& g, const GaugeDev& G, const double* mu, int nsys, hipStream_t st, SapArgs& a) {
+    if (g.lb[3] % 2 != 0)
+        return fail(TM_ERR_BLOCKS, "even-odd block solves need an even block extent in x (got %d)", g.lb[3]);
+    if (!G.eo) return fail(TM_ERR_ARG, "gauge entry without an even-odd cache");
+    EoCache& c = *G.eo;
+    double want[kMaxEoMu];
+    int nwant = 0;
+    a.eo_adj = 0;
+    for (int k = 0; k < nsys; ++k) {
+        const double am = std::fabs(mu[k]);
+        int j = 0;
+        while (j < nwant && want[j] != am) ++j;
+        if (j == nwant) {
+            if (nwant == kMaxEoMu)
+                return fail(TM_ERR_ARG, "even-odd block solves take at most %d distinct |mu| per call", kMaxEoMu);
+            want[nwant++] = am;
+        }
+        a.eo_sel[k] = (unsigned char)j;
+        if (mu[k] < 0) a.eo_adj |= 1ull << k;
+    }
+    // keep the cache to the sets this call needs when it would overflow
+    int missing = 0;
+    for (int j = 0; j < nwant; ++j) {
+        bool found = false;
+        for (int i = 0; i < c.n; ++i) found |= c.absmu[i] == want[j];
+        missing += !found;
+    }
+    if (c.n + missing > kMaxEoMu) c.release();
+    for (int j = 0; j < nwant; ++j) {
+        int i = 0;
+        while (i < c.n && c.absmu[i] != want[j]) ++i;
+        if (i == c.n) {
+            void* p = nullptr;
+            hipError_t h = hipMalloc(&p, eo_inverse_bytes(g, G.clover_prec));
+            if (h != hipSuccess) return hip_fail(h, "even-odd inverses");
+            if ((h = launch_eo_inverse(g, G.clover_prec, G.clover, want[j], p, st)) != hipSuccess) {
+                (void)hipFree(p);
+                return hip_fail(h, "even-odd inverses");
+            }
+            c.absmu[c.n] = want[j];
+            c.inv[c.n] = p;
+            ++c.n;
+        }
+        a.eo_inv[j] = c.inv[i];
+    }
+    return TM_OK;
+}
+
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,
-            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st) {
+            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st, bool eo) {
     SapArgs a;
+    a.eo = eo ? 1 : 0;
+    a.eo_adj = 0;
+    for (int k = 0; k < kMaxEoMu; ++k) a.eo_inv[k] = nullptr;
+    for (int k = 0; k < kMaxSys; ++k) a.eo_sel[k] = 0;
+    if (eo) {
+        int rc = prepare_eo(g, G, mu, nsys, st, a);
+        if (rc) return rc;
+    }
     a.g = g;
     a.links = G.links;
     a.clover = G.clover;
@@ -303,6 +371,22 @@ int check_sap_blocks(const tm_geom* geom, const int* block_dims, int tile[4]) {
     }
     if ((long long)tile[0] * tile[1] * tile[2] * tile[3] > 1024) return fail(TM_ERR_BLOCKS, "block holds more than 1024 sites");
     return TM_OK;
+}
+
+void drop_gauge(DeviceState* ds, const GaugeDev* G) {
+    std::lock_guard<std::mutex> lock(ds->mutex);
+    for (auto it = ds->gauge.begin(); it != ds->gauge.end(); ++it)
+        if (&(*it)->dev == G) {
+            ds->gauge.erase(it);
+            return;
+        }
+}
+
+bool gauge_held(DeviceState* ds, const GaugeDev* G) {
+    std::lock_guard<std::mutex> lock(ds->mutex);
+    for (auto& e : ds->gauge)
+        if (&e->dev == G) return true;
+    return false;
 }
 
 }  // namespace tmsap
@@ -446,7 +530,7 @@ int tm_sap_smooth(const tm_geom* geom, const void* U, const void* b, void* x, do
     if (opts->io == TM_IO_INTERNAL) {
         SpinorBuf bb = wrap_internal(const_cast<void*>(b), g, geom->nsys, sp);
         SpinorBuf xx = wrap_internal(x, g, geom->nsys, sp);
-        return run_sap(g, *G, bb, xx, mu, geom->nsys, n_cycles, mr_iters, false, 0, st);
+        return run_sap(g, *G, bb, xx, mu, geom->nsys, n_cycles, mr_iters, false, opts->sys_tile, st, opts->sap_eo);
     }
     size_t nb = internal_bytes(g, geom->nsys, sp);
     hipError_t h = ds->io.ensure(2 * nb);
@@ -458,7 +542,8 @@ int tm_sap_smooth(const tm_geom* geom, const void* U, const void* b, void* x, do
         return hip_fail(h, "spinor import");
     if ((h = launch_spinor_import(g, xx, x, (unsigned*)ds->stats.ptr + 2, st)) != hipSuccess)
         return hip_fail(h, "spinor import");
-    if ((rc = run_sap(g, *G, bb, xx, mu, geom->nsys, n_cycles, mr_iters, false, 0, st))) return rc;
+    if ((rc = run_sap(g, *G, bb, xx, mu, geom->nsys, n_cycles, mr_iters, false, opts->sys_tile, st, opts->sap_eo)))
+        return rc;
     if ((h = launch_spinor_export(g, xx, x, st)) != hipSuccess) return hip_fail(h, "spinor export");
     return TM_OK;
 }

@@ -27,6 +27,7 @@ struct GaugeEntry {
     double kappa = 0, csw = 0;
     Geo g{};
     GaugeDev dev;
+    EoCache eo;                        // even-odd site inverses derived from dev.clover
     unsigned long long last_call = 0;  // call that last used this entry (never evicted by that call)
     ~GaugeEntry();
 };
@@ -55,11 +56,19 @@ Geo make_geo(const tm_geom* geom, const int tile[4]);
 Prec clover_prec_for(Prec link_p);
 int get_gauge(DeviceState* ds, const Geo& g, const void* U, double kappa, double csw, Prec link_p,
               unsigned long long tag, hipStream_t st, const GaugeDev** out);
+// Gauge cache entries: whether G is still held, and dropping it (frees its memory).
+bool gauge_held(DeviceState* ds, const GaugeDev* G);
+void drop_gauge(DeviceState* ds, const GaugeDev* G);
+// SAP tuning cache: the stored (block shape, systems per workgroup) for this
+// problem, if any; returns false when nothing is stored.
+bool tune_lookup(const tm_geom* geom, int storage, int n_cycles, int mr_iters, int eo, int block[4], int* sys_tile);
 SpinorBuf wrap_internal(void* base, const Geo& g, int nsys, Prec p);
 size_t internal_bytes(const Geo& g, int nsys, Prec p);
 void fill_mu(const tm_geom* geom, double* mu);
+// n_cycles red-black SAP cycles; eo selects even-odd preconditioned block
+// solves (site inverses built on first use for each |mu| and kept with G).
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,
-            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st);
+            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st, bool eo = false);
 int run_dirac(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu, int nsys,
               Prec compute, hipStream_t st);
 

@@ -43,5 +43,7 @@ hipError_t blas_residual(Prec p, const VecRef& b, const VecRef& ax, const VecRef
 hipError_t blas_accumulate(Prec px, Prec pc, const VecRef& x, const VecRef& c, int nsys, long long V, hipStream_t st);
 // zero a buffer with a kernel (bytes a multiple of 16)
 hipError_t blas_zero(void* p, size_t bytes, hipStream_t st);
+// fill an internal field with a fixed bounded pattern (FP16 scales set to 1); tuning inputs
+hipError_t blas_fill_pattern(const SpinorBuf& b, long long V, unsigned seed, hipStream_t st);
 
 }  // namespace tmsap

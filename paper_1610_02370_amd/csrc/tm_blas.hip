@@ -6,6 +6,8 @@
 // second kernel in a fixed order, so results do not depend on scheduling.
 #include "tm_blas.h"
 
+#include <type_traits>
+
 namespace tmsap {
 
 namespace {
@@ -200,6 +202,31 @@ __global__ void k_zero(void* p, size_t n16) {
         reinterpret_cast<float4*>(p)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Test pattern in [-1, 1) from a 32-bit integer hash of the index (timing
+// inputs only: values need be finite and of unit size, not random).
+__device__ inline float pattern_value(size_t i, unsigned seed) {
+    unsigned h = (unsigned)i * 0x9E3779B1u ^ (unsigned)(i >> 32) ^ seed;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return (float)(h >> 8) * (2.0f / 16777216.0f) - 1.0f;
+}
+
+template <class T>
+__global__ void k_fill_pattern(T* data, size_t n, float* scale, size_t nscale, unsigned seed) {
+    const size_t stride = (size_t)gridDim.x * kThreads;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const float v = pattern_value(i, seed);
+        if constexpr (std::is_same<T, bf16>::value)
+            data[i] = to_bf16(v);
+        else
+            data[i] = (T)v;
+    }
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nscale; i += stride) scale[i] = 1.0f;
+}
+
 }  // namespace
 
 int blas_blocks(long long V) {
@@ -270,6 +297,16 @@ hipError_t blas_zero(void* p, size_t bytes, hipStream_t st) {
     const size_t n16 = bytes / 16;
     const unsigned nb = (unsigned)((n16 + kThreads - 1) / kThreads < 4096 ? (n16 + kThreads - 1) / kThreads : 4096);
     hipLaunchKernelGGL(k_zero, dim3(nb > 0 ? nb : 1), dim3(kThreads), 0, st, p, n16);
+    return hipGetLastError();
+}
+
+hipError_t blas_fill_pattern(const SpinorBuf& b, long long V, unsigned seed, hipStream_t st) {
+    const size_t nreal = spinor_data_bytes(V, b.nsys, b.prec) / (unit_bytes(b.prec) / 4);
+    const size_t nscale = b.scale ? (size_t)b.nsys * V : 0;
+    const unsigned nb = 4096;
+    TM_DISPATCH_VEC(b.prec, T,
+                    hipLaunchKernelGGL(k_fill_pattern<T>, dim3(nb), dim3(kThreads), 0, st, static_cast<T*>(b.data),
+                                       nreal, b.scale, nscale, seed));
     return hipGetLastError();
 }
 

@@ -33,11 +33,25 @@ inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 // Gauge data on the device at one precision: links [4][3 units][V] and the
 // packed clover [18 units][V] holding (m+4) + clover.
+// Site-diagonal inverses for even-odd block solves, one set per |mu|:
+// [36 units][V/2] at the clover precision, entry h for the even site of the
+// pair (2h, 2h+1) (block x-extent even); units 0..17 hold (A_up + i|mu|)^-1,
+// units 18..35 hold (A_dn - i|mu|)^-1, each 6x6 row-major as (re, im) pairs.
+constexpr int kMaxEoMu = 8;
+struct EoCache {
+    int n = 0;
+    double absmu[kMaxEoMu] = {};
+    void* inv[kMaxEoMu] = {};
+    void release();
+    ~EoCache() { release(); }
+};
+
 struct GaugeDev {
     void* links = nullptr;
     void* clover = nullptr;
     Prec link_prec = P_F64;
     Prec clover_prec = P_F64;
+    EoCache* eo = nullptr;  // owned by the cache entry that holds this
 };
 
 struct DiracArgs {
@@ -66,6 +80,10 @@ struct SapArgs {
     int mr_iters;
     int own_zero;        // 1: x is zero on this colour's blocks (skip reading it)
     int halo_zero;       // 1: x is zero on the other colour's blocks too (then r = b)
+    int eo;              // 1: even-odd preconditioned block solves
+    unsigned long long eo_adj;            // bit k: system k uses the adjoint inverses (mu_k < 0)
+    const void* eo_inv[kMaxEoMu];         // inverse sets by |mu|
+    unsigned char eo_sel[kMaxSys];        // system -> inverse set
     double mu[kMaxSys];
 };
 
@@ -77,6 +95,9 @@ hipError_t launch_spinor_import(const Geo& g, const SpinorBuf& dst, const void* 
                                 hipStream_t st);
 hipError_t launch_spinor_export(const Geo& g, const SpinorBuf& src, void* canon, hipStream_t st);
 hipError_t launch_spinor_convert(const Geo& g, const SpinorBuf& src, const SpinorBuf& dst, hipStream_t st);
+// (A_up + i absmu)^-1 and (A_dn - i absmu)^-1 at every even site, from the packed clover (FP64 arithmetic)
+hipError_t launch_eo_inverse(const Geo& g, Prec C, const void* clover, double absmu, void* inv, hipStream_t st);
+inline size_t eo_inverse_bytes(const Geo& g, Prec C) { return (size_t)36 * (g.V / 2) * unit_bytes(C); }
 
 // ---- operator (tm_dirac.hip)
 hipError_t launch_dirac(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_p, Prec clover_p, Prec compute,

@@ -273,6 +273,84 @@ __global__ void __launch_bounds__(kThreads) k_spinor_convert(Geo g, int nsys, co
 
 }  // namespace
 
+// Even-odd site inverses: thread h takes the even site of the pair (2h, 2h+1)
+// (one even and one odd site, since the block x-extent is even), forms the
+// two chiral blocks A_up + i absmu and A_dn - i absmu of the packed clover
+// (A = (m+4) + clover, Hermitian) and inverts each by Gauss-Jordan with
+// partial pivoting in FP64.
+template <class C>
+__global__ void __launch_bounds__(kThreads) k_eo_inverse(Geo g, const void* __restrict__ clover, double absmu,
+                                                         void* inv) {
+    const long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long half = g.V / 2;
+    if (h >= half) return;
+    long long s = 2 * h;
+    int c[4];
+    site_coords(g, s, c);
+    if ((c[0] + c[1] + c[2] + c[3]) & 1) ++s;
+    Clover<double> A;
+    load_clover<double, C>(clover, g.V, s, A);
+    for (int blk = 0; blk < 2; ++blk) {
+        const double* P = A.a + 36 * blk;
+        const double tw = blk == 0 ? absmu : -absmu;
+        cplx<double> M[6][6], X[6][6];
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                M[i][j] = cmk(0.0, 0.0);
+                X[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
+            }
+        for (int i = 0; i < 6; ++i) M[i][i] = cmk(P[i], tw);
+        int k = 6;
+        for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j) {
+                M[i][j] = cmk(P[k], P[k + 1]);
+                M[j][i] = cmk(P[k], -P[k + 1]);
+                k += 2;
+            }
+        for (int col = 0; col < 6; ++col) {
+            int p = col;
+            double best = M[col][col].re * M[col][col].re + M[col][col].im * M[col][col].im;
+            for (int i = col + 1; i < 6; ++i) {
+                const double m2 = M[i][col].re * M[i][col].re + M[i][col].im * M[i][col].im;
+                if (m2 > best) {
+                    best = m2;
+                    p = i;
+                }
+            }
+            if (p != col)
+                for (int j = 0; j < 6; ++j) {
+                    cplx<double> t = M[col][j];
+                    M[col][j] = M[p][j];
+                    M[p][j] = t;
+                    t = X[col][j];
+                    X[col][j] = X[p][j];
+                    X[p][j] = t;
+                }
+            const cplx<double> d = M[col][col];
+            const double dn = 1.0 / (d.re * d.re + d.im * d.im);
+            const cplx<double> di = cmk(d.re * dn, -d.im * dn);
+            for (int j = 0; j < 6; ++j) {
+                M[col][j] = di * M[col][j];
+                X[col][j] = di * X[col][j];
+            }
+            for (int i = 0; i < 6; ++i) {
+                if (i == col) continue;
+                const cplx<double> f = M[i][col];
+                for (int j = 0; j < 6; ++j) {
+                    M[i][j] = M[i][j] - f * M[col][j];
+                    X[i][j] = X[i][j] - f * X[col][j];
+                }
+            }
+        }
+        for (int u = 0; u < 18; ++u) {
+            const int e0 = 2 * u, e1 = 2 * u + 1;
+            const double w[4] = {X[e0 / 6][e0 % 6].re, X[e0 / 6][e0 % 6].im, X[e1 / 6][e1 % 6].re,
+                                 X[e1 / 6][e1 % 6].im};
+            Unit<C>::store(inv, (size_t)(18 * blk + u) * half + h, w);
+        }
+    }
+}
+
 #define TM_DISPATCH_PREC(P, T, ...)                  \
     switch (P) {                                     \
         case P_F64: { typedef double T; __VA_ARGS__; break; } \
@@ -317,6 +395,15 @@ hipError_t launch_spinor_convert(const Geo& g, const SpinorBuf& src, const Spino
                      TM_DISPATCH_PREC(dst.prec, To,
                                       hipLaunchKernelGGL((k_spinor_convert<Ti, To>), grid, dim3(kThreads), 0, st, g,
                                                          src.nsys, src.data, src.scale, dst.data, dst.scale)));
+    return hipGetLastError();
+}
+
+hipError_t launch_eo_inverse(const Geo& g, Prec C, const void* clover, double absmu, void* inv, hipStream_t st) {
+    if (C != P_F64 && C != P_F32) return hipErrorInvalidValue;
+    const long long half = g.V / 2;
+    const unsigned nb = (unsigned)((half + kThreads - 1) / kThreads);
+    TM_DISPATCH_PREC(C, T, hipLaunchKernelGGL(k_eo_inverse<T>, dim3(nb > 0 ? nb : 1), dim3(kThreads), 0, st, g,
+                                              clover, absmu, inv));
     return hipGetLastError();
 }
 

@@ -100,18 +100,22 @@ __device__ inline void lds_get(const R* sh, int stride, int l, Spinor<R>& p) {
     for (int i = 0; i < 12; ++i) p.v[i] = cmk(sh[(2 * i) * stride + l], sh[(2 * i + 1) * stride + l]);
 }
 
-template <class S, class G, class C, class R, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Geo& g = a.g;
-    const int Vb = g.Vb;
-    const int l = threadIdx.x;
-    const int nt = blockDim.x;
-    const bool active = l < Vb;
-    R* sh = reinterpret_cast<R*>(smem_raw);
-    R* red = sh + 24 * nt;
+// Per-thread geometry of the generic kernel: the thread's site, its
+// neighbours as local indices inside the block (-1 when outside) or global
+// sites outside it, the antiperiodic signs, and the site parity.
+template <class R>
+struct GenSite {
+    long long s, s0;  // site, first site of the block
+    int nlf[4], nlb[4];
+    long long ngf[4], ngb[4];
+    R sgf[4], sgb[4];
+    int parity;  // (t + z + y + x) mod 2 of the global coordinates
+};
 
-    // ---- which block: the blockIdx.x-th block of this colour
+// The blockIdx.x-th block of colour `colour`, thread l.
+template <class R>
+__device__ inline void gen_site_setup(const Geo& g, int colour, int l, bool active, GenSite<R>& t) {
+    const int Vb = g.Vb;
     const int half3 = g.nb[3] >> 1;
     int j = blockIdx.x;
     const int k3 = j % half3;
@@ -120,18 +124,18 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
     j /= g.nb[2];
     const int B1 = j % g.nb[1];
     const int B0 = j / g.nb[1];
-    const int B3 = 2 * k3 + ((a.colour + B0 + B1 + B2) & 1);
+    const int B3 = 2 * k3 + ((colour + B0 + B1 + B2) & 1);
     const int Bc[4] = {B0, B1, B2, B3};
     const long long blk = (((long long)B0 * g.nb[1] + B1) * g.nb[2] + B2) * g.nb[3] + B3;
-    const long long s = blk * Vb + (active ? l : 0);
+    t.s0 = blk * Vb;
+    t.s = t.s0 + (active ? l : 0);
 
-    // ---- neighbours: local index inside the block, or the global site outside it
     int Lc[4];
     {
-        int t = active ? l : 0;
+        int u = active ? l : 0;
         for (int ax = 3; ax >= 0; --ax) {
-            Lc[ax] = t % g.lb[ax];
-            t /= g.lb[ax];
+            Lc[ax] = u % g.lb[ax];
+            u /= g.lb[ax];
         }
     }
     int lstride[4];
@@ -139,44 +143,138 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
     lstride[2] = g.lb[3];
     lstride[1] = g.lb[3] * g.lb[2];
     lstride[0] = g.lb[3] * g.lb[2] * g.lb[1];
-    int nlf[4], nlb[4];
-    long long ngf[4], ngb[4];
-    R sgf[4], sgb[4];
+    int c[4];
+    for (int q = 0; q < 4; ++q) c[q] = Bc[q] * g.lb[q] + Lc[q];
+    t.parity = (c[0] + c[1] + c[2] + c[3]) & 1;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const int ax = axis_of(mu);
-        int c[4];
-        for (int q = 0; q < 4; ++q) c[q] = Bc[q] * g.lb[q] + Lc[q];
-        sgf[mu] = sgb[mu] = (R)1;
+        t.sgf[mu] = t.sgb[mu] = (R)1;
         if (Lc[ax] + 1 < g.lb[ax]) {
-            nlf[mu] = l + lstride[ax];
-            ngf[mu] = 0;
+            t.nlf[mu] = l + lstride[ax];
+            t.ngf[mu] = 0;
         } else {
-            nlf[mu] = -1;
+            t.nlf[mu] = -1;
             int n[4] = {c[0], c[1], c[2], c[3]};
             if (++n[ax] == g.d[ax]) {
                 n[ax] = 0;
-                if (mu == 0 && g.antiperiodic_t) sgf[mu] = (R)-1;
+                if (mu == 0 && g.antiperiodic_t) t.sgf[mu] = (R)-1;
             }
-            ngf[mu] = coords_site(g, n);
+            t.ngf[mu] = coords_site(g, n);
         }
         if (Lc[ax] > 0) {
-            nlb[mu] = l - lstride[ax];
-            ngb[mu] = 0;
+            t.nlb[mu] = l - lstride[ax];
+            t.ngb[mu] = 0;
         } else {
-            nlb[mu] = -1;
+            t.nlb[mu] = -1;
             int n[4] = {c[0], c[1], c[2], c[3]};
             if (--n[ax] < 0) {
                 n[ax] = g.d[ax] - 1;
-                if (mu == 0 && g.antiperiodic_t) sgb[mu] = (R)-1;
+                if (mu == 0 && g.antiperiodic_t) t.sgb[mu] = (R)-1;
             }
-            ngb[mu] = coords_site(g, n);
+            t.ngb[mu] = coords_site(g, n);
         }
     }
-    const long long s0 = blk * Vb;
+}
+
+// r = b - D x on the block for one system: diagonal and in-block hops from
+// LDS, hops from the neighbouring blocks straight from memory.  When x is
+// still zero on this colour only the halo hops remain; xv returns the old x
+// (zero when it was not read).  Contains barriers: every thread calls it.
+template <class S, class G, class R>
+__device__ inline void gen_residual(const SapArgs& a, const GenSite<R>& t, const Clover<R>& A, R mu_tw, bool active,
+                                    R* sh, int nt, int l, const void* bb, const float* bsc, const void* xx,
+                                    const float* xsc, Spinor<R>& r, Spinor<R>& xv) {
+    const Geo& g = a.g;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) xv.v[i] = cmk<R>(0, 0);
+    if (active) load_spinor<R, S>(bb, bsc, g.V, t.s, r);
+    if (a.own_zero && a.halo_zero) return;
+    const bool own = !a.own_zero;
+    if (own) {
+        if (active) {
+            load_spinor<R, S>(xx, xsc, g.V, t.s, xv);
+            lds_put(sh, nt, l, xv);
+        }
+        __syncthreads();
+    }
+    if (active) {
+        Spinor<R> acc, dx;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) acc.v[i] = cmk<R>(0, 0);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            Link<R> Lk;
+            Spinor<R> p;
+            if (t.nlf[mu] < 0 || own) {
+                load_link<R, G>(a.links, g.V, t.s, mu, Lk);
+                if (t.nlf[mu] >= 0)
+                    lds_get(sh, nt, t.nlf[mu], p);
+                else
+                    load_spinor<R, S>(xx, xsc, g.V, t.ngf[mu], p);
+                hop_forward(mu, Lk, p, t.sgf[mu], acc);
+            }
+            if (t.nlb[mu] >= 0) {
+                if (own) {
+                    lds_get(sh, nt, t.nlb[mu], p);
+                    load_link<R, G>(a.links, g.V, t.s0 + t.nlb[mu], mu, Lk);
+                    hop_backward(mu, Lk, p, t.sgb[mu], acc);
+                }
+            } else {
+                load_spinor<R, S>(xx, xsc, g.V, t.ngb[mu], p);
+                load_link<R, G>(a.links, g.V, t.ngb[mu], mu, Lk);
+                hop_backward(mu, Lk, p, t.sgb[mu], acc);
+            }
+        }
+        if (own) {
+            clover_apply(A, mu_tw, xv, dx);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) dx.v[i] = cmk<R>(0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] - (dx.v[i] - (R)0.5 * acc.v[i]);
+    }
+    if (own) __syncthreads();
+}
+
+// acc = sum over in-block neighbours of the hop terms (before the factor
+// -1/2) of the block vector held in LDS.
+template <class G, class R>
+__device__ inline void gen_block_hops(const SapArgs& a, const GenSite<R>& t, const R* sh, int nt, Spinor<R>& acc) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc.v[i] = cmk<R>(0, 0);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        Link<R> Lk;
+        Spinor<R> p;
+        if (t.nlf[mu] >= 0) {
+            load_link<R, G>(a.links, a.g.V, t.s, mu, Lk);
+            lds_get(sh, nt, t.nlf[mu], p);
+            hop_forward(mu, Lk, p, t.sgf[mu], acc);
+        }
+        if (t.nlb[mu] >= 0) {
+            load_link<R, G>(a.links, a.g.V, t.s0 + t.nlb[mu], mu, Lk);
+            lds_get(sh, nt, t.nlb[mu], p);
+            hop_backward(mu, Lk, p, t.sgb[mu], acc);
+        }
+    }
+}
+
+template <class S, class G, class C, class R, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Geo& g = a.g;
+    const int l = threadIdx.x;
+    const int nt = blockDim.x;
+    const bool active = l < g.Vb;
+    R* sh = reinterpret_cast<R*>(smem_raw);
+    R* red = sh + 24 * nt;
+    GenSite<R> t;
+    gen_site_setup(g, a.colour, l, active, t);
 
     Clover<R> A;
-    if (active) load_clover<R, C>(a.clover, g.V, s, A);
+    if (active) load_clover<R, C>(a.clover, g.V, t.s, A);
 
     const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
     const int sys_begin = blockIdx.y * a.sys_tile;
@@ -190,60 +288,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
         float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
 
         Spinor<R> r, xv;
-#pragma unroll
-        for (int i = 0; i < 12; ++i) xv.v[i] = cmk<R>(0, 0);
-        if (active) load_spinor<R, S>(bb, bsc, g.V, s, r);
-        if (!(a.own_zero && a.halo_zero)) {
-            // r = b - D x on the block: diagonal and in-block hops from LDS,
-            // hops from the neighbouring blocks straight from memory.  When x
-            // is still zero on this colour only the halo hops remain.
-            const bool own = !a.own_zero;
-            if (own) {
-                if (active) {
-                    load_spinor<R, S>(xx, xsc, g.V, s, xv);
-                    lds_put(sh, nt, l, xv);
-                }
-                __syncthreads();
-            }
-            if (active) {
-                Spinor<R> acc, dx;
-#pragma unroll
-                for (int i = 0; i < 12; ++i) acc.v[i] = cmk<R>(0, 0);
-#pragma unroll
-                for (int mu = 0; mu < 4; ++mu) {
-                    Link<R> Lk;
-                    Spinor<R> p;
-                    if (nlf[mu] < 0 || own) {
-                        load_link<R, G>(a.links, g.V, s, mu, Lk);
-                        if (nlf[mu] >= 0)
-                            lds_get(sh, nt, nlf[mu], p);
-                        else
-                            load_spinor<R, S>(xx, xsc, g.V, ngf[mu], p);
-                        hop_forward(mu, Lk, p, sgf[mu], acc);
-                    }
-                    if (nlb[mu] >= 0) {
-                        if (own) {
-                            lds_get(sh, nt, nlb[mu], p);
-                            load_link<R, G>(a.links, g.V, s0 + nlb[mu], mu, Lk);
-                            hop_backward(mu, Lk, p, sgb[mu], acc);
-                        }
-                    } else {
-                        load_spinor<R, S>(xx, xsc, g.V, ngb[mu], p);
-                        load_link<R, G>(a.links, g.V, ngb[mu], mu, Lk);
-                        hop_backward(mu, Lk, p, sgb[mu], acc);
-                    }
-                }
-                if (own) {
-                    clover_apply(A, mu_tw, xv, dx);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 12; ++i) dx.v[i] = cmk<R>(0, 0);
-                }
-#pragma unroll
-                for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] - (dx.v[i] - (R)0.5 * acc.v[i]);
-            }
-            if (own) __syncthreads();
-        }
+        gen_residual<S, G, R>(a, t, A, mu_tw, active, sh, nt, l, bb, bsc, xx, xsc, r, xv);
 
         // ---- minimal residual on D_BB from e = 0
         Spinor<R> e, rho = r;
@@ -256,23 +301,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
             R qr_re = 0, qr_im = 0, qq = 0;
             if (active) {
                 Spinor<R> acc;
-#pragma unroll
-                for (int i = 0; i < 12; ++i) acc.v[i] = cmk<R>(0, 0);
-#pragma unroll
-                for (int mu = 0; mu < 4; ++mu) {
-                    Link<R> Lk;
-                    Spinor<R> p;
-                    if (nlf[mu] >= 0) {
-                        load_link<R, G>(a.links, g.V, s, mu, Lk);
-                        lds_get(sh, nt, nlf[mu], p);
-                        hop_forward(mu, Lk, p, sgf[mu], acc);
-                    }
-                    if (nlb[mu] >= 0) {
-                        load_link<R, G>(a.links, g.V, s0 + nlb[mu], mu, Lk);
-                        lds_get(sh, nt, nlb[mu], p);
-                        hop_backward(mu, Lk, p, sgb[mu], acc);
-                    }
-                }
+                gen_block_hops<G, R>(a, t, sh, nt, acc);
                 clover_apply(A, mu_tw, rho, q);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
@@ -296,8 +325,157 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
         if (active) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) e.v[i] = e.v[i] + xv.v[i];
-            store_spinor<R, S>(xx, xsc, g.V, s, e);
+            store_spinor<R, S>(xx, xsc, g.V, t.s, e);
         }
+    }
+}
+
+// out = D_ee^-1 in at an even site: the two 6x6 chiral-block inverses of one
+// inverse set (h = s / 2); adj uses their adjoints (the inverses for -mu).
+template <class C, class R>
+__device__ inline void eo_inverse_apply(const void* inv, long long half, long long h, bool adj, const Spinor<R>& in,
+                                        Spinor<R>& out) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) out.v[i] = cmk<R>(0, 0);
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const cplx<R>* v = in.v + 6 * blk;
+        cplx<R>* o = out.v + 6 * blk;
+#pragma unroll
+        for (int u = 0; u < 18; ++u) {
+            R w[4];
+            Unit<C>::load(inv, (size_t)(18 * blk + u) * half + h, w);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int e = 2 * u + k, i = e / 6, j = e % 6;
+                const cplx<R> m = cmk(w[2 * k], w[2 * k + 1]);
+                if (adj)
+                    o[j] = cjmad(m, v[i], o[j]);
+                else
+                    o[i] = cmad(m, v[j], o[i]);
+            }
+        }
+    }
+}
+
+// Half-sweep with even-odd preconditioned block solves (section 2.5): the
+// block system D_BB e = r is reduced to its odd sites,
+//   rhat_o = r_o - D_oe D_ee^-1 r_e,  Dhat = D_oo - D_oe D_ee^-1 D_eo,
+// MR runs on Dhat e_o = rhat_o from e_o = 0, and e_e = D_ee^-1 (r_e - D_eo e_o).
+// D_oe and D_eo are the in-block hops (factor -1/2 included), D_ee and D_oo
+// the site-diagonal parts; parity from the global coordinates.
+template <class S, class G, class C, class R, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Geo& g = a.g;
+    const int l = threadIdx.x;
+    const int nt = blockDim.x;
+    const bool active = l < g.Vb;
+    R* sh = reinterpret_cast<R*>(smem_raw);
+    R* red = sh + 24 * nt;
+    GenSite<R> t;
+    gen_site_setup(g, a.colour, l, active, t);
+    const bool odd = active && t.parity == 1;
+    const bool even = active && t.parity == 0;
+    const long long half = g.V / 2, h = t.s >> 1;
+
+    Clover<R> A;  // every site for the residual; odd sites also for D_oo
+    if (active) load_clover<R, C>(a.clover, g.V, t.s, A);
+
+    const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
+    const int sys_begin = blockIdx.y * a.sys_tile;
+    const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
+
+    for (int sys = sys_begin; sys < sys_end; ++sys) {
+        const R mu_tw = (R)a.mu[sys];
+        const void* inv = a.eo_inv[a.eo_sel[sys]];
+        const bool adj = (a.eo_adj >> sys) & 1ull;
+        const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
+        void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
+        const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
+        float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
+
+        Spinor<R> r, xv, tv, acc;
+        gen_residual<S, G, R>(a, t, A, mu_tw, active, sh, nt, l, bb, bsc, xx, xsc, r, xv);
+
+        // rhat_o = r_o - D_oe (D_ee^-1 r_e)
+#pragma unroll
+        for (int i = 0; i < 12; ++i) tv.v[i] = cmk<R>(0, 0);
+        if (even) eo_inverse_apply<C, R>(inv, half, h, adj, r, tv);
+        if (active) lds_put(sh, nt, l, tv);
+        __syncthreads();
+        Spinor<R> rho, e;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            rho.v[i] = cmk<R>(0, 0);
+            e.v[i] = cmk<R>(0, 0);
+        }
+        if (odd) {
+            gen_block_hops<G, R>(a, t, sh, nt, acc);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) rho.v[i] = r.v[i] + (R)0.5 * acc.v[i];
+        }
+
+        // MR on Dhat over the odd sites
+        for (int it = 0; it < a.mr_iters; ++it) {
+            __syncthreads();
+            if (active) lds_put(sh, nt, l, rho);
+            __syncthreads();
+            // even: t_e = D_ee^-1 D_eo rho_o
+#pragma unroll
+            for (int i = 0; i < 12; ++i) tv.v[i] = cmk<R>(0, 0);
+            if (even) {
+                gen_block_hops<G, R>(a, t, sh, nt, acc);
+                Spinor<R> u;
+#pragma unroll
+                for (int i = 0; i < 12; ++i) u.v[i] = (R)-0.5 * acc.v[i];
+                eo_inverse_apply<C, R>(inv, half, h, adj, u, tv);
+            }
+            __syncthreads();
+            if (active) lds_put(sh, nt, l, tv);
+            __syncthreads();
+            // odd: q_o = D_oo rho_o - D_oe t_e
+            Spinor<R> q;
+            R qr_re = 0, qr_im = 0, qq = 0;
+            if (odd) {
+                gen_block_hops<G, R>(a, t, sh, nt, acc);
+                clover_apply(A, mu_tw, rho, q);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    q.v[i] = q.v[i] + (R)0.5 * acc.v[i];
+                    qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
+                    qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
+                    qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
+                }
+            }
+            block_sum3(red, qr_re, qr_im, qq);
+            if (odd && qq > (R)0) {
+                const cplx<R> alpha = cmk(qr_re / qq, qr_im / qq);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    e.v[i] = cmad(alpha, rho.v[i], e.v[i]);
+                    rho.v[i] = rho.v[i] - alpha * q.v[i];
+                }
+            }
+        }
+
+        // e_e = D_ee^-1 (r_e - D_eo e_o)
+        __syncthreads();
+        if (active) lds_put(sh, nt, l, e);
+        __syncthreads();
+        if (even) {
+            gen_block_hops<G, R>(a, t, sh, nt, acc);
+            Spinor<R> v;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) v.v[i] = r.v[i] + (R)0.5 * acc.v[i];
+            eo_inverse_apply<C, R>(inv, half, h, adj, v, e);
+        }
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) e.v[i] = e.v[i] + xv.v[i];
+            store_spinor<R, S>(xx, xsc, g.V, t.s, e);
+        }
+        __syncthreads();
     }
 }
 
@@ -962,6 +1140,19 @@ hipError_t run(const SapArgs& a, hipStream_t st) {
     if (lds > 65536) {
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
+    }
+    if (a.eo) {
+        const void* fe = nt <= 256 ? reinterpret_cast<const void*>(&k_sap_half_eo<S, G, C, R, 256>)
+                                   : reinterpret_cast<const void*>(&k_sap_half_eo<S, G, C, R, 1024>);
+        if (lds > 65536) {
+            e = hipFuncSetAttribute(fe, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        if (nt <= 256)
+            hipLaunchKernelGGL((k_sap_half_eo<S, G, C, R, 256>), grid, dim3(nt), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_sap_half_eo<S, G, C, R, 1024>), grid, dim3(nt), lds, st, a);
+        return hipGetLastError();
     }
     if constexpr (sizeof(R) == 4) {
         if (nt <= kV2 && !sap_v1_forced()) {

@@ -1,6 +1,6 @@
 // Flexible GMRES right-preconditioned by SAP (section 2.5), the mixed-
 // precision defect-correction form (section 3.1: an FP64 residual loop around
-// FP32 FGMRES solves to a relative 1e-6), and the SAP block-shape tuner.
+// FP32 FGMRES solves to a relative 1e-6).
 //
 // All systems of a group advance together; each keeps its own Hessenberg
 // matrix, Givens rotations and Krylov dimension.  A system whose residual
@@ -67,6 +67,8 @@ struct Ctx {
     int nsys;
     double mu[kMaxSys];
     int n_cycles, mr_iters;
+    int sys_tile;  // SAP systems per workgroup (0 = all)
+    bool eo;       // even-odd preconditioned SAP block solves
     const GaugeDev* op;  // operator for w = D z and residuals
     Prec op_compute;
     const GaugeDev* sap;  // smoother gauge
@@ -216,7 +218,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             }
             // z_j = SAP(v_j) from a zero guess; w = D z_j
             if ((rc = hcheck(hipEventRecord(c.ev[0], c.st), "event"))) return rc;
-            if ((rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, 0, c.st))) return rc;
+            if ((rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, c.sys_tile, c.st, c.eo))) return rc;
             if ((rc = hcheck(hipEventRecord(c.ev[1], c.st), "event"))) return rc;
             c.sap_cycles += c.n_cycles;
             c.sap_sys_cycles += (long long)c.n_cycles * ns;
@@ -409,9 +411,13 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     const bool dc = so->form == TM_SOLVE_DEFECT_CORRECTION;
     if (dc && sp == P_F64) return fail(TM_ERR_PREC, "defect correction needs FP32/FP16/BF16 smoother storage");
     if (dc && !(so->inner_tol > 0 && so->inner_tol < 1)) return fail(TM_ERR_ARG, "inner_tol must be in (0, 1)");
-    int bd[4];
+    // block_dims all zero: the tuned shape for this problem if one is cached, else 4^4
+    int bd[4], tuned_tile = 0;
     const bool bd_given = so->block_dims[0] | so->block_dims[1] | so->block_dims[2] | so->block_dims[3];
-    for (int a = 0; a < 4; ++a) bd[a] = bd_given ? so->block_dims[a] : 4;
+    if (bd_given)
+        for (int a = 0; a < 4; ++a) bd[a] = so->block_dims[a];
+    else if (!tune_lookup(geom, opts->storage, so->n_cycles, so->mr_iters, opts->sap_eo, bd, &tuned_tile))
+        for (int a = 0; a < 4; ++a) bd[a] = 4;
     int tile[4];
     if ((rc = check_sap_blocks(geom, bd, tile))) return rc;
     if (!sap_supported(sp, sp, clover_prec_for(sp), sp == P_F64 ? P_F64 : P_F32))
@@ -446,6 +452,8 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     c.g = g;
     c.n_cycles = so->n_cycles;
     c.mr_iters = so->mr_iters;
+    c.sys_tile = opts->sys_tile > 0 ? opts->sys_tile : tuned_tile;
+    c.eo = opts->sap_eo != 0;
     c.sap = gs;
     c.vp = vp;
     c.sp = sp;
@@ -563,10 +571,6 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     rep.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     if (report) *report = rep;
     return all_conv ? TM_OK : TM_NOT_CONVERGED;
-}
-
-int tm_autotune_sap(const tm_geom*, const void*, double, double, int, int, const tm_opts*, int*) {
-    return fail(TM_ERR_ARG, "tm_autotune_sap: not built yet");
 }
 
 }  // extern "C"
