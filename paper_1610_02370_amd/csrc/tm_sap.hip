@@ -64,6 +64,15 @@ __device__ inline float wave_sum<float>(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
+// Smallest normal number.  An MR step is taken only when <q,q> is at least
+// this: a block whose residual has (nearly) vanished keeps e, and neither the
+// hardware reciprocal nor a flushed division meets a subnormal divisor
+// (which would turn the step length into inf or NaN).
+template <class R>
+__device__ constexpr R min_normal() {
+    return sizeof(R) == 8 ? (R)2.2250738585072014e-308 : (R)1.17549435e-38f;
+}
+
 // Sum of three values over the workgroup; every thread gets the result.
 template <class R>
 __device__ inline void block_sum3(R* red, R& a, R& b, R& c) {
@@ -312,7 +321,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
                 }
             }
             block_sum3(red, qr_re, qr_im, qq);
-            if (active && qq > (R)0) {
+            if (active && qq >= min_normal<R>()) {
                 const cplx<R> alpha = cmk(qr_re / qq, qr_im / qq);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
@@ -449,7 +458,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
                 }
             }
             block_sum3(red, qr_re, qr_im, qq);
-            if (odd && qq > (R)0) {
+            if (odd && qq >= min_normal<R>()) {
                 const cplx<R> alpha = cmk(qr_re / qq, qr_im / qq);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
@@ -897,7 +906,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
                 }
             }
             block_sum3(sm.red, qr_re, qr_im, qq);
-            if (active && qq > 0.f) {
+            if (active && qq >= min_normal<float>()) {
                 // with q = -2 D_BB rho: rho -= a q and e += -2 a rho, a = <q,rho>/<q,q>
                 const float inv = __builtin_amdgcn_rcpf(qq);
                 const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
@@ -1109,7 +1118,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
                 qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
             }
             block_sum3(sm.red, qr_re, qr_im, qq);
-            if (qq > 0.f) {
+            if (qq >= min_normal<float>()) {
                 const float inv = __builtin_amdgcn_rcpf(qq);
                 const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
                 const cplx<float> beta = cmk(-2.f * alpha.re, -2.f * alpha.im);

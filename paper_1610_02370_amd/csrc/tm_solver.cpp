@@ -31,6 +31,17 @@ namespace {
 
 typedef std::complex<double> zc;
 
+// TM_VERBOSE=1: one progress line per Arnoldi step and per outer
+// defect-correction step on stderr.
+bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("TM_VERBOSE");
+        v = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
 struct Pinned {
     double* p = nullptr;
     size_t n = 0;
@@ -157,6 +168,7 @@ int residual(Ctx& c, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, cons
     for (int k = 0; k < c.nsys; ++k) {
         rn2[k] = c.hstage[2 * k];
         bn2[k] = c.hstage[2 * k + 1];
+        if (!std::isfinite(rn2[k])) return fail(TM_ERR_NONFINITE, "non-finite residual of system %d", k);
     }
     return TM_OK;
 }
@@ -249,6 +261,12 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             float ms = 0;
             if (hipEventElapsedTime(&ms, c.ev[0], c.ev[1]) == hipSuccess) c.t_sap += ms * 1e-3;
             ++steps;
+            // a non-finite Hessenberg entry (an overflow in the preconditioner
+            // or the operator) would otherwise read as a breakdown
+            for (size_t i = 0; i < 2 * nh + (size_t)ns; ++i)
+                if (!std::isfinite(c.hstage[i]))
+                    return fail(TM_ERR_NONFINITE, "non-finite value in the Arnoldi step %d (preconditioned vector)",
+                                steps);
             bool all_frozen = true;
             std::vector<double> inv(ns, 0.0);
             for (int k = 0; k < ns; ++k) {
@@ -292,6 +310,18 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                 all_frozen &= (bool)frozen[k];
             }
             jdone = j + 1;
+            if (verbose()) {
+                double worst = 0.0;
+                int active = 0;
+                for (int k = 0; k < ns; ++k) {
+                    const zc* gk = &gv[(size_t)k * (m + 1)];
+                    if (bnorm[k] > 0) worst = std::max(worst, std::abs(gk[kdim[k]]) / bnorm[k]);
+                    active += !frozen[k];
+                }
+                std::fprintf(stderr, "[tm] %s step %d: max residual estimate %.3e, %d of %d systems active, sap %.3f s\n",
+                             c.vp == P_F64 ? "fgmres" : "inner fgmres", steps, worst, active, ns, c.t_sap);
+                std::fflush(stderr);
+            }
             for (int k = 0; k < ns; ++k) c.hinv[k] = inv[k];
             if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st),
                              "copy")))
@@ -534,6 +564,13 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                 }
                 int maxit = 0;
                 for (int k = 0; k < ns; ++k) maxit = std::max(maxit, iters[k]);
+                if (verbose()) {
+                    double worst = 0.0;
+                    for (int k = 0; k < ns; ++k) worst = std::max(worst, rep.true_rel_res[g0 + k]);
+                    std::fprintf(stderr, "[tm] systems %d..%d outer %d: max true residual %.3e after %d iterations\n",
+                                 g0, g0 + ns - 1, outer, worst, maxit);
+                    std::fflush(stderr);
+                }
                 if (done || outer >= so->max_outer || maxit >= so->max_iters) break;
                 // inner FP32 solve of D c = r to inner_tol, then x += c
                 if ((rc = hcheck(launch_spinor_convert(g, rr, r32, st), "convert"))) return rc;

@@ -27,6 +27,8 @@ CASES = [
     ((8, 4, 8, 8), (4, 2, 4, 4), 0.6, 0.1373, [0.0009], 1.5, 1, 4, False),      # 128 sites
     ((8, 8, 4, 16), (4, 4, 2, 8), 0.6, 0.1373, [0.0009], 1.5, 1, 2, False),     # 256 sites, long x
     ((8, 8, 8, 16), (4, 4, 4, 8), 0.5, 0.1373, [0.0009], 1.5, 1, 2, False),     # 512 sites: large groups
+    ((16, 16, 16, 16), (4, 4, 4, 4), 0.6, 0.1373, [0.0009, -0.0009], 1.5, 2, 4, False),  # 4 blocks per axis
+    ((16, 8, 16, 24), (4, 4, 4, 4), 0.6, 0.1373, [0.0009], 1.5, 2, 4, True),   # 4, 2, 4, 6 blocks per axis
 ]
 
 
@@ -88,3 +90,24 @@ def test_sap_error_paths(fields):
         tm.tm_sap_smooth((16, 16, 16, 16), dev(np.zeros((16 ** 4, 4, 3, 3))), dev(b), x, kappa, mus, csw,
                          (8, 8, 8, 4), cyc, mr)
     assert e.value.code == -3  # 2048-site block
+
+
+@pytest.mark.parametrize("prec,bd", [("f32", (4, 4, 4, 4)), ("f32", (4, 4, 2, 4)), ("f16", (4, 4, 4, 4)),
+                                     ("bf16", (4, 4, 4, 4)), ("f32", (4, 4, 4, 8))])
+def test_sap_blocks_with_vanishing_residual(prec, bd):
+    # Far from a point source the block residuals shrink below the smallest
+    # normal FP32 number once squared; such blocks must keep e (a step length
+    # from a subnormal <q,q> is inf or NaN).  One O(1) site, every other
+    # component ~1e-21, so <q,q> ~ 1e-39 in the other blocks.
+    dims, kappa, mu, csw = (8, 8, 8, 16), 0.1373, 0.0009, 1.5
+    U = synth.gauge_field(dims, 0.6, seed=21)
+    b = 1e-21 * synth.gaussian_spinor(dims, 1, seed=121)
+    b[0, 0, 0, 0] = 1.0
+    announce(f"sap vanishing residual prec={prec} block={bd}")
+    x = dev(np.zeros_like(b))
+    tm.tm_sap_smooth(dims, dev(U), dev(b), x, kappa, [mu], csw, bd, 2, 4, storage=prec)
+    got = host(x)[0]
+    assert np.isfinite(got).all()
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), mu, csw)
+    ref = op.sap(b[0], bd, 2, 4).reshape(-1, 4, 3)
+    assert rel_err(got, ref) < TOL[prec]

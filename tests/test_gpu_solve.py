@@ -143,3 +143,24 @@ def test_solver_error_paths(cfg_4444):
     rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(np.zeros_like(b)), x, kappa, [mu], csw, TOL,
                                  block_dims=(2, 2, 2, 2))
     assert rc == 0
+
+
+def test_16x16x16x16_twelve_sources_defect_correction():
+    # the 48^3x96 workload's parameters and solver form on a lattice with
+    # four blocks per axis: 12 point sources, FP32 SAP in defect correction,
+    # restart 8
+    dims, kappa, mu, csw = (16, 16, 16, 16), 0.1373, 0.0009, 1.5
+    U = synth.gauge_field(dims, 0.6, seed=16)
+    b = synth.all_point_sources(dims)
+    announce("solve 16^4 twelve sources defect correction f32")
+    x = dev(np.zeros_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu] * 12, csw, TOL, storage="f32",
+                                 form="defect_correction", restart=8, n_cycles=4, mr_iters=4,
+                                 block_dims=(4, 4, 4, 4), max_iters=400)
+    assert rc == 0, rep
+    assert rep["iters"] < 100, rep
+    xg = host(x)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), mu, csw)
+    for k in (0, 4, 11):
+        r = b[k].reshape(-1, 4, 3) - op.apply(xg[k])
+        assert np.linalg.norm(r) / np.linalg.norm(b[k]) <= TOL * RES_SLACK
