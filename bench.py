@@ -115,6 +115,12 @@ def sap_source_hash() -> str:
     return h.hexdigest()
 
 
+# rocprofv3 counter summaries (FETCH_SIZE / WRITE_SIZE) by (kernel, workload)
+TRAFFIC_SUMMARIES = {
+    ("k_sap_half_44", "48^3x96_12rhs_f32"): "sap_half_44_48cube_x96_12rhs_f32_traffic.txt",
+}
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of the SAP kernel from the committed rocprofv3 counter summary.
 
@@ -123,7 +129,9 @@ def measured_traffic(kernel: str, workload: str):
     known size gives for the same counter, and the hash of the kernel's
     sources when the counters were taken; a changed kernel gives None.
     """
-    name = f"{kernel}_{workload.replace('^', '')}_traffic.txt"
+    name = TRAFFIC_SUMMARIES.get((kernel, workload))
+    if name is None:
+        return None
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
