@@ -198,6 +198,13 @@ TM_API size_t tm_spinor_bytes(const tm_geom* geom, const tm_opts* opts);
 TM_API int tm_spinor_import(const tm_geom* geom, const void* canon, void* internal, const tm_opts* opts);
 /* internal -> canonical complex128 */
 TM_API int tm_spinor_export(const tm_geom* geom, const void* internal, void* canon, const tm_opts* opts);
+/* As tm_spinor_import / tm_spinor_export for systems first .. first+count-1 of an internal buffer
+ * that holds geom->nsys systems; canon holds `count` systems [count][V][4][3].  Lets a caller fill or
+ * read a large resident batch one system at a time.  TM_ERR_ARG when the range leaves 0..nsys-1. */
+TM_API int tm_spinor_import_range(const tm_geom* geom, const void* canon, void* internal, int first, int count,
+                                  const tm_opts* opts);
+TM_API int tm_spinor_export_range(const tm_geom* geom, const void* internal, void* canon, int first, int count,
+                                  const tm_opts* opts);
 
 /* --------------------------------------------------------------- tuning */
 /*

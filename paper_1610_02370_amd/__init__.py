@@ -30,7 +30,7 @@ MAX_SYS = 64
 EXPORTS = (
     "tm_opts_default", "tm_init", "tm_finalize", "tm_last_error", "tm_gauge_release", "tm_dirac_apply",
     "tm_sap_smooth", "tm_solver_opts_default", "tm_fgmres_solve", "tm_spinor_bytes", "tm_spinor_import",
-    "tm_spinor_export", "tm_autotune_sap",
+    "tm_spinor_export", "tm_spinor_import_range", "tm_spinor_export_range", "tm_autotune_sap",
 )
 
 
@@ -93,6 +93,8 @@ def lib():
         L.tm_spinor_bytes.restype = ctypes.c_size_t
         L.tm_spinor_import.argtypes = [P(Geom), vp, vp, P(Opts)]
         L.tm_spinor_export.argtypes = [P(Geom), vp, vp, P(Opts)]
+        L.tm_spinor_import_range.argtypes = [P(Geom), vp, vp, ctypes.c_int, ctypes.c_int, P(Opts)]
+        L.tm_spinor_export_range.argtypes = [P(Geom), vp, vp, ctypes.c_int, ctypes.c_int, P(Opts)]
         L.tm_autotune_sap.argtypes = [P(Geom), vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       P(Opts), P(ctypes.c_int), P(ctypes.c_int)]
         _lib = L
@@ -253,6 +255,26 @@ def tm_spinor_export(dims, internal, canon, *, storage: str, layout_block=None, 
     g = make_geom(dims, [0.0] * nsys)
     o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
     _check(lib().tm_spinor_export(ctypes.byref(g), _ptr(internal), _canon(canon, "canon"), ctypes.byref(o)))
+    return canon
+
+
+def tm_spinor_import_range(dims, canon, internal, nsys: int, first: int, *, storage: str, layout_block=None,
+                           stream=None):
+    """canon ([count][V][4][3]) -> systems first..first+count-1 of an internal buffer of nsys systems."""
+    g = make_geom(dims, [0.0] * nsys)
+    o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
+    _check(lib().tm_spinor_import_range(ctypes.byref(g), _canon(canon, "canon"), _ptr(internal), int(first),
+                                        int(canon.shape[0]), ctypes.byref(o)))
+    return internal
+
+
+def tm_spinor_export_range(dims, internal, canon, nsys: int, first: int, *, storage: str, layout_block=None,
+                           stream=None):
+    """Systems first..first+count-1 of an internal buffer of nsys systems -> canon ([count][V][4][3])."""
+    g = make_geom(dims, [0.0] * nsys)
+    o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
+    _check(lib().tm_spinor_export_range(ctypes.byref(g), _ptr(internal), _canon(canon, "canon"), int(first),
+                                        int(canon.shape[0]), ctypes.byref(o)))
     return canon
 
 

@@ -469,6 +469,55 @@ int tm_spinor_export(const tm_geom* geom, const void* internal, void* canon, con
     return TM_OK;
 }
 
+// View of systems [first, first + count) of an internal buffer of geom->nsys systems.
+static int internal_range(const tm_geom* geom, const void* internal, int first, int count, const tm_opts* opts,
+                          Geo& g, SpinorBuf& view) {
+    int rc;
+    if ((rc = check_geom(geom)) || (rc = check_opts(opts))) return rc;
+    if (!internal) return fail(TM_ERR_ARG, "null buffer");
+    if (first < 0 || count < 1 || first + count > geom->nsys)
+        return fail(TM_ERR_ARG, "systems %d..%d outside 0..%d", first, first + count - 1, geom->nsys - 1);
+    int tile[4];
+    if ((rc = choose_tile(geom, opts->layout_block, tile))) return rc;
+    g = make_geo(geom, tile);
+    const Prec p = (Prec)opts->storage;
+    SpinorBuf all = wrap_internal(const_cast<void*>(internal), g, geom->nsys, p);
+    view = all;
+    view.data = static_cast<char*>(all.data) + (size_t)first * 6 * g.V * unit_bytes(p);
+    view.scale = all.scale ? all.scale + (size_t)first * g.V : nullptr;
+    view.nsys = count;
+    return TM_OK;
+}
+
+int tm_spinor_import_range(const tm_geom* geom, const void* canon, void* internal, int first, int count,
+                           const tm_opts* opts) {
+    int rc;
+    Geo g;
+    SpinorBuf dst;
+    if ((rc = internal_range(geom, internal, first, count, opts, g, dst))) return rc;
+    if (!canon) return fail(TM_ERR_ARG, "null buffer");
+    DeviceState* ds = device_state(&rc);
+    if (!ds) return rc;
+    hipError_t h = ds->stats.ensure(256);
+    if (h != hipSuccess) return hip_fail(h, "stats");
+    if ((h = launch_spinor_import(g, dst, canon, (unsigned*)ds->stats.ptr + 2, (hipStream_t)opts->stream)) !=
+        hipSuccess)
+        return hip_fail(h, "spinor import");
+    return TM_OK;
+}
+
+int tm_spinor_export_range(const tm_geom* geom, const void* internal, void* canon, int first, int count,
+                           const tm_opts* opts) {
+    int rc;
+    Geo g;
+    SpinorBuf src;
+    if ((rc = internal_range(geom, internal, first, count, opts, g, src))) return rc;
+    if (!canon) return fail(TM_ERR_ARG, "null buffer");
+    hipError_t h = launch_spinor_export(g, src, canon, (hipStream_t)opts->stream);
+    if (h != hipSuccess) return hip_fail(h, "spinor export");
+    return TM_OK;
+}
+
 int tm_dirac_apply(const tm_geom* geom, const void* U, const void* psi, void* out, double kappa, double c_sw,
                    const tm_opts* opts) {
     int rc;
