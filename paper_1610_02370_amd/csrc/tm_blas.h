@@ -23,13 +23,19 @@ inline VecRef vec_ref(const SpinorBuf& b, long long V) {
 int blas_blocks(long long V);
 int blas_max_vec();
 
-// Gram-Schmidt pass over basis vectors 0..nvec-1 (vector i at basis.data + i*vec_stride, FP64 or FP32, no scales):
-//   mode 0: out[sys][i] = <v_i, w>
-//   mode 1: w -= sum_i coef[sys][i] v_i, then out[sys][i] = <v_i, w>
-//   mode 2: w -= sum_i coef[sys][i] v_i, then out[sys] = ||w||^2
-// complex values as (re, im) pairs; accumulate != 0 adds to out.
+// Gram-Schmidt passes over basis vectors 0..nvec-1 (vector i at basis.data + i*vec_stride, FP64 or FP32, no
+// scales; nvec < kMaxVec); coefficients per system at coef + sys*coef_stride as (re, im) pairs:
+//   mode 0: out[sys] = (<v_i, w>)_i                                   (2 nvec values)
+//   mode 1: w -= sum_i coef_i v_i, then out[sys] = (<v_i, w>)_i, ||w||^2  (2 nvec + 1 values)
+//   mode 2: w -= sum_i coef_i v_i, then out[sys] = ||w||^2
+//   mode 3: t = w - sum_i coef_i v_i; y = fac[sys] t (w unchanged); out[sys] = ||t||^2
+// Values per system are contiguous in out; accumulate != 0 adds to out.
 hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, const VecRef& w, const double* coef,
-                   int mode, double* partials, double* out, int accumulate, int nsys, long long V, hipStream_t st);
+                   int coef_stride, int mode, const VecRef& y, const double* fac, double* partials, double* out,
+                   int accumulate, int nsys, long long V, hipStream_t st);
+// s[k] = 1/sqrt(hn_k[2 nvec] - sum_i hn_k[i]^2) for the mode-1 output hn (2 nvec + 1 values per system):
+// the norm after the second projection by Pythagoras; 0 for bit k of `off` set or a vanishing norm.
+hipError_t blas_pythagoras(const double* hn, int nvec, int nsys, unsigned long long off, double* s, hipStream_t st);
 // y = a[sys] x
 hipError_t blas_scale(Prec pi, Prec po, const VecRef& x, const double* a, const VecRef& y, int nsys, long long V,
                       hipStream_t st);

@@ -33,12 +33,15 @@ __device__ inline void st(const VecRef& r, int sys, long long V, long long s, co
                             r.scale ? r.scale + (size_t)sys * V : nullptr, V, s, v);
 }
 
-// Workgroup reduction of n values per thread into partials[(sys*n + i)*nblk + blockIdx.x].
+// Workgroup reduction of the first n of N values per thread into
+// partials[(sys*n + i)*nblk + blockIdx.x] (compile-time N keeps vals in registers).
+template <int N>
 __device__ inline void reduce_out(double* vals, int n, double* lds, double* partials, int sys, int nblk) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = 0; i < n; ++i) {
-        double v = wave_sum_d(vals[i]);
-        if (lane == 0) lds[w * 2 * kMaxVec + i] = v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double v = wave_sum_d(i < n ? vals[i] : 0.0);
+        if (lane == 0 && i < n) lds[w * 2 * kMaxVec + i] = v;
     }
     __syncthreads();
     if ((int)threadIdx.x < n) {
@@ -48,66 +51,94 @@ __device__ inline void reduce_out(double* vals, int n, double* lds, double* part
     }
 }
 
-// mode 0: partial <v_i, w> for i < nvec (2 doubles each)
-// mode 1: w -= sum_i coef_i v_i, then partial <v_i, w_new> for i < nvec
-// mode 2: w -= sum_i coef_i v_i, then partial ||w_new||^2
-template <class P>
+// Gram-Schmidt passes over basis vectors v_0..v_{nvec-1} (nvec <= NV), w and
+// the coefficients c (per system at coef + sys * coef_stride, complex pairs):
+//   mode 0: out = <v_i, w>                                   (2 nvec values)
+//   mode 1: w <- w - sum_i c_i v_i; out = <v_i, w>, ||w||^2  (2 nvec + 1 values)
+//   mode 2: w <- w - sum_i c_i v_i; out = ||w||^2            (1 value)
+//   mode 3: t = w - sum_i c_i v_i; y <- fac[sys] t (w kept); out = ||t||^2
+// Arithmetic at the vectors' precision R (FP64 or FP32) per site; the sums
+// over sites accumulate in FP64.  Norms and dots are of the stored values.
+template <class P, int NV>
 __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride, int nvec, VecRef w,
-                                                 const double* coef, int mode, double* partials, long long V) {
+                                                 const double* __restrict__ coef, int coef_stride, int mode, VecRef y,
+                                                 const double* __restrict__ fac, double* partials, long long V) {
+    typedef typename std::conditional<std::is_same<P, double>::value, double, float>::type R;
     __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
     const int sys = blockIdx.y;
     const int nblk = gridDim.x;
-    double acc[2 * kMaxVec];
+    double acc[2 * NV + 1];
 #pragma unroll
-    for (int i = 0; i < 2 * kMaxVec; ++i) acc[i] = 0;
-    cplx<double> c[kMaxVec];
-#pragma unroll
-    for (int i = 0; i < kMaxVec; ++i)
-        c[i] = (mode != 0 && i < nvec) ? cmk(coef[((size_t)sys * nvec + i) * 2], coef[((size_t)sys * nvec + i) * 2 + 1])
-                                        : cmk(0.0, 0.0);
+    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0;
+    const double* cf = coef + (size_t)sys * coef_stride;
+    const R f = mode == 3 ? (R)fac[sys] : (R)1;
+    const char* b0 = static_cast<const char*>(basis.data) + (size_t)sys * basis.sys_stride;
+    const char* w0 = static_cast<const char*>(w.data) + (size_t)sys * w.sys_stride;
     for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
-        Spinor<double> wv;
-        ld<P>(w, sys, V, s, wv);
+        Spinor<R> wv;
+        load_spinor<R, P>(w0, nullptr, V, s, wv);
         if (mode != 0) {
 #pragma unroll
-            for (int i = 0; i < kMaxVec; ++i) {
-                if (i >= nvec) break;
-                VecRef vi = basis;
-                vi.data = static_cast<char*>(basis.data) + i * vec_stride;
-                vi.scale = nullptr;
-                Spinor<double> v;
-                ld<P>(vi, sys, V, s, v);
+            for (int i = 0; i < NV; ++i) {
+                if (i < nvec) {
+                    Spinor<R> v;
+                    load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
+                    const cplx<R> c = cmk((R)cf[2 * i], (R)cf[2 * i + 1]);
 #pragma unroll
-                for (int k = 0; k < 12; ++k) wv.v[k] = wv.v[k] - c[i] * v.v[k];
-            }
-            st<P>(w, sys, V, s, wv);
-            // the stored (rounded) value is what later passes see
-            ld<P>(w, sys, V, s, wv);
-        }
-        if (mode == 2) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) acc[0] += wv.v[k].re * wv.v[k].re + wv.v[k].im * wv.v[k].im;
-        } else {
-#pragma unroll
-            for (int i = 0; i < kMaxVec; ++i) {
-                if (i >= nvec) break;
-                VecRef vi = basis;
-                vi.data = static_cast<char*>(basis.data) + i * vec_stride;
-                vi.scale = nullptr;
-                Spinor<double> v;
-                ld<P>(vi, sys, V, s, v);
-                double re = 0, im = 0;
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    re += v.v[k].re * wv.v[k].re + v.v[k].im * wv.v[k].im;
-                    im += v.v[k].re * wv.v[k].im - v.v[k].im * wv.v[k].re;
+                    for (int k = 0; k < 12; ++k) wv.v[k] = wv.v[k] - c * v.v[k];
                 }
-                acc[2 * i] += re;
-                acc[2 * i + 1] += im;
+            }
+            if (mode == 3) {
+                Spinor<R> t;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) t.v[k] = f * wv.v[k];
+                store_spinor<R, P>(static_cast<char*>(y.data) + (size_t)sys * y.sys_stride, nullptr, V, s, t);
+            } else {
+                store_spinor<R, P>(const_cast<char*>(w0), nullptr, V, s, wv);
+            }
+            R n2 = 0;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) n2 += wv.v[k].re * wv.v[k].re + wv.v[k].im * wv.v[k].im;
+            acc[2 * NV] += (double)n2;
+        }
+        if (mode <= 1) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                if (i < nvec) {
+                    Spinor<R> v;
+                    load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
+                    R re = 0, im = 0;
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        re += v.v[k].re * wv.v[k].re + v.v[k].im * wv.v[k].im;
+                        im += v.v[k].re * wv.v[k].im - v.v[k].im * wv.v[k].re;
+                    }
+                    acc[2 * i] += (double)re;
+                    acc[2 * i + 1] += (double)im;
+                }
             }
         }
     }
-    reduce_out(acc, mode == 2 ? 1 : 2 * nvec, lds, partials, sys, nblk);
+    // move the norm next to the dots (mode 1) or to the front (modes 2, 3)
+    const int pos = mode == 1 ? 2 * nvec : 0;
+#pragma unroll
+    for (int i = 0; i < 2 * NV; ++i)
+        if (mode >= 1 && i == pos) acc[i] = acc[2 * NV];
+    const int n = mode == 0 ? 2 * nvec : (mode == 1 ? 2 * nvec + 1 : 1);
+    reduce_out<2 * NV + 1>(acc, n, lds, partials, sys, nblk);
+}
+
+// s[k] = 1 / sqrt(||w'||^2 - sum_i |h_i|^2): the norm of w' - V h by Pythagoras
+// (V orthonormal), from the mode-1 output hn = [h (2 nvec), ||w'||^2] per
+// system; 0 for systems in `off` (frozen) or when the difference vanishes.
+__global__ void k_pythagoras(const double* hn, int nvec, int nsys, unsigned long long off, double* s) {
+    const int k = threadIdx.x;
+    if (k >= nsys) return;
+    const double* h = hn + (size_t)k * (2 * nvec + 1);
+    double t = h[2 * nvec];
+    const double w2 = t;
+    for (int i = 0; i < 2 * nvec; ++i) t -= h[i] * h[i];
+    s[k] = ((off >> k) & 1ull) || !(t > 1e-28 * w2) || !(t > 0) ? 0.0 : 1.0 / sqrt(t);
 }
 
 // out[sys*n + i] = sum over blocks (fixed order), optionally added to out.
@@ -180,7 +211,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(VecRef b, VecRef ax, VecR
         }
         st<P>(r, sys, V, s, av);
     }
-    reduce_out(acc, 2, lds, partials, sys, gridDim.x);
+    reduce_out<2>(acc, 2, lds, partials, sys, gridDim.x);
 }
 
 // x (Px) += c (Pc)
@@ -245,16 +276,36 @@ int blas_max_vec() { return kMaxVec; }
     }
 
 hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, const VecRef& w, const double* coef,
-                   int mode, double* partials, double* out, int accumulate, int nsys, long long V, hipStream_t st) {
-    if (nvec > kMaxVec || (p != P_F64 && p != P_F32)) return hipErrorInvalidValue;
+                   int coef_stride, int mode, const VecRef& y, const double* fac, double* partials, double* out,
+                   int accumulate, int nsys, long long V, hipStream_t st) {
+    if (nvec > kMaxVec - 1 || (p != P_F64 && p != P_F32) || mode < 0 || mode > 3) return hipErrorInvalidValue;
+    if (mode != 0 && nvec > 0 && !coef) return hipErrorInvalidValue;
     const int nblk = blas_blocks(V);
     dim3 grid(nblk, nsys);
-    TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL(k_gs<T>, grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, coef,
-                                             mode, partials, V));
+    static const double zero[1] = {0.0};
+    const double* cf = coef ? coef : zero;
+#define TM_GS_LAUNCH(NVT)                                                                                          \
+    TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL((k_gs<T, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, \
+                                             cf, coef_stride, mode, y, fac, partials, V))
+    if (nvec <= 4) {
+        TM_GS_LAUNCH(4);
+    } else if (nvec <= 8) {
+        TM_GS_LAUNCH(8);
+    } else if (nvec <= 16) {
+        TM_GS_LAUNCH(16);
+    } else {
+        TM_GS_LAUNCH(kMaxVec - 1);
+    }
+#undef TM_GS_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nval = nsys * (mode == 2 ? 1 : 2 * nvec);
+    const int nval = nsys * (mode == 0 ? 2 * nvec : (mode == 1 ? 2 * nvec + 1 : 1));
     hipLaunchKernelGGL(k_reduce, dim3(nval), dim3(kThreads), 0, st, partials, nblk, nval, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t blas_pythagoras(const double* hn, int nvec, int nsys, unsigned long long off, double* s, hipStream_t st) {
+    hipLaunchKernelGGL(k_pythagoras, dim3(1), dim3(64), 0, st, hn, nvec, nsys, off, s);
     return hipGetLastError();
 }
 

@@ -161,6 +161,63 @@ __host__ __device__ inline long long coords_site(const Geo& g, const int c[4]) {
     return blk * g.Vb + l;
 }
 
+// The 8 neighbours of site s in the tiled layout, s +- mu (periodic), and
+// the sign (-1 across an antiperiodic t boundary).  32-bit arithmetic: the
+// library limits the volume to 2^29 sites.  In-tile neighbours are s plus a
+// fixed stride; across a tile face the local coordinate wraps and the tile
+// index steps (with the lattice's periodic wrap).
+__device__ inline void tiled_neighbours(const Geo& g, long long s, int nf[4], int nbk[4], float sf[4],
+                                        float sb[4]) {
+    const unsigned su = (unsigned)s;
+    const unsigned Vb = (unsigned)g.Vb;
+    const unsigned blk = su / Vb;
+    const unsigned l = su - blk * Vb;
+    int L[4], B[4];
+    unsigned t = l, tb = blk;
+#pragma unroll
+    for (int a = 3; a >= 0; --a) {
+        const unsigned lb = (unsigned)g.lb[a], nb = (unsigned)g.nb[a];
+        const unsigned tq = t / lb, bq = tb / nb;
+        L[a] = (int)(t - tq * lb);
+        B[a] = (int)(tb - bq * nb);
+        t = tq;
+        tb = bq;
+    }
+    int ls[4], bs[4];
+    ls[3] = 1;
+    bs[3] = 1;
+#pragma unroll
+    for (int a = 2; a >= 0; --a) {
+        ls[a] = ls[a + 1] * g.lb[a + 1];
+        bs[a] = bs[a + 1] * g.nb[a + 1];
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int a = axis_of(mu);
+        sf[mu] = sb[mu] = 1.f;
+        if (L[a] + 1 < g.lb[a]) {
+            nf[mu] = (int)su + ls[a];
+        } else {
+            int bn = (int)blk + bs[a];
+            if (B[a] + 1 == g.nb[a]) {
+                bn -= g.nb[a] * bs[a];
+                if (mu == 0 && g.antiperiodic_t) sf[mu] = -1.f;
+            }
+            nf[mu] = bn * g.Vb + (int)l - (g.lb[a] - 1) * ls[a];
+        }
+        if (L[a] > 0) {
+            nbk[mu] = (int)su - ls[a];
+        } else {
+            int bn = (int)blk - bs[a];
+            if (B[a] == 0) {
+                bn += g.nb[a] * bs[a];
+                if (mu == 0 && g.antiperiodic_t) sb[mu] = -1.f;
+            }
+            nbk[mu] = bn * g.Vb + (int)l + (g.lb[a] - 1) * ls[a];
+        }
+    }
+}
+
 // Lexicographic (canonical) index of coordinates.
 __host__ __device__ inline long long lex_site(const Geo& g, const int c[4]) {
     return (((long long)c[0] * g.d[1] + c[1]) * g.d[2] + c[2]) * g.d[3] + c[3];

@@ -12,37 +12,14 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// Neighbour of internal site s along direction mu, dir = +-1; sets *sign to -1
-// when the hop crosses an antiperiodic t boundary.
-__device__ inline long long neighbour(const Geo& g, const int c[4], int mu, int dir, float* sign) {
-    int n[4] = {c[0], c[1], c[2], c[3]};
-    int a = axis_of(mu);
-    n[a] += dir;
-    *sign = 1.f;
-    if (n[a] < 0) {
-        n[a] += g.d[a];
-        if (mu == 0 && g.antiperiodic_t) *sign = -1.f;
-    } else if (n[a] >= g.d[a]) {
-        n[a] -= g.d[a];
-        if (mu == 0 && g.antiperiodic_t) *sign = -1.f;
-    }
-    return coords_site(g, n);
-}
-
 template <class Si, class So, class G, class C, class R>
 __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
     const Geo& g = a.g;
     long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
-    int c[4];
-    site_coords(g, s, c);
-    long long nf[4], nbk[4];
+    int nf[4], nbk[4];
     float sf[4], sb[4];
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        nf[mu] = neighbour(g, c, mu, +1, &sf[mu]);
-        nbk[mu] = neighbour(g, c, mu, -1, &sb[mu]);
-    }
+    tiled_neighbours(g, s, nf, nbk, sf, sb);
     Clover<R> A;
     load_clover<R, C>(a.clover, g.V, s, A);
     const size_t in_stride = (size_t)6 * g.V * Unit<Si>::bytes;

@@ -145,7 +145,8 @@ int residual(Ctx& c, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, cons
     if (x_zero) {
         if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(rhs, V), c.sc.ones, vec_ref(r, V), c.nsys, V, c.st), "copy")))
             return rc;
-        if ((rc = hcheck(blas_gs(c.vp, vec_ref(r, V), 0, 0, vec_ref(r, V), nullptr, 2, c.sc.partials, c.sc.res, 0,
+        if ((rc = hcheck(blas_gs(c.vp, vec_ref(r, V), 0, 0, vec_ref(r, V), nullptr, 0, 2, vec_ref(r, V), nullptr,
+                                 c.sc.partials, c.sc.res, 0,
                                  c.nsys, V, c.st),
                          "norm")))
             return rc;
@@ -235,27 +236,40 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             c.sap_cycles += c.n_cycles;
             c.sap_sys_cycles += (long long)c.n_cycles * ns;
             if ((rc = run_dirac(c.g, *c.op, zj, K.w, c.mu, ns, c.op_compute, c.st))) return rc;
-            // classical Gram-Schmidt, twice
+            // classical Gram-Schmidt, twice, in three passes: h1 = V^H w; w -= V h1 with h2 = V^H w and
+            // ||w||^2; v_{j+1} = (w - V h2) s with s = 1 / sqrt(||w||^2 - |h2|^2) (Pythagoras), which
+            // also returns ||w - V h2||^2 to check the normalisation
             const VecRef basis = vec_ref(K.Vb(c, 0), V), wr = vec_ref(K.w, V);
+            const SpinorBuf vn = K.Vb(c, j + 1);
             const int nv = j + 1;
-            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, nullptr, 0, c.sc.partials, c.sc.h1, 0, ns, V, c.st),
+            unsigned long long off = 0;
+            for (int k = 0; k < ns; ++k)
+                if (frozen[k]) off |= 1ull << k;
+            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, nullptr, 0, 0, wr, nullptr, c.sc.partials,
+                                     c.sc.h1, 0, ns, V, c.st),
                              "gs")))
                 return rc;
-            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h1, 1, c.sc.partials, c.sc.h2, 0, ns, V, c.st),
+            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h1, 2 * nv, 1, wr, nullptr, c.sc.partials,
+                                     c.sc.h2, 0, ns, V, c.st),
                              "gs")))
                 return rc;
-            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h2, 2, c.sc.partials, c.sc.nrm, 0, ns, V, c.st),
+            if ((rc = hcheck(blas_pythagoras(c.sc.h2, nv, ns, off, c.sc.inv, c.st), "gs"))) return rc;
+            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h2, 2 * nv + 1, 3, vec_ref(vn, V),
+                                     c.sc.inv, c.sc.partials, c.sc.nrm, 0, ns, V, c.st),
                              "gs")))
                 return rc;
-            const size_t nh = (size_t)ns * nv * 2;
-            if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.h1, nh * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
+            const size_t nh1 = (size_t)ns * nv * 2, nh2 = (size_t)ns * (2 * nv + 1);
+            double* st_h1 = c.hstage;
+            double* st_h2 = st_h1 + nh1;
+            double* st_nrm = st_h2 + nh2;
+            double* st_s = st_nrm + ns;
+            if ((rc = hcheck(hipMemcpyAsync(st_h1, c.sc.h1, nh1 * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
                 return rc;
-            if ((rc = hcheck(hipMemcpyAsync(c.hstage + nh, c.sc.h2, nh * sizeof(double), hipMemcpyDeviceToHost, c.st),
-                             "copy")))
+            if ((rc = hcheck(hipMemcpyAsync(st_h2, c.sc.h2, nh2 * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
                 return rc;
-            if ((rc = hcheck(hipMemcpyAsync(c.hstage + 2 * nh, c.sc.nrm, ns * sizeof(double), hipMemcpyDeviceToHost,
-                                            c.st),
-                             "copy")))
+            if ((rc = hcheck(hipMemcpyAsync(st_nrm, c.sc.nrm, ns * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
+                return rc;
+            if ((rc = hcheck(hipMemcpyAsync(st_s, c.sc.inv, ns * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
                 return rc;
             if ((rc = hcheck(hipStreamSynchronize(c.st), "arnoldi step"))) return rc;
             float ms = 0;
@@ -263,22 +277,35 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             ++steps;
             // a non-finite Hessenberg entry (an overflow in the preconditioner
             // or the operator) would otherwise read as a breakdown
-            for (size_t i = 0; i < 2 * nh + (size_t)ns; ++i)
+            for (size_t i = 0; i < nh1 + nh2 + 2 * (size_t)ns; ++i)
                 if (!std::isfinite(c.hstage[i]))
                     return fail(TM_ERR_NONFINITE, "non-finite value in the Arnoldi step %d (preconditioned vector)",
                                 steps);
-            bool all_frozen = true;
-            std::vector<double> inv(ns, 0.0);
+            bool all_frozen = true, rescale = false;
+            std::vector<double> fix(ns, 1.0);
             for (int k = 0; k < ns; ++k) {
                 if (frozen[k]) continue;
                 ++out.iters[k];
                 zc* Hk = &H[(size_t)k * (m + 1) * m];
                 for (int i = 0; i < nv; ++i) {
-                    const double* a = c.hstage + ((size_t)k * nv + i) * 2;
-                    const double* b2 = c.hstage + nh + ((size_t)k * nv + i) * 2;
+                    const double* a = st_h1 + ((size_t)k * nv + i) * 2;
+                    const double* b2 = st_h2 + (size_t)k * (2 * nv + 1) + 2 * i;
                     Hk[i * m + j] = zc(a[0] + b2[0], a[1] + b2[1]);
                 }
-                const double hn = std::sqrt(std::max(0.0, c.hstage[2 * nh + k]));
+                // v_{j+1} = (w - V h2) s, so h_{j+1,j} = 1/s keeps the Arnoldi relation exact; when the
+                // Pythagorean norm was off (cancellation), v_{j+1} is rescaled to unit norm
+                const double sk = st_s[k], t2 = std::max(0.0, st_nrm[k]);
+                double hn = 0.0;
+                if (sk > 0 && t2 > 0) {
+                    const double ratio = sk * std::sqrt(t2);  // ||v_{j+1}||
+                    if (std::fabs(ratio - 1.0) > 1e-4) {
+                        fix[k] = 1.0 / ratio;
+                        rescale = true;
+                        hn = std::sqrt(t2);
+                    } else {
+                        hn = 1.0 / sk;
+                    }
+                }
                 Hk[(j + 1) * m + j] = hn;
                 double* csk = &cs[(size_t)k * m];
                 zc* snk = &sn[(size_t)k * m];
@@ -303,10 +330,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                 gk[j] = csk[j] * gk[j];
                 kdim[k] = j + 1;
                 const bool done = std::abs(gk[j + 1]) <= tol * bnorm[k] || hn == 0.0;
-                if (done)
-                    frozen[k] = 1;
-                else
-                    inv[k] = 1.0 / hn;
+                if (done) frozen[k] = 1;
                 all_frozen &= (bool)frozen[k];
             }
             jdone = j + 1;
@@ -322,12 +346,15 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                              c.vp == P_F64 ? "fgmres" : "inner fgmres", steps, worst, active, ns, c.t_sap);
                 std::fflush(stderr);
             }
-            for (int k = 0; k < ns; ++k) c.hinv[k] = inv[k];
-            if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st),
-                             "copy")))
-                return rc;
-            const SpinorBuf vn = K.Vb(c, j + 1);
-            if ((rc = hcheck(blas_scale(c.vp, c.vp, wr, c.sc.inv, vec_ref(vn, V), ns, V, c.st), "scale"))) return rc;
+            if (rescale && !all_frozen) {
+                for (int k = 0; k < ns; ++k) c.hinv[k] = fix[k];
+                if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st),
+                                 "copy")))
+                    return rc;
+                if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(vn, V), c.sc.inv, vec_ref(vn, V), ns, V, c.st),
+                                 "scale")))
+                    return rc;
+            }
             if (all_frozen) break;
         }
         // x += Z y, y = R^-1 g per system (zero beyond its Krylov dimension)
