@@ -86,6 +86,10 @@ def _load():
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Report),
         ]
         lib.or_fgmres_eo.restype = ctypes.c_int
+        lib.or_dhat.argtypes = [ctypes.POINTER(_Op), vp, vp]
+        lib.or_dhat_dag.argtypes = [ctypes.POINTER(_Op), vp, vp]
+        lib.or_cg_eo.argtypes = [ctypes.POINTER(_Op), vp, vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Report)]
+        lib.or_cg_eo.restype = ctypes.c_int
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -199,6 +203,28 @@ class Operator:
                              int(bool(eo)), ctypes.byref(rep))
         return x, {"iters": rep.iters, "restarts": rep.restarts, "converged": bool(rep.converged),
                    "true_rel_res": rep.true_rel_res}
+
+    def dhat(self, v) -> np.ndarray:
+        """Even-odd reduced operator D_ee - D_eo D_oo^-1 D_oe on the even sites of v."""
+        v = self._vec(v)
+        out = np.empty_like(v)
+        _load().or_dhat(ctypes.byref(self._op), v.ctypes.data, out.ctypes.data)
+        return out
+
+    def dhat_dag(self, v) -> np.ndarray:
+        v = self._vec(v)
+        out = np.empty_like(v)
+        _load().or_dhat_dag(ctypes.byref(self._op), v.ctypes.data, out.ctypes.data)
+        return out
+
+    def cg_eo(self, b, tol: float, max_iters: int = 100000, x0=None):
+        """CG on the squared even-odd reduced system, then the odd sites; returns (x, report)."""
+        b = self._vec(b)
+        x = np.zeros_like(b) if x0 is None else self._vec(x0).copy()
+        rep = _Report()
+        _load().or_cg_eo(ctypes.byref(self._op), b.ctypes.data, x.ctypes.data, float(tol), int(max_iters),
+                         ctypes.byref(rep))
+        return x, {"iters": rep.iters, "converged": bool(rep.converged), "true_rel_res": rep.true_rel_res}
 
     def dense(self) -> np.ndarray:
         """Dense matrix of D (12V x 12V), built column by column; tiny lattices only."""

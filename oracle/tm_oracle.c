@@ -30,6 +30,11 @@
  *                   x_n = (I - E^n) D^-1 b + E^n x_0, E = (I-B1 D)(I-B0 D);
  *                   residual vanishes on the colour just swept;
  *                   1-homogeneity; block-order independence.
+ *   or_dhat         equals the dense Schur complement D_ee - D_eo D_oo^-1 D_oe
+ *                   of the dense D split by site parity (numpy); or_dhat_dag
+ *                   its conjugate transpose.
+ *   or_cg_eo        solution against dense LU; the odd rows of the full
+ *                   residual vanish; the reduced residual equals the full one.
  *   or_fgmres       solution against dense LU (numpy); identity-
  *                   preconditioned GMRES(N) exact termination.
  */
@@ -673,6 +678,134 @@ int or_sap_eo(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, i
     }
     free(r);
     return 0;
+}
+
+/* ------------------------------------------- even-odd reduced operator, CG */
+
+static double vnorm(const or_cplx* a, long n);
+static double true_residual(const or_op* op, const or_cplx* b, const or_cplx* x, or_cplx* r, long n);
+
+/* Zero the sites whose parity differs from par. */
+static void mask_parity(const int dims[4], int par, or_cplx* v) {
+    long V = or_volume(dims);
+    for (long x = 0; x < V; ++x)
+        if (site_parity(dims, x) != par)
+            for (int i = 0; i < 12; ++i) v[x * 12 + i] = 0;
+}
+
+/* out = D_pp^-1 in on the sites of parity par (site-diagonal part of D), zero elsewhere. */
+static void diag_solve_parity(const or_op* op, int par, const or_cplx* in, or_cplx* out) {
+    long V = or_volume(op->dims);
+    or_cplx g5[16];
+    or_gamma(4, g5);
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        if (site_parity(op->dims, x) == par)
+            diag_solve(op, g5, x, in + x * 12, out + x * 12);
+        else
+            for (int i = 0; i < 12; ++i) out[x * 12 + i] = 0;
+    }
+}
+
+void or_dhat(const or_op* op, const or_cplx* in, or_cplx* out) {
+    long n = or_volume(op->dims) * 12;
+    or_cplx* v = malloc(sizeof(or_cplx) * n);
+    or_cplx* u = malloc(sizeof(or_cplx) * n);
+    or_cplx* t = malloc(sizeof(or_cplx) * n);
+    or_cplx* w = malloc(sizeof(or_cplx) * n);
+    memcpy(v, in, sizeof(or_cplx) * n);
+    mask_parity(op->dims, 0, v);
+    or_dirac(op, v, u);                    /* u_e = D_ee v_e, u_o = D_oe v_e */
+    diag_solve_parity(op, 1, u, t);        /* t_o = D_oo^-1 D_oe v_e */
+    or_dirac(op, t, w);                    /* w_e = D_eo t_o */
+    for (long i = 0; i < n; ++i) out[i] = u[i] - w[i];
+    mask_parity(op->dims, 0, out);
+    free(v);
+    free(u);
+    free(t);
+    free(w);
+}
+
+void or_dhat_dag(const or_op* op, const or_cplx* in, or_cplx* out) {
+    /* Dhat(mu)^+ = Gamma5 Dhat(-mu) Gamma5, from D(mu)^+ = Gamma5 D(-mu) Gamma5 (section 2.1)
+     * and Gamma5 being site-diagonal */
+    long n = or_volume(op->dims) * 12;
+    or_cplx* v = malloc(sizeof(or_cplx) * n);
+    or_cplx g5[16];
+    or_gamma(4, g5);
+    for (long x = 0; x < n / 12; ++x)
+        for (int s = 0; s < 4; ++s)
+            for (int c = 0; c < 3; ++c) v[x * 12 + 3 * s + c] = g5[5 * s] * in[x * 12 + 3 * s + c];
+    or_op neg = *op;
+    neg.mu = -op->mu;
+    or_dhat(&neg, v, out);
+    for (long x = 0; x < n / 12; ++x)
+        for (int s = 0; s < 4; ++s)
+            for (int c = 0; c < 3; ++c) out[x * 12 + 3 * s + c] *= g5[5 * s];
+    free(v);
+}
+
+int or_cg_eo(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int max_iters, or_report* rep) {
+    long n = or_volume(op->dims) * 12;
+    or_cplx* bh = malloc(sizeof(or_cplx) * n);
+    or_cplx* r = malloc(sizeof(or_cplx) * n);
+    or_cplx* s = malloc(sizeof(or_cplx) * n);
+    or_cplx* p = malloc(sizeof(or_cplx) * n);
+    or_cplx* q = malloc(sizeof(or_cplx) * n);
+    or_cplx* t = malloc(sizeof(or_cplx) * n);
+    double bnorm = vnorm(b, n);
+    int iters = 0;
+    /* reduced right-hand side bhat_e = b_e - D_eo D_oo^-1 b_o */
+    diag_solve_parity(op, 1, b, t);
+    or_dirac(op, t, q);
+    for (long i = 0; i < n; ++i) bh[i] = b[i] - q[i];
+    mask_parity(op->dims, 0, bh);
+    /* CG on Dhat^+ Dhat x_e = Dhat^+ bhat (in the least-squares form: r is the residual of the
+     * reduced system, s = Dhat^+ r the residual of the normal equations) */
+    mask_parity(op->dims, 0, x);
+    or_dhat(op, x, q);
+    for (long i = 0; i < n; ++i) r[i] = bh[i] - q[i];
+    or_dhat_dag(op, r, s);
+    memcpy(p, s, sizeof(or_cplx) * n);
+    double gamma = vnorm(s, n);
+    gamma *= gamma;
+    while (vnorm(r, n) > tol * bnorm && iters < max_iters && gamma > 0) {
+        or_dhat(op, p, q);
+        double qq = vnorm(q, n);
+        double alpha = gamma / (qq * qq);
+        for (long i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        or_dhat_dag(op, r, s);
+        double gnew = vnorm(s, n);
+        gnew *= gnew;
+        double beta = gnew / gamma;
+        for (long i = 0; i < n; ++i) p[i] = s[i] + beta * p[i];
+        gamma = gnew;
+        ++iters;
+    }
+    /* odd sites: x_o = D_oo^-1 (b_o - D_oe x_e) */
+    or_dirac(op, x, q);
+    for (long i = 0; i < n; ++i) t[i] = b[i] - q[i];
+    diag_solve_parity(op, 1, t, q);
+    for (long xs = 0; xs < n / 12; ++xs)
+        if (site_parity(op->dims, xs) == 1)
+            for (int i = 0; i < 12; ++i) x[xs * 12 + i] = q[xs * 12 + i];
+    double rel = bnorm > 0 ? true_residual(op, b, x, t, n) / bnorm : 0.0;
+    if (rep) {
+        rep->iters = iters;
+        rep->restarts = 0;
+        rep->converged = rel <= tol;
+        rep->true_rel_res = rel;
+    }
+    free(bh);
+    free(r);
+    free(s);
+    free(p);
+    free(q);
+    free(t);
+    return rel <= tol ? 0 : 1;
 }
 
 /* ---------------------------------------------------------------- FGMRES */

@@ -88,6 +88,21 @@ int or_sap(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, cons
 int or_sap_eo(const or_op* op, const int bdims[4], int n_cycles, int mr_iters, int eo,
               const or_cplx* b, or_cplx* x);
 
+/* Even-odd reduced operator of eq. (oereduced), even sites kept:
+ * Dhat = D_ee - D_eo D_oo^-1 D_oe (parity of t+z+y+x, 0 = even).  in and out
+ * are full-lattice vectors; only even sites are read, odd sites of out are 0. */
+void or_dhat(const or_op* op, const or_cplx* in, or_cplx* out);
+/* out = Dhat^+ in (even sites), as Gamma5 Dhat(-mu) Gamma5. */
+void or_dhat_dag(const or_op* op, const or_cplx* in, or_cplx* out);
+/* CG on the squared even-odd reduced system (section 3, the CG comparison):
+ * Dhat^+ Dhat x_e = Dhat^+ bhat with bhat = b_e - D_eo D_oo^-1 b_o, run in the
+ * least-squares form (the reduced residual r = bhat - Dhat x_e is updated
+ * alongside), then x_o = D_oo^-1 (b_o - D_oe x_e).  The reduced residual is
+ * the even part of the full residual and the odd part vanishes, so it stops
+ * when ||r|| <= tol ||b||.  x is in/out (its even part is the initial guess).
+ * Returns 0 when converged. */
+int or_cg_eo(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int max_iters, or_report* rep);
+
 /* Flexible GMRES(restart) with right preconditioning (precond: 0 = none,
  * 1 = SAP with the given parameters), modified Gram-Schmidt, complex Givens
  * rotations.  x is in/out (initial guess).  Stops when the true relative

@@ -40,6 +40,10 @@ MUTATIONS = {
     # even-odd: even sites taken as the reduced ones (parity flipped in the reconstruction)
     "eo_parity_flip": ("if (site_parity(op->dims, sites[l]) == 0)\n            for (int i = 0; i < 12; ++i) e[l * 12 + i] = t[l * 12 + i];",
                        "if (site_parity(op->dims, sites[l]) == 1)\n            for (int i = 0; i < 12; ++i) e[l * 12 + i] = t[l * 12 + i];"),
+    # reduced operator with + instead of - before the Schur term
+    "eo_dhat_sign": ("for (long i = 0; i < n; ++i) out[i] = u[i] - w[i];", "for (long i = 0; i < n; ++i) out[i] = u[i] + w[i];"),
+    # reduced right-hand side without D_oo^-1 (b_o used directly)
+    "eo_cg_rhs_no_inverse": ("diag_solve_parity(op, 1, b, t);\n    or_dirac(op, t, q);", "memcpy(t, b, sizeof(or_cplx) * n);\n    mask_parity(op->dims, 1, t);\n    or_dirac(op, t, q);"),
     # Givens rotation without the conjugate
     "givens_conj": ("g[j + 1] = -conj(sn[j]) * g[j];", "g[j + 1] = -sn[j] * g[j];"),
 }
