@@ -64,6 +64,15 @@ HOP_FLOPS = 24 + 132 + 12
 RESID_FLOPS = 8 * HOP_FLOPS + 552 + 48
 MR_FLOPS = 6 * HOP_FLOPS + 552 + 24 + 336
 REAL_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+# Even-odd block solves (section 2.5), per site averaged over the two parities:
+#   reduction r_o - D_oe D_ee^-1 r_e: D_ee^-1 on even sites (two 6x6 complex products, 552)
+#   and the in-block hops on odd sites (6 x 168 + 24), half each = 792
+#   each MR step on the reduced operator: even sites hops + D_ee^-1 (1560), odd sites hops +
+#   clover + combine + dots and updates (1008 + 552 + 24 + 192 = 1776), half each = 1668
+#   recovery e_e = D_ee^-1 (r_e - D_eo e_o): 1560 on even sites = 780
+#   plus the site inverses read once per launch (144 reals per even site = 72 per site)
+EO_REDUCE_FLOPS, EO_MR_FLOPS, EO_RECOVER_FLOPS = 792, 1668, 780
+EO_INV_REALS = 72
 
 
 def _real_bytes(storage):
@@ -79,18 +88,18 @@ def sap_bytes_per_site_cycle(storage: str, nsys: int) -> float:
     return LINK_REALS * rb + CLOVER_REALS * cb + nsys * 3 * (SPINOR_REALS * rb + sb)
 
 
-def sap_application_model(storage: str, nsys: int, n_cycles: int, mr: int):
+def sap_application_model(storage: str, nsys: int, n_cycles: int, mr: int, eo: bool = False):
     """Algorithmic bytes and flops per site of one SAP application from a zero guess
     (the preconditioner): in the first cycle x is not read and the colour-0 sweep
     has no residual to form (r = b), the colour-1 sweep only the hops from colour 0
     (2 of 8 hops per site on average for 4^4 blocks)."""
     rb, cb, sb = _real_bytes(storage)
-    shared = LINK_REALS * rb + CLOVER_REALS * cb
+    shared = LINK_REALS * rb + CLOVER_REALS * cb + (EO_INV_REALS * cb if eo else 0)
     spin = SPINOR_REALS * rb + sb
     first = shared + nsys * 2 * spin               # b read, x written
     rest = shared + nsys * 3 * spin
     bytes_app = first + (n_cycles - 1) * rest
-    mr_f = mr * MR_FLOPS
+    mr_f = EO_REDUCE_FLOPS + mr * EO_MR_FLOPS + EO_RECOVER_FLOPS if eo else mr * MR_FLOPS
     first_f = 0.5 * (mr_f) + 0.5 * (2 * HOP_FLOPS + 24 + mr_f)  # two half-sweeps, per site of a cycle
     rest_f = RESID_FLOPS + mr_f
     flops_app = nsys * (first_f + (n_cycles - 1) * rest_f)
@@ -230,11 +239,11 @@ def sap_sweep_phase(wl, Ud, mus, torch, tm, reps):
     }
 
 
-def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group):
+def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False):
     x.zero_()
     rc, rep = tm.tm_fgmres_solve(wl["dims"], Ud, b, x, wl["kappa"], mus, wl["csw"], TOL, storage=wl["storage"],
                                  form="defect_correction", restart=restart, n_cycles=N_CYCLES, mr_iters=MR_ITERS,
-                                 block_dims=BLOCK, group=group, gauge_tag=0)
+                                 block_dims=BLOCK, group=group, gauge_tag=0, eo=eo)
     return rc, rep
 
 
@@ -309,6 +318,8 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-only", action="store_true", help="only the all-systems SAP sweep (profiling)")
+    ap.add_argument("--eo", action="store_true",
+                    help="even-odd preconditioned SAP block solves (section 2.5) instead of MR on the full block")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB elementwise kernel before the timed region (counter calibration)")
     args = ap.parse_args()
@@ -345,13 +356,13 @@ def main():
 
     x = torch.zeros_like(b)
     for w in range(args.warmup):
-        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group)
+        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group, args.eo)
         log(f"warmup {w}: status {rc} iters {rep['iters']} outer {rep['outer']} t {rep['t_total']:.2f}s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
     for s in range(args.steps):
-        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group)
+        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group, args.eo)
         reps.append((rc, rep))
         log(f"step {s}: status {rc} iters {rep['iters']} outer {rep['outer']} group {rep['group']} "
             f"sap {rep['t_sap']:.2f}s total {rep['t_total']:.2f}s max res {max(rep['true_rel_res']):.2e}")
@@ -366,8 +377,8 @@ def main():
     sys_cycles = sum(r["sap_sys_cycles"] for _, r in reps)
     group = reps[0][1]["group"]
     apps = sap_cycles // N_CYCLES
-    b_shared, f_shared = sap_application_model(wl["storage"], 0, N_CYCLES, MR_ITERS)
-    b_one, f_one = sap_application_model(wl["storage"], 1, N_CYCLES, MR_ITERS)
+    b_shared, f_shared = sap_application_model(wl["storage"], 0, N_CYCLES, MR_ITERS, args.eo)
+    b_one, f_one = sap_application_model(wl["storage"], 1, N_CYCLES, MR_ITERS, args.eo)
     sys_apps = sys_cycles / N_CYCLES
     sap_bytes = V * (b_shared * apps + (b_one - b_shared) * sys_apps)
     sap_flops = V * (f_one - f_shared) * sys_apps
@@ -390,6 +401,8 @@ def main():
     achieved_tflops = sap_flops / t_sap / 1e12
     kernel = ("k_sap_half_44" if tuple(BLOCK) == (4, 4, 4, 4) else "k_sap_half_v2") if wl["storage"] != "f64" \
         else "k_sap_half"
+    if args.eo:
+        kernel = "k_sap_half_eo"
     traffic = measured_traffic(kernel, args.workload)
     if wl["storage"] != "f64":
         roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -415,7 +428,8 @@ def main():
         "dtype": wl["storage"],
         "data": "synthetic",
         "config": {"workload": args.workload, "dims_TZYX": list(dims), "systems": nsys, "block": list(BLOCK),
-                   "n_cycles": N_CYCLES, "mr_iters": MR_ITERS, "tol": TOL, "restart": args.restart,
+                   "n_cycles": N_CYCLES, "mr_iters": MR_ITERS, "block_solve": "even-odd MR" if args.eo else "MR",
+                   "tol": TOL, "restart": args.restart,
                    "group": group, "parallelism": "single GPU"},
         "converged": ok,
         "sap": {"GBps": achieved_gbps, "hbm_frac": achieved_gbps / HBM_PEAK_GBPS, "TFLOPs": achieved_tflops,

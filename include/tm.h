@@ -191,6 +191,24 @@ typedef struct {
 TM_API int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw,
                     double tol, const tm_solver_opts* sopts, const tm_opts* opts, tm_solve_report* report);
 
+/*
+ * CG on the squared even-odd reduced system, the plain FP64 baseline of the
+ * paper's solver comparison (section 3): Dhat^+ Dhat x_e = Dhat^+ bhat with
+ * Dhat = D_ee - D_eo D_oo^-1 D_oe (eq. (oereduced), even sites kept, parity
+ * of t+z+y+x) and bhat = b_e - D_eo D_oo^-1 b_o, run in the least-squares form;
+ * then x_o = D_oo^-1 (b_o - D_oe x_e).  The odd rows of b - D x vanish by
+ * construction and the even rows are the reduced residual, so CG stops when
+ * that residual is <= tol ||b|| per system; report->true_rel_res is then
+ * recomputed as ||b - D x|| / ||b|| with the full operator.  FP64 throughout
+ * (opts->storage TM_F64), canonical buffers, x in/out (the even-site part of x
+ * is the initial guess).  Needs even dims (TM_ERR_DIMS) and at most 8 distinct
+ * |mu| per call; systems are solved in groups that fit device memory
+ * (report->group).  Returns TM_NOT_CONVERGED when max_iters CG steps did not
+ * reach tol (x then holds the last iterate).
+ */
+TM_API int tm_cg_solve(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw,
+                       double tol, int max_iters, const tm_opts* opts, tm_solve_report* report);
+
 /* ------------------------------------------------------ internal buffers */
 /* Bytes of an internal spinor buffer for geom->nsys systems at opts->storage. */
 TM_API size_t tm_spinor_bytes(const tm_geom* geom, const tm_opts* opts);

@@ -30,7 +30,7 @@ MAX_SYS = 64
 EXPORTS = (
     "tm_opts_default", "tm_init", "tm_finalize", "tm_last_error", "tm_gauge_release", "tm_dirac_apply",
     "tm_sap_smooth", "tm_solver_opts_default", "tm_fgmres_solve", "tm_spinor_bytes", "tm_spinor_import",
-    "tm_spinor_export", "tm_spinor_import_range", "tm_spinor_export_range", "tm_autotune_sap",
+    "tm_spinor_export", "tm_spinor_import_range", "tm_spinor_export_range", "tm_autotune_sap", "tm_cg_solve",
 )
 
 
@@ -93,6 +93,8 @@ def lib():
         L.tm_spinor_bytes.restype = ctypes.c_size_t
         L.tm_spinor_import.argtypes = [P(Geom), vp, vp, P(Opts)]
         L.tm_spinor_export.argtypes = [P(Geom), vp, vp, P(Opts)]
+        L.tm_cg_solve.argtypes = [P(Geom), vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                  P(Opts), P(Report)]
         L.tm_spinor_import_range.argtypes = [P(Geom), vp, vp, ctypes.c_int, ctypes.c_int, P(Opts)]
         L.tm_spinor_export_range.argtypes = [P(Geom), vp, vp, ctypes.c_int, ctypes.c_int, P(Opts)]
         L.tm_autotune_sap.argtypes = [P(Geom), vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -233,6 +235,19 @@ def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *,
                 "true_rel_res": [rep.true_rel_res[k] for k in range(n)], "t_total": rep.t_total,
                 "t_sap": rep.t_sap, "sap_cycles": rep.sap_cycles, "sap_sys_cycles": rep.sap_sys_cycles,
                 "group": rep.group}
+
+
+def tm_cg_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, max_iters: int = 100000,
+                antiperiodic_t: bool = False, stream=None, gauge_tag: int = 0):
+    """CG on the squared even-odd reduced system (FP64 baseline); returns (status, report dict)."""
+    g = make_geom(dims, mu, antiperiodic_t)
+    o = make_opts("f64", stream=stream, gauge_tag=gauge_tag)
+    rep = Report()
+    rc = _check(lib().tm_cg_solve(ctypes.byref(g), _canon(U, "U"), _canon(b, "b"), _canon(x, "x"), float(kappa),
+                                  float(c_sw), float(tol), int(max_iters), ctypes.byref(o), ctypes.byref(rep)))
+    n = len(list(mu))
+    return rc, {"iters": rep.iters, "converged": rep.converged,
+                "true_rel_res": [rep.true_rel_res[k] for k in range(n)], "t_total": rep.t_total, "group": rep.group}
 
 
 def tm_spinor_bytes(dims, nsys: int, storage: str, layout_block=None) -> int:

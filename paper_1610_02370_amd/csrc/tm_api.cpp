@@ -252,54 +252,60 @@ void fill_mu(const tm_geom* geom, double* mu) {
     for (int k = 0; k < kMaxSys; ++k) mu[k] = k < geom->nsys ? geom->mu[k] : 0.0;
 }
 
-// Even-odd inverse sets for the systems' |mu| values: built on first use and
-// kept with the gauge entry; sets a.eo_inv / eo_sel / eo_adj.
-static int prepare_eo(const Geo& g, const GaugeDev& G, const double* mu, int nsys, hipStream_t st, SapArgs& a) {
+// Inverse sets of one parity for the systems' |mu| values: built on first use
+// and kept with the gauge entry; fills inv / sel / adj.
+int prepare_site_inverses(const Geo& g, const GaugeDev& G, const double* mu, int nsys, int parity, hipStream_t st,
+                          const void* inv[kMaxEoMu], unsigned char sel[kMaxSys], unsigned long long* adj) {
     if (g.lb[3] % 2 != 0)
-        return fail(TM_ERR_BLOCKS, "even-odd block solves need an even block extent in x (got %d)", g.lb[3]);
+        return fail(TM_ERR_BLOCKS, "even-odd solves need an even tile extent in x (got %d)", g.lb[3]);
     if (!G.eo) return fail(TM_ERR_ARG, "gauge entry without an even-odd cache");
     EoCache& c = *G.eo;
     double want[kMaxEoMu];
     int nwant = 0;
-    a.eo_adj = 0;
+    *adj = 0;
     for (int k = 0; k < nsys; ++k) {
         const double am = std::fabs(mu[k]);
         int j = 0;
         while (j < nwant && want[j] != am) ++j;
         if (j == nwant) {
             if (nwant == kMaxEoMu)
-                return fail(TM_ERR_ARG, "even-odd block solves take at most %d distinct |mu| per call", kMaxEoMu);
+                return fail(TM_ERR_ARG, "even-odd solves take at most %d distinct |mu| per call", kMaxEoMu);
             want[nwant++] = am;
         }
-        a.eo_sel[k] = (unsigned char)j;
-        if (mu[k] < 0) a.eo_adj |= 1ull << k;
+        sel[k] = (unsigned char)j;
+        if (mu[k] < 0) *adj |= 1ull << k;
     }
     // keep the cache to the sets this call needs when it would overflow
     int missing = 0;
     for (int j = 0; j < nwant; ++j) {
         bool found = false;
-        for (int i = 0; i < c.n; ++i) found |= c.absmu[i] == want[j];
+        for (int i = 0; i < c.n; ++i) found |= c.absmu[i] == want[j] && c.parity[i] == parity;
         missing += !found;
     }
     if (c.n + missing > kMaxEoMu) c.release();
     for (int j = 0; j < nwant; ++j) {
         int i = 0;
-        while (i < c.n && c.absmu[i] != want[j]) ++i;
+        while (i < c.n && !(c.absmu[i] == want[j] && c.parity[i] == parity)) ++i;
         if (i == c.n) {
             void* p = nullptr;
             hipError_t h = hipMalloc(&p, eo_inverse_bytes(g, G.clover_prec));
             if (h != hipSuccess) return hip_fail(h, "even-odd inverses");
-            if ((h = launch_eo_inverse(g, G.clover_prec, G.clover, want[j], p, st)) != hipSuccess) {
+            if ((h = launch_eo_inverse(g, G.clover_prec, G.clover, want[j], parity, p, st)) != hipSuccess) {
                 (void)hipFree(p);
                 return hip_fail(h, "even-odd inverses");
             }
             c.absmu[c.n] = want[j];
+            c.parity[c.n] = parity;
             c.inv[c.n] = p;
             ++c.n;
         }
-        a.eo_inv[j] = c.inv[i];
+        inv[j] = c.inv[i];
     }
     return TM_OK;
+}
+
+static int prepare_eo(const Geo& g, const GaugeDev& G, const double* mu, int nsys, hipStream_t st, SapArgs& a) {
+    return prepare_site_inverses(g, G, mu, nsys, 0, st, a.eo_inv, a.eo_sel, &a.eo_adj);
 }
 
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,

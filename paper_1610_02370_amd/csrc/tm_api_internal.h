@@ -65,6 +65,14 @@ bool tune_lookup(const tm_geom* geom, int storage, int n_cycles, int mr_iters, i
 SpinorBuf wrap_internal(void* base, const Geo& g, int nsys, Prec p);
 size_t internal_bytes(const Geo& g, int nsys, Prec p);
 void fill_mu(const tm_geom* geom, double* mu);
+// Site-diagonal inverse sets (A + i mu Gamma5)^-1 at the sites of one parity for
+// the systems' |mu| values, cached with G; sel[k] picks system k's set, bit k of
+// *adj marks mu_k < 0 (use the adjoint).
+int prepare_site_inverses(const Geo& g, const GaugeDev& G, const double* mu, int nsys, int parity, hipStream_t st,
+                          const void* inv[kMaxEoMu], unsigned char sel[kMaxSys], unsigned long long* adj);
+// Largest group of systems (at most `group` when positive) whose per-system
+// workspace fits in 92 % of the free device memory (plus the solver buffer).
+int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed);
 // n_cycles red-black SAP cycles; eo selects even-odd preconditioned block
 // solves (site inverses built on first use for each |mu| and kept with G).
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,

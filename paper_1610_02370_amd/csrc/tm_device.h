@@ -457,6 +457,35 @@ __device__ inline void clover_apply(const Clover<R>& C, R mu, const Spinor<R>& i
     clover_block_apply(C.a + 36, -mu, in.v + 6, out.v + 6);
 }
 
+// out = D_pp^-1 in at a site of the parity of an inverse set (entry h = s / 2):
+// the two 6x6 chiral-block inverses; adj uses their adjoints (the inverses for
+// -mu, the diagonal block being Hermitian up to the twist).
+template <class C, class R>
+__device__ inline void eo_inverse_apply(const void* inv, long long half, long long h, bool adj, const Spinor<R>& in,
+                                        Spinor<R>& out) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) out.v[i] = cmk<R>(0, 0);
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const cplx<R>* v = in.v + 6 * blk;
+        cplx<R>* o = out.v + 6 * blk;
+#pragma unroll
+        for (int u = 0; u < 18; ++u) {
+            R w[4];
+            Unit<C>::load(inv, (size_t)(18 * blk + u) * half + h, w);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int e = 2 * u + k, i = e / 6, j = e % 6;
+                const cplx<R> m = cmk(w[2 * k], w[2 * k + 1]);
+                if (adj)
+                    o[j] = cjmad(m, v[i], o[j]);
+                else
+                    o[i] = cmad(m, v[j], o[i]);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------- field access
 
 template <class R, class S>

@@ -33,14 +33,16 @@ inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 // Gauge data on the device at one precision: links [4][3 units][V] and the
 // packed clover [18 units][V] holding (m+4) + clover.
-// Site-diagonal inverses for even-odd block solves, one set per |mu|:
-// [36 units][V/2] at the clover precision, entry h for the even site of the
-// pair (2h, 2h+1) (block x-extent even); units 0..17 hold (A_up + i|mu|)^-1,
-// units 18..35 hold (A_dn - i|mu|)^-1, each 6x6 row-major as (re, im) pairs.
+// Site-diagonal inverses for even-odd solves, one set per (|mu|, parity):
+// [36 units][V/2] at the clover precision, entry h for the site of that
+// parity in the pair (2h, 2h+1) (tile x-extent even); units 0..17 hold
+// (A_up + i|mu|)^-1, units 18..35 hold (A_dn - i|mu|)^-1, each 6x6 row-major
+// as (re, im) pairs.
 constexpr int kMaxEoMu = 8;
 struct EoCache {
     int n = 0;
     double absmu[kMaxEoMu] = {};
+    int parity[kMaxEoMu] = {};
     void* inv[kMaxEoMu] = {};
     void release();
     ~EoCache() { release(); }
@@ -87,6 +89,44 @@ struct SapArgs {
     double mu[kMaxSys];
 };
 
+// One step of the even-odd reduced operator on compact parity fields
+// [nsys][6 units][V/2] (FP64): out_p = (D_pp^-1)? [hop_sign * H in_hop +
+// D_pp in_diag + add_sign * in_add] with H = -1/2 sum of the hops between
+// the parities; null inputs are skipped; the Gamma5 flags multiply the hop
+// input, the diagonal input and the output (Dhat^+ = Gamma5 Dhat(-mu) Gamma5).
+struct ParityArgs {
+    Geo g;
+    const void* links;   // FP64 [4][3 units][V]
+    const void* clover;  // FP64 [18 units][V]
+    const void* inv[kMaxEoMu];  // site inverse sets of parity p
+    unsigned char sel[kMaxSys];
+    int p;
+    const double* in_hop;
+    double hop_sign;
+    const double* in_diag;
+    const double* in_add;
+    double add_sign;
+    int do_inv;
+    int g5_hop, g5_diag, g5_out;
+    double mu_sign;
+    double* out;
+    int nsys;
+    double mu[kMaxSys];
+};
+
+// ---- even-odd reduced operator and CG (tm_cg.hip)
+hipError_t launch_parity_op(const ParityArgs& a, hipStream_t st);
+hipError_t launch_parity_import(const Geo& g, int nsys, const void* canon, double* even, double* odd, unsigned* flag,
+                                hipStream_t st);
+hipError_t launch_parity_export(const Geo& g, int nsys, const double* even, const double* odd, void* canon,
+                                hipStream_t st);
+// y = a[sys] x + b[sys] y over n_per_sys doubles per system
+hipError_t launch_axpby(const double* x, const double* a, double* y, const double* b, int nsys, long long n_per_sys,
+                        hipStream_t st);
+// mode 0: out = gamma / v (step length), neg = -out; mode 1: out = v / gamma, gamma = v; frozen systems get 0
+hipError_t launch_cg_scalars(int mode, int nsys, unsigned long long frozen, double* gamma, const double* v,
+                             double* out, double* neg, hipStream_t st);
+
 // ---- layout kernels (tm_layout.hip)
 hipError_t launch_link_ingest(const Geo& g, Prec G, const void* Ucanon, void* links, unsigned* stats, hipStream_t st);
 hipError_t launch_clover_build(const Geo& g, Prec C, const void* Ucanon, double m4, double csw, void* clover,
@@ -95,8 +135,10 @@ hipError_t launch_spinor_import(const Geo& g, const SpinorBuf& dst, const void* 
                                 hipStream_t st);
 hipError_t launch_spinor_export(const Geo& g, const SpinorBuf& src, void* canon, hipStream_t st);
 hipError_t launch_spinor_convert(const Geo& g, const SpinorBuf& src, const SpinorBuf& dst, hipStream_t st);
-// (A_up + i absmu)^-1 and (A_dn - i absmu)^-1 at every even site, from the packed clover (FP64 arithmetic)
-hipError_t launch_eo_inverse(const Geo& g, Prec C, const void* clover, double absmu, void* inv, hipStream_t st);
+// (A_up + i absmu)^-1 and (A_dn - i absmu)^-1 at every site of one parity, from the packed clover (FP64
+// arithmetic)
+hipError_t launch_eo_inverse(const Geo& g, Prec C, const void* clover, double absmu, int parity, void* inv,
+                             hipStream_t st);
 inline size_t eo_inverse_bytes(const Geo& g, Prec C) { return (size_t)36 * (g.V / 2) * unit_bytes(C); }
 
 // ---- operator (tm_dirac.hip)

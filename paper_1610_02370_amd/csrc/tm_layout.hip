@@ -273,21 +273,21 @@ __global__ void __launch_bounds__(kThreads) k_spinor_convert(Geo g, int nsys, co
 
 }  // namespace
 
-// Even-odd site inverses: thread h takes the even site of the pair (2h, 2h+1)
+// Even-odd site inverses: thread h takes the site of the requested parity in the pair (2h, 2h+1)
 // (one even and one odd site, since the block x-extent is even), forms the
 // two chiral blocks A_up + i absmu and A_dn - i absmu of the packed clover
 // (A = (m+4) + clover, Hermitian) and inverts each by Gauss-Jordan with
 // partial pivoting in FP64.
 template <class C>
 __global__ void __launch_bounds__(kThreads) k_eo_inverse(Geo g, const void* __restrict__ clover, double absmu,
-                                                         void* inv) {
+                                                         int parity, void* inv) {
     const long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long half = g.V / 2;
     if (h >= half) return;
     long long s = 2 * h;
     int c[4];
     site_coords(g, s, c);
-    if ((c[0] + c[1] + c[2] + c[3]) & 1) ++s;
+    if (((c[0] + c[1] + c[2] + c[3]) & 1) != parity) ++s;
     Clover<double> A;
     load_clover<double, C>(clover, g.V, s, A);
     for (int blk = 0; blk < 2; ++blk) {
@@ -398,12 +398,13 @@ hipError_t launch_spinor_convert(const Geo& g, const SpinorBuf& src, const Spino
     return hipGetLastError();
 }
 
-hipError_t launch_eo_inverse(const Geo& g, Prec C, const void* clover, double absmu, void* inv, hipStream_t st) {
+hipError_t launch_eo_inverse(const Geo& g, Prec C, const void* clover, double absmu, int parity, void* inv,
+                             hipStream_t st) {
     if (C != P_F64 && C != P_F32) return hipErrorInvalidValue;
     const long long half = g.V / 2;
     const unsigned nb = (unsigned)((half + kThreads - 1) / kThreads);
     TM_DISPATCH_PREC(C, T, hipLaunchKernelGGL(k_eo_inverse<T>, dim3(nb > 0 ? nb : 1), dim3(kThreads), 0, st, g,
-                                              clover, absmu, inv));
+                                              clover, absmu, parity, inv));
     return hipGetLastError();
 }
 

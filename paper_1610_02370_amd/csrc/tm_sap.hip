@@ -339,34 +339,6 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
     }
 }
 
-// out = D_ee^-1 in at an even site: the two 6x6 chiral-block inverses of one
-// inverse set (h = s / 2); adj uses their adjoints (the inverses for -mu).
-template <class C, class R>
-__device__ inline void eo_inverse_apply(const void* inv, long long half, long long h, bool adj, const Spinor<R>& in,
-                                        Spinor<R>& out) {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) out.v[i] = cmk<R>(0, 0);
-#pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-        const cplx<R>* v = in.v + 6 * blk;
-        cplx<R>* o = out.v + 6 * blk;
-#pragma unroll
-        for (int u = 0; u < 18; ++u) {
-            R w[4];
-            Unit<C>::load(inv, (size_t)(18 * blk + u) * half + h, w);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int e = 2 * u + k, i = e / 6, j = e % 6;
-                const cplx<R> m = cmk(w[2 * k], w[2 * k + 1]);
-                if (adj)
-                    o[j] = cjmad(m, v[i], o[j]);
-                else
-                    o[i] = cmad(m, v[j], o[i]);
-            }
-        }
-    }
-}
-
 // Half-sweep with even-odd preconditioned block solves (section 2.5): the
 // block system D_BB e = r is reduced to its odd sites,
 //   rhat_o = r_o - D_oe D_ee^-1 r_e,  Dhat = D_oo - D_oe D_ee^-1 D_eo,

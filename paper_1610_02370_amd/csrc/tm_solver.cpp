@@ -418,6 +418,9 @@ int carve_scratch(Ctx& c) {
     return e == hipSuccess ? TM_OK : hip_fail(e, "scratch init");
 }
 
+
+}  // namespace
+
 // Largest group of systems whose workspace fits in free device memory.
 int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed) {
     int gsz = group > 0 ? std::min(group, nsys) : nsys;
@@ -427,8 +430,6 @@ int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed
     while (gsz > 1 && fixed + per_sys * (size_t)gsz > avail) gsz = (gsz + 1) / 2;
     return gsz;
 }
-
-}  // namespace
 
 }  // namespace tmsap
 
