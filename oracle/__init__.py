@@ -43,6 +43,8 @@ class _Op(ctypes.Structure):
         ("clov", ctypes.c_void_p),
         ("m", ctypes.c_double),
         ("mu", ctypes.c_double),
+        ("theta", ctypes.c_double * 4),
+        ("mu_shift", ctypes.c_double * 2),
     ]
 
 
@@ -132,7 +134,11 @@ class Operator:
     """D(mu) = (m+4) + clover - 1/2 hops + i mu Gamma5 on a periodic lattice."""
 
     def __init__(self, dims, U, m: float, mu: float, csw: float = 0.0, antiperiodic_t: bool = False,
-                 clov: np.ndarray | None = None):
+                 clov: np.ndarray | None = None, theta=(0.0, 0.0, 0.0, 0.0), mu_shift=(0.0, 0.0)):
+        """theta: twisted boundary phases (radians) for t, x, y, z; mu_shift: added to mu on
+        even / odd sites."""
+        self.theta = tuple(float(t) for t in theta)
+        self.mu_shift = tuple(float(t) for t in mu_shift)
         self.dims = tuple(int(d) for d in dims)
         self.V = volume(self.dims)
         self.U = _c128(U).reshape(self.V, 4, 3, 3)
@@ -145,10 +151,12 @@ class Operator:
         else:
             self.clov = None
         self._op = _Op(_i4(self.dims), int(self.antiperiodic_t), self.U.ctypes.data,
-                       self.clov.ctypes.data if self.clov is not None else None, self.m, self.mu)
+                       self.clov.ctypes.data if self.clov is not None else None, self.m, self.mu,
+                       (ctypes.c_double * 4)(*self.theta), (ctypes.c_double * 2)(*self.mu_shift))
 
     def with_mu(self, mu: float) -> "Operator":
-        return Operator(self.dims, self.U, self.m, mu, self.csw, self.antiperiodic_t, self.clov)
+        return Operator(self.dims, self.U, self.m, mu, self.csw, self.antiperiodic_t, self.clov, self.theta,
+                        self.mu_shift)
 
     def _vec(self, v):
         v = _c128(v)

@@ -13,7 +13,10 @@
  *                   gauge covariant; closed form on a constant abelian
  *                   field strength.
  *   or_dirac        plane-wave closed form on the free field (with and
- *                   without constant abelian phases); Gamma5-hermiticity;
+ *                   without constant abelian phases, with twisted boundary
+ *                   phases); twisted boundaries equal periodic ones with the
+ *                   phase on the boundary links; parity shifts of mu equal to
+ *                   each other reduce to a shifted mu; Gamma5-hermiticity;
  *                   D(mu)^+ D(mu) = D(0)^+ D(0) + mu^2; smallest singular
  *                   value >= |mu|; conjugate spectra of +-mu; gauge
  *                   covariance.
@@ -241,10 +244,20 @@ void or_clover(const int dims[4], const or_cplx* U, double csw, or_cplx* clov) {
 
 /* -------------------------------------------------------------- operator */
 
+/* Boundary phase of a hop along mu that crosses the lattice boundary in the
+ * direction dir (+1 forward, -1 backward): exp(i dir theta_mu), times -1 for t
+ * when antiperiodic; 1 when the hop does not cross. */
+static or_cplx bc_phase(const or_op* op, int mu, int dir, int wrapped) {
+    if (!wrapped) return 1.0;
+    or_cplx ph = cexp(_Complex_I * (double)dir * op->theta[mu]);
+    if (mu == 0 && op->antiperiodic_t) ph = -ph;
+    return ph;
+}
+
 /* Contribution of one hop: out += -1/2 (I + sgn*gamma_mu) (x) W  psi_n, with
  * sgn = -1 for the forward hop (W = U_mu(x)) and +1 for the backward hop
- * (W = U_mu(x-mu)^+); phase is -1 across an antiperiodic t boundary. */
-static void add_hop(const or_cplx* gmu, double sgn, const or_cplx* W, const or_cplx* psi_n, double phase,
+ * (W = U_mu(x-mu)^+); phase is the boundary phase of the hop. */
+static void add_hop(const or_cplx* gmu, double sgn, const or_cplx* W, const or_cplx* psi_n, or_cplx phase,
                     or_cplx* out) {
     for (int s = 0; s < 4; ++s)
         for (int c = 0; c < 3; ++c) {
@@ -260,8 +273,12 @@ static void add_hop(const or_cplx* gmu, double sgn, const or_cplx* W, const or_c
         }
 }
 
-/* Diagonal part at one site: (m+4) psi + clov psi + i mu gamma5 psi. */
+static int site_parity(const int dims[4], long s);
+
+/* Diagonal part at one site: (m+4) psi + clov psi + i mu(x) gamma5 psi with
+ * mu(x) = mu + mu_shift[parity of x]. */
 static void add_diag(const or_op* op, const or_cplx* g5, long x, const or_cplx* psi, or_cplx* out) {
+    const double mux = op->mu + op->mu_shift[site_parity(op->dims, x)];
     for (int i = 0; i < 12; ++i) out[i] += (op->m + 4.0) * psi[i];
     if (op->clov) {
         const or_cplx* C = op->clov + (size_t)x * 144;
@@ -274,7 +291,7 @@ static void add_diag(const or_op* op, const or_cplx* g5, long x, const or_cplx* 
     for (int s = 0; s < 4; ++s)
         for (int sp = 0; sp < 4; ++sp) {
             if (g5[4 * s + sp] == 0) continue;
-            for (int c = 0; c < 3; ++c) out[3 * s + c] += _Complex_I * op->mu * g5[4 * s + sp] * psi[3 * sp + c];
+            for (int c = 0; c < 3; ++c) out[3 * s + c] += _Complex_I * mux * g5[4 * s + sp] * psi[3 * sp + c];
         }
 }
 
@@ -307,8 +324,8 @@ static void dirac_generic(const or_op* op, const int* bdims, const or_cplx* in, 
             int wf, wb;
             long xf = neighbour(op->dims, x, mu, +1, &wf);
             long xb = neighbour(op->dims, x, mu, -1, &wb);
-            double pf = (op->antiperiodic_t && mu == 0 && wf) ? -1.0 : 1.0;
-            double pb = (op->antiperiodic_t && mu == 0 && wb) ? -1.0 : 1.0;
+            or_cplx pf = bc_phase(op, mu, +1, wf);
+            or_cplx pb = bc_phase(op, mu, -1, wb);
             if (!bdims || same_block(op->dims, bdims, x, xf))
                 add_hop(g[mu], -1.0, link(op->U, x, mu), in + (size_t)xf * 12, pf, acc);
             if (!bdims || same_block(op->dims, bdims, x, xb)) {
@@ -384,8 +401,8 @@ static void dirac_block_local(const or_op* op, const int bdims[4], const int B[4
             long xb = neighbour(op->dims, x, mu, -1, &wb);
             long lf = local_index(op->dims, bdims, B, xf);
             long lb = local_index(op->dims, bdims, B, xb);
-            double pf = (op->antiperiodic_t && mu == 0 && wf) ? -1.0 : 1.0;
-            double pb = (op->antiperiodic_t && mu == 0 && wb) ? -1.0 : 1.0;
+            or_cplx pf = bc_phase(op, mu, +1, wf);
+            or_cplx pb = bc_phase(op, mu, -1, wb);
             if (lf >= 0) add_hop(g[mu], -1.0, link(op->U, x, mu), in + lf * 12, pf, acc);
             if (lb >= 0) {
                 or_cplx Wd[9];
@@ -738,6 +755,8 @@ void or_dhat_dag(const or_op* op, const or_cplx* in, or_cplx* out) {
             for (int c = 0; c < 3; ++c) v[x * 12 + 3 * s + c] = g5[5 * s] * in[x * 12 + 3 * s + c];
     or_op neg = *op;
     neg.mu = -op->mu;
+    neg.mu_shift[0] = -op->mu_shift[0];
+    neg.mu_shift[1] = -op->mu_shift[1];
     or_dhat(&neg, v, out);
     for (long x = 0; x < n / 12; ++x)
         for (int s = 0; s < 4; ++s)

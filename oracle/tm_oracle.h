@@ -38,6 +38,10 @@ typedef struct {
     const or_cplx* clov;    /* [V][12][12], may be NULL when csw == 0 */
     double m;               /* bare mass: D contains (m + 4) */
     double mu;              /* twisted mass: D contains + i mu Gamma5 */
+    double theta[4];        /* twisted boundary phases (radians), mu = t, x, y, z:
+                               psi(x + L_mu e_mu) = exp(i theta_mu) psi(x); added to the
+                               -1 of antiperiodic_t */
+    double mu_shift[2];     /* added to mu on even / odd sites (parity of t+z+y+x) */
 } or_op;
 
 typedef struct {

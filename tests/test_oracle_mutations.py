@@ -44,6 +44,10 @@ MUTATIONS = {
     "eo_dhat_sign": ("for (long i = 0; i < n; ++i) out[i] = u[i] - w[i];", "for (long i = 0; i < n; ++i) out[i] = u[i] + w[i];"),
     # reduced right-hand side without D_oo^-1 (b_o used directly)
     "eo_cg_rhs_no_inverse": ("diag_solve_parity(op, 1, b, t);\n    or_dirac(op, t, q);", "memcpy(t, b, sizeof(or_cplx) * n);\n    mask_parity(op->dims, 1, t);\n    or_dirac(op, t, q);"),
+    # twisted boundary phase with the wrong sign on backward hops
+    "bc_phase_sign": ("cexp(_Complex_I * (double)dir * op->theta[mu])", "cexp(_Complex_I * op->theta[mu])"),
+    # parity shifts of mu swapped
+    "mu_shift_parity": ("op->mu_shift[site_parity(op->dims, x)]", "op->mu_shift[1 - site_parity(op->dims, x)]"),
     # Givens rotation without the conjugate
     "givens_conj": ("g[j + 1] = -conj(sn[j]) * g[j];", "g[j + 1] = -sn[j] * g[j];"),
 }

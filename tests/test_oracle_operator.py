@@ -274,3 +274,67 @@ def test_singular_values_and_conjugate_spectra():
     cost = np.abs(ep[:, None] - np.conj(em)[None, :])
     r, c = linear_sum_assignment(cost)
     assert cost[r, c].max() < 1e-10
+
+
+# ------------------------------------------------- twisted boundaries, mu shifts
+
+def test_twisted_boundary_plane_waves():
+    # psi(x + L e_mu) = exp(i theta_mu) psi(x): plane waves with p = (2 pi n + theta) / L
+    dims = (4, 6, 4, 8)
+    V = oracle.volume(dims)
+    U = np.broadcast_to(np.eye(3, dtype=complex), (V, 4, 3, 3)).copy()
+    theta = (0.3, -1.1, 2.0, 0.7)
+    rng = np.random.default_rng(9)
+    m, mu = -0.875, 0.01
+    op = oracle.Operator(dims, U, m, mu, theta=theta)
+    X = coords(dims)
+    for n in [(0, 0, 0, 0), (1, 2, 3, 1)]:
+        p = [(2 * np.pi * n[d] + theta[d]) / dir_extent(dims, d) for d in range(4)]
+        chi = rng.normal(size=12) + 1j * rng.normal(size=12)
+        phase = np.exp(1j * (X @ np.asarray(p)))
+        out = op.apply(phase[:, None] * chi[None, :]).reshape(-1, 12)
+        expect = phase[:, None] * (plane_wave_matrix(p, [np.eye(3)] * 4, m, mu) @ chi)[None, :]
+        assert np.abs(out - expect).max() < 1e-13
+
+
+def test_twisted_boundary_equals_phased_boundary_links():
+    # the boundary phase can be moved onto the links that cross the boundary; plaquettes
+    # see it once forward and once backward, so the clover does not change
+    dims = (4, 4, 2, 4)
+    U = synth.gauge_field(dims, 0.5, seed=31)
+    theta = (0.9, -0.4, 1.7, 0.25)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(0.15), 0.02, csw=1.5, theta=theta, antiperiodic_t=True)
+    Up = U.reshape(dims + (4, 3, 3)).copy()
+    axis = {0: 0, 1: 3, 2: 2, 3: 1}
+    for d in range(4):
+        a = axis[d]
+        idx = [slice(None)] * 4
+        idx[a] = dims[a] - 1
+        ph = np.exp(1j * theta[d]) * (-1.0 if d == 0 else 1.0)
+        Up[tuple(idx) + (d,)] *= ph
+    Up = Up.reshape(-1, 4, 3, 3)
+    opp = oracle.Operator(dims, Up, oracle.kappa_to_m(0.15), 0.02, csw=1.5)
+    assert np.abs(opp.clov - op.clov).max() < 1e-13
+    rng = np.random.default_rng(10)
+    v = rng.normal(size=op.V * 12) + 1j * rng.normal(size=op.V * 12)
+    assert np.abs(op.apply(v) - opp.apply(v)).max() < 1e-13
+
+
+def test_mu_shifts_reduce_and_gamma5_hermiticity():
+    dims = (4, 4, 2, 2)
+    U = synth.gauge_field(dims, 0.5, seed=32)
+    m = oracle.kappa_to_m(0.16)
+    rng = np.random.default_rng(11)
+    v = rng.normal(size=oracle.volume(dims) * 12) + 1j * rng.normal(size=oracle.volume(dims) * 12)
+    a = oracle.Operator(dims, U, m, 0.01, csw=1.5, mu_shift=(0.03, 0.03))
+    b = oracle.Operator(dims, U, m, 0.04, csw=1.5)
+    assert np.abs(a.apply(v) - b.apply(v)).max() < 1e-14
+    c = oracle.Operator(dims, U, m, 0.01, csw=1.5, mu_shift=(0.05, -0.02), theta=(0.4, 0, 0, 0))
+    cn = oracle.Operator(dims, U, m, -0.01, csw=1.5, mu_shift=(-0.05, 0.02), theta=(0.4, 0, 0, 0))
+    D, Dn = c.dense(), cn.dense()
+    G5 = np.kron(np.eye(oracle.volume(dims)), np.kron(oracle.gamma(4), np.eye(3)))
+    assert np.abs(D.conj().T - G5 @ Dn @ G5).max() < 1e-14
+    # the shift acts on the sites of its parity only: D - D(no shift) is i mu_p Gamma5 there
+    x = synth.point_sources(dims, [(0, 0)], site=1)[0].ravel()  # site 1 is odd
+    c0 = oracle.Operator(dims, U, m, 0.01, csw=1.5, theta=(0.4, 0, 0, 0))
+    assert np.abs(c.apply(x) - c0.apply(x) - 1j * (-0.02) * (G5 @ x)).max() < 1e-14
