@@ -84,6 +84,12 @@ typedef struct {
     int antiperiodic_t;   /* 1: spinor hops across the t boundary get a factor -1 */
     int nsys;             /* number of systems in psi / b / x (1 .. TM_MAX_SYS) */
     const double* mu;     /* HOST array [nsys]: twisted mass of each system */
+    double theta[4];      /* twisted boundary conditions (radians) for mu = t, x, y, z:
+                             psi(x + L_mu e_mu) = exp(i theta_mu) psi(x), so a hop across the
+                             boundary along +mu takes exp(i theta_mu) and along -mu its conjugate;
+                             combined with antiperiodic_t (which adds pi to theta_t); 0 = periodic */
+    double mu_shift[2];   /* added to every system's mu on even / odd sites (parity of t+z+y+x):
+                             the twist is i (mu_k + mu_shift[parity]) Gamma5; 0 = none */
 } tm_geom;
 
 typedef struct {
@@ -123,7 +129,9 @@ TM_API int tm_gauge_release(const void* U);  /* drops every cached copy derived 
  *       - 1/2 sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)]
  *       + i mu Gamma5,
  * with Q_munu the four-leaf clover of plaquettes.  Periodic in every
- * direction (antiperiodic in t on request).  psi and out must not alias.
+ * direction unless geom->antiperiodic_t / geom->theta twist the boundaries;
+ * geom->mu_shift adds a parity-dependent shift to the twist (both are operator
+ * variants of the library beyond the paper's runs).  psi and out must not alias.
  * Precision: opts->storage / opts->compute; the clover is built in FP64 and
  * rounded to storage (FP32 for FP16/BF16 storage).
  */

@@ -42,7 +42,8 @@ class TMError(RuntimeError):
 
 class Geom(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("antiperiodic_t", ctypes.c_int), ("nsys", ctypes.c_int),
-                ("mu", ctypes.POINTER(ctypes.c_double))]
+                ("mu", ctypes.POINTER(ctypes.c_double)), ("theta", ctypes.c_double * 4),
+                ("mu_shift", ctypes.c_double * 2)]
 
 
 class Opts(ctypes.Structure):
@@ -119,11 +120,15 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_geom(dims: Sequence[int], mu, antiperiodic_t: bool = False):
+def make_geom(dims: Sequence[int], mu, antiperiodic_t: bool = False, theta=None, mu_shift=None):
+    """theta: twisted boundary phases (radians) for t, x, y, z; mu_shift: added to mu on even / odd sites."""
     mus = [float(mu)] if isinstance(mu, (int, float)) else [float(m) for m in mu]
     arr = (ctypes.c_double * len(mus))(*mus)
+    th = [float(t) for t in (theta or (0.0, 0.0, 0.0, 0.0))]
+    ms = [float(t) for t in (mu_shift or (0.0, 0.0))]
     g = Geom((ctypes.c_int * 4)(*[int(d) for d in dims]), int(bool(antiperiodic_t)), len(mus),
-             ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+             ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)), (ctypes.c_double * 4)(*th),
+             (ctypes.c_double * 2)(*ms))
     g._keep = arr
     return g
 
@@ -172,11 +177,12 @@ def tm_gauge_release(U) -> None:
 
 def tm_dirac_apply(dims, U, psi, kappa: float, mu, c_sw: float, out=None, *, storage: str = "f64",
                    antiperiodic_t: bool = False, stream=None, io: str = "canonical", layout_block=None,
+                   theta=None, mu_shift=None,
                    gauge_tag: int = 0):
     """out_k = D(mu_k) psi_k for every system k (psi: [nsys, V, 4, 3] complex128, or internal buffers)."""
     import torch
 
-    g = make_geom(dims, mu, antiperiodic_t)
+    g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts(storage, stream=stream, io=io, layout_block=layout_block, gauge_tag=gauge_tag)
     if out is None:
         out = torch.empty_like(psi)
@@ -189,11 +195,12 @@ def tm_dirac_apply(dims, U, psi, kappa: float, mu, c_sw: float, out=None, *, sto
 
 def tm_sap_smooth(dims, U, b, x, kappa: float, mu, c_sw: float, block_dims, n_cycles: int, mr_iters: int, *,
                   storage: str = "f64", antiperiodic_t: bool = False, stream=None, io: str = "canonical",
+                  theta=None, mu_shift=None,
                   gauge_tag: int = 0, sys_tile: int = 0, eo: bool = False):
     """x <- SAP(b, x): n_cycles red-black cycles, mr_iters MR steps per block (x is in/out).
 
     eo: even-odd preconditioned block solves (MR on the odd-site Schur complement)."""
-    g = make_geom(dims, mu, antiperiodic_t)
+    g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts(storage, stream=stream, io=io, layout_block=block_dims, gauge_tag=gauge_tag)
     o.sys_tile = int(sys_tile)
     o.sap_eo = int(bool(eo))
@@ -219,9 +226,10 @@ def solver_opts(form: str = "flexible", restart: int = 20, max_iters: int = 2000
 
 def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, storage: str = "f32",
                     antiperiodic_t: bool = False, stream=None, gauge_tag: int = 0, sys_tile: int = 0,
+                    theta=None, mu_shift=None,
                     eo: bool = False, **solver_kw):
     """Solve D(mu_k) x_k = b_k to a true relative residual tol; returns (status, report dict)."""
-    g = make_geom(dims, mu, antiperiodic_t)
+    g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts(storage, stream=stream, gauge_tag=gauge_tag)
     o.sys_tile = int(sys_tile)
     o.sap_eo = int(bool(eo))
@@ -238,9 +246,9 @@ def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *,
 
 
 def tm_cg_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, max_iters: int = 100000,
-                antiperiodic_t: bool = False, stream=None, gauge_tag: int = 0):
+                antiperiodic_t: bool = False, theta=None, mu_shift=None, stream=None, gauge_tag: int = 0):
     """CG on the squared even-odd reduced system (FP64 baseline); returns (status, report dict)."""
-    g = make_geom(dims, mu, antiperiodic_t)
+    g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts("f64", stream=stream, gauge_tag=gauge_tag)
     rep = Report()
     rc = _check(lib().tm_cg_solve(ctypes.byref(g), _canon(U, "U"), _canon(b, "b"), _canon(x, "x"), float(kappa),

@@ -100,6 +100,10 @@ int check_geom(const tm_geom* geom) {
     if (geom->nsys < 1 || geom->nsys > TM_MAX_SYS)
         return fail(TM_ERR_ARG, "nsys = %d outside 1..%d", geom->nsys, TM_MAX_SYS);
     if (!geom->mu) return fail(TM_ERR_ARG, "geom->mu is NULL");
+    for (int a = 0; a < 4; ++a)
+        if (!std::isfinite(geom->theta[a])) return fail(TM_ERR_NONFINITE, "theta[%d] is not finite", a);
+    if (!std::isfinite(geom->mu_shift[0]) || !std::isfinite(geom->mu_shift[1]))
+        return fail(TM_ERR_NONFINITE, "mu_shift is not finite");
     for (int k = 0; k < geom->nsys; ++k)
         if (!std::isfinite(geom->mu[k])) return fail(TM_ERR_NONFINITE, "mu[%d] is not finite", k);
     return TM_OK;
@@ -146,7 +150,18 @@ Geo make_geo(const tm_geom* geom, const int tile[4]) {
         g.V *= geom->dims[a];
         g.Vb *= tile[a];
     }
-    g.antiperiodic_t = geom->antiperiodic_t ? 1 : 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        double th = geom->theta[mu];
+        if (mu == 0 && geom->antiperiodic_t) th += M_PI;
+        g.bcr[mu] = std::cos(th);
+        g.bci[mu] = std::sin(th);
+        if (geom->theta[mu] == 0.0) {  // exact signs for the plain boundaries
+            g.bcr[mu] = (mu == 0 && geom->antiperiodic_t) ? -1.0 : 1.0;
+            g.bci[mu] = 0.0;
+        }
+    }
+    g.mu_shift[0] = geom->mu_shift[0];
+    g.mu_shift[1] = geom->mu_shift[1];
     return g;
 }
 
@@ -305,7 +320,9 @@ int prepare_site_inverses(const Geo& g, const GaugeDev& G, const double* mu, int
 }
 
 static int prepare_eo(const Geo& g, const GaugeDev& G, const double* mu, int nsys, hipStream_t st, SapArgs& a) {
-    return prepare_site_inverses(g, G, mu, nsys, 0, st, a.eo_inv, a.eo_sel, &a.eo_adj);
+    double mue[kMaxSys];  // the twist on the even sites, whose inverses the block solves use
+    for (int k = 0; k < nsys; ++k) mue[k] = mu[k] + g.mu_shift[0];
+    return prepare_site_inverses(g, G, mue, nsys, 0, st, a.eo_inv, a.eo_sel, &a.eo_adj);
 }
 
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,

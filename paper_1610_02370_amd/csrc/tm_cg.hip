@@ -45,12 +45,12 @@ __global__ void __launch_bounds__(kThreads) k_parity_op(ParityArgs a) {
     if (h >= half) return;
     unsigned s = 2u * (unsigned)h;
     if (site_parity_tiled(g, s) != a.p) ++s;
-    int nf[4], nbk[4];
-    float sf[4], sb[4];
-    if (HOP) tiled_neighbours(g, s, nf, nbk, sf, sb);
+    int nf[4], nbk[4], par = a.p;
+    unsigned wrap = 0;
+    if (HOP) tiled_neighbours(g, s, nf, nbk, &wrap, &par);
     const size_t vs = (size_t)6 * half;  // units per system
     for (int sys = 0; sys < a.nsys; ++sys) {
-        const double mu = a.mu_sign * a.mu[sys];
+        const double mu = a.mu_sign * (a.mu[sys] + g.mu_shift[a.p]);
         Spinor<double> v;
 #pragma unroll
         for (int i = 0; i < 12; ++i) v.v[i] = cmk(0.0, 0.0);
@@ -74,11 +74,25 @@ __global__ void __launch_bounds__(kThreads) k_parity_op(ParityArgs a) {
                 load_link<double, double>(a.links, g.V, s, m, L);
                 load_spinor<double, double>(in, nullptr, half, nf[m] >> 1, p);
                 if (G5HOP) gamma5(p);
-                hop_forward(m, L, p, (double)sf[m], acc);
+                {  // boundary phase (1 inside the lattice), branch-free: fewer registers
+                    const bool w = wrap & (1u << m);
+                    const double re = w ? g.bcr[m] : 1.0, im = w ? g.bci[m] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < 12; ++i)
+                        p.v[i] = cmk(re * p.v[i].re - im * p.v[i].im, re * p.v[i].im + im * p.v[i].re);
+                }
+                hop_forward(m, L, p, 1.0, acc);
                 load_link<double, double>(a.links, g.V, nbk[m], m, L);
                 load_spinor<double, double>(in, nullptr, half, nbk[m] >> 1, p);
                 if (G5HOP) gamma5(p);
-                hop_backward(m, L, p, (double)sb[m], acc);
+                {
+                    const bool w = wrap & (16u << m);
+                    const double re = w ? g.bcr[m] : 1.0, im = w ? -g.bci[m] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < 12; ++i)
+                        p.v[i] = cmk(re * p.v[i].re - im * p.v[i].im, re * p.v[i].im + im * p.v[i].re);
+                }
+                hop_backward(m, L, p, 1.0, acc);
             }
 #pragma unroll
             for (int i = 0; i < 12; ++i) v.v[i] = v.v[i] + (-0.5 * a.hop_sign) * acc.v[i];

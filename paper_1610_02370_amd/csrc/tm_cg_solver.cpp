@@ -145,7 +145,9 @@ int tm_cg_solve(const tm_geom* geom, const void* U, const void* b, void* x, doub
         for (int k = 0; k < kMaxSys; ++k) c.mu[k] = k < ns ? geom->mu[g0 + k] : 0.0;
         unsigned long long adj = 0;  // the kernels take the adjoint from the sign of the effective mu
         for (int k = 0; k < kMaxEoMu; ++k) c.inv[k] = nullptr;
-        if ((rc = prepare_site_inverses(g, *G, c.mu, ns, 1, st, c.inv, c.sel, &adj))) return rc;
+        double muo[kMaxSys];  // the twist on the odd sites, whose inverses D_oo^-1 uses
+        for (int k = 0; k < ns; ++k) muo[k] = c.mu[k] + g.mu_shift[1];
+        if ((rc = prepare_site_inverses(g, *G, muo, ns, 1, st, c.inv, c.sel, &adj))) return rc;
 
         hipError_t h = ds->solver.ensure(8 * cfield * ns);
         if (h != hipSuccess) return hip_fail(h, "CG workspace");

@@ -131,8 +131,12 @@ struct Geo {
     int nb[4];   // tiles per axis
     int Vb;      // sites per tile
     long long V; // sites
-    int antiperiodic_t;
+    double bcr[4], bci[4];  // boundary phase of a forward hop across the lattice boundary along mu
+                            // (a backward one takes the conjugate): exp(i theta_mu), -1 for
+                            // antiperiodic t
+    double mu_shift[2];     // added to the twisted mass on even / odd sites
 };
+
 
 // Array axis of direction mu (t, x, y, z) -> (0, 3, 2, 1).
 __host__ __device__ inline int axis_of(int mu) { return mu == 0 ? 0 : 4 - mu; }
@@ -161,28 +165,32 @@ __host__ __device__ inline long long coords_site(const Geo& g, const int c[4]) {
     return blk * g.Vb + l;
 }
 
-// The 8 neighbours of site s in the tiled layout, s +- mu (periodic), and
-// the sign (-1 across an antiperiodic t boundary).  32-bit arithmetic: the
-// library limits the volume to 2^29 sites.  In-tile neighbours are s plus a
-// fixed stride; across a tile face the local coordinate wraps and the tile
-// index steps (with the lattice's periodic wrap).
-__device__ inline void tiled_neighbours(const Geo& g, long long s, int nf[4], int nbk[4], float sf[4],
-                                        float sb[4]) {
+// The 8 neighbours of site s in the tiled layout, s +- mu (periodic), the
+// hops that cross the lattice boundary (bit mu forward, bit 4+mu backward) and
+// the parity of s.  32-bit arithmetic: the library limits the volume to 2^29
+// sites.  In-tile neighbours are s plus a fixed stride; across a tile face the
+// local coordinate wraps and the tile index steps (with the lattice's
+// periodic wrap).
+__device__ inline void tiled_neighbours(const Geo& g, long long s, int nf[4], int nbk[4], unsigned* wrap,
+                                        int* parity) {
     const unsigned su = (unsigned)s;
     const unsigned Vb = (unsigned)g.Vb;
     const unsigned blk = su / Vb;
     const unsigned l = su - blk * Vb;
     int L[4], B[4];
     unsigned t = l, tb = blk;
+    int csum = 0;
 #pragma unroll
     for (int a = 3; a >= 0; --a) {
         const unsigned lb = (unsigned)g.lb[a], nb = (unsigned)g.nb[a];
         const unsigned tq = t / lb, bq = tb / nb;
         L[a] = (int)(t - tq * lb);
         B[a] = (int)(tb - bq * nb);
+        csum += B[a] * g.lb[a] + L[a];
         t = tq;
         tb = bq;
     }
+    *parity = csum & 1;
     int ls[4], bs[4];
     ls[3] = 1;
     bs[3] = 1;
@@ -191,17 +199,17 @@ __device__ inline void tiled_neighbours(const Geo& g, long long s, int nf[4], in
         ls[a] = ls[a + 1] * g.lb[a + 1];
         bs[a] = bs[a + 1] * g.nb[a + 1];
     }
+    unsigned w = 0;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const int a = axis_of(mu);
-        sf[mu] = sb[mu] = 1.f;
         if (L[a] + 1 < g.lb[a]) {
             nf[mu] = (int)su + ls[a];
         } else {
             int bn = (int)blk + bs[a];
             if (B[a] + 1 == g.nb[a]) {
                 bn -= g.nb[a] * bs[a];
-                if (mu == 0 && g.antiperiodic_t) sf[mu] = -1.f;
+                w |= 1u << mu;
             }
             nf[mu] = bn * g.Vb + (int)l - (g.lb[a] - 1) * ls[a];
         }
@@ -211,11 +219,12 @@ __device__ inline void tiled_neighbours(const Geo& g, long long s, int nf[4], in
             int bn = (int)blk - bs[a];
             if (B[a] == 0) {
                 bn += g.nb[a] * bs[a];
-                if (mu == 0 && g.antiperiodic_t) sb[mu] = -1.f;
+                w |= 1u << (4 + mu);
             }
             nbk[mu] = bn * g.Vb + (int)l + (g.lb[a] - 1) * ls[a];
         }
     }
+    *wrap = w;
 }
 
 // Lexicographic (canonical) index of coordinates.
@@ -296,6 +305,15 @@ template <class R> __device__ inline void su3_dag_mul(const Link<R>& L, const Ha
 template <class R> struct Spinor {
     cplx<R> v[12];
 };
+
+// p <- phase p for a hop along mu that crosses the lattice boundary
+// (dir = +1 forward, -1 backward).
+template <class R>
+__device__ inline void apply_bc(const Geo& g, int mu, int dir, Spinor<R>& p) {
+    const R re = (R)g.bcr[mu], im = dir > 0 ? (R)g.bci[mu] : -(R)g.bci[mu];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) p.v[i] = cmk(re * p.v[i].re - im * p.v[i].im, re * p.v[i].im + im * p.v[i].re);
+}
 
 // Hop accumulators: the operator adds -1/2 (hu; hd) at the end.
 // Forward hop into x from x+mu: (1 - gamma_mu) U_mu(x) psi(x+mu):

@@ -17,9 +17,9 @@ __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
     const Geo& g = a.g;
     long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
-    int nf[4], nbk[4];
-    float sf[4], sb[4];
-    tiled_neighbours(g, s, nf, nbk, sf, sb);
+    int nf[4], nbk[4], par;
+    unsigned wrap;
+    tiled_neighbours(g, s, nf, nbk, &wrap, &par);
     Clover<R> A;
     load_clover<R, C>(a.clover, g.V, s, A);
     const size_t in_stride = (size_t)6 * g.V * Unit<Si>::bytes;
@@ -36,14 +36,26 @@ __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
             Spinor<R> p;
             load_link<R, G>(a.links, g.V, s, mu, L);
             load_spinor<R, Si>(in, isc, g.V, nf[mu], p);
-            hop_forward(mu, L, p, (R)sf[mu], acc);
+            {  // boundary phase (1 for hops inside the lattice), branch-free: fewer registers
+                const bool w = wrap & (1u << mu);
+                const R re = w ? (R)g.bcr[mu] : (R)1, im = w ? (R)g.bci[mu] : (R)0;
+#pragma unroll
+                for (int i = 0; i < 12; ++i) p.v[i] = cmk(re * p.v[i].re - im * p.v[i].im, re * p.v[i].im + im * p.v[i].re);
+            }
+            hop_forward(mu, L, p, (R)1, acc);
             load_link<R, G>(a.links, g.V, nbk[mu], mu, L);
             load_spinor<R, Si>(in, isc, g.V, nbk[mu], p);
-            hop_backward(mu, L, p, (R)sb[mu], acc);
+            {
+                const bool w = wrap & (16u << mu);
+                const R re = w ? (R)g.bcr[mu] : (R)1, im = w ? -(R)g.bci[mu] : (R)0;
+#pragma unroll
+                for (int i = 0; i < 12; ++i) p.v[i] = cmk(re * p.v[i].re - im * p.v[i].im, re * p.v[i].im + im * p.v[i].re);
+            }
+            hop_backward(mu, L, p, (R)1, acc);
         }
         Spinor<R> self, out;
         load_spinor<R, Si>(in, isc, g.V, s, self);
-        clover_apply(A, (R)a.mu[sys], self, out);
+        clover_apply(A, (R)(a.mu[sys] + g.mu_shift[par]), self, out);
 #pragma unroll
         for (int i = 0; i < 12; ++i) out.v[i] = out.v[i] - (R)0.5 * acc.v[i];
         store_spinor<R, So>(reinterpret_cast<char*>(a.out) + sys * out_stride,

@@ -111,13 +111,14 @@ __device__ inline void lds_get(const R* sh, int stride, int l, Spinor<R>& p) {
 
 // Per-thread geometry of the generic kernel: the thread's site, its
 // neighbours as local indices inside the block (-1 when outside) or global
-// sites outside it, the antiperiodic signs, and the site parity.
+// sites outside it, the hops that cross the lattice boundary (bit mu forward,
+// bit 4+mu backward), and the site parity.
 template <class R>
 struct GenSite {
     long long s, s0;  // site, first site of the block
     int nlf[4], nlb[4];
     long long ngf[4], ngb[4];
-    R sgf[4], sgb[4];
+    unsigned wrap;
     int parity;  // (t + z + y + x) mod 2 of the global coordinates
 };
 
@@ -155,10 +156,10 @@ __device__ inline void gen_site_setup(const Geo& g, int colour, int l, bool acti
     int c[4];
     for (int q = 0; q < 4; ++q) c[q] = Bc[q] * g.lb[q] + Lc[q];
     t.parity = (c[0] + c[1] + c[2] + c[3]) & 1;
+    t.wrap = 0;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const int ax = axis_of(mu);
-        t.sgf[mu] = t.sgb[mu] = (R)1;
         if (Lc[ax] + 1 < g.lb[ax]) {
             t.nlf[mu] = l + lstride[ax];
             t.ngf[mu] = 0;
@@ -167,7 +168,7 @@ __device__ inline void gen_site_setup(const Geo& g, int colour, int l, bool acti
             int n[4] = {c[0], c[1], c[2], c[3]};
             if (++n[ax] == g.d[ax]) {
                 n[ax] = 0;
-                if (mu == 0 && g.antiperiodic_t) t.sgf[mu] = (R)-1;
+                t.wrap |= 1u << mu;
             }
             t.ngf[mu] = coords_site(g, n);
         }
@@ -179,7 +180,7 @@ __device__ inline void gen_site_setup(const Geo& g, int colour, int l, bool acti
             int n[4] = {c[0], c[1], c[2], c[3]};
             if (--n[ax] < 0) {
                 n[ax] = g.d[ax] - 1;
-                if (mu == 0 && g.antiperiodic_t) t.sgb[mu] = (R)-1;
+                t.wrap |= 16u << mu;
             }
             t.ngb[mu] = coords_site(g, n);
         }
@@ -217,22 +218,25 @@ __device__ inline void gen_residual(const SapArgs& a, const GenSite<R>& t, const
             Spinor<R> p;
             if (t.nlf[mu] < 0 || own) {
                 load_link<R, G>(a.links, g.V, t.s, mu, Lk);
-                if (t.nlf[mu] >= 0)
+                if (t.nlf[mu] >= 0) {
                     lds_get(sh, nt, t.nlf[mu], p);
-                else
+                } else {
                     load_spinor<R, S>(xx, xsc, g.V, t.ngf[mu], p);
-                hop_forward(mu, Lk, p, t.sgf[mu], acc);
+                    if (t.wrap & (1u << mu)) apply_bc(g, mu, +1, p);
+                }
+                hop_forward(mu, Lk, p, (R)1, acc);
             }
             if (t.nlb[mu] >= 0) {
                 if (own) {
                     lds_get(sh, nt, t.nlb[mu], p);
                     load_link<R, G>(a.links, g.V, t.s0 + t.nlb[mu], mu, Lk);
-                    hop_backward(mu, Lk, p, t.sgb[mu], acc);
+                    hop_backward(mu, Lk, p, (R)1, acc);
                 }
             } else {
                 load_spinor<R, S>(xx, xsc, g.V, t.ngb[mu], p);
+                if (t.wrap & (16u << mu)) apply_bc(g, mu, -1, p);
                 load_link<R, G>(a.links, g.V, t.ngb[mu], mu, Lk);
-                hop_backward(mu, Lk, p, t.sgb[mu], acc);
+                hop_backward(mu, Lk, p, (R)1, acc);
             }
         }
         if (own) {
@@ -257,15 +261,15 @@ __device__ inline void gen_block_hops(const SapArgs& a, const GenSite<R>& t, con
     for (int mu = 0; mu < 4; ++mu) {
         Link<R> Lk;
         Spinor<R> p;
-        if (t.nlf[mu] >= 0) {
+        if (t.nlf[mu] >= 0) {  // in-block hops never cross the lattice boundary
             load_link<R, G>(a.links, a.g.V, t.s, mu, Lk);
             lds_get(sh, nt, t.nlf[mu], p);
-            hop_forward(mu, Lk, p, t.sgf[mu], acc);
+            hop_forward(mu, Lk, p, (R)1, acc);
         }
         if (t.nlb[mu] >= 0) {
             load_link<R, G>(a.links, a.g.V, t.s0 + t.nlb[mu], mu, Lk);
             lds_get(sh, nt, t.nlb[mu], p);
-            hop_backward(mu, Lk, p, t.sgb[mu], acc);
+            hop_backward(mu, Lk, p, (R)1, acc);
         }
     }
 }
@@ -290,7 +294,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
     const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
 
     for (int sys = sys_begin; sys < sys_end; ++sys) {
-        const R mu_tw = (R)a.mu[sys];
+        const R mu_tw = (R)(a.mu[sys] + g.mu_shift[t.parity]);
         const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
         void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
         const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
@@ -368,7 +372,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
     const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
 
     for (int sys = sys_begin; sys < sys_end; ++sys) {
-        const R mu_tw = (R)a.mu[sys];
+        const R mu_tw = (R)(a.mu[sys] + g.mu_shift[t.parity]);
         const void* inv = a.eo_inv[a.eo_sel[sys]];
         const bool adj = (a.eo_adj >> sys) & 1ull;
         const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
@@ -702,7 +706,8 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
     const bool stage_halo = nhalo <= kHaloMax;
     int hent_f[4], hent_b[4];
     long long nbk[4];
-    float sgf[4], sgb[4];
+    unsigned wrap = 0;  // hops that cross the lattice boundary: bit mu forward, bit 4+mu backward
+    int parity = 0;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const int ax = axis_of(mu);
@@ -713,8 +718,9 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
         hent_b[mu] = hoff[2 * ax] + p;
         int c[4];
         for (int q = 0; q < 4; ++q) c[q] = Bc[q] * g.lb[q] + Lc[q];
-        sgf[mu] = (mu == 0 && g.antiperiodic_t && c[0] == g.d[0] - 1) ? -1.f : 1.f;
-        sgb[mu] = (mu == 0 && g.antiperiodic_t && c[0] == 0) ? -1.f : 1.f;
+        if (mu == 0) parity = (c[0] + c[1] + c[2] + c[3]) & 1;
+        if (c[ax] == g.d[ax] - 1) wrap |= 1u << mu;
+        if (c[ax] == 0) wrap |= 16u << mu;
         c[ax] = c[ax] == 0 ? g.d[ax] - 1 : c[ax] - 1;
         nbk[mu] = coords_site(g, c);
     }
@@ -738,7 +744,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
     const bool halo = !(a.own_zero && a.halo_zero);
 
     for (int sys = sys_begin; sys < sys_end; ++sys) {
-        const float mu_tw = (float)a.mu[sys];
+        const float mu_tw = (float)(a.mu[sys] + g.mu_shift[parity]);
         const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
         void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
         const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
@@ -803,7 +809,8 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
 #pragma unroll
                         for (int i = 0; i < 12; ++i)
                             p.v[i] = cmk(hb[(2 * i) * kHaloMax + hent_f[mu]], hb[(2 * i + 1) * kHaloMax + hent_f[mu]]);
-                        hop_forward(mu, Uo[mu], p, sgf[mu], acc);
+                        if (wrap & (1u << mu)) apply_bc(g, mu, +1, p);
+                        hop_forward(mu, Uo[mu], p, 1.f, acc);
                     }
                     if (!bin[mu]) {
                         Spinor<float> p;
@@ -812,7 +819,8 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
                             p.v[i] = cmk(hb[(2 * i) * kHaloMax + hent_b[mu]], hb[(2 * i + 1) * kHaloMax + hent_b[mu]]);
                         Link<float> L;
                         expand_link(Lb[mu], L);
-                        hop_backward(mu, L, p, sgb[mu], acc);
+                        if (wrap & (16u << mu)) apply_bc(g, mu, -1, p);
+                        hop_backward(mu, L, p, 1.f, acc);
                     }
                 }
             }
@@ -825,28 +833,22 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
                 int n[4];
                 for (int q = 0; q < 4; ++q) n[q] = Bcc[q] * g.lb[q] + Lc[q];
                 if (!fin[mu]) {
-                    float sg = 1.f;
-                    if (++n[ax] == g.d[ax]) {
-                        n[ax] = 0;
-                        if (mu == 0 && g.antiperiodic_t) sg = -1.f;
-                    }
+                    if (++n[ax] == g.d[ax]) n[ax] = 0;
                     Spinor<float> p;
                     load_spinor<float, S>(xx, xsc, g.V, coords_site(g, n), p);
-                    hop_forward(mu, Uo[mu], p, sg, acc);
+                    if (wrap & (1u << mu)) apply_bc(g, mu, +1, p);
+                    hop_forward(mu, Uo[mu], p, 1.f, acc);
                     n[ax] = Bcc[ax] * g.lb[ax] + Lc[ax];
                 }
                 if (!bin[mu]) {
-                    float sg = 1.f;
-                    if (--n[ax] < 0) {
-                        n[ax] = g.d[ax] - 1;
-                        if (mu == 0 && g.antiperiodic_t) sg = -1.f;
-                    }
+                    if (--n[ax] < 0) n[ax] = g.d[ax] - 1;
                     const long long nb = coords_site(g, n);
                     Spinor<float> p;
                     Link<float> Lk;
                     load_spinor<float, S>(xx, xsc, g.V, nb, p);
                     load_link<float, G>(a.links, g.V, nb, mu, Lk);
-                    hop_backward(mu, Lk, p, sg, acc);
+                    if (wrap & (16u << mu)) apply_bc(g, mu, -1, p);
+                    hop_backward(mu, Lk, p, 1.f, acc);
                 }
             }
         }
@@ -965,7 +967,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
     const int wax = __builtin_amdgcn_readfirstlane(l >> 6);
     const int hp = l & 63;
     int up_site, dn_site;
-    float up_sign = 1.f, dn_sign = 1.f;
+    bool up_wrap, dn_wrap;  // the staged hop crosses the lattice boundary
     {
         int c[4];
         int p = hp;
@@ -980,12 +982,12 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
         bool wrap = false;
         if (c[wax] >= g.d[wax]) { c[wax] -= g.d[wax]; wrap = true; }
         up_site = (int)coords_site(g, c);
-        if (wrap && wax == 0 && g.antiperiodic_t) up_sign = -1.f;
+        up_wrap = wrap;
         c[wax] = Bc[wax] * 4 - 1;
         wrap = false;
         if (c[wax] < 0) { c[wax] += g.d[wax]; wrap = true; }
         dn_site = (int)coords_site(g, c);
-        if (wrap && wax == 0 && g.antiperiodic_t) dn_sign = -1.f;
+        dn_wrap = wrap;
     }
     const int wmu = wax == 0 ? 0 : 4 - wax;
     Link<float> Ldn;  // U_mu(site below the lower face)
@@ -1006,7 +1008,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
     const bool halo = !(a.own_zero && a.halo_zero);
 
     for (int sys = sys_begin; sys < sys_end; ++sys) {
-        const float mu_tw = (float)a.mu[sys];
+        const float mu_tw = (float)(a.mu[sys] + g.mu_shift[(Lc[0] + Lc[1] + Lc[2] + Lc[3]) & 1]);
         const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
         void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
         const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
@@ -1023,14 +1025,14 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
             load_spinor<float, S>(xx, xsc, g.V, up_site, hu);
             load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
             v2_push(sx, l, true, fin, Uo, e);
-#pragma unroll
-            for (int i = 0; i < 12; ++i) hu.v[i] = up_sign * hu.v[i];
+            if (up_wrap) apply_bc(g, wmu, +1, hu);
+            if (dn_wrap) apply_bc(g, wmu, -1, hd);
             v2_put_spinor(sm.hf, l, hu);
             switch (wax) {
-                case 0: s44_stage_backward<0>(Ldn, hd, dn_sign, sm.hb, l); break;
-                case 1: s44_stage_backward<3>(Ldn, hd, dn_sign, sm.hb, l); break;
-                case 2: s44_stage_backward<2>(Ldn, hd, dn_sign, sm.hb, l); break;
-                default: s44_stage_backward<1>(Ldn, hd, dn_sign, sm.hb, l); break;
+                case 0: s44_stage_backward<0>(Ldn, hd, 1.f, sm.hb, l); break;
+                case 1: s44_stage_backward<3>(Ldn, hd, 1.f, sm.hb, l); break;
+                case 2: s44_stage_backward<2>(Ldn, hd, 1.f, sm.hb, l); break;
+                default: s44_stage_backward<1>(Ldn, hd, 1.f, sm.hb, l); break;
             }
             __syncthreads();
             Spinor<float> acc;
