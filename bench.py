@@ -14,7 +14,8 @@ Printed on one JSON line:
   roofline         the dominant kernel (SAP half-sweep) against its binding
                    peak, with algorithmic bytes / flops per launch
   solve            time per RHS of the batched mixed-precision solve vs the
-                   plain FP64 single-RHS solve, both to 1e-10
+                   plain FP64 single-RHS solve and the FP64 CG on the squared
+                   even-odd reduced system, all to 1e-10
   cpu_baseline     the FP64 CPU oracle's SAP on a bounded sample of the same
                    workload, on the host cores
 """
@@ -267,6 +268,25 @@ def fp64_baseline(wl, Ud, torch, tm):
     return {"s_per_rhs": dt, "iters": rep["iters"], "true_rel_res": rep["true_rel_res"][0], "status": rc}
 
 
+def cg_baseline(wl, Ud, torch, tm):
+    """FP64 CG on the squared even-odd reduced system (the paper's comparison solver), one point source."""
+    import numpy as np
+
+    dims = wl["dims"]
+    V = int(np.prod(dims))
+    b = torch.zeros((1, V, 4, 3), dtype=torch.complex128, device="cuda")
+    s, c, sg = wl["sources"][0]
+    b[0, 0, s, c] = 1.0
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, rep = tm.tm_cg_solve(dims, Ud, b, x, wl["kappa"], [sg * wl["mu"]], wl["csw"], TOL, max_iters=100000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del b, x
+    return {"s_per_rhs": dt, "iters": rep["iters"], "true_rel_res": rep["true_rel_res"][0], "status": rc}
+
+
 def cpu_baseline(wl, target_s: float = 12.0):
     """FP64 CPU oracle SAP cycles (4^4 blocks, 4 MR steps, one system) on a 16^3 x 32
     sample of the workload (same eps, kappa, mu, c_sw), all host threads."""
@@ -317,6 +337,7 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time SAP cycles with every system in one launch")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cg-baseline", action="store_true")
     ap.add_argument("--sweep-only", action="store_true", help="only the all-systems SAP sweep (profiling)")
     ap.add_argument("--eo", action="store_true",
                     help="even-odd preconditioned SAP block solves (section 2.5) instead of MR on the full block")
@@ -391,6 +412,10 @@ def main():
     fp64 = None if args.no_fp64_baseline else fp64_baseline(wl, Ud, torch, tm)
     if fp64:
         log(f"FP64 1-RHS solve: {fp64['s_per_rhs']:.2f}s iters {fp64['iters']} res {fp64['true_rel_res']:.2e}")
+    cg = None if args.no_cg_baseline else cg_baseline(wl, Ud, torch, tm)
+    if cg:
+        log(f"FP64 CG (even-odd normal equations) 1-RHS: {cg['s_per_rhs']:.2f}s iters {cg['iters']} "
+            f"res {cg['true_rel_res']:.2e}")
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     if cpu:
         log(f"CPU oracle: {cpu['value']:.3f} GB/s-equivalent on {cpu['cores']} threads")
@@ -440,7 +465,10 @@ def main():
                   "max_true_rel_res": max(max(r["true_rel_res"]) for _, r in reps),
                   "s_per_rhs_fp64_1rhs": fp64["s_per_rhs"] if fp64 else None,
                   "fp64_iters": fp64["iters"] if fp64 else None,
-                  "speedup_per_rhs": (fp64["s_per_rhs"] / t_rhs) if fp64 else None},
+                  "speedup_per_rhs": (fp64["s_per_rhs"] / t_rhs) if fp64 else None,
+                  "s_per_rhs_cg_fp64": cg["s_per_rhs"] if cg else None,
+                  "cg_iters": cg["iters"] if cg else None,
+                  "speedup_per_rhs_over_cg": (cg["s_per_rhs"] / t_rhs) if cg else None},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
