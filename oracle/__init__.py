@@ -57,6 +57,23 @@ class _Report(ctypes.Structure):
     ]
 
 
+class _MG(ctypes.Structure):
+    _fields_ = [
+        ("adims", ctypes.c_int * 4),
+        ("nv", ctypes.c_int),
+        ("delta", ctypes.c_double),
+        ("coarse_tol", ctypes.c_double),
+        ("coarse_restart", ctypes.c_int),
+        ("coarse_max_restarts", ctypes.c_int),
+        ("post_cycles", ctypes.c_int),
+        ("mr_iters", ctypes.c_int),
+        ("setup_iters", ctypes.c_int),
+        ("setup_cycles", ctypes.c_int),
+        ("P", ctypes.c_void_p),
+        ("Dc", ctypes.c_void_p),
+    ]
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -92,6 +109,21 @@ def _load():
         lib.or_dhat_dag.argtypes = [ctypes.POINTER(_Op), vp, vp]
         lib.or_cg_eo.argtypes = [ctypes.POINTER(_Op), vp, vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Report)]
         lib.or_cg_eo.restype = ctypes.c_int
+        cp = ctypes.c_void_p
+        lib.or_mg_block_orthonormalize.argtypes = [ip, ip, ctypes.c_int, vp, vp]
+        lib.or_mg_restrict.argtypes = [ip, ip, ctypes.c_int, vp, vp, vp]
+        lib.or_mg_prolong.argtypes = [ip, ip, ctypes.c_int, vp, vp, vp]
+        lib.or_mg_coarse_build.argtypes = [ctypes.POINTER(_Op), ip, ctypes.c_int, vp, vp]
+        lib.or_mg_coarse_apply.argtypes = [ip, ctypes.c_int, vp, ctypes.c_double, vp, vp]
+        lib.or_mg_coarse_gmres.argtypes = [ip, ctypes.c_int, vp, ctypes.c_double, vp, vp, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Report)]
+        lib.or_mg_coarse_gmres.restype = ctypes.c_int
+        lib.or_mg_precond.argtypes = [ctypes.POINTER(_Op), ctypes.POINTER(_MG), vp, vp]
+        lib.or_fgmres_mg.argtypes = [ctypes.POINTER(_Op), ctypes.POINTER(_MG), vp, vp, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, ctypes.POINTER(_Report)]
+        lib.or_fgmres_mg.restype = ctypes.c_int
+        lib.or_mg_setup.argtypes = [ctypes.POINTER(_Op), ctypes.POINTER(_MG), vp, cp]
+        lib.or_mg_setup.restype = ctypes.c_int
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -262,3 +294,101 @@ def num_threads() -> int:
 
 def set_num_threads(n: int) -> None:
     _load().or_set_num_threads(int(n))
+
+
+class MG:
+    """Two-level method of sections 2.3-2.6 on one Operator's lattice.
+
+    Aggregates: blocks `adims` x spin halves ({0,1}, {2,3}) x colour.  P holds
+    nv lattice vectors [nv][V][4][3] orthonormal on every aggregate; a coarse
+    vector is [nc][2 nv] (coarse sites lexicographic in block coordinates,
+    component sg*nv + i); Dc [nc][9][2nv][2nv] is the Galerkin stencil without
+    the twist (term 0 = the site, 1 + mu = from one aggregate forward along mu,
+    5 + mu = backward); the coarse operator is Dc + i delta mu Gamma5c.
+    """
+
+    def __init__(self, op: Operator, adims, nv: int, delta: float = 1.0, coarse_tol: float = 0.1,
+                 coarse_restart: int = 100, coarse_max_restarts: int = 5, post_cycles: int = 4, mr_iters: int = 4,
+                 setup_iters: int = 0, setup_cycles: int = 4):
+        self.op = op
+        self.adims = tuple(int(a) for a in adims)
+        self.nv = int(nv)
+        self.cdims = tuple(d // a for d, a in zip(op.dims, self.adims))
+        self.nc = volume(self.cdims)
+        self.P = np.zeros((self.nv, op.V, 4, 3), np.complex128)
+        self.Dc = np.zeros((self.nc, 9, 2 * self.nv, 2 * self.nv), np.complex128)
+        self._mg = _MG(_i4(self.adims), self.nv, float(delta), float(coarse_tol), int(coarse_restart),
+                       int(coarse_max_restarts), int(post_cycles), int(mr_iters), int(setup_iters), int(setup_cycles),
+                       self.P.ctypes.data, self.Dc.ctypes.data)
+
+    @property
+    def delta(self) -> float:
+        return self._mg.delta
+
+    def setup(self, v0) -> np.ndarray:
+        """Adaptive setup from the starting vectors v0 [nv][V][4][3]; setup_iters = 0 only orthonormalises v0
+        aggregate-wise and builds the coarse stencil.  Returns the final test vectors."""
+        v0 = _c128(v0).reshape(self.nv, self.op.V, 4, 3)
+        out = np.zeros_like(v0)
+        rc = _load().or_mg_setup(ctypes.byref(self.op._op), ctypes.byref(self._mg), v0.ctypes.data, out.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"or_mg_setup failed (code {rc})")
+        return out
+
+    def block_orthonormalize(self, v) -> np.ndarray:
+        v = _c128(v).reshape(self.nv, self.op.V, 4, 3)
+        out = np.empty_like(v)
+        _load().or_mg_block_orthonormalize(_i4(self.op.dims), _i4(self.adims), self.nv, v.ctypes.data,
+                                           out.ctypes.data)
+        return out
+
+    def restrict(self, r) -> np.ndarray:
+        r = self.op._vec(r)
+        c = np.empty((self.nc, 2 * self.nv), np.complex128)
+        _load().or_mg_restrict(_i4(self.op.dims), _i4(self.adims), self.nv, self.P.ctypes.data, r.ctypes.data,
+                               c.ctypes.data)
+        return c
+
+    def prolong(self, c) -> np.ndarray:
+        c = _c128(c).reshape(self.nc, 2 * self.nv)
+        e = np.empty((self.op.V, 4, 3), np.complex128)
+        _load().or_mg_prolong(_i4(self.op.dims), _i4(self.adims), self.nv, self.P.ctypes.data, c.ctypes.data,
+                              e.ctypes.data)
+        return e
+
+    def coarse_build(self, op: Operator | None = None) -> None:
+        _load().or_mg_coarse_build(ctypes.byref((op or self.op)._op), _i4(self.adims), self.nv, self.P.ctypes.data,
+                                   self.Dc.ctypes.data)
+
+    def coarse_apply(self, x, mu_c: float) -> np.ndarray:
+        x = _c128(x).reshape(self.nc, 2 * self.nv)
+        y = np.empty_like(x)
+        _load().or_mg_coarse_apply(_i4(self.cdims), self.nv, self.Dc.ctypes.data, float(mu_c), x.ctypes.data,
+                                   y.ctypes.data)
+        return y
+
+    def coarse_gmres(self, b, mu_c: float, tol: float, restart: int, max_restarts: int):
+        b = _c128(b).reshape(self.nc, 2 * self.nv)
+        x = np.empty_like(b)
+        rep = _Report()
+        _load().or_mg_coarse_gmres(_i4(self.cdims), self.nv, self.Dc.ctypes.data, float(mu_c), b.ctypes.data,
+                                   x.ctypes.data, float(tol), int(restart), int(max_restarts), ctypes.byref(rep))
+        return x, {"iters": rep.iters, "restarts": rep.restarts, "met": bool(rep.converged),
+                   "rel_estimate": rep.true_rel_res}
+
+    def precond(self, r, op: Operator | None = None) -> np.ndarray:
+        op = op or self.op
+        r = op._vec(r)
+        z = np.empty_like(r)
+        _load().or_mg_precond(ctypes.byref(op._op), ctypes.byref(self._mg), r.ctypes.data, z.ctypes.data)
+        return z
+
+    def fgmres(self, b, tol: float, restart: int = 20, max_iters: int = 2000, op: Operator | None = None, x0=None):
+        op = op or self.op
+        b = op._vec(b)
+        x = np.zeros_like(b) if x0 is None else op._vec(x0).copy()
+        rep = _Report()
+        _load().or_fgmres_mg(ctypes.byref(op._op), ctypes.byref(self._mg), b.ctypes.data, x.ctypes.data, float(tol),
+                             int(restart), int(max_iters), ctypes.byref(rep))
+        return x, {"iters": rep.iters, "restarts": rep.restarts, "converged": bool(rep.converged),
+                   "true_rel_res": rep.true_rel_res}

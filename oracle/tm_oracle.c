@@ -846,8 +846,36 @@ int or_fgmres(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int res
     return or_fgmres_eo(op, b, x, tol, restart, max_iters, precond, bdims, n_cycles, mr_iters, 0, rep);
 }
 
+/* Right preconditioner of FGMRES: z = M v (z is overwritten). */
+typedef void (*or_precond_fn)(const void* ctx, const or_cplx* v, or_cplx* z);
+
+typedef struct {
+    const or_op* op;
+    const int* bdims;
+    int n_cycles, mr_iters, eo;
+} sap_ctx;
+
+/* SAP from a zero guess. */
+static void sap_precond(const void* ctx, const or_cplx* v, or_cplx* z) {
+    const sap_ctx* c = (const sap_ctx*)ctx;
+    long n = or_volume(c->op->dims) * 12;
+    for (long i = 0; i < n; ++i) z[i] = 0;
+    or_sap_eo(c->op, c->bdims, c->n_cycles, c->mr_iters, c->eo, v, z);
+}
+
+static int fgmres_core(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
+                       or_precond_fn prec, const void* pctx, or_report* rep);
+
 int or_fgmres_eo(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
                  int precond, const int bdims[4], int n_cycles, int mr_iters, int eo, or_report* rep) {
+    sap_ctx c = {op, bdims, n_cycles, mr_iters, eo};
+    return fgmres_core(op, b, x, tol, restart, max_iters, precond ? sap_precond : NULL, &c, rep);
+}
+
+/* Flexible GMRES(restart): right preconditioning by prec (NULL: none), modified
+ * Gram-Schmidt, complex Givens rotations; stops on the true residual. */
+static int fgmres_core(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
+                       or_precond_fn prec, const void* pctx, or_report* rep) {
     long n = or_volume(op->dims) * 12;
     int m = restart;
     or_cplx* Vv = malloc(sizeof(or_cplx) * n * (m + 1));
@@ -879,9 +907,8 @@ int or_fgmres_eo(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int 
             or_cplx* vj = Vv + (size_t)j * n;
             or_cplx* zj = Z + (size_t)j * n;
             /* z_j = M v_j */
-            if (precond) {
-                for (long i = 0; i < n; ++i) zj[i] = 0;
-                or_sap_eo(op, bdims, n_cycles, mr_iters, eo, vj, zj);
+            if (prec) {
+                prec(pctx, vj, zj);
             } else {
                 memcpy(zj, vj, sizeof(or_cplx) * n);
             }
@@ -949,6 +976,392 @@ done:
     free(g);
     free(y);
     return converged ? 0 : 1;
+}
+
+/* ------------------------------------------------- two-level method (2.3, 2.4) */
+
+/* Coarse lattice: one site per aggregate block; coarse index lexicographic in
+ * the block coordinates (t slowest), like the fine sites. */
+static void mg_cdims(const int dims[4], const int adims[4], int cd[4]) {
+    for (int a = 0; a < 4; ++a) cd[a] = dims[a] / adims[a];
+}
+
+static long mg_coarse_of_site(const int dims[4], const int adims[4], long s) {
+    int c[4], cd[4];
+    site_coords(dims, s, c);
+    mg_cdims(dims, adims, cd);
+    long j = 0;
+    for (int a = 0; a < 4; ++a) j = j * cd[a] + c[a] / adims[a];
+    return j;
+}
+
+/* Coarse site coupled through stencil term t: 0 = j itself, 1 + mu = the
+ * aggregate one step forward along mu, 5 + mu = one step backward. */
+static long mg_coarse_nbr(const int cd[4], long j, int t) {
+    int J[4];
+    site_coords(cd, j, J);
+    if (t >= 1) {
+        int mu = (t - 1) % 4, dir = t <= 4 ? +1 : -1, a = axis_of(mu);
+        J[a] = (J[a] + dir + cd[a]) % cd[a];
+    }
+    return coords_site(cd, J);
+}
+
+/* <a, b> over the sites of one aggregate, spin half sg (spins 2sg, 2sg+1). */
+static or_cplx agg_dot(const or_cplx* a, const or_cplx* b, const long* sites, long Vb, int sg) {
+    or_cplx t = 0;
+    for (long l = 0; l < Vb; ++l)
+        for (int k = 6 * sg; k < 6 * sg + 6; ++k) t += conj(a[(size_t)sites[l] * 12 + k]) * b[(size_t)sites[l] * 12 + k];
+    return t;
+}
+
+/* Aggregate-wise orthonormalisation of the test vectors (section 2.3): on every
+ * aggregate A_{j,+-} = block j x spins {0,1} or {2,3} x colour, modified
+ * Gram-Schmidt over i = 0 .. nv-1.  Column (j, sg, i) of P is P_i restricted
+ * to A_{j,sg}, so Gamma5 P = P Gamma5c holds by construction. */
+void or_mg_block_orthonormalize(const int dims[4], const int adims[4], int nv, const or_cplx* v, or_cplx* P) {
+    long V = or_volume(dims), Vb = or_volume(adims), nc = V / Vb;
+    int cd[4];
+    mg_cdims(dims, adims, cd);
+    memcpy(P, v, sizeof(or_cplx) * (size_t)nv * V * 12);
+#pragma omp parallel for schedule(dynamic)
+    for (long j = 0; j < nc; ++j) {
+        int J[4];
+        site_coords(cd, j, J);
+        long* sites = malloc(sizeof(long) * Vb);
+        block_sites(dims, adims, J, sites);
+        for (int sg = 0; sg < 2; ++sg)
+            for (int i = 0; i < nv; ++i) {
+                or_cplx* Pi = P + (size_t)i * V * 12;
+                for (int k = 0; k < i; ++k) {
+                    const or_cplx* Pk = P + (size_t)k * V * 12;
+                    or_cplx h = agg_dot(Pk, Pi, sites, Vb, sg);
+                    for (long l = 0; l < Vb; ++l)
+                        for (int q = 6 * sg; q < 6 * sg + 6; ++q) Pi[(size_t)sites[l] * 12 + q] -= h * Pk[(size_t)sites[l] * 12 + q];
+                }
+                double nrm = sqrt(creal(agg_dot(Pi, Pi, sites, Vb, sg)));
+                if (nrm > 0)
+                    for (long l = 0; l < Vb; ++l)
+                        for (int q = 6 * sg; q < 6 * sg + 6; ++q) Pi[(size_t)sites[l] * 12 + q] /= nrm;
+            }
+        free(sites);
+    }
+}
+
+/* c = P^+ r: c[j][sg*nv + i] = <P_i on A_{j,sg}, r>. */
+void or_mg_restrict(const int dims[4], const int adims[4], int nv, const or_cplx* P, const or_cplx* r, or_cplx* c) {
+    long V = or_volume(dims), Vb = or_volume(adims), nc = V / Vb;
+    int cd[4];
+    mg_cdims(dims, adims, cd);
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < nc; ++j) {
+        int J[4];
+        site_coords(cd, j, J);
+        long* sites = malloc(sizeof(long) * Vb);
+        block_sites(dims, adims, J, sites);
+        for (int sg = 0; sg < 2; ++sg)
+            for (int i = 0; i < nv; ++i) c[(size_t)j * 2 * nv + sg * nv + i] = agg_dot(P + (size_t)i * V * 12, r, sites, Vb, sg);
+        free(sites);
+    }
+}
+
+/* e = P c: e(x, s, col) = sum_i P_i(x, s, col) c[j(x)][sg(s)*nv + i]. */
+void or_mg_prolong(const int dims[4], const int adims[4], int nv, const or_cplx* P, const or_cplx* c, or_cplx* e) {
+    long V = or_volume(dims);
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        long j = mg_coarse_of_site(dims, adims, x);
+        for (int q = 0; q < 12; ++q) {
+            int sg = q / 6;
+            or_cplx t = 0;
+            for (int i = 0; i < nv; ++i) t += P[((size_t)i * V + x) * 12 + q] * c[(size_t)j * 2 * nv + sg * nv + i];
+            e[(size_t)x * 12 + q] = t;
+        }
+    }
+}
+
+/* Coarse basis vector (src, b) at fine site y: P_i on A_{src,sg} (b = sg*nv + i), zero elsewhere. */
+static void mg_basis_at(const int dims[4], const int adims[4], int nv, const or_cplx* P, long src, int b, long y,
+                        or_cplx out[12]) {
+    for (int q = 0; q < 12; ++q) out[q] = 0;
+    if (mg_coarse_of_site(dims, adims, y) != src) return;
+    long V = or_volume(dims);
+    int sg = b / nv, i = b % nv;
+    for (int q = 6 * sg; q < 6 * sg + 6; ++q) out[q] = P[((size_t)i * V + y) * 12 + q];
+}
+
+/* One term of D at fine site x applied to the basis vector (src, b):
+ * t = 0: the block-diagonal part D_BB (diagonal and the hops inside x's aggregate);
+ * t = 1 + mu: the forward hop along mu when it leaves the aggregate;
+ * t = 5 + mu: the backward hop along mu when it leaves the aggregate. */
+static void mg_term_at(const or_op* op, const int adims[4], int nv, const or_cplx* P, int t, long src, int b, long x,
+                       or_cplx out[12]) {
+    or_cplx g[4][16], g5[16], e[12];
+    for (int mu = 0; mu < 4; ++mu) or_gamma(mu, g[mu]);
+    or_gamma(4, g5);
+    for (int q = 0; q < 12; ++q) out[q] = 0;
+    if (t == 0) {
+        mg_basis_at(op->dims, adims, nv, P, src, b, x, e);
+        add_diag(op, g5, x, e, out);
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+        int wf, wb;
+        long xf = neighbour(op->dims, x, mu, +1, &wf);
+        long xb = neighbour(op->dims, x, mu, -1, &wb);
+        int inf = same_block(op->dims, adims, x, xf), inb = same_block(op->dims, adims, x, xb);
+        if ((t == 0 && inf) || (t == 1 + mu && !inf)) {
+            mg_basis_at(op->dims, adims, nv, P, src, b, xf, e);
+            add_hop(g[mu], -1.0, link(op->U, x, mu), e, bc_phase(op, mu, +1, wf), out);
+        }
+        if ((t == 0 && inb) || (t == 5 + mu && !inb)) {
+            or_cplx Wd[9];
+            dag(link(op->U, xb, mu), Wd);
+            mg_basis_at(op->dims, adims, nv, P, src, b, xb, e);
+            add_hop(g[mu], +1.0, Wd, e, bc_phase(op, mu, -1, wb), out);
+        }
+    }
+}
+
+/* Coarse stencil of the Galerkin operator P^+ D P (section 2.3) without the
+ * twist: Dc[j][t][a][b] = < column (j, a), D_t column (nbr_t(j), b) > with D_t
+ * the term of mg_term_at, computed at op with mu = 0 (its mu_shift stays: a
+ * site-dependent twist enters through the Galerkin product).  The coarse
+ * operator is then D_c(mu, delta) = Dc + i delta mu Gamma5c. */
+void or_mg_coarse_build(const or_op* op, const int adims[4], int nv, const or_cplx* P, or_cplx* Dc) {
+    or_op op0 = *op;
+    op0.mu = 0.0;
+    long V = or_volume(op->dims), Vb = or_volume(adims), nc = V / Vb;
+    int cd[4], n2 = 2 * nv;
+    mg_cdims(op->dims, adims, cd);
+#pragma omp parallel for schedule(dynamic)
+    for (long j = 0; j < nc; ++j) {
+        int J[4];
+        site_coords(cd, j, J);
+        long* sites = malloc(sizeof(long) * Vb);
+        or_cplx* w = malloc(sizeof(or_cplx) * Vb * 12);
+        block_sites(op->dims, adims, J, sites);
+        for (int t = 0; t < 9; ++t) {
+            long src = mg_coarse_nbr(cd, j, t);
+            for (int b = 0; b < n2; ++b) {
+                for (long l = 0; l < Vb; ++l) mg_term_at(&op0, adims, nv, P, t, src, b, sites[l], w + l * 12);
+                for (int a = 0; a < n2; ++a) {
+                    int sg = a / nv, i = a % nv;
+                    or_cplx acc = 0;
+                    for (long l = 0; l < Vb; ++l)
+                        for (int q = 6 * sg; q < 6 * sg + 6; ++q)
+                            acc += conj(P[((size_t)i * V + sites[l]) * 12 + q]) * w[l * 12 + q];
+                    Dc[(((size_t)j * 9 + t) * n2 + a) * n2 + b] = acc;
+                }
+            }
+        }
+        free(sites);
+        free(w);
+    }
+}
+
+/* y = (Dc + i mu_c Gamma5c) x on the coarse lattice, Gamma5c = +1 on the first
+ * nv components of a coarse site and -1 on the other nv. */
+void or_mg_coarse_apply(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* x, or_cplx* y) {
+    long nc = or_volume(cdims);
+    int n2 = 2 * nv;
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < nc; ++j) {
+        for (int a = 0; a < n2; ++a) {
+            or_cplx acc = _Complex_I * mu_c * (a < nv ? 1.0 : -1.0) * x[(size_t)j * n2 + a];
+            for (int t = 0; t < 9; ++t) {
+                long src = mg_coarse_nbr(cdims, j, t);
+                const or_cplx* M = Dc + (((size_t)j * 9 + t) * n2 + a) * n2;
+                for (int b = 0; b < n2; ++b) acc += M[b] * x[(size_t)src * n2 + b];
+            }
+            y[(size_t)j * n2 + a] = acc;
+        }
+    }
+}
+
+/* GMRES(restart) for (Dc + i mu_c Gamma5c) x = b from x = 0, modified
+ * Gram-Schmidt and Givens rotations.  Stops when the residual estimate
+ * |g_{j+1}| <= tol ||b|| (tol <= 0: never) or after max_restarts cycles; each
+ * cycle restarts from the recomputed residual.  Returns 0 when the estimate
+ * met tol. */
+int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* b, or_cplx* x,
+                       double tol, int restart, int max_restarts, or_report* rep) {
+    long n = or_volume(cdims) * 2 * nv;
+    int m = restart;
+    or_cplx* Vv = malloc(sizeof(or_cplx) * n * (m + 1));
+    or_cplx* w = malloc(sizeof(or_cplx) * n);
+    or_cplx* H = calloc((size_t)(m + 1) * m, sizeof(or_cplx));
+    double* cs = malloc(sizeof(double) * m);
+    or_cplx* sn = malloc(sizeof(or_cplx) * m);
+    or_cplx* g = malloc(sizeof(or_cplx) * (m + 1));
+    or_cplx* y = malloc(sizeof(or_cplx) * m);
+    for (long i = 0; i < n; ++i) x[i] = 0;
+    double bnorm = vnorm(b, n), est = bnorm;
+    int iters = 0, cycles = 0, met = bnorm == 0.0;
+    while (!met && cycles < max_restarts) {
+        /* r = b - A x */
+        or_mg_coarse_apply(cdims, nv, Dc, mu_c, x, w);
+        for (long i = 0; i < n; ++i) w[i] = b[i] - w[i];
+        double beta = vnorm(w, n);
+        est = beta;
+        if (beta == 0.0 || (tol > 0 && beta <= tol * bnorm)) {
+            met = 1;
+            break;
+        }
+        for (long i = 0; i < n; ++i) Vv[i] = w[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0;
+        g[0] = beta;
+        int jd = 0;
+        for (int j = 0; j < m; ++j) {
+            or_mg_coarse_apply(cdims, nv, Dc, mu_c, Vv + (size_t)j * n, w);
+            for (int i = 0; i <= j; ++i) {
+                or_cplx h = vdot(Vv + (size_t)i * n, w, n);
+                H[i * m + j] = h;
+                for (long k = 0; k < n; ++k) w[k] -= h * Vv[(size_t)i * n + k];
+            }
+            double hn = vnorm(w, n);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0)
+                for (long k = 0; k < n; ++k) Vv[(size_t)(j + 1) * n + k] = w[k] / hn;
+            for (int i = 0; i < j; ++i) {
+                or_cplx a = H[i * m + j], c2 = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c2;
+                H[(i + 1) * m + j] = -conj(sn[i]) * a + cs[i] * c2;
+            }
+            or_cplx a = H[j * m + j], c2 = H[(j + 1) * m + j];
+            double tt = sqrt(creal(a) * creal(a) + cimag(a) * cimag(a) + creal(c2) * creal(c2) + cimag(c2) * cimag(c2));
+            if (cabs(a) == 0.0) {
+                cs[j] = 0.0;
+                sn[j] = 1.0;
+            } else {
+                cs[j] = cabs(a) / tt;
+                sn[j] = (a / cabs(a)) * conj(c2) / tt;
+            }
+            H[j * m + j] = cs[j] * a + sn[j] * c2;
+            H[(j + 1) * m + j] = 0;
+            g[j + 1] = -conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            ++iters;
+            jd = j + 1;
+            est = cabs(g[j + 1]);
+            if ((tol > 0 && est <= tol * bnorm) || hn == 0.0) {
+                met = tol > 0 && est <= tol * bnorm;
+                if (hn == 0.0) met = 1;
+                break;
+            }
+        }
+        for (int i = jd - 1; i >= 0; --i) {
+            or_cplx t2 = g[i];
+            for (int k = i + 1; k < jd; ++k) t2 -= H[i * m + k] * y[k];
+            y[i] = t2 / H[i * m + i];
+        }
+        for (int k = 0; k < jd; ++k)
+            for (long i = 0; i < n; ++i) x[i] += y[k] * Vv[(size_t)k * n + i];
+        ++cycles;
+    }
+    if (rep) {
+        rep->iters = iters;
+        rep->restarts = cycles;
+        rep->converged = met;
+        rep->true_rel_res = bnorm > 0 ? est / bnorm : 0.0;
+    }
+    free(Vv);
+    free(w);
+    free(H);
+    free(cs);
+    free(sn);
+    free(g);
+    free(y);
+    return met ? 0 : 1;
+}
+
+/* Two-level preconditioner (eq. (multigrid_preconditioning) followed by
+ * post-smoothing, no pre-smoothing): z = P D_c(mu, delta)^-1 P^+ r with the
+ * coarse system solved by GMRES, then post_cycles SAP cycles on D z = r
+ * starting from that z. */
+void or_mg_precond(const or_op* op, const or_mg* mg, const or_cplx* r, or_cplx* z) {
+    int cd[4];
+    mg_cdims(op->dims, mg->adims, cd);
+    long nc = or_volume(cd), n2 = 2 * mg->nv;
+    or_cplx* c = malloc(sizeof(or_cplx) * nc * n2);
+    or_cplx* ec = malloc(sizeof(or_cplx) * nc * n2);
+    or_mg_restrict(op->dims, mg->adims, mg->nv, mg->P, r, c);
+    or_mg_coarse_gmres(cd, mg->nv, mg->Dc, mg->delta * op->mu, c, ec, mg->coarse_tol, mg->coarse_restart,
+                       mg->coarse_max_restarts, NULL);
+    or_mg_prolong(op->dims, mg->adims, mg->nv, mg->P, ec, z);
+    if (mg->post_cycles > 0) or_sap_eo(op, mg->adims, mg->post_cycles, mg->mr_iters, 0, r, z);
+    free(c);
+    free(ec);
+}
+
+typedef struct {
+    const or_op* op;
+    const or_mg* mg;
+} mg_ctx;
+
+static void mg_precond_fn(const void* ctx, const or_cplx* v, or_cplx* z) {
+    const mg_ctx* c = (const mg_ctx*)ctx;
+    or_mg_precond(c->op, c->mg, v, z);
+}
+
+int or_fgmres_mg(const or_op* op, const or_mg* mg, const or_cplx* b, or_cplx* x, double tol, int restart,
+                 int max_iters, or_report* rep) {
+    mg_ctx c = {op, mg};
+    return fgmres_core(op, b, x, tol, restart, max_iters, mg_precond_fn, &c, rep);
+}
+
+/* Global modified Gram-Schmidt of nv lattice vectors, in order. */
+static void mg_orthonormalize(long n, int nv, or_cplx* v) {
+    for (int i = 0; i < nv; ++i) {
+        or_cplx* vi = v + (size_t)i * n;
+        for (int k = 0; k < i; ++k) {
+            const or_cplx* vk = v + (size_t)k * n;
+            or_cplx h = vdot(vk, vi, n);
+            for (long q = 0; q < n; ++q) vi[q] -= h * vk[q];
+        }
+        double nrm = vnorm(vi, n);
+        if (nrm > 0)
+            for (long q = 0; q < n; ++q) vi[q] /= nrm;
+    }
+}
+
+/* Adaptive setup (section 2.6): iteration 1 replaces each test vector v_i by
+ * setup_cycles SAP cycles applied to it (as a right-hand side, from a zero
+ * guess); iterations 2 .. setup_iters replace it by the two-level method
+ * applied to it.  After every iteration the vectors are orthonormalised and P
+ * and the coarse stencil rebuilt from them.  v0 holds the nv starting vectors
+ * ([nv][V][12], the random draws); v (optional) receives the final vectors. */
+int or_mg_setup(const or_op* op, or_mg* mg, const or_cplx* v0, or_cplx* v_out) {
+    long V = or_volume(op->dims), n = V * 12;
+    int nv = mg->nv;
+    or_cplx* v = malloc(sizeof(or_cplx) * (size_t)nv * n);
+    or_cplx* t = malloc(sizeof(or_cplx) * n);
+    memcpy(v, v0, sizeof(or_cplx) * (size_t)nv * n);
+    int rc = 0;
+    for (int k = 1; k <= mg->setup_iters; ++k) {
+        for (int i = 0; i < nv; ++i) {
+            or_cplx* vi = v + (size_t)i * n;
+            if (k == 1) {
+                for (long q = 0; q < n; ++q) t[q] = 0;
+                rc = or_sap_eo(op, mg->adims, mg->setup_cycles, mg->mr_iters, 0, vi, t);
+                if (rc) goto out;
+            } else {
+                or_mg_precond(op, mg, vi, t);
+            }
+            memcpy(vi, t, sizeof(or_cplx) * n);
+        }
+        mg_orthonormalize(n, nv, v);
+        or_mg_block_orthonormalize(op->dims, mg->adims, nv, v, mg->P);
+        or_mg_coarse_build(op, mg->adims, nv, mg->P, mg->Dc);
+    }
+    if (mg->setup_iters <= 0) {
+        or_mg_block_orthonormalize(op->dims, mg->adims, nv, v, mg->P);
+        or_mg_coarse_build(op, mg->adims, nv, mg->P, mg->Dc);
+    }
+    if (v_out) memcpy(v_out, v, sizeof(or_cplx) * (size_t)nv * n);
+out:
+    free(v);
+    free(t);
+    return rc;
 }
 
 int or_num_threads(void) {

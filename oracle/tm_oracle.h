@@ -118,6 +118,42 @@ int or_fgmres(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int res
 int or_fgmres_eo(const or_op* op, const or_cplx* b, or_cplx* x, double tol, int restart, int max_iters,
                  int precond, const int bdims[4], int n_cycles, int mr_iters, int eo, or_report* rep);
 
+/* ------------------------------------------------ two-level method (2.3-2.6)
+ *
+ * Aggregates are blocks of adims sites split by spin half (spins {0,1} and
+ * {2,3}, where gamma5 = +1 and -1).  Coarse vectors are [nc][2 nv] with the
+ * coarse site index lexicographic in block coordinates (t slowest) and
+ * component sg*nv + i for test vector i on spin half sg; Gamma5c = +1 on the
+ * first nv components.  P is stored as nv lattice vectors [nv][V][12]; the
+ * coarse stencil as Dc[nc][9][2nv][2nv], term t = 0 (the site itself), 1 + mu
+ * (coupling to the aggregate one step forward along mu), 5 + mu (backward). */
+typedef struct {
+    int adims[4];           /* aggregate = Schwarz block of the smoother */
+    int nv;                 /* test vectors */
+    double delta;           /* coarse twist: mu_c = delta * mu (eq. (delta)) */
+    double coarse_tol;      /* coarse GMRES: relative residual estimate target (<= 0: run every step) */
+    int coarse_restart;     /* coarse GMRES restart length */
+    int coarse_max_restarts;
+    int post_cycles;        /* SAP post-smoothing cycles */
+    int mr_iters;           /* MR steps per block solve */
+    int setup_iters;        /* setup iterations (the first one is SAP only) */
+    int setup_cycles;       /* SAP cycles per test vector in setup iteration 1 */
+    or_cplx* P;             /* [nv][V][12], caller-allocated */
+    or_cplx* Dc;            /* [nc][9][2nv][2nv], caller-allocated */
+} or_mg;
+
+void or_mg_block_orthonormalize(const int dims[4], const int adims[4], int nv, const or_cplx* v, or_cplx* P);
+void or_mg_restrict(const int dims[4], const int adims[4], int nv, const or_cplx* P, const or_cplx* r, or_cplx* c);
+void or_mg_prolong(const int dims[4], const int adims[4], int nv, const or_cplx* P, const or_cplx* c, or_cplx* e);
+void or_mg_coarse_build(const or_op* op, const int adims[4], int nv, const or_cplx* P, or_cplx* Dc);
+void or_mg_coarse_apply(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* x, or_cplx* y);
+int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* b, or_cplx* x,
+                       double tol, int restart, int max_restarts, or_report* rep);
+void or_mg_precond(const or_op* op, const or_mg* mg, const or_cplx* r, or_cplx* z);
+int or_fgmres_mg(const or_op* op, const or_mg* mg, const or_cplx* b, or_cplx* x, double tol, int restart,
+                 int max_iters, or_report* rep);
+int or_mg_setup(const or_op* op, or_mg* mg, const or_cplx* v0, or_cplx* v_out);
+
 /* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
 int or_num_threads(void);
 void or_set_num_threads(int n);

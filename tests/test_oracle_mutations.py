@@ -21,7 +21,7 @@ MUTATIONS = {
     # link transposed in the colour product
     "link_transposed": ("col += W[3 * c + cp] * psi_n[3 * sp + cp];", "col += W[3 * cp + c] * psi_n[3 * sp + cp];"),
     # twisted mass with the wrong sign
-    "twist_sign": ("out[3 * s + c] += _Complex_I * op->mu", "out[3 * s + c] -= _Complex_I * op->mu"),
+    "twist_sign": ("out[3 * s + c] += _Complex_I * mux", "out[3 * s + c] -= _Complex_I * mux"),
     # one clover leaf dropped
     "clover_leaf_dropped": ("mm4(d1, d2, link(U, xmm_mn, mu), link(U, xmn, nu), leaf);\n    for (int i = 0; i < 9; ++i) Q[i] += leaf[i];",
                             "mm4(d1, d2, link(U, xmm_mn, mu), link(U, xmn, nu), leaf);"),
@@ -50,6 +50,23 @@ MUTATIONS = {
     "mu_shift_parity": ("op->mu_shift[site_parity(op->dims, x)]", "op->mu_shift[1 - site_parity(op->dims, x)]"),
     # Givens rotation without the conjugate
     "givens_conj": ("g[j + 1] = -conj(sn[j]) * g[j];", "g[j + 1] = -sn[j] * g[j];"),
+    # two-level method: aggregate inner product without the conjugate
+    "mg_aggregate_dot_conj": ("t += conj(a[(size_t)sites[l] * 12 + k]) * b[(size_t)sites[l] * 12 + k];",
+                              "t += a[(size_t)sites[l] * 12 + k] * b[(size_t)sites[l] * 12 + k];"),
+    # coarse Gamma5 with the spin halves swapped
+    "mg_gamma5c_sign": ("(a < nv ? 1.0 : -1.0)", "(a < nv ? -1.0 : 1.0)"),
+    # coarse twist not scaled by delta
+    "mg_delta_ignored": ("mg->delta * op->mu", "op->mu"),
+    # forward and backward coarse couplings exchanged
+    "mg_term_direction": ("dir = t <= 4 ? +1 : -1", "dir = t <= 4 ? -1 : +1"),
+    # twist counted twice (Galerkin product taken at mu, then delta mu added)
+    "mg_twist_twice": ("    op0.mu = 0.0;\n", "\n"),
+    # post-smoothing skipped
+    "mg_no_post_smoothing": ("if (mg->post_cycles > 0) or_sap_eo", "if (0) or_sap_eo"),
+    # prolongation puts spin half 1 coefficients on spins 2 and 3 of half 0
+    "mg_prolong_half": ("int sg = q / 6;", "int sg = q / 9;"),
+    # setup without the global orthonormalisation
+    "mg_setup_no_orthonormalization": ("        mg_orthonormalize(n, nv, v);\n", "\n"),
 }
 
 
@@ -59,6 +76,9 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     old, new = MUTATIONS[name][:2]
     # mistakes in the even-odd block solve only reach the even-odd pins
     select = ["-k", "eo"] if name.startswith("eo_") else []
+    pins = ["test_oracle_operator.py", "test_oracle_sap.py"]
+    if name.startswith("mg_"):
+        pins = ["test_oracle_mg.py"]
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation anchor for {name} not found"
     mutated = tmp_path / "tm_oracle.c"
@@ -69,6 +89,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, TM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run(
         [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *select,
-         os.path.join(ROOT, "tests", "test_oracle_operator.py"), os.path.join(ROOT, "tests", "test_oracle_sap.py")],
+         *[os.path.join(ROOT, "tests", p) for p in pins]],
         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} was not caught:\n{r.stdout[-2000:]}"
