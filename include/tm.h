@@ -157,6 +157,8 @@ TM_API int tm_sap_smooth(const tm_geom* geom, const void* U, const void* b, void
 #define TM_SOLVE_FLEXIBLE 0          /* FP64 FGMRES, SAP at opts->storage */
 #define TM_SOLVE_DEFECT_CORRECTION 1 /* FP64 residual loop around an FP32 FGMRES+SAP solve */
 
+typedef struct tm_mg tm_mg;  /* two-level method, see tm_mg_setup */
+
 typedef struct {
     int form;             /* TM_SOLVE_FLEXIBLE or TM_SOLVE_DEFECT_CORRECTION */
     int restart;          /* FGMRES restart length (outer, or inner for defect correction) */
@@ -167,10 +169,18 @@ typedef struct {
     double inner_tol;     /* defect correction: relative tolerance of each inner solve */
     int max_outer;        /* defect correction: cap on outer corrections */
     int group;            /* systems solved together (0 = all nsys) */
+    tm_mg* mg;            /* NULL: SAP preconditioner.  Else the two-level method of this handle
+                             (tm_mg_setup) preconditions FGMRES: its blocks, post-smoothing and
+                             coarse solve replace block_dims, n_cycles and mr_iters; needs
+                             opts->storage TM_F32 and geom equal to the handle's but for nsys and mu.
+                             The preconditioner uses the handle's own gauge copy and the operator
+                             this call's U, kappa and c_sw: a handle set up for other ones still
+                             gives solutions to tol (FGMRES admits any preconditioner), only in
+                             more iterations */
 } tm_solver_opts;
 
 /* restart 20, max_iters 2000, 4 cycles, 4 MR steps, 4^4 blocks, flexible form,
- * inner_tol 1e-6, max_outer 50, group 0. */
+ * inner_tol 1e-6, max_outer 50, group 0, no two-level method. */
 TM_API void tm_solver_opts_default(tm_solver_opts* sopts);
 
 typedef struct {
@@ -231,6 +241,99 @@ TM_API int tm_spinor_import_range(const tm_geom* geom, const void* canon, void* 
                                   const tm_opts* opts);
 TM_API int tm_spinor_export_range(const tm_geom* geom, const void* internal, void* canon, int first, int count,
                                   const tm_opts* opts);
+
+/* ------------------------------------------ two-level method (2.3 - 2.6) */
+/*
+ * Aggregation-based coarse-grid correction with SAP post-smoothing, the
+ * multigrid preconditioner of section 2.2 with two levels.  Aggregates are
+ * the smoother's Schwarz blocks (section 2.4 fixes them equal) split by spin
+ * half, spins {0,1} and {2,3} (section 2.3, "standard aggregation"), so the
+ * prolongation commutes with Gamma5 (eq. (gamma5_symmetry)).  On each
+ * aggregate the N_v test vectors are orthonormalised (modified Gram-Schmidt
+ * in vector order); P is built from them, R = P^+, and the coarse operator is
+ * D_c(mu) = P^+ D P + i delta mu Gamma5c (eq. (delta)) where the Galerkin
+ * product is taken at mu = 0 with the parity shifts of mu (geom->mu_shift)
+ * kept, so that with no shifts D_c(mu) equals P^+ D(mu) P at delta = 1.
+ * The coarse lattice has one site per block, index lexicographic in block
+ * coordinates (t slowest); a coarse vector is [nsys][nc][2 N_v] complex128
+ * with component sg * N_v + i for test vector i on spin half sg (Gamma5c = +1
+ * on sg = 0).  The stencil D_c is [nc][9][2 N_v][2 N_v] complex128, row-major
+ * per matrix: term 0 couples a site to itself, 1 + mu to the aggregate one
+ * step forward along mu (t, x, y, z), 5 + mu one step backward.
+ *
+ * Preconditioner application (eq. (error_propagation), no pre-smoothing):
+ * z = P D_c(mu)^-1 P^+ r with D_c solved by GMRES(coarse_restart) from zero
+ * to coarse_tol (relative residual estimate), at most coarse_max_restarts
+ * cycles, then post_cycles SAP cycles on D z = r starting from that z.
+ *
+ * Setup (section 2.6): setup iteration 1 replaces each starting vector v_i by
+ * setup_cycles SAP cycles applied to it (v_i as right-hand side, zero guess);
+ * iterations 2 .. setup_iters apply the two-level method built from the
+ * previous vectors instead.  After every iteration the vectors are
+ * orthonormalised over the whole lattice (in order) and P and D_c rebuilt.
+ * The twist of the setup is geom->mu[0].
+ *
+ * Everything runs at FP32 (opts->storage and opts->compute TM_F32); inner
+ * products accumulate in FP64.  The handle holds P (N_v FP32 spinor fields),
+ * D_c (nc * 9 * (2 N_v)^2 * 8 bytes) and its own FP32 copy of the links and
+ * the clover term (480 bytes per site) made at setup, so U may be freed after
+ * tm_mg_setup; all of it lives on the device that was current at setup, every
+ * call must run with that device current, and calls that use one handle must
+ * not overlap.
+ */
+typedef struct {
+    int block_dims[4];       /* aggregates = Schwarz blocks; an even number (>= 2) per direction,
+                                at most 1024 sites */
+    int n_vec;               /* test vectors N_v, 1 .. 32 */
+    int setup_iters;         /* n_setup (0: P from the starting vectors as given) */
+    int setup_cycles;        /* SAP cycles per test vector in setup iteration 1 */
+    double delta;            /* coarse twist factor */
+    double coarse_tol;       /* coarse GMRES target of ||b - D_c x|| / ||b|| (0: run every step) */
+    int coarse_restart;      /* 1 .. 128 */
+    int coarse_max_restarts; /* >= 1 */
+    int post_cycles;         /* SAP post-smoothing cycles (>= 0) */
+    int mr_iters;            /* MR steps per block solve */
+} tm_mg_params;
+
+typedef struct {
+    int cdims[4];              /* coarse lattice (T, Z, Y, X) */
+    int n_vec;
+    double t_setup;            /* seconds in tm_mg_setup */
+    long long applications;    /* preconditioner applications since setup (systems counted once per call) */
+    long long coarse_iters;    /* coarse GMRES steps over those applications (max over systems per call) */
+    double t_coarse;           /* seconds in coarse solves (event-timed) */
+} tm_mg_info;
+
+/* Table 1 values where a two-level method has them: 4^4 blocks, N_v 28,
+ * 5 setup iterations, delta 5.2, coarse GMRES(100) with at most 5 restarts to
+ * 1e-1, 4 post-smoothing cycles, 3 MR steps; setup_cycles 4 (the paper says
+ * "some steps"). */
+TM_API void tm_mg_params_default(tm_mg_params* p);
+/* Builds the two-level method for D(geom->mu[0]) (geom->nsys must be 1).  v0: the
+ * N_v starting vectors (the setup's random draws), canonical complex128
+ * [N_v][V][4][3] on the device.  *mg receives the handle. */
+TM_API int tm_mg_setup(const tm_geom* geom, const void* U, double kappa, double c_sw, const tm_mg_params* params,
+                       const void* v0, tm_mg** mg, const tm_opts* opts);
+TM_API int tm_mg_destroy(tm_mg* mg);
+TM_API int tm_mg_get_info(const tm_mg* mg, tm_mg_info* info);
+/* Copies P (canonical complex128 [N_v][V][4][3]: test vector i orthonormalised on
+ * every aggregate) and D_c (layout above) to device buffers; either may be NULL. */
+TM_API int tm_mg_export(tm_mg* mg, void* P, void* Dc, const tm_opts* opts);
+/* c = P^+ r for nsys fine vectors (canonical [nsys][V][4][3]) into coarse vectors. */
+TM_API int tm_mg_restrict(tm_mg* mg, int nsys, const void* r, void* c, const tm_opts* opts);
+/* e = P c. */
+TM_API int tm_mg_prolong(tm_mg* mg, int nsys, const void* c, void* e, const tm_opts* opts);
+/* y_k = (D_c + i mu_c[k] Gamma5c) x_k; mu_c a host array [nsys]. */
+TM_API int tm_mg_coarse_apply(tm_mg* mg, int nsys, const double* mu_c, const void* x, void* y, const tm_opts* opts);
+/* GMRES(restart) for (D_c + i mu_c[k] Gamma5c) x_k = b_k from x = 0, stopping per system
+ * when the residual estimate is <= tol ||b_k|| (tol 0: never) or after max_restarts
+ * cycles; *iters (may be NULL) gets the largest step count. */
+TM_API int tm_mg_coarse_solve(tm_mg* mg, int nsys, const double* mu_c, const void* b, void* x, double tol,
+                              int restart, int max_restarts, int* iters, const tm_opts* opts);
+/* z = the two-level preconditioner applied to r, for geom->nsys systems with twists
+ * geom->mu (coarse twists delta * mu); canonical fine vectors.  geom must equal the
+ * handle's but for nsys and mu. */
+TM_API int tm_mg_precond(const tm_geom* geom, tm_mg* mg, const void* r, void* z, const tm_opts* opts);
 
 /* --------------------------------------------------------------- tuning */
 /*

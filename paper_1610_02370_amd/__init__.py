@@ -31,6 +31,8 @@ EXPORTS = (
     "tm_opts_default", "tm_init", "tm_finalize", "tm_last_error", "tm_gauge_release", "tm_dirac_apply",
     "tm_sap_smooth", "tm_solver_opts_default", "tm_fgmres_solve", "tm_spinor_bytes", "tm_spinor_import",
     "tm_spinor_export", "tm_spinor_import_range", "tm_spinor_export_range", "tm_autotune_sap", "tm_cg_solve",
+    "tm_mg_params_default", "tm_mg_setup", "tm_mg_destroy", "tm_mg_get_info", "tm_mg_export", "tm_mg_restrict",
+    "tm_mg_prolong", "tm_mg_coarse_apply", "tm_mg_coarse_solve", "tm_mg_precond",
 )
 
 
@@ -55,7 +57,21 @@ class Opts(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("n_cycles", ctypes.c_int), ("mr_iters", ctypes.c_int), ("block_dims", ctypes.c_int * 4),
-                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("group", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("group", ctypes.c_int),
+                ("mg", ctypes.c_void_p)]
+
+
+class MgParams(ctypes.Structure):
+    _fields_ = [("block_dims", ctypes.c_int * 4), ("n_vec", ctypes.c_int), ("setup_iters", ctypes.c_int),
+                ("setup_cycles", ctypes.c_int), ("delta", ctypes.c_double), ("coarse_tol", ctypes.c_double),
+                ("coarse_restart", ctypes.c_int), ("coarse_max_restarts", ctypes.c_int),
+                ("post_cycles", ctypes.c_int), ("mr_iters", ctypes.c_int)]
+
+
+class MgInfo(ctypes.Structure):
+    _fields_ = [("cdims", ctypes.c_int * 4), ("n_vec", ctypes.c_int), ("t_setup", ctypes.c_double),
+                ("applications", ctypes.c_longlong), ("coarse_iters", ctypes.c_longlong),
+                ("t_coarse", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -98,6 +114,19 @@ def lib():
                                   P(Opts), P(Report)]
         L.tm_spinor_import_range.argtypes = [P(Geom), vp, vp, ctypes.c_int, ctypes.c_int, P(Opts)]
         L.tm_spinor_export_range.argtypes = [P(Geom), vp, vp, ctypes.c_int, ctypes.c_int, P(Opts)]
+        L.tm_mg_params_default.argtypes = [P(MgParams)]
+        L.tm_mg_params_default.restype = None
+        L.tm_mg_setup.argtypes = [P(Geom), vp, ctypes.c_double, ctypes.c_double, P(MgParams), vp,
+                                  P(ctypes.c_void_p), P(Opts)]
+        L.tm_mg_destroy.argtypes = [vp]
+        L.tm_mg_get_info.argtypes = [vp, P(MgInfo)]
+        L.tm_mg_export.argtypes = [vp, vp, vp, P(Opts)]
+        L.tm_mg_restrict.argtypes = [vp, ctypes.c_int, vp, vp, P(Opts)]
+        L.tm_mg_prolong.argtypes = [vp, ctypes.c_int, vp, vp, P(Opts)]
+        L.tm_mg_coarse_apply.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), vp, vp, P(Opts)]
+        L.tm_mg_coarse_solve.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), vp, vp, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int, P(ctypes.c_int), P(Opts)]
+        L.tm_mg_precond.argtypes = [P(Geom), vp, vp, vp, P(Opts)]
         L.tm_autotune_sap.argtypes = [P(Geom), vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       P(Opts), P(ctypes.c_int), P(ctypes.c_int)]
         _lib = L
@@ -227,13 +256,17 @@ def solver_opts(form: str = "flexible", restart: int = 20, max_iters: int = 2000
 def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, storage: str = "f32",
                     antiperiodic_t: bool = False, stream=None, gauge_tag: int = 0, sys_tile: int = 0,
                     theta=None, mu_shift=None,
-                    eo: bool = False, **solver_kw):
-    """Solve D(mu_k) x_k = b_k to a true relative residual tol; returns (status, report dict)."""
+                    eo: bool = False, mg: "MG | None" = None, **solver_kw):
+    """Solve D(mu_k) x_k = b_k to a true relative residual tol; returns (status, report dict).
+
+    mg: a two-level handle (MG) whose method preconditions FGMRES instead of SAP."""
     g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts(storage, stream=stream, gauge_tag=gauge_tag)
     o.sys_tile = int(sys_tile)
     o.sap_eo = int(bool(eo))
     s = solver_opts(**solver_kw)
+    if mg is not None:
+        s.mg = mg.handle
     rep = Report()
     rc = _check(lib().tm_fgmres_solve(ctypes.byref(g), _canon(U, "U"), _canon(b, "b"), _canon(x, "x"), float(kappa),
                                       float(c_sw), float(tol), ctypes.byref(s), ctypes.byref(o), ctypes.byref(rep)),
@@ -312,3 +345,124 @@ def tm_autotune_sap(dims, U, kappa: float, mu, c_sw: float, n_cycles: int, mr_it
     _check(lib().tm_autotune_sap(ctypes.byref(g), _canon(U, "U"), float(kappa), float(c_sw), int(n_cycles),
                                  int(mr_iters), ctypes.byref(o), best, ctypes.byref(tile)))
     return tuple(best), tile.value
+
+
+def mg_params(**kw) -> MgParams:
+    """Two-level parameters: the library defaults (Table 1) overridden by keyword."""
+    p = MgParams()
+    lib().tm_mg_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "block_dims":
+            p.block_dims = (ctypes.c_int * 4)(*[int(a) for a in v])
+        elif k in ("delta", "coarse_tol"):
+            setattr(p, k, float(v))
+        else:
+            setattr(p, k, int(v))
+    return p
+
+
+class MG:
+    """Two-level method (tm_mg_setup); `close()` (or garbage collection) frees it.
+
+    Coarse vectors are complex128 tensors [nsys, nc, 2 n_vec]; fine vectors [nsys, V, 4, 3]."""
+
+    def __init__(self, dims, U, kappa: float, mu: float, c_sw: float, v0, *, antiperiodic_t: bool = False,
+                 theta=None, mu_shift=None, stream=None, gauge_tag: int = 0, **params):
+        self.dims = tuple(int(d) for d in dims)
+        self.antiperiodic_t, self.theta, self.mu_shift = antiperiodic_t, theta, mu_shift
+        self.params = mg_params(**params)
+        self.gauge_tag = gauge_tag
+        g = make_geom(dims, [float(mu)], antiperiodic_t, theta, mu_shift)
+        o = make_opts("f32", stream=stream, gauge_tag=gauge_tag)
+        h = ctypes.c_void_p()
+        _check(lib().tm_mg_setup(ctypes.byref(g), _canon(U, "U"), float(kappa), float(c_sw),
+                                 ctypes.byref(self.params), _canon(v0, "v0"), ctypes.byref(h), ctypes.byref(o)))
+        self.handle = h
+        self.n_vec = self.params.n_vec
+        self.cdims = tuple(d // b for d, b in zip(self.dims, self.params.block_dims))
+        self.nc = 1
+        for c in self.cdims:
+            self.nc *= c
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().tm_mg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = MgInfo()
+        _check(lib().tm_mg_get_info(self.handle, ctypes.byref(i)))
+        return {"cdims": tuple(i.cdims), "n_vec": i.n_vec, "t_setup": i.t_setup, "applications": i.applications,
+                "coarse_iters": i.coarse_iters, "t_coarse": i.t_coarse}
+
+    def _opts(self, stream=None):
+        return make_opts("f32", stream=stream, gauge_tag=self.gauge_tag)
+
+    def export(self, stream=None):
+        """(P [n_vec, V, 4, 3], Dc [nc, 9, 2 n_vec, 2 n_vec]) as complex128 tensors."""
+        import torch
+
+        V = 1
+        for d in self.dims:
+            V *= d
+        n2 = 2 * self.n_vec
+        P = torch.empty((self.n_vec, V, 4, 3), dtype=torch.complex128, device="cuda")
+        Dc = torch.empty((self.nc, 9, n2, n2), dtype=torch.complex128, device="cuda")
+        _check(lib().tm_mg_export(self.handle, _ptr(P), _ptr(Dc), ctypes.byref(self._opts(stream))))
+        torch.cuda.synchronize()
+        return P, Dc
+
+    def restrict(self, r, stream=None):
+        import torch
+
+        ns = r.shape[0]
+        c = torch.empty((ns, self.nc, 2 * self.n_vec), dtype=torch.complex128, device=r.device)
+        _check(lib().tm_mg_restrict(self.handle, ns, _canon(r, "r"), _ptr(c), ctypes.byref(self._opts(stream))))
+        return c
+
+    def prolong(self, c, stream=None):
+        import torch
+
+        ns = c.shape[0]
+        V = 1
+        for d in self.dims:
+            V *= d
+        e = torch.empty((ns, V, 4, 3), dtype=torch.complex128, device=c.device)
+        _check(lib().tm_mg_prolong(self.handle, ns, _canon(c, "c"), _ptr(e), ctypes.byref(self._opts(stream))))
+        return e
+
+    def coarse_apply(self, x, mu_c, stream=None):
+        import torch
+
+        ns = x.shape[0]
+        mus = (ctypes.c_double * ns)(*[float(m) for m in mu_c])
+        y = torch.empty_like(x)
+        _check(lib().tm_mg_coarse_apply(self.handle, ns, mus, _canon(x, "x"), _ptr(y),
+                                        ctypes.byref(self._opts(stream))))
+        return y
+
+    def coarse_solve(self, b, mu_c, tol: float, restart: int, max_restarts: int, stream=None):
+        import torch
+
+        ns = b.shape[0]
+        mus = (ctypes.c_double * ns)(*[float(m) for m in mu_c])
+        x = torch.empty_like(b)
+        it = ctypes.c_int(0)
+        _check(lib().tm_mg_coarse_solve(self.handle, ns, mus, _canon(b, "b"), _ptr(x), float(tol), int(restart),
+                                        int(max_restarts), ctypes.byref(it), ctypes.byref(self._opts(stream))))
+        return x, it.value
+
+    def precond(self, r, mu, stream=None):
+        import torch
+
+        g = make_geom(self.dims, mu, self.antiperiodic_t, self.theta, self.mu_shift)
+        z = torch.empty_like(r)
+        _check(lib().tm_mg_precond(ctypes.byref(g), self.handle, _canon(r, "r"), _ptr(z),
+                                   ctypes.byref(self._opts(stream))))
+        return z

@@ -80,4 +80,13 @@ int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf
 int run_dirac(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu, int nsys,
               Prec compute, hipStream_t st);
 
+// ---- two-level method (tm_mg_api.cpp)
+// z = the handle's two-level preconditioner applied to r: FP32 internal fields
+// of ns systems tiled by the handle's aggregates (the handle holds its gauge copy).
+int mg_apply(tm_mg* mg, DeviceState* ds, const SpinorBuf& r, const SpinorBuf& z, const double* mu, int ns,
+             hipStream_t st);
+// TM_OK when geom has the handle's dims, boundary phases and shifts and its device is current.
+int mg_matches(const tm_mg* mg, const tm_geom* geom);
+void mg_block_dims(const tm_mg* mg, int bd[4]);
+
 }  // namespace tmsap

@@ -1,0 +1,638 @@
+// Two-level method (sections 2.3 and 2.4): the aggregation basis P, the
+// restriction P^+ and prolongation P, the Galerkin coarse stencil P^+ D P and
+// the coarse operator D_c + i delta mu Gamma5c, plus the vector kernels of the
+// coarse GMRES.  Layouts are described in tm_mg.h.
+//
+// Per-aggregate kernels run one workgroup per aggregate (tile) with one site
+// per thread; their reductions go through wavefront shuffles and LDS in a
+// fixed order, so results do not depend on scheduling.
+#include "tm_mg.h"
+
+namespace tmsap {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kCoarseSys = 16;  // systems per coarse-operator workgroup
+constexpr int kDots = 16;       // basis vectors per dot / axpy pass
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline const void* field(const void* base, size_t stride, int i) {
+    return static_cast<const char*>(base) + (size_t)i * stride;
+}
+
+// Column b of P at site y: field b % nv with the other spin half zeroed.
+__device__ inline void load_column(const MgArgs& m, int b, long long y, Spinor<float>& p) {
+    const int i = b % m.nv, sg = b / m.nv;
+    load_spinor<float, float>(field(m.P, m.P_stride, i), nullptr, m.g.V, y, p);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) p.v[sg == 0 ? 6 + q : q] = cmk(0.f, 0.f);
+}
+
+template <int T>
+__global__ void __launch_bounds__(kThreads) k_mg_term(MgArgs m, const void* __restrict__ links,
+                                                      const void* __restrict__ clover, int b0, int nb, void* out,
+                                                      size_t out_stride) {
+    constexpr int t = T;
+    const Geo& g = m.g;
+    const long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (s >= g.V) return;
+    int nf[4], nbk[4], par;
+    unsigned wrap;
+    tiled_neighbours(g, s, nf, nbk, &wrap, &par);
+    const unsigned blk = (unsigned)s / (unsigned)g.Vb;
+    constexpr int mu = t == 0 ? 0 : (t - 1) % 4;
+    constexpr bool fwd = t >= 1 && t <= 4;
+    // neighbours along mu picked with static indices (no private-array indexing)
+    int nfm = nf[0], nbm = nbk[0];
+#pragma unroll
+    for (int d = 1; d < 4; ++d)
+        if (d == mu) {
+            nfm = nf[d];
+            nbm = nbk[d];
+        }
+    // the face hop of term t exists at this site only when it leaves the aggregate
+    const bool face = t == 0 ? false : ((unsigned)(fwd ? nfm : nbm) / (unsigned)g.Vb != blk);
+    Clover<float> A;
+    if (t == 0) load_clover<float, float>(clover, g.V, s, A);
+    for (int b = b0; b < b0 + nb; ++b) {
+        Spinor<float> o, h, p;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) o.v[q] = h.v[q] = cmk(0.f, 0.f);
+        if (t == 0) {
+            load_column(m, b, s, p);
+            clover_apply(A, (float)g.mu_shift[par], p, o);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                if ((unsigned)nf[d] / (unsigned)g.Vb == blk) {
+                    Link<float> L;
+                    load_link<float, float>(links, g.V, s, d, L);
+                    load_column(m, b, nf[d], p);
+                    if (wrap & (1u << d)) apply_bc(g, d, +1, p);
+                    hop_forward(d, L, p, 1.f, h);
+                }
+                if ((unsigned)nbk[d] / (unsigned)g.Vb == blk) {
+                    Link<float> L;
+                    load_link<float, float>(links, g.V, nbk[d], d, L);
+                    load_column(m, b, nbk[d], p);
+                    if (wrap & (16u << d)) apply_bc(g, d, -1, p);
+                    hop_backward(d, L, p, 1.f, h);
+                }
+            }
+        } else if (face) {
+            Link<float> L;
+            if (fwd) {
+                load_link<float, float>(links, g.V, s, mu, L);
+                load_column(m, b, nfm, p);
+                if (wrap & (1u << mu)) apply_bc(g, mu, +1, p);
+                hop_forward(mu, L, p, 1.f, h);
+            } else {
+                load_link<float, float>(links, g.V, nbm, mu, L);
+                load_column(m, b, nbm, p);
+                if (wrap & (16u << mu)) apply_bc(g, mu, -1, p);
+                hop_backward(mu, L, p, 1.f, h);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 12; ++q) o.v[q] = o.v[q] - 0.5f * h.v[q];
+        store_spinor<float, float>(static_cast<char*>(out) + (size_t)(b - b0) * out_stride, nullptr, g.V, s, o);
+    }
+}
+
+// Restriction of S systems per workgroup (one aggregate of at most NT sites).
+template <int S, int NT>
+__global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __restrict__ x, size_t x_stride,
+                                                      int nsys, float2* out, size_t base, size_t s_stride,
+                                                      size_t j_stride) {
+    extern __shared__ float red[];  // [waves][S][nv][4]
+    const Geo& g = m.g;
+    const int j = blockIdx.x, l = threadIdx.x;
+    const bool on = l < g.Vb;
+    const long long s = (long long)j * g.Vb + l;
+    const int s0 = blockIdx.y * S;
+    const int ns = min(S, nsys - s0);
+    const int lane = l & 63, w = l >> 6, nw = blockDim.x >> 6, nv = m.nv;
+    Spinor<float> xv[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        if (on && k < ns)
+            load_spinor<float, float>(field(x, x_stride, s0 + k), nullptr, g.V, s, xv[k]);
+        else
+#pragma unroll
+            for (int q = 0; q < 12; ++q) xv[k].v[q] = cmk(0.f, 0.f);
+    }
+    for (int i = 0; i < nv; ++i) {
+        Spinor<float> p;
+        if (on)
+            load_spinor<float, float>(field(m.P, m.P_stride, i), nullptr, g.V, s, p);
+        else
+#pragma unroll
+            for (int q = 0; q < 12; ++q) p.v[q] = cmk(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            float d[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const int h = q < 6 ? 0 : 2;
+                d[h] += p.v[q].re * xv[k].v[q].re + p.v[q].im * xv[k].v[q].im;
+                d[h + 1] += p.v[q].re * xv[k].v[q].im - p.v[q].im * xv[k].v[q].re;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = wave_sum(d[e]);
+                if (lane == 0) red[((w * S + k) * nv + i) * 4 + e] = v;
+            }
+        }
+    }
+    __syncthreads();
+    const int n2 = 2 * nv;
+    for (int idx = l; idx < ns * n2; idx += blockDim.x) {
+        const int k = idx / n2, a = idx - k * n2, sg = a / nv, i = a - sg * nv;
+        float re = 0.f, im = 0.f;
+        for (int q = 0; q < nw; ++q) {
+            re += red[((q * S + k) * nv + i) * 4 + 2 * sg];
+            im += red[((q * S + k) * nv + i) * 4 + 2 * sg + 1];
+        }
+        out[base + (size_t)(s0 + k) * s_stride + (size_t)j * j_stride + a] = make_float2(re, im);
+    }
+}
+
+template <int S, int NT>
+__global__ void __launch_bounds__(NT) k_mg_prolong(MgArgs m, const float2* __restrict__ c, int nsys, void* e,
+                                                     size_t e_stride) {
+    extern __shared__ float2 cs[];  // [S][2 nv]
+    const Geo& g = m.g;
+    const int j = blockIdx.x, l = threadIdx.x, nv = m.nv, n2 = 2 * nv;
+    const long long nc = g.V / g.Vb;
+    const int s0 = blockIdx.y * S;
+    const int ns = min(S, nsys - s0);
+    for (int idx = l; idx < ns * n2; idx += blockDim.x) {
+        const int k = idx / n2, a = idx - k * n2;
+        cs[idx] = c[((size_t)(s0 + k) * nc + j) * n2 + a];
+    }
+    __syncthreads();
+    if (l >= g.Vb) return;
+    const long long s = (long long)j * g.Vb + l;
+    Spinor<float> acc[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+#pragma unroll
+        for (int q = 0; q < 12; ++q) acc[k].v[q] = cmk(0.f, 0.f);
+    for (int i = 0; i < nv; ++i) {
+        Spinor<float> p;
+        load_spinor<float, float>(field(m.P, m.P_stride, i), nullptr, g.V, s, p);
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            if (k < ns) {
+                const float2 c0 = cs[k * n2 + i], c1 = cs[k * n2 + nv + i];
+                const cplx<float> u = cmk(c0.x, c0.y), d = cmk(c1.x, c1.y);
+#pragma unroll
+                for (int q = 0; q < 12; ++q) acc[k].v[q] = cmad(p.v[q], q < 6 ? u : d, acc[k].v[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+        if (k < ns) store_spinor<float, float>(static_cast<char*>(e) + (size_t)(s0 + k) * e_stride, nullptr, g.V, s,
+                                               acc[k]);
+}
+
+// Sum of (a, b) over the workgroup, returned to every thread (FP64).
+__device__ inline void block_sum2(double* lds, double& a, double& b) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    a = wave_sum_d(a);
+    b = wave_sum_d(b);
+    if (lane == 0) {
+        lds[2 * w] = a;
+        lds[2 * w + 1] = b;
+    }
+    __syncthreads();
+    a = 0;
+    b = 0;
+    for (int q = 0; q < nw; ++q) {
+        a += lds[2 * q];
+        b += lds[2 * q + 1];
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_mg_block_orthonormalize(MgArgs m, void* P) {
+    __shared__ double lds[32];
+    const Geo& g = m.g;
+    const int j = blockIdx.x, sg = blockIdx.y, l = threadIdx.x;
+    const bool on = l < g.Vb;
+    const long long s = (long long)j * g.Vb + l;
+    const int u0 = 3 * sg;
+    for (int i = 0; i < m.nv; ++i) {
+        float4* Pi = reinterpret_cast<float4*>(static_cast<char*>(P) + (size_t)i * m.P_stride);
+        float4 v[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) v[u] = on ? Pi[(size_t)(u0 + u) * g.V + s] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int k = 0; k < i; ++k) {
+            const float4* Pk = reinterpret_cast<const float4*>(static_cast<const char*>(P) + (size_t)k * m.P_stride);
+            float4 q[3];
+            double re = 0, im = 0;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                q[u] = on ? Pk[(size_t)(u0 + u) * g.V + s] : make_float4(0.f, 0.f, 0.f, 0.f);
+                re += (double)q[u].x * v[u].x + (double)q[u].y * v[u].y + (double)q[u].z * v[u].z +
+                      (double)q[u].w * v[u].w;
+                im += (double)q[u].x * v[u].y - (double)q[u].y * v[u].x + (double)q[u].z * v[u].w -
+                      (double)q[u].w * v[u].z;
+            }
+            block_sum2(lds, re, im);
+            const float hr = (float)re, hi = (float)im;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                v[u].x -= hr * q[u].x - hi * q[u].y;
+                v[u].y -= hr * q[u].y + hi * q[u].x;
+                v[u].z -= hr * q[u].z - hi * q[u].w;
+                v[u].w -= hr * q[u].w + hi * q[u].z;
+            }
+        }
+        double n2 = 0, dummy = 0;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+            n2 += (double)v[u].x * v[u].x + (double)v[u].y * v[u].y + (double)v[u].z * v[u].z +
+                  (double)v[u].w * v[u].w;
+        block_sum2(lds, n2, dummy);
+        const float f = n2 > 0 ? (float)(1.0 / sqrt(n2)) : 0.f;
+        if (on)
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                Pi[(size_t)(u0 + u) * g.V + s] = make_float4(f * v[u].x, f * v[u].y, f * v[u].z, f * v[u].w);
+    }
+}
+
+// Coarse site one step along the stencil term t (tile grid, periodic).
+__device__ inline long long coarse_nbr(const Geo& g, long long j, int t) {
+    if (t == 0) return j;
+    int B[4];
+    long long r = j;
+    for (int a = 3; a >= 0; --a) {
+        B[a] = (int)(r % g.nb[a]);
+        r /= g.nb[a];
+    }
+    const int mu = (t - 1) % 4, a = axis_of(mu), dir = t <= 4 ? 1 : -1;
+    B[a] = (B[a] + dir + g.nb[a]) % g.nb[a];
+    long long out = 0;
+    for (int q = 0; q < 4; ++q) out = out * g.nb[q] + B[q];
+    return out;
+}
+
+// One workgroup per coarse site and group of kCoarseSys systems; wave w handles
+// the terms t = w, w + 4, w + 8 with one lane per row a, so a column of a stencil
+// matrix is one coalesced load; the neighbours' x are staged in LDS.
+__global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, const float2* __restrict__ Dc,
+                                                              const double* __restrict__ mu_c,
+                                                              const float2* __restrict__ x, float2* y, int nsys) {
+    extern __shared__ float2 sh[];  // xs [9][kCoarseSys][n2]; reused for [4][kCoarseSys][64] partial sums
+    const int n2 = 2 * nv;
+    const long long nc = g.V / g.Vb;
+    const long long j = blockIdx.x;
+    const int s0 = blockIdx.y * kCoarseSys;
+    const int ns = min(kCoarseSys, nsys - s0);
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < 9 * ns * n2; idx += kThreads) {
+        const int t = idx / (ns * n2), r = idx - t * ns * n2, k = r / n2, b = r - k * n2;
+        sh[(t * kCoarseSys + k) * n2 + b] = x[((size_t)(s0 + k) * nc + coarse_nbr(g, j, t)) * n2 + b];
+    }
+    __syncthreads();
+    const int w = tid >> 6, a = tid & 63;
+    float2 acc[kCoarseSys];
+#pragma unroll
+    for (int k = 0; k < kCoarseSys; ++k) acc[k] = make_float2(0.f, 0.f);
+    if (a < n2) {
+        for (int t = w; t < 9; t += 4) {
+            const float2* A = Dc + ((size_t)j * 9 + t) * n2 * n2 + a;
+            const float2* xs = sh + t * kCoarseSys * n2;
+            for (int b = 0; b < n2; ++b) {
+                const float2 mv = A[(size_t)b * n2];
+#pragma unroll
+                for (int k = 0; k < kCoarseSys; ++k) {
+                    if (k < ns) {
+                        const float2 xv = xs[k * n2 + b];
+                        acc[k].x += mv.x * xv.x - mv.y * xv.y;
+                        acc[k].y += mv.x * xv.y + mv.y * xv.x;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (a < n2)
+#pragma unroll
+        for (int k = 0; k < kCoarseSys; ++k)
+            if (k < ns) sh[(w * kCoarseSys + k) * 64 + a] = acc[k];
+    __syncthreads();
+    for (int idx = tid; idx < ns * n2; idx += kThreads) {
+        const int k = idx / n2, r = idx - k * n2;
+        float2 sum = make_float2(0.f, 0.f);
+        for (int q = 0; q < 4; ++q) {
+            const float2 v = sh[(q * kCoarseSys + k) * 64 + r];
+            sum.x += v.x;
+            sum.y += v.y;
+        }
+        const size_t at = ((size_t)(s0 + k) * nc + j) * n2 + r;
+        const float2 xv = x[at];
+        const float tw = (float)mu_c[s0 + k] * (r < nv ? 1.f : -1.f);
+        sum.x -= tw * xv.y;
+        sum.y += tw * xv.x;
+        y[at] = sum;
+    }
+}
+
+__global__ void k_mg_stencil_export(long long nc, int nv, const float2* __restrict__ Dc, double2* out) {
+    const int n2 = 2 * nv;
+    const long long total = nc * 9 * n2 * n2;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        // e indexes the row-major output [j][t][a][b]
+        const long long mt = e / (n2 * n2);
+        const int r = (int)(e - mt * n2 * n2), a = r / n2, b = r - a * n2;
+        const float2 v = Dc[(size_t)mt * n2 * n2 + (size_t)b * n2 + a];
+        out[e] = make_double2(v.x, v.y);
+    }
+}
+
+__global__ void k_mg_coarse_import(const double2* __restrict__ in, float2* v, long long n, unsigned* flag) {
+    bool bad = false;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const double2 t = in[e];
+        bad |= !isfinite(t.x) || !isfinite(t.y);
+        v[e] = make_float2((float)t.x, (float)t.y);
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
+__global__ void k_mg_coarse_export(const float2* __restrict__ v, double2* out, long long n) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        out[e] = make_double2(v[e].x, v[e].y);
+}
+
+// ---- coarse vector kernels (float2 pairs read as float4; n is even)
+
+__global__ void __launch_bounds__(kThreads) k_cdots(const float2* __restrict__ basis, size_t vec_stride, int cnt,
+                                                    const float2* __restrict__ w, size_t sys_stride, long long n,
+                                                    double* partials) {
+    __shared__ double lds[(kThreads / 64) * 2 * kDots];
+    const int sys = blockIdx.y, nblk = gridDim.x;
+    const float4* w4 = reinterpret_cast<const float4*>(w + (size_t)sys * sys_stride);
+    double acc[2 * kDots];
+#pragma unroll
+    for (int i = 0; i < 2 * kDots; ++i) acc[i] = 0;
+    const long long n4 = n / 2;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n4; e += (long long)nblk * kThreads) {
+        const float4 wv = w4[e];
+#pragma unroll
+        for (int i = 0; i < kDots; ++i) {
+            if (i < cnt) {
+                const float4 v = reinterpret_cast<const float4*>(basis + (size_t)i * vec_stride + (size_t)sys * sys_stride)[e];
+                acc[2 * i] += (double)(v.x * wv.x + v.y * wv.y + v.z * wv.z + v.w * wv.w);
+                acc[2 * i + 1] += (double)(v.x * wv.y - v.y * wv.x + v.z * wv.w - v.w * wv.z);
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 2 * kDots; ++i) {
+        if (i < 2 * cnt) {
+            const double v = wave_sum_d(acc[i]);
+            if (lane == 0) lds[wv * 2 * kDots + i] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * cnt) {
+        double t = 0;
+        for (int q = 0; q < kThreads / 64; ++q) t += lds[q * 2 * kDots + threadIdx.x];
+        partials[((size_t)sys * 2 * cnt + threadIdx.x) * nblk + blockIdx.x] = t;
+    }
+}
+
+// out values (per system, nval consecutive doubles) from the per-workgroup partials, summed in order
+__global__ void k_reduce(const double* __restrict__ partials, int nval, int nblk, int nsys, double* out,
+                         int out_stride) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nval * nsys) return;
+    const int sys = k / nval, v = k - sys * nval;
+    double t = 0;
+    for (int b = 0; b < nblk; ++b) t += partials[(size_t)k * nblk + b];
+    out[(size_t)sys * out_stride + v] = t;
+}
+
+__global__ void __launch_bounds__(kThreads) k_caxpy(const float2* __restrict__ basis, size_t vec_stride, int cnt,
+                                                    const double2* __restrict__ coef, int coef_stride, float sign,
+                                                    float2* w, size_t sys_stride, long long n) {
+    const int sys = blockIdx.y;
+    float cr[kDots], ci[kDots];
+#pragma unroll
+    for (int i = 0; i < kDots; ++i) {
+        const double2 c = i < cnt ? coef[(size_t)sys * coef_stride + i] : make_double2(0.0, 0.0);
+        cr[i] = sign * (float)c.x;
+        ci[i] = sign * (float)c.y;
+    }
+    float4* w4 = reinterpret_cast<float4*>(w + (size_t)sys * sys_stride);
+    const long long n4 = n / 2;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n4; e += (long long)gridDim.x * kThreads) {
+        float4 t = w4[e];
+#pragma unroll
+        for (int i = 0; i < kDots; ++i) {
+            if (i < cnt) {
+                const float4 v = reinterpret_cast<const float4*>(basis + (size_t)i * vec_stride + (size_t)sys * sys_stride)[e];
+                t.x += cr[i] * v.x - ci[i] * v.y;
+                t.y += cr[i] * v.y + ci[i] * v.x;
+                t.z += cr[i] * v.z - ci[i] * v.w;
+                t.w += cr[i] * v.w + ci[i] * v.z;
+            }
+        }
+        w4[e] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_cnorm2(const float2* __restrict__ w, size_t sys_stride, long long n,
+                                                     double* partials) {
+    __shared__ double lds[kThreads / 64];
+    const int sys = blockIdx.y, nblk = gridDim.x;
+    const float4* w4 = reinterpret_cast<const float4*>(w + (size_t)sys * sys_stride);
+    double acc = 0;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n / 2; e += (long long)nblk * kThreads) {
+        const float4 v = w4[e];
+        acc += (double)(v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w);
+    }
+    acc = wave_sum_d(acc);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int q = 0; q < kThreads / 64; ++q) t += lds[q];
+        partials[(size_t)sys * nblk + blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_cscale(const float2* __restrict__ x, const double* __restrict__ f,
+                                                     float2* y, size_t sys_stride, long long n) {
+    const int sys = blockIdx.y;
+    const float a = (float)f[sys];
+    const float4* x4 = reinterpret_cast<const float4*>(x + (size_t)sys * sys_stride);
+    float4* y4 = reinterpret_cast<float4*>(y + (size_t)sys * sys_stride);
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n / 2; e += (long long)gridDim.x * kThreads) {
+        const float4 v = x4[e];
+        y4[e] = make_float4(a * v.x, a * v.y, a * v.z, a * v.w);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_csub_from(const float2* __restrict__ x, float2* y, size_t sys_stride,
+                                                        long long n) {
+    const int sys = blockIdx.y;
+    const float4* x4 = reinterpret_cast<const float4*>(x + (size_t)sys * sys_stride);
+    float4* y4 = reinterpret_cast<float4*>(y + (size_t)sys * sys_stride);
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n / 2; e += (long long)gridDim.x * kThreads) {
+        const float4 a = x4[e], b = y4[e];
+        y4[e] = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+    }
+}
+
+int agg_threads(const Geo& g) { return (g.Vb + 63) & ~63; }
+
+}  // namespace
+
+hipError_t launch_mg_term(const MgArgs& m, const void* links, const void* clover, int t, int b0, int nb, void* out,
+                          size_t out_stride, hipStream_t st) {
+    if (t < 0 || t > 8 || nb <= 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((m.g.V + kThreads - 1) / kThreads)), blk(kThreads);
+    switch (t) {
+        case 0: hipLaunchKernelGGL(k_mg_term<0>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        case 1: hipLaunchKernelGGL(k_mg_term<1>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        case 2: hipLaunchKernelGGL(k_mg_term<2>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        case 3: hipLaunchKernelGGL(k_mg_term<3>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        case 4: hipLaunchKernelGGL(k_mg_term<4>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        case 5: hipLaunchKernelGGL(k_mg_term<5>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        case 6: hipLaunchKernelGGL(k_mg_term<6>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        case 7: hipLaunchKernelGGL(k_mg_term<7>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+        default: hipLaunchKernelGGL(k_mg_term<8>, grid, blk, 0, st, m, links, clover, b0, nb, out, out_stride); break;
+    }
+    return hipGetLastError();
+}
+
+// Aggregates of up to 256 sites take 4 systems per workgroup, larger ones 2 (register budget).
+hipError_t launch_mg_restrict(const MgArgs& m, const void* x, size_t x_stride, int nsys, float2* out, size_t base,
+                              size_t s_stride, size_t j_stride, hipStream_t st) {
+    const int nt = agg_threads(m.g);
+    if (nt > 1024 || m.nv < 1 || m.nv > kMgMaxVec || nsys < 1) return hipErrorInvalidValue;
+    const int S = nt <= 256 ? 4 : 2;
+    const size_t lds = (size_t)(nt / 64) * S * m.nv * 4 * sizeof(float);
+    const dim3 grid((unsigned)(m.g.V / m.g.Vb), (unsigned)((nsys + S - 1) / S));
+    if (nt <= 256)
+        hipLaunchKernelGGL((k_mg_restrict<4, 256>), grid, dim3(nt), lds, st, m, x, x_stride, nsys, out, base,
+                           s_stride, j_stride);
+    else
+        hipLaunchKernelGGL((k_mg_restrict<2, 1024>), grid, dim3(nt), lds, st, m, x, x_stride, nsys, out, base,
+                           s_stride, j_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_prolong(const MgArgs& m, const float2* c, int nsys, void* e, size_t e_stride, hipStream_t st) {
+    const int nt = agg_threads(m.g);
+    if (nt > 1024 || m.nv < 1 || m.nv > kMgMaxVec || nsys < 1) return hipErrorInvalidValue;
+    const int S = nt <= 256 ? 4 : 2;
+    const size_t lds = (size_t)S * 2 * m.nv * sizeof(float2);
+    const dim3 grid((unsigned)(m.g.V / m.g.Vb), (unsigned)((nsys + S - 1) / S));
+    if (nt <= 256)
+        hipLaunchKernelGGL((k_mg_prolong<4, 256>), grid, dim3(nt), lds, st, m, c, nsys, e, e_stride);
+    else
+        hipLaunchKernelGGL((k_mg_prolong<2, 1024>), grid, dim3(nt), lds, st, m, c, nsys, e, e_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_block_orthonormalize(const MgArgs& m, void* P, hipStream_t st) {
+    const int nt = agg_threads(m.g);
+    if (nt > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mg_block_orthonormalize, dim3((unsigned)(m.g.V / m.g.Vb), 2), dim3(nt), 0, st, m, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_coarse_apply(const Geo& g, int nv, const float2* Dc, const double* mu_c, const float2* x,
+                                  float2* y, int nsys, hipStream_t st) {
+    if (nv < 1 || nv > kMgMaxVec || nsys < 1 || nsys > kMaxSys) return hipErrorInvalidValue;
+    const int n2 = 2 * nv;
+    const size_t xs = (size_t)9 * kCoarseSys * n2, red = (size_t)4 * kCoarseSys * 64;
+    const size_t lds = (xs > red ? xs : red) * sizeof(float2);
+    const dim3 grid((unsigned)(g.V / g.Vb), (unsigned)((nsys + kCoarseSys - 1) / kCoarseSys));
+    hipLaunchKernelGGL(k_mg_coarse_apply, grid, dim3(kThreads), lds, st, g, nv, Dc, mu_c, x, y, nsys);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_stencil_export(long long nc, int nv, const float2* Dc, void* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_stencil_export, dim3(1024), dim3(kThreads), 0, st, nc, nv, Dc, (double2*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_coarse_import(const void* canon, float2* v, long long n, unsigned* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_coarse_import, dim3(1024), dim3(kThreads), 0, st, (const double2*)canon, v, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_coarse_export(const float2* v, void* canon, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_coarse_export, dim3(1024), dim3(kThreads), 0, st, v, (double2*)canon, n);
+    return hipGetLastError();
+}
+
+int mg_blas_blocks(long long n) {
+    const long long b = (n / 2 + kThreads - 1) / kThreads;
+    return (int)(b < 1 ? 1 : (b > 512 ? 512 : b));
+}
+
+hipError_t mg_blas_dots(const float2* basis, size_t vec_stride, int cnt, const float2* w, size_t sys_stride, int nsys,
+                        long long n, double* partials, double2* out, int out_stride, hipStream_t st) {
+    if (cnt < 1 || cnt > kDots || (n & 1)) return hipErrorInvalidValue;
+    const int nblk = mg_blas_blocks(n);
+    hipLaunchKernelGGL(k_cdots, dim3(nblk, nsys), dim3(kThreads), 0, st, basis, vec_stride, cnt, w, sys_stride, n,
+                       partials);
+    const int tot = 2 * cnt * nsys;
+    hipLaunchKernelGGL(k_reduce, dim3((tot + 63) / 64), dim3(64), 0, st, partials, 2 * cnt, nblk, nsys,
+                       reinterpret_cast<double*>(out), 2 * out_stride);
+    return hipGetLastError();
+}
+
+hipError_t mg_blas_axpy(const float2* basis, size_t vec_stride, int cnt, const double2* coef, int coef_stride,
+                        double sign, float2* w, size_t sys_stride, int nsys, long long n, hipStream_t st) {
+    if (cnt < 1 || cnt > kDots || (n & 1)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_caxpy, dim3(mg_blas_blocks(n), nsys), dim3(kThreads), 0, st, basis, vec_stride, cnt, coef,
+                       coef_stride, (float)sign, w, sys_stride, n);
+    return hipGetLastError();
+}
+
+hipError_t mg_blas_norm2(const float2* w, size_t sys_stride, int nsys, long long n, double* partials, double* out,
+                         hipStream_t st) {
+    if (n & 1) return hipErrorInvalidValue;
+    const int nblk = mg_blas_blocks(n);
+    hipLaunchKernelGGL(k_cnorm2, dim3(nblk, nsys), dim3(kThreads), 0, st, w, sys_stride, n, partials);
+    hipLaunchKernelGGL(k_reduce, dim3((nsys + 63) / 64), dim3(64), 0, st, partials, 1, nblk, nsys, out, 1);
+    return hipGetLastError();
+}
+
+hipError_t mg_blas_scale(const float2* x, const double* f, float2* y, size_t sys_stride, int nsys, long long n,
+                         hipStream_t st) {
+    if (n & 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cscale, dim3(mg_blas_blocks(n), nsys), dim3(kThreads), 0, st, x, f, y, sys_stride, n);
+    return hipGetLastError();
+}
+
+hipError_t mg_blas_sub_from(const float2* x, float2* y, size_t sys_stride, int nsys, long long n, hipStream_t st) {
+    if (n & 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_csub_from, dim3(mg_blas_blocks(n), nsys), dim3(kThreads), 0, st, x, y, sys_stride, n);
+    return hipGetLastError();
+}
+
+}  // namespace tmsap

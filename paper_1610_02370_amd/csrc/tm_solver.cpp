@@ -83,6 +83,7 @@ struct Ctx {
     const GaugeDev* op;  // operator for w = D z and residuals
     Prec op_compute;
     const GaugeDev* sap;  // smoother gauge
+    tm_mg* mg = nullptr;  // two-level preconditioner (else SAP)
     Prec vp;              // Krylov vectors
     Prec sp;              // smoother storage (preconditioned vectors z)
     Scratch sc;
@@ -231,7 +232,11 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             }
             // z_j = SAP(v_j) from a zero guess; w = D z_j
             if ((rc = hcheck(hipEventRecord(c.ev[0], c.st), "event"))) return rc;
-            if ((rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, c.sys_tile, c.st, c.eo))) return rc;
+            if (c.mg)
+                rc = mg_apply(c.mg, c.ds, src, zj, c.mu, ns, c.st);
+            else
+                rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, c.sys_tile, c.st, c.eo);
+            if (rc) return rc;
             if ((rc = hcheck(hipEventRecord(c.ev[1], c.st), "event"))) return rc;
             c.sap_cycles += c.n_cycles;
             c.sap_sys_cycles += (long long)c.n_cycles * ns;
@@ -469,10 +474,19 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     const bool dc = so->form == TM_SOLVE_DEFECT_CORRECTION;
     if (dc && sp == P_F64) return fail(TM_ERR_PREC, "defect correction needs FP32/FP16/BF16 smoother storage");
     if (dc && !(so->inner_tol > 0 && so->inner_tol < 1)) return fail(TM_ERR_ARG, "inner_tol must be in (0, 1)");
-    // block_dims all zero: the tuned shape for this problem if one is cached, else 4^4
+    // block_dims all zero: the tuned shape for this problem if one is cached, else 4^4; with a
+    // two-level handle its aggregates
     int bd[4], tuned_tile = 0;
+    tm_mg* mg = so->mg;
+    if (mg) {
+        if (sp != P_F32) return fail(TM_ERR_PREC, "the two-level preconditioner needs FP32 storage");
+        if (opts->sap_eo) return fail(TM_ERR_ARG, "the two-level preconditioner smooths without even-odd blocks");
+        if ((rc = mg_matches(mg, geom))) return rc;
+    }
     const bool bd_given = so->block_dims[0] | so->block_dims[1] | so->block_dims[2] | so->block_dims[3];
-    if (bd_given)
+    if (mg)
+        mg_block_dims(mg, bd);
+    else if (bd_given)
         for (int a = 0; a < 4; ++a) bd[a] = so->block_dims[a];
     else if (!tune_lookup(geom, opts->storage, so->n_cycles, so->mr_iters, opts->sap_eo, bd, &tuned_tile))
         for (int a = 0; a < 4; ++a) bd[a] = 4;
@@ -513,6 +527,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     c.sys_tile = opts->sys_tile > 0 ? opts->sys_tile : tuned_tile;
     c.eo = opts->sap_eo != 0;
     c.sap = gs;
+    c.mg = mg;
     c.vp = vp;
     c.sp = sp;
     if ((rc = hcheck(hipEventCreate(&c.ev[0]), "event")) || (rc = hcheck(hipEventCreate(&c.ev[1]), "event"))) return rc;

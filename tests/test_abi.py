@@ -66,3 +66,52 @@ def test_bad_arguments_rejected_on_host():
     g = tm.make_geom((4, 4, 4, 4), 0.1)
     rc = tm.lib().tm_dirac_apply(ctypes.byref(g), None, None, None, 0.15, 0.0, ctypes.byref(o))
     assert rc == -4
+
+
+def read_golden(name):
+    vals = {}
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, *v = line.split()
+                vals[k] = v
+    return vals
+
+
+def test_table1_multigrid_defaults_match_library():
+    # the two-level defaults are the paper's tuned set (Table 1) where a two-level method has the parameter
+    vals = read_golden("table1_mg_defaults.txt")
+    p = tm.mg_params()
+    assert p.setup_iters == int(vals["setup_iterations"][0])
+    assert p.n_vec == int(vals["test_vectors_level1"][0])
+    assert tuple(p.block_dims) == tuple(int(v) for v in vals["aggregate_dims"])
+    assert tuple(p.block_dims) == tuple(int(v) for v in vals["smoother_block_dims"])
+    assert p.post_cycles == int(vals["post_smoothing_steps"][0])
+    assert p.delta == float(vals["coarse_mu_factor"][0])
+    assert p.coarse_restart == int(vals["coarse_restart"][0])
+    assert p.coarse_max_restarts == int(vals["coarse_max_restarts"][0])
+    assert p.coarse_tol == float(vals["coarse_relative_tolerance"][0])
+    sap = read_golden("table1_sap_defaults.txt")
+    assert p.mr_iters == int(sap["block_mr_iterations"][0])
+
+
+def test_two_level_setup_rejects_bad_input_on_host():
+    g = tm.make_geom((8, 8, 8, 8), 0.01)
+    o = tm.make_opts("f32", stream=False)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)
+    L = tm.lib()
+    for kw, code in (({"n_vec": 0}, -1), ({"n_vec": 33}, -1), ({"coarse_restart": 129}, -1), ({"delta": 0.0}, -1),
+                     ({"block_dims": (4, 4, 4, 3)}, -2), ({"block_dims": (8, 4, 4, 4)}, -3)):
+        p = tm.mg_params(**kw)
+        rc = L.tm_mg_setup(ctypes.byref(g), dummy, 0.15, 1.0, ctypes.byref(p), dummy, ctypes.byref(h), ctypes.byref(o))
+        assert rc == code, (kw, rc)
+        assert not h.value
+    # FP32 only, one setup twist
+    p = tm.mg_params()
+    o64 = tm.make_opts("f64", stream=False)
+    assert L.tm_mg_setup(ctypes.byref(g), dummy, 0.15, 1.0, ctypes.byref(p), dummy, ctypes.byref(h),
+                         ctypes.byref(o64)) == -4
+    g2 = tm.make_geom((8, 8, 8, 8), [0.01, -0.01])
+    assert L.tm_mg_setup(ctypes.byref(g2), dummy, 0.15, 1.0, ctypes.byref(p), dummy, ctypes.byref(h),
+                         ctypes.byref(o)) == -1
