@@ -70,15 +70,45 @@ MUTATIONS = {
 }
 
 
+# The pin that must catch each planted mistake (one test of the pin files; every
+# parametrisation of it runs).  Running one pin per mistake keeps the CPU suite short.
+CATCHES = {
+    "backward_link_site": "test_oracle_operator.py::test_gauge_covariance_of_D",
+    "bc_phase_sign": "test_oracle_operator.py::test_twisted_boundary_plane_waves",
+    "clover_leaf_dropped": "test_oracle_operator.py::test_clover_constant_abelian_field_closed_form",
+    "clover_norm": "test_oracle_operator.py::test_clover_constant_abelian_field_closed_form",
+    "eo_cg_rhs_no_inverse": "test_oracle_sap.py::test_cg_eo_against_dense_lu",
+    "eo_dhat_sign": "test_oracle_sap.py::test_dhat_is_the_dense_schur_complement",
+    "eo_parity_flip": "test_oracle_sap.py::test_mr_eo_dense_replica_and_exact_limit",
+    "eo_rhs_uncorrected": "test_oracle_sap.py::test_mr_eo_dense_replica_and_exact_limit",
+    "eo_schur_sign": "test_oracle_sap.py::test_mr_eo_dense_replica_and_exact_limit",
+    "givens_conj": "test_oracle_sap.py::test_gmres_identity_preconditioner_terminates",
+    "link_transposed": "test_oracle_operator.py::test_constant_nonabelian_links_plane_wave",
+    "mg_aggregate_dot_conj": "test_oracle_mg.py::test_aggregate_basis_is_phase_fixed_qr",
+    "mg_delta_ignored": "test_oracle_mg.py::test_unitary_prolongation_with_exact_coarse_solve_inverts_D",
+    "mg_gamma5c_sign": "test_oracle_mg.py::test_coarse_operator_galerkin_on_uneven_coarse_grid",
+    "mg_no_post_smoothing": "test_oracle_mg.py::test_two_level_error_propagation",
+    "mg_prolong_half": "test_oracle_mg.py::test_prolongation_commutes_with_gamma5",
+    "mg_setup_no_orthonormalization": "test_oracle_mg.py::test_setup_iterations_follow_the_paper",
+    "mg_term_direction": "test_oracle_mg.py::test_coarse_operator_galerkin_on_uneven_coarse_grid",
+    "mg_twist_twice": "test_oracle_mg.py::test_coarse_operator_galerkin_on_uneven_coarse_grid",
+    "mr_alpha_conj": "test_oracle_sap.py::test_mr_monotone_optimal_and_converges",
+    "mu_shift_parity": "test_oracle_operator.py::test_mu_shifts_reduce_and_gamma5_hermiticity",
+    "no_dirichlet_cut": "test_oracle_sap.py::test_sap_exact_blocks_closed_form",
+    "projector_sign": "test_oracle_operator.py::test_free_field_eigenvalues_closed_form",
+    "sap_colour_order": "test_oracle_sap.py::test_sap_exact_blocks_closed_form",
+    "twist_sign": "test_oracle_operator.py::test_free_field_plane_waves",
+}
+
+
+def test_every_mistake_names_its_pin():
+    assert sorted(CATCHES) == sorted(MUTATIONS)
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_pins_catch_planted_mistake(name, tmp_path):
     old, new = MUTATIONS[name][:2]
-    # mistakes in the even-odd block solve only reach the even-odd pins
-    select = ["-k", "eo"] if name.startswith("eo_") else []
-    pins = ["test_oracle_operator.py", "test_oracle_sap.py"]
-    if name.startswith("mg_"):
-        pins = ["test_oracle_mg.py"]
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation anchor for {name} not found"
     mutated = tmp_path / "tm_oracle.c"
@@ -88,7 +118,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     subprocess.check_call(["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(mutated), "-lm"])
     env = dict(os.environ, TM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run(
-        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *select,
-         *[os.path.join(ROOT, "tests", p) for p in pins]],
+        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", os.path.join(ROOT, "tests", CATCHES[name])],
         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, f"planted mistake {name} was not caught:\n{r.stdout[-2000:]}"
+    assert r.returncode != 0, f"planted mistake {name} was not caught by {CATCHES[name]}:\n{r.stdout[-2000:]}"
