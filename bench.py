@@ -287,6 +287,68 @@ def cg_baseline(wl, Ud, torch, tm):
     return {"s_per_rhs": dt, "iters": rep["iters"], "true_rel_res": rep["true_rel_res"][0], "status": rc}
 
 
+# Two-level method (sections 2.3 - 2.6) with the library defaults (Table 1 where a two-level
+# method has the parameter): 4^4 aggregates, 28 test vectors, 5 setup iterations, coarse twist
+# 5.2 mu, coarse GMRES(100) to 0.1, 4 post-smoothing cycles of 3 MR steps.
+MG_NVEC = 28
+
+
+def two_level_phase(wl, Ud, torch, tm, restart):
+    """Setup of the two-level method (seeded Gaussian starting vectors drawn on the GPU) and the
+    same multi-RHS defect-correction solve preconditioned by it instead of SAP."""
+    import numpy as np
+
+    dims = wl["dims"]
+    V = int(np.prod(dims))
+    # the earlier legs' library workspaces (Krylov bases, gauge copies) are released first
+    tm.tm_finalize()
+    torch.cuda.empty_cache()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2024)
+    v0 = torch.randn((MG_NVEC, V, 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = tm.MG(dims, Ud, wl["kappa"], wl["mu"], wl["csw"], v0, n_vec=MG_NVEC)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    del v0
+    torch.cuda.empty_cache()
+    log(f"two-level setup: {t_setup:.2f}s")
+    nsys = len(wl["sources"])
+    b = torch.zeros((nsys, V, 4, 3), dtype=torch.complex128, device="cuda")
+    for k, (s, c, _) in enumerate(wl["sources"]):
+        b[k, 0, s, c] = 1.0
+    mus = [sg * wl["mu"] for (_, _, sg) in wl["sources"]]
+    x = torch.zeros_like(b)
+    # the first solve also builds the operator's gauge copies and the solver workspaces; the
+    # second is the steady state that is reported
+    times = []
+    for _ in range(2):
+        x.zero_()
+        before = mg.info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, rep = tm.tm_fgmres_solve(dims, Ud, b, x, wl["kappa"], mus, wl["csw"], TOL, storage="f32",
+                                     form="defect_correction", restart=restart, mg=mg, gauge_tag=11)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"two-level solve: {times[-1]:.2f}s iters {rep['iters']} outer {rep['outer']} group {rep['group']} "
+            f"max res {max(rep['true_rel_res']):.2e}")
+    info = mg.info()
+    apps = info["applications"] - before["applications"]
+    mg.close()
+    tm.tm_gauge_release(Ud)
+    del b, x
+    torch.cuda.empty_cache()
+    dt = times[-1]
+    return {"setup_s": t_setup, "s_per_rhs": dt / nsys, "first_call_s_per_rhs": times[0] / nsys,
+            "iters": rep["iters"], "outer": rep["outer"], "group": rep["group"], "status": rc,
+            "max_true_rel_res": max(rep["true_rel_res"]), "n_vec": MG_NVEC,
+            "coarse_dims_TZYX": list(info["cdims"]), "applications": apps,
+            "coarse_steps_per_application": (info["coarse_iters"] - before["coarse_iters"]) / max(1, apps),
+            "coarse_share": (info["t_coarse"] - before["t_coarse"]) / dt}
+
+
 def cpu_baseline(wl, target_s: float = 12.0):
     """FP64 CPU oracle SAP cycles (4^4 blocks, 4 MR steps, one system) on a 16^3 x 32
     sample of the workload (same eps, kappa, mu, c_sw), all host threads."""
@@ -338,6 +400,9 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cg-baseline", action="store_true")
+    ap.add_argument("--no-two-level", action="store_true", help="skip the two-level method's setup and solve")
+    ap.add_argument("--two-level-only", action="store_true",
+                    help="only the two-level method's setup and solves (profiling)")
     ap.add_argument("--sweep-only", action="store_true", help="only the all-systems SAP sweep (profiling)")
     ap.add_argument("--eo", action="store_true",
                     help="even-odd preconditioned SAP block solves (section 2.5) instead of MR on the full block")
@@ -364,6 +429,11 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch)
+
+    if args.two_level_only:
+        del b
+        print(json.dumps({"two_level": two_level_phase(wl, Ud, torch, tm, args.restart)}), flush=True)
+        return
 
     sweep = None
     if args.sweep or args.sweep_only:
@@ -416,6 +486,9 @@ def main():
     if cg:
         log(f"FP64 CG (even-odd normal equations) 1-RHS: {cg['s_per_rhs']:.2f}s iters {cg['iters']} "
             f"res {cg['true_rel_res']:.2e}")
+    two = None
+    if not args.no_two_level and wl["storage"] == "f32":
+        two = two_level_phase(wl, Ud, torch, tm, args.restart)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     if cpu:
         log(f"CPU oracle: {cpu['value']:.3f} GB/s-equivalent on {cpu['cores']} threads")
@@ -469,6 +542,7 @@ def main():
                   "s_per_rhs_cg_fp64": cg["s_per_rhs"] if cg else None,
                   "cg_iters": cg["iters"] if cg else None,
                   "speedup_per_rhs_over_cg": (cg["s_per_rhs"] / t_rhs) if cg else None},
+        "two_level": two,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -88,5 +88,7 @@ int mg_apply(tm_mg* mg, DeviceState* ds, const SpinorBuf& r, const SpinorBuf& z,
 // TM_OK when geom has the handle's dims, boundary phases and shifts and its device is current.
 int mg_matches(const tm_mg* mg, const tm_geom* geom);
 void mg_block_dims(const tm_mg* mg, int bd[4]);
+// device bytes per system of one preconditioner application (coarse vectors and Krylov basis)
+size_t mg_workspace_per_sys(const tm_mg* mg);
 
 }  // namespace tmsap

@@ -110,12 +110,37 @@ __global__ void __launch_bounds__(kThreads) k_mg_term(MgArgs m, const void* __re
     }
 }
 
+// Sum over the 64 lanes of a wave of 64 values per lane: after the exchange lane l
+// holds the sum of value l.  Each step halves the values a lane keeps (it keeps the
+// half selected by its lane bit and adds its partner's copy of that half), so the
+// reduction costs 63 exchanges instead of 6 per value.
+template <int H>
+__device__ inline void transpose_step(float (&v)[64], int lane) {
+    const bool up = lane & H;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float send = up ? v[i] : v[i + H];
+        const float keep = up ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, H, 64);
+    }
+    if constexpr (H > 1) transpose_step<H / 2>(v, lane);
+}
+
+__device__ inline float transpose_sum64(float (&v)[64]) {
+    transpose_step<32>(v, threadIdx.x & 63);
+    return v[0];
+}
+
 // Restriction of S systems per workgroup (one aggregate of at most NT sites).
+// Per site and test vector the 4 S partial sums (two spin halves, re / im, per
+// system) of 16 / S test vectors at a time go through one wave-level transpose
+// sum; the wave sums meet in LDS.
 template <int S, int NT>
 __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __restrict__ x, size_t x_stride,
                                                       int nsys, float2* out, size_t base, size_t s_stride,
                                                       size_t j_stride) {
-    extern __shared__ float red[];  // [waves][S][nv][4]
+    constexpr int PER = 16 / S;  // test vectors per 64-value chunk
+    extern __shared__ float red[];  // [waves][chunks][64]
     const Geo& g = m.g;
     const int j = blockIdx.x, l = threadIdx.x;
     const bool on = l < g.Vb;
@@ -123,6 +148,7 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __rest
     const int s0 = blockIdx.y * S;
     const int ns = min(S, nsys - s0);
     const int lane = l & 63, w = l >> 6, nw = blockDim.x >> 6, nv = m.nv;
+    const int nch = (nv + PER - 1) / PER;
     Spinor<float> xv[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
@@ -132,37 +158,41 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __rest
 #pragma unroll
             for (int q = 0; q < 12; ++q) xv[k].v[q] = cmk(0.f, 0.f);
     }
-    for (int i = 0; i < nv; ++i) {
-        Spinor<float> p;
-        if (on)
-            load_spinor<float, float>(field(m.P, m.P_stride, i), nullptr, g.V, s, p);
-        else
+    for (int c = 0; c < nch; ++c) {
+        float v[64];
 #pragma unroll
-            for (int q = 0; q < 12; ++q) p.v[q] = cmk(0.f, 0.f);
+        for (int ii = 0; ii < PER; ++ii) {
+            const int i = c * PER + ii;
+            Spinor<float> p;
+            if (on && i < nv)
+                load_spinor<float, float>(field(m.P, m.P_stride, i), nullptr, g.V, s, p);
+            else
 #pragma unroll
-        for (int k = 0; k < S; ++k) {
-            float d[4] = {0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q < 12; ++q) p.v[q] = cmk(0.f, 0.f);
 #pragma unroll
-            for (int q = 0; q < 12; ++q) {
-                const int h = q < 6 ? 0 : 2;
-                d[h] += p.v[q].re * xv[k].v[q].re + p.v[q].im * xv[k].v[q].im;
-                d[h + 1] += p.v[q].re * xv[k].v[q].im - p.v[q].im * xv[k].v[q].re;
-            }
+            for (int k = 0; k < S; ++k) {
+                float d[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float v = wave_sum(d[e]);
-                if (lane == 0) red[((w * S + k) * nv + i) * 4 + e] = v;
+                for (int q = 0; q < 12; ++q) {
+                    const int h = q < 6 ? 0 : 2;
+                    d[h] += p.v[q].re * xv[k].v[q].re + p.v[q].im * xv[k].v[q].im;
+                    d[h + 1] += p.v[q].re * xv[k].v[q].im - p.v[q].im * xv[k].v[q].re;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[(ii * S + k) * 4 + e] = d[e];
             }
         }
+        red[(w * nch + c) * 64 + lane] = transpose_sum64(v);
     }
     __syncthreads();
     const int n2 = 2 * nv;
     for (int idx = l; idx < ns * n2; idx += blockDim.x) {
         const int k = idx / n2, a = idx - k * n2, sg = a / nv, i = a - sg * nv;
+        const int c = i / PER, vi = ((i - c * PER) * S + k) * 4 + 2 * sg;
         float re = 0.f, im = 0.f;
         for (int q = 0; q < nw; ++q) {
-            re += red[((q * S + k) * nv + i) * 4 + 2 * sg];
-            im += red[((q * S + k) * nv + i) * 4 + 2 * sg + 1];
+            re += red[(q * nch + c) * 64 + vi];
+            im += red[(q * nch + c) * 64 + vi + 1];
         }
         out[base + (size_t)(s0 + k) * s_stride + (size_t)j * j_stride + a] = make_float2(re, im);
     }
@@ -291,14 +321,19 @@ __device__ inline long long coarse_nbr(const Geo& g, long long j, int t) {
     return out;
 }
 
-// One workgroup per coarse site and group of kCoarseSys systems; wave w handles
-// the terms t = w, w + 4, w + 8 with one lane per row a, so a column of a stencil
-// matrix is one coalesced load; the neighbours' x are staged in LDS.
+// One workgroup per coarse site and group of kCoarseSys systems.  The 9 stencil
+// matrices of the site are 9 * n2 columns of n2 complex numbers, stored one after
+// the other; thread t takes the row pair (2p, 2p + 1) with p = t % nv of the columns
+// c = t / nv, t / nv + G, ... (G = 256 / nv column groups), so a wavefront reads
+// consecutive 16-byte pieces and every thread has its own stream of loads.  The
+// neighbours' x are staged in LDS; the column groups' partial sums meet there too.
 __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, const float2* __restrict__ Dc,
                                                               const double* __restrict__ mu_c,
                                                               const float2* __restrict__ x, float2* y, int nsys) {
-    extern __shared__ float2 sh[];  // xs [9][kCoarseSys][n2]; reused for [4][kCoarseSys][64] partial sums
+    // xs [9][ks][n2]; then [G][ks][n2] partial sums, ks = systems per workgroup (LDS sized by it)
+    extern __shared__ float2 sh[];
     const int n2 = 2 * nv;
+    const int ks = min(kCoarseSys, nsys);
     const long long nc = g.V / g.Vb;
     const long long j = blockIdx.x;
     const int s0 = blockIdx.y * kCoarseSys;
@@ -306,41 +341,47 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
     const int tid = threadIdx.x;
     for (int idx = tid; idx < 9 * ns * n2; idx += kThreads) {
         const int t = idx / (ns * n2), r = idx - t * ns * n2, k = r / n2, b = r - k * n2;
-        sh[(t * kCoarseSys + k) * n2 + b] = x[((size_t)(s0 + k) * nc + coarse_nbr(g, j, t)) * n2 + b];
+        sh[(t * ks + k) * n2 + b] = x[((size_t)(s0 + k) * nc + coarse_nbr(g, j, t)) * n2 + b];
     }
     __syncthreads();
-    const int w = tid >> 6, a = tid & 63;
-    float2 acc[kCoarseSys];
+    const int G = kThreads / nv;
+    const int p = tid % nv, grp = tid / nv;
+    float2 acc0[kCoarseSys], acc1[kCoarseSys];
 #pragma unroll
-    for (int k = 0; k < kCoarseSys; ++k) acc[k] = make_float2(0.f, 0.f);
-    if (a < n2) {
-        for (int t = w; t < 9; t += 4) {
-            const float2* A = Dc + ((size_t)j * 9 + t) * n2 * n2 + a;
-            const float2* xs = sh + t * kCoarseSys * n2;
-            for (int b = 0; b < n2; ++b) {
-                const float2 mv = A[(size_t)b * n2];
+    for (int k = 0; k < kCoarseSys; ++k) acc0[k] = acc1[k] = make_float2(0.f, 0.f);
+    if (grp < G) {
+        const float4* A = reinterpret_cast<const float4*>(Dc + (size_t)j * 9 * n2 * n2);
+        const int ncol = 9 * n2;
+#pragma unroll 8
+        for (int c = grp; c < ncol; c += G) {
+            const float4 mv = A[(size_t)c * nv + p];  // rows 2p, 2p + 1 of column c
+            const float2* xs = sh + ((c / n2) * ks) * n2 + (c % n2);
 #pragma unroll
-                for (int k = 0; k < kCoarseSys; ++k) {
-                    if (k < ns) {
-                        const float2 xv = xs[k * n2 + b];
-                        acc[k].x += mv.x * xv.x - mv.y * xv.y;
-                        acc[k].y += mv.x * xv.y + mv.y * xv.x;
-                    }
+            for (int k = 0; k < kCoarseSys; ++k) {
+                if (k < ns) {
+                    const float2 xv = xs[k * n2];
+                    acc0[k].x += mv.x * xv.x - mv.y * xv.y;
+                    acc0[k].y += mv.x * xv.y + mv.y * xv.x;
+                    acc1[k].x += mv.z * xv.x - mv.w * xv.y;
+                    acc1[k].y += mv.z * xv.y + mv.w * xv.x;
                 }
             }
         }
     }
     __syncthreads();
-    if (a < n2)
+    if (grp < G)
 #pragma unroll
         for (int k = 0; k < kCoarseSys; ++k)
-            if (k < ns) sh[(w * kCoarseSys + k) * 64 + a] = acc[k];
+            if (k < ns) {
+                sh[(grp * ks + k) * n2 + 2 * p] = acc0[k];
+                sh[(grp * ks + k) * n2 + 2 * p + 1] = acc1[k];
+            }
     __syncthreads();
     for (int idx = tid; idx < ns * n2; idx += kThreads) {
         const int k = idx / n2, r = idx - k * n2;
         float2 sum = make_float2(0.f, 0.f);
-        for (int q = 0; q < 4; ++q) {
-            const float2 v = sh[(q * kCoarseSys + k) * 64 + r];
+        for (int q = 0; q < G; ++q) {
+            const float2 v = sh[(q * ks + k) * n2 + r];
             sum.x += v.x;
             sum.y += v.y;
         }
@@ -525,19 +566,20 @@ hipError_t launch_mg_term(const MgArgs& m, const void* links, const void* clover
     return hipGetLastError();
 }
 
-// Aggregates of up to 256 sites take 4 systems per workgroup, larger ones 2 (register budget).
+// Aggregates of up to 256 sites take 4 systems per workgroup, larger ones 1 (register budget).
 hipError_t launch_mg_restrict(const MgArgs& m, const void* x, size_t x_stride, int nsys, float2* out, size_t base,
                               size_t s_stride, size_t j_stride, hipStream_t st) {
     const int nt = agg_threads(m.g);
     if (nt > 1024 || m.nv < 1 || m.nv > kMgMaxVec || nsys < 1) return hipErrorInvalidValue;
-    const int S = nt <= 256 ? 4 : 2;
-    const size_t lds = (size_t)(nt / 64) * S * m.nv * 4 * sizeof(float);
+    const int S = nt <= 256 ? 4 : 1;
+    const int nch = (m.nv + 16 / S - 1) / (16 / S);
+    const size_t lds = (size_t)(nt / 64) * nch * 64 * sizeof(float);
     const dim3 grid((unsigned)(m.g.V / m.g.Vb), (unsigned)((nsys + S - 1) / S));
     if (nt <= 256)
         hipLaunchKernelGGL((k_mg_restrict<4, 256>), grid, dim3(nt), lds, st, m, x, x_stride, nsys, out, base,
                            s_stride, j_stride);
     else
-        hipLaunchKernelGGL((k_mg_restrict<2, 1024>), grid, dim3(nt), lds, st, m, x, x_stride, nsys, out, base,
+        hipLaunchKernelGGL((k_mg_restrict<1, 1024>), grid, dim3(nt), lds, st, m, x, x_stride, nsys, out, base,
                            s_stride, j_stride);
     return hipGetLastError();
 }
@@ -565,8 +607,8 @@ hipError_t launch_mg_block_orthonormalize(const MgArgs& m, void* P, hipStream_t 
 hipError_t launch_mg_coarse_apply(const Geo& g, int nv, const float2* Dc, const double* mu_c, const float2* x,
                                   float2* y, int nsys, hipStream_t st) {
     if (nv < 1 || nv > kMgMaxVec || nsys < 1 || nsys > kMaxSys) return hipErrorInvalidValue;
-    const int n2 = 2 * nv;
-    const size_t xs = (size_t)9 * kCoarseSys * n2, red = (size_t)4 * kCoarseSys * 64;
+    const int n2 = 2 * nv, ks = nsys < kCoarseSys ? nsys : kCoarseSys;
+    const size_t xs = (size_t)9 * ks * n2, red = (size_t)(kThreads / nv) * ks * n2;
     const size_t lds = (xs > red ? xs : red) * sizeof(float2);
     const dim3 grid((unsigned)(g.V / g.Vb), (unsigned)((nsys + kCoarseSys - 1) / kCoarseSys));
     hipLaunchKernelGGL(k_mg_coarse_apply, grid, dim3(kThreads), lds, st, g, nv, Dc, mu_c, x, y, nsys);

@@ -9,6 +9,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -47,6 +49,16 @@ namespace {
 typedef std::complex<double> zc;
 
 int hc(hipError_t e, const char* where) { return e == hipSuccess ? TM_OK : hip_fail(e, where); }
+
+// TM_VERBOSE=1: a progress line per setup iteration and per coarse solve on stderr.
+bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("TM_VERBOSE");
+        v = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
 
 MgArgs margs(const tm_mg* mg) {
     MgArgs m;
@@ -322,6 +334,11 @@ int mg_apply(tm_mg* mg, DeviceState* ds, const SpinorBuf& r, const SpinorBuf& z,
     if (rc) return rc;
     mg->applications += 1;
     mg->coarse_iters += it;
+    if (verbose()) {
+        std::fprintf(stderr, "[tm] two-level: coarse GMRES %d steps for %d systems, coarse time so far %.3f s\n", it, ns,
+                     mg->t_coarse);
+        std::fflush(stderr);
+    }
     if ((rc = hc(launch_mg_prolong(ma, ec, ns, z.data, fb, st), "prolongation"))) return rc;
     if (mg->p.post_cycles > 0)
         return run_sap(mg->g, mg->gauge, r, z, mu, ns, mg->p.post_cycles, mg->p.mr_iters, false, 0, st);
@@ -402,6 +419,10 @@ int mg_matches(const tm_mg* mg, const tm_geom* geom) {
     if (!same_geometry(&mg->geom, geom))
         return fail(TM_ERR_ARG, "geometry differs from the two-level handle's (dims, boundary phases or mu shifts)");
     return check_device(mg);
+}
+
+size_t mg_workspace_per_sys(const tm_mg* mg) {
+    return (size_t)(mg->p.coarse_restart + 4) * mg->nc * mg->n2 * sizeof(float2);
 }
 
 void mg_block_dims(const tm_mg* mg, int bd[4]) {
@@ -505,9 +526,19 @@ int tm_mg_setup(const tm_geom* geom, const void* U, double kappa, double c_sw, c
         std::swap(vcur, vnext);
         if ((rc = orthonormalize_fields(mg.get(), reinterpret_cast<float2*>(vcur), nv, st))) return rc;
         if ((rc = build_coarse(mg.get(), *G, vcur, W, chunk, st))) return rc;
+        if (verbose()) {
+            (void)hipStreamSynchronize(st);
+            std::fprintf(stderr, "[tm] two-level setup iteration %d of %d done at %.2f s\n", it, params->setup_iters,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            std::fflush(stderr);
+        }
     }
     if (params->setup_iters == 0 && (rc = build_coarse(mg.get(), *G, vcur, W, chunk, st))) return rc;
     if ((rc = hc(hipStreamSynchronize(st), "setup"))) return rc;
+    // the setup's workspaces (test vectors, stencil terms, the coarse basis for n_vec systems)
+    // are not needed by the solves
+    mg->fine.release();
+    mg->coarse.release();
     mg->applications = 0;
     mg->coarse_iters = 0;
     mg->t_coarse = 0;

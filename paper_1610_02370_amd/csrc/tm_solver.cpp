@@ -515,7 +515,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     // bytes per system: outer FP64 vectors (b, x, and r for defect correction) + Krylov space (+ r32, c32)
     const size_t b64 = internal_bytes(g, 1, P_F64);
     const size_t per_sys = (dc ? 3 : 2) * b64 + krylov_bytes(g, 1, m, vp, sp) +
-                           (dc ? 2 * internal_bytes(g, 1, P_F32) : 0);
+                           (dc ? 2 * internal_bytes(g, 1, P_F32) : 0) + (mg ? mg_workspace_per_sys(mg) : 0);
     const int group = fit_group(ds, geom->nsys, so->group, per_sys, 0);
 
     Ctx c;
