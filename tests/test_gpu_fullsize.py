@@ -289,3 +289,143 @@ def test_sap_64x128_24_systems_internal_point_sources(lattice_64x128, prec):
     del Ud, bi, xi, one
     tm.tm_finalize()
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- two-level method at 48^3x96
+# With no setup iterations the aggregate basis on an aggregate depends only on the starting
+# vectors there, and a row of the coarse stencil only on the basis of the aggregate and its eight
+# neighbours and on the links and clover between them.  So the oracle builds the method on a 12^4
+# window of 3^4 aggregates centred on a sampled aggregate (periodic boundaries: the window's own
+# wrap only touches its outer aggregates) and its central coarse site is exact; restriction,
+# prolongation and the coarse operator are checked there too.
+
+MG_NV = 8
+
+
+def mg_windows(cdims):
+    rng = np.random.default_rng(48)
+    picks = [np.zeros(4, int), np.array(cdims) - 1] + [rng.integers(0, cdims) for _ in range(2)]
+    return [tuple(int(v) for v in p) for p in picks]
+
+
+@pytest.fixture(scope="module")
+def mg_48x96(lattice_48x96):
+    import torch
+
+    dims, U = lattice_48x96
+    kappa, csw, mu = 0.1373, 1.5, 0.0009
+    announce("full-size two-level method 48^3x96: 8 starting vectors, no setup iterations")
+    v0 = synth.gaussian_spinor(dims, MG_NV, seed=480)
+    Ud = torch.from_numpy(U).cuda()
+    g = tm.MG(dims, Ud, kappa, mu, csw, torch.from_numpy(v0).cuda(), n_vec=MG_NV, setup_iters=0,
+              block_dims=BLOCK)
+    torch.cuda.empty_cache()
+    yield dims, U, v0, g, kappa, csw, mu
+    g.close()
+    del Ud
+    tm.tm_finalize()
+    torch.cuda.empty_cache()
+
+
+def window_mg(U, v0, dims, J, kappa, csw, mu):
+    origin = [4 * (J[a] - 1) for a in range(4)]
+    w = window_sites(dims, origin, (12, 12, 12, 12))
+    op = oracle.Operator((12, 12, 12, 12), U[w], oracle.kappa_to_m(kappa), mu, csw)
+    o = oracle.MG(op, BLOCK, MG_NV, delta=1.0)
+    o.setup(v0[:, w])
+    return o, w
+
+
+def coarse_index(cdims, J):
+    return ((J[0] * cdims[1] + J[1]) * cdims[2] + J[2]) * cdims[3] + J[3]
+
+
+def test_two_level_48x96_stencil_restriction_prolongation(mg_48x96):
+    import torch
+
+    dims, U, v0, g, kappa, csw, mu = mg_48x96
+    cdims = g.cdims
+    _, Dc = g.export()
+    Dc = host(Dc)
+    r = synth.gaussian_spinor(dims, 1, seed=481)
+    c = host(g.restrict(torch.from_numpy(r).cuda()))[0]
+    rng = np.random.default_rng(482)
+    cx = rng.normal(size=(1, g.nc, 2 * MG_NV)) + 1j * rng.normal(size=(1, g.nc, 2 * MG_NV))
+    e = host(g.prolong(torch.from_numpy(cx).cuda()))[0]
+    y = host(g.coarse_apply(torch.from_numpy(cx).cuda(), [2 * mu]))[0]
+    centre = coarse_index((3, 3, 3, 3), (1, 1, 1, 1))
+    for J in mg_windows(cdims):
+        announce(f"two-level window around aggregate {J}")
+        o, w = window_mg(U, v0, dims, J, kappa, csw, mu)
+        j = coarse_index(cdims, J)
+        assert np.abs(Dc[j] - o.Dc[centre]).max() < 1e-5 * np.abs(o.Dc[centre]).max()
+        assert rel_err(c[j], o.restrict(r[0][w])[centre]) < 1e-5
+        # the window's coarse vector: the full one at the window's aggregates
+        wJ = np.array(np.unravel_index(np.arange(81), (3, 3, 3, 3))).T
+        full_j = [coarse_index(cdims, [(J[a] - 1 + q[a]) % cdims[a] for a in range(4)]) for q in wJ]
+        cw = cx[0][full_j]
+        ew = o.prolong(cw).reshape(12, 12, 12, 12, 4, 3)[4:8, 4:8, 4:8, 4:8]
+        eg = e[w].reshape(12, 12, 12, 12, 4, 3)[4:8, 4:8, 4:8, 4:8]
+        assert rel_err(eg, ew) < 1e-6
+        assert rel_err(y[j], o.coarse_apply(cw, 2 * mu)[centre]) < 1e-5
+
+
+def test_two_level_48x96_galerkin_and_orthonormality(mg_48x96):
+    # at every site: R P = 1 and D_c(mu, delta = 1) = P^+ D(mu) P (FP64 operator), both on the GPU
+    import torch
+
+    dims, U, v0, g, kappa, csw, mu = mg_48x96
+    rng = np.random.default_rng(483)
+    cx = rng.normal(size=(1, g.nc, 2 * MG_NV)) + 1j * rng.normal(size=(1, g.nc, 2 * MG_NV))
+    cd = torch.from_numpy(cx).cuda()
+    e = g.prolong(cd)
+    assert rel_err(host(g.restrict(e)), cx) < 1e-5
+    Ud = torch.from_numpy(U).cuda()
+    De = tm.tm_dirac_apply(dims, Ud, e, kappa, [mu], csw, storage="f64")
+    ref = host(g.restrict(De))
+    assert rel_err(host(g.coarse_apply(cd, [mu])), ref) < 1e-5
+    del Ud, De, e
+
+
+def test_two_level_48x96_solve_sampled_residual(lattice_48x96):
+    # the benchmark's configuration: 28 vectors, 5 setup iterations, 12 point sources
+    import torch
+
+    dims, U = lattice_48x96
+    kappa, csw, mu = 0.1373, 1.5, 0.0009
+    V = U.shape[0]
+    announce("full-size two-level solve 48^3x96: 28 vectors, 5 setup iterations, 12 point sources")
+    Ud = torch.from_numpy(U).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2024)
+    v0 = torch.randn((28, V, 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
+    g = tm.MG(dims, Ud, kappa, mu, csw, v0)
+    del v0
+    torch.cuda.empty_cache()
+    b = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device="cuda")
+    for k in range(12):
+        b[k, 0, k // 3, k % 3] = 1.0
+    x = torch.zeros_like(b)
+    rc, rep = tm.tm_fgmres_solve(dims, Ud, b, x, kappa, [mu] * 12, csw, 1e-10, storage="f32",
+                                 form="defect_correction", restart=8, mg=g)
+    assert rc == 0, rep
+    assert max(rep["true_rel_res"][:12]) <= 1e-10
+    g.close()
+    rng = np.random.default_rng(97)
+    sites = [0, lex(dims, [0, 0, 0, 1]), lex(dims, [95, 47, 47, 47])] + list(rng.integers(0, V, 6))
+    for s in sites:
+        c = np.array(np.unravel_index(s, dims))
+        origin = c - 2
+        w = window_sites(dims, origin, (4, 4, 4, 4))
+        xw = host(x[:, torch.from_numpy(w).cuda()])
+        op = window_op(U, dims, origin, (4, 4, 4, 4), kappa, csw).with_mu(mu)
+        centre = lex((4, 4, 4, 4), [2, 2, 2, 2])
+        for k in range(12):
+            dx = op.apply(xw[k]).reshape(-1, 4, 3)[centre]
+            bs = np.zeros((4, 3), complex)
+            if s == 0:
+                bs[k // 3, k % 3] = 1.0
+            assert np.linalg.norm(bs - dx) <= 1.05e-10, (s, k)
+    del Ud, b, x
+    tm.tm_finalize()
+    torch.cuda.empty_cache()
