@@ -29,6 +29,8 @@ CASES = {
     # dims, aggregate, n_vec, antiperiodic, theta, shift
     "4^4 aggregates": ((8, 8, 8, 8), (4, 4, 4, 4), 6, True, THETA, SHIFT),
     "2^4 aggregates, uneven coarse grid": ((16, 8, 8, 8), (2, 2, 2, 2), 5, False, (0.3, 0.0, 0.0, -0.9), (0.0, 0.0)),
+    # 512-site aggregates: the kernels' large-aggregate variants and the generic smoother
+    "8x4^3 aggregates": ((16, 8, 8, 8), (8, 4, 4, 4), 4, True, (0.0, 0.0, 0.5, 0.0), (0.001, 0.0)),
 }
 
 
