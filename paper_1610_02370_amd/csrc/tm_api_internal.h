@@ -71,8 +71,9 @@ void fill_mu(const tm_geom* geom, double* mu);
 int prepare_site_inverses(const Geo& g, const GaugeDev& G, const double* mu, int nsys, int parity, hipStream_t st,
                           const void* inv[kMaxEoMu], unsigned char sel[kMaxSys], unsigned long long* adj);
 // Largest group of systems (at most `group` when positive) whose per-system
-// workspace fits in 92 % of the free device memory (plus the solver buffer).
-int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed);
+// workspace fits in 92 % of the free device memory plus the solver buffer and
+// `reusable` bytes the caller already holds for the same purpose.
+int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed, size_t reusable = 0);
 // n_cycles red-black SAP cycles; eo selects even-odd preconditioned block
 // solves (site inverses built on first use for each |mu| and kept with G).
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,
@@ -90,5 +91,7 @@ int mg_matches(const tm_mg* mg, const tm_geom* geom);
 void mg_block_dims(const tm_mg* mg, int bd[4]);
 // device bytes per system of one preconditioner application (coarse vectors and Krylov basis)
 size_t mg_workspace_per_sys(const tm_mg* mg);
+// device bytes of that workspace the handle holds now
+size_t mg_workspace_held(const tm_mg* mg);
 
 }  // namespace tmsap

@@ -421,6 +421,8 @@ int mg_matches(const tm_mg* mg, const tm_geom* geom) {
     return check_device(mg);
 }
 
+size_t mg_workspace_held(const tm_mg* mg) { return mg->coarse.bytes + mg->small.bytes; }
+
 size_t mg_workspace_per_sys(const tm_mg* mg) {
     return (size_t)(mg->p.coarse_restart + 4) * mg->nc * mg->n2 * sizeof(float2);
 }

@@ -427,11 +427,11 @@ int carve_scratch(Ctx& c) {
 }  // namespace
 
 // Largest group of systems whose workspace fits in free device memory.
-int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed) {
+int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed, size_t reusable) {
     int gsz = group > 0 ? std::min(group, nsys) : nsys;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return gsz;
-    const size_t avail = (size_t)((double)(free_b + ds->solver.bytes) * 0.92);
+    const size_t avail = (size_t)((double)(free_b + ds->solver.bytes + reusable) * 0.92);
     while (gsz > 1 && fixed + per_sys * (size_t)gsz > avail) gsz = (gsz + 1) / 2;
     return gsz;
 }
@@ -516,7 +516,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
     const size_t b64 = internal_bytes(g, 1, P_F64);
     const size_t per_sys = (dc ? 3 : 2) * b64 + krylov_bytes(g, 1, m, vp, sp) +
                            (dc ? 2 * internal_bytes(g, 1, P_F32) : 0) + (mg ? mg_workspace_per_sys(mg) : 0);
-    const int group = fit_group(ds, geom->nsys, so->group, per_sys, 0);
+    const int group = fit_group(ds, geom->nsys, so->group, per_sys, 0, mg ? mg_workspace_held(mg) : 0);
 
     Ctx c;
     c.ds = ds;
