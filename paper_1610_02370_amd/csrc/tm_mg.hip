@@ -609,7 +609,12 @@ hipError_t launch_mg_coarse_apply(const Geo& g, int nv, const float2* Dc, const 
     if (nv < 1 || nv > kMgMaxVec || nsys < 1 || nsys > kMaxSys) return hipErrorInvalidValue;
     const int n2 = 2 * nv, ks = nsys < kCoarseSys ? nsys : kCoarseSys;
     const size_t xs = (size_t)9 * ks * n2, red = (size_t)(kThreads / nv) * ks * n2;
-    const size_t lds = (xs > red ? xs : red) * sizeof(float2);
+    const size_t lds = (xs > red ? xs : red) * sizeof(float2);  // at most 9 * 16 * 64 * 8 = 72 KiB
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_coarse_apply),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid((unsigned)(g.V / g.Vb), (unsigned)((nsys + kCoarseSys - 1) / kCoarseSys));
     hipLaunchKernelGGL(k_mg_coarse_apply, grid, dim3(kThreads), lds, st, g, nv, Dc, mu_c, x, y, nsys);
     return hipGetLastError();

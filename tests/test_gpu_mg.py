@@ -31,6 +31,10 @@ CASES = {
     "2^4 aggregates, uneven coarse grid": ((16, 8, 8, 8), (2, 2, 2, 2), 5, False, (0.3, 0.0, 0.0, -0.9), (0.0, 0.0)),
     # 512-site aggregates: the kernels' large-aggregate variants and the generic smoother
     "8x4^3 aggregates": ((16, 8, 8, 8), (8, 4, 4, 4), 4, True, (0.0, 0.0, 0.5, 0.0), (0.001, 0.0)),
+    # the largest number of test vectors (64 coarse components, every lane of a coarse row)
+    "32 test vectors": ((8, 8, 8, 8), (4, 4, 4, 4), 32, False, (0.0, 0.0, 0.0, 0.0), (0.0, 0.0)),
+    # one test vector (two coarse components per aggregate)
+    "1 test vector": ((8, 8, 8, 8), (4, 4, 2, 2), 1, False, (0.2, 0.0, 0.0, 0.0), (0.0, 0.0)),
 }
 
 
