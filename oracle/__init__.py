@@ -69,6 +69,7 @@ class _MG(ctypes.Structure):
         ("mr_iters", ctypes.c_int),
         ("setup_iters", ctypes.c_int),
         ("setup_cycles", ctypes.c_int),
+        ("coarse_eo", ctypes.c_int),
         ("P", ctypes.c_void_p),
         ("Dc", ctypes.c_void_p),
     ]
@@ -119,6 +120,10 @@ def _load():
                                            ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Report)]
         lib.or_mg_coarse_gmres.restype = ctypes.c_int
         lib.or_mg_precond.argtypes = [ctypes.POINTER(_Op), ctypes.POINTER(_MG), vp, vp]
+        lib.or_mg_coarse_dhat.argtypes = [ip, ctypes.c_int, vp, ctypes.c_double, vp, vp]
+        lib.or_mg_coarse_gmres_eo.argtypes = [ip, ctypes.c_int, vp, ctypes.c_double, vp, vp, ctypes.c_double,
+                                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Report)]
+        lib.or_mg_coarse_gmres_eo.restype = ctypes.c_int
         lib.or_fgmres_mg.argtypes = [ctypes.POINTER(_Op), ctypes.POINTER(_MG), vp, vp, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_int, ctypes.POINTER(_Report)]
         lib.or_fgmres_mg.restype = ctypes.c_int
@@ -309,7 +314,7 @@ class MG:
 
     def __init__(self, op: Operator, adims, nv: int, delta: float = 1.0, coarse_tol: float = 0.1,
                  coarse_restart: int = 100, coarse_max_restarts: int = 5, post_cycles: int = 4, mr_iters: int = 4,
-                 setup_iters: int = 0, setup_cycles: int = 4):
+                 setup_iters: int = 0, setup_cycles: int = 4, coarse_eo: bool = False):
         self.op = op
         self.adims = tuple(int(a) for a in adims)
         self.nv = int(nv)
@@ -319,7 +324,7 @@ class MG:
         self.Dc = np.zeros((self.nc, 9, 2 * self.nv, 2 * self.nv), np.complex128)
         self._mg = _MG(_i4(self.adims), self.nv, float(delta), float(coarse_tol), int(coarse_restart),
                        int(coarse_max_restarts), int(post_cycles), int(mr_iters), int(setup_iters), int(setup_cycles),
-                       self.P.ctypes.data, self.Dc.ctypes.data)
+                       int(bool(coarse_eo)), self.P.ctypes.data, self.Dc.ctypes.data)
 
     @property
     def delta(self) -> float:
@@ -373,6 +378,23 @@ class MG:
         rep = _Report()
         _load().or_mg_coarse_gmres(_i4(self.cdims), self.nv, self.Dc.ctypes.data, float(mu_c), b.ctypes.data,
                                    x.ctypes.data, float(tol), int(restart), int(max_restarts), ctypes.byref(rep))
+        return x, {"iters": rep.iters, "restarts": rep.restarts, "met": bool(rep.converged),
+                   "rel_estimate": rep.true_rel_res}
+
+    def coarse_dhat(self, x, mu_c: float) -> np.ndarray:
+        """Even-odd reduced coarse operator on the odd coarse sites of x (even parts ignored, zero in the result)."""
+        x = _c128(x).reshape(self.nc, 2 * self.nv)
+        y = np.empty_like(x)
+        _load().or_mg_coarse_dhat(_i4(self.cdims), self.nv, self.Dc.ctypes.data, float(mu_c), x.ctypes.data,
+                                  y.ctypes.data)
+        return y
+
+    def coarse_gmres_eo(self, b, mu_c: float, tol: float, restart: int, max_restarts: int):
+        b = _c128(b).reshape(self.nc, 2 * self.nv)
+        x = np.empty_like(b)
+        rep = _Report()
+        _load().or_mg_coarse_gmres_eo(_i4(self.cdims), self.nv, self.Dc.ctypes.data, float(mu_c), b.ctypes.data,
+                                      x.ctypes.data, float(tol), int(restart), int(max_restarts), ctypes.byref(rep))
         return x, {"iters": rep.iters, "restarts": rep.restarts, "met": bool(rep.converged),
                    "rel_estimate": rep.true_rel_res}
 

@@ -1178,14 +1178,14 @@ void or_mg_coarse_apply(const int cdims[4], int nv, const or_cplx* Dc, double mu
     }
 }
 
-/* GMRES(restart) for (Dc + i mu_c Gamma5c) x = b from x = 0, modified
- * Gram-Schmidt and Givens rotations.  Stops when the residual estimate
- * |g_{j+1}| <= tol ||b|| (tol <= 0: never) or after max_restarts cycles; each
- * cycle restarts from the recomputed residual.  Returns 0 when the estimate
- * met tol. */
-int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* b, or_cplx* x,
-                       double tol, int restart, int max_restarts, or_report* rep) {
-    long n = or_volume(cdims) * 2 * nv;
+typedef void (*or_apply_fn)(const void* ctx, const or_cplx* in, or_cplx* out);
+
+/* GMRES(restart) for A x = b from x = 0, modified Gram-Schmidt and Givens
+ * rotations.  Stops when the residual estimate |g_{j+1}| <= tol * bref
+ * (tol <= 0: never) or after max_restarts cycles; each cycle restarts from
+ * the recomputed residual.  Returns 0 when the estimate met tol. */
+static int gmres_op(long n, or_apply_fn A, const void* actx, const or_cplx* b, or_cplx* x, double tol, double bref,
+                    int restart, int max_restarts, or_report* rep) {
     int m = restart;
     or_cplx* Vv = malloc(sizeof(or_cplx) * n * (m + 1));
     or_cplx* w = malloc(sizeof(or_cplx) * n);
@@ -1195,11 +1195,11 @@ int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_
     or_cplx* g = malloc(sizeof(or_cplx) * (m + 1));
     or_cplx* y = malloc(sizeof(or_cplx) * m);
     for (long i = 0; i < n; ++i) x[i] = 0;
-    double bnorm = vnorm(b, n), est = bnorm;
-    int iters = 0, cycles = 0, met = bnorm == 0.0;
+    double bnorm = bref, est = vnorm(b, n);
+    int iters = 0, cycles = 0, met = est == 0.0;
     while (!met && cycles < max_restarts) {
         /* r = b - A x */
-        or_mg_coarse_apply(cdims, nv, Dc, mu_c, x, w);
+        A(actx, x, w);
         for (long i = 0; i < n; ++i) w[i] = b[i] - w[i];
         double beta = vnorm(w, n);
         est = beta;
@@ -1212,7 +1212,7 @@ int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_
         g[0] = beta;
         int jd = 0;
         for (int j = 0; j < m; ++j) {
-            or_mg_coarse_apply(cdims, nv, Dc, mu_c, Vv + (size_t)j * n, w);
+            A(actx, Vv + (size_t)j * n, w);
             for (int i = 0; i <= j; ++i) {
                 or_cplx h = vdot(Vv + (size_t)i * n, w, n);
                 H[i * m + j] = h;
@@ -1274,6 +1274,180 @@ int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_
     return met ? 0 : 1;
 }
 
+typedef struct {
+    const int* cdims;
+    int nv;
+    const or_cplx* Dc;
+    double mu_c;
+    const or_cplx* Minv;  /* even-odd: inverses of the even-site blocks */
+    or_cplx* t;           /* even-odd: workspace, two coarse vectors */
+} coarse_ctx;
+
+static void coarse_apply_fn(const void* ctx, const or_cplx* in, or_cplx* out) {
+    const coarse_ctx* c = (const coarse_ctx*)ctx;
+    or_mg_coarse_apply(c->cdims, c->nv, c->Dc, c->mu_c, in, out);
+}
+
+/* GMRES(restart) for (Dc + i mu_c Gamma5c) x = b from x = 0; the stopping
+ * estimate is relative to ||b||. */
+int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* b, or_cplx* x,
+                       double tol, int restart, int max_restarts, or_report* rep) {
+    long n = or_volume(cdims) * 2 * nv;
+    coarse_ctx c = {cdims, nv, Dc, mu_c, NULL, NULL};
+    return gmres_op(n, coarse_apply_fn, &c, b, x, tol, vnorm(b, n), restart, max_restarts, rep);
+}
+
+/* Parity of a coarse site: sum of its coordinates mod 2 (0 = even). */
+static int coarse_parity(const int cdims[4], long j) {
+    int J[4];
+    site_coords(cdims, j, J);
+    return (J[0] + J[1] + J[2] + J[3]) & 1;
+}
+
+/* out = [s_self (Dc[j][0] + i mu_c Gamma5c) x_self + sum_{t>=1} Dc[j][t] x_hop(nbr_t(j))] on the
+ * coarse sites of parity p, 0 on the others; a NULL input is a zero vector. */
+static void coarse_part(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, int p, const or_cplx* x_self,
+                        const or_cplx* x_hop, or_cplx* out) {
+    long nc = or_volume(cdims);
+    int n2 = 2 * nv;
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < nc; ++j) {
+        for (int a = 0; a < n2; ++a) {
+            or_cplx acc = 0;
+            if (coarse_parity(cdims, j) == p) {
+                if (x_self) {
+                    acc = _Complex_I * mu_c * (a < nv ? 1.0 : -1.0) * x_self[(size_t)j * n2 + a];
+                    const or_cplx* M = Dc + (((size_t)j * 9) * n2 + a) * n2;
+                    for (int b = 0; b < n2; ++b) acc += M[b] * x_self[(size_t)j * n2 + b];
+                }
+                if (x_hop)
+                    for (int t = 1; t < 9; ++t) {
+                        long src = mg_coarse_nbr(cdims, j, t);
+                        const or_cplx* M = Dc + (((size_t)j * 9 + t) * n2 + a) * n2;
+                        for (int b = 0; b < n2; ++b) acc += M[b] * x_hop[(size_t)src * n2 + b];
+                    }
+            }
+            out[(size_t)j * n2 + a] = acc;
+        }
+    }
+}
+
+/* Inverses of the site blocks Dc[j][0] + i mu_c Gamma5c at the sites of parity p
+ * (Gauss-Jordan elimination with partial pivoting); Minv [nc][n2][n2]. */
+static void coarse_block_inverses(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, int p, or_cplx* Minv) {
+    long nc = or_volume(cdims);
+    int n2 = 2 * nv;
+#pragma omp parallel for schedule(dynamic)
+    for (long j = 0; j < nc; ++j) {
+        if (coarse_parity(cdims, j) != p) continue;
+        or_cplx* a = malloc(sizeof(or_cplx) * n2 * 2 * n2);  /* [A | I] */
+        for (int r = 0; r < n2; ++r)
+            for (int c = 0; c < 2 * n2; ++c) {
+                or_cplx v = c < n2 ? Dc[(((size_t)j * 9) * n2 + r) * n2 + c] : (c - n2 == r ? 1.0 : 0.0);
+                if (c == r) v += _Complex_I * mu_c * (r < nv ? 1.0 : -1.0);
+                a[r * 2 * n2 + c] = v;
+            }
+        for (int k = 0; k < n2; ++k) {
+            int piv = k;
+            for (int r = k + 1; r < n2; ++r)
+                if (cabs(a[r * 2 * n2 + k]) > cabs(a[piv * 2 * n2 + k])) piv = r;
+            if (piv != k)
+                for (int c = 0; c < 2 * n2; ++c) {
+                    or_cplx t = a[k * 2 * n2 + c];
+                    a[k * 2 * n2 + c] = a[piv * 2 * n2 + c];
+                    a[piv * 2 * n2 + c] = t;
+                }
+            or_cplx d = a[k * 2 * n2 + k];
+            for (int c = 0; c < 2 * n2; ++c) a[k * 2 * n2 + c] /= d;
+            for (int r = 0; r < n2; ++r) {
+                if (r == k) continue;
+                or_cplx f = a[r * 2 * n2 + k];
+                if (f == 0) continue;
+                for (int c = 0; c < 2 * n2; ++c) a[r * 2 * n2 + c] -= f * a[k * 2 * n2 + c];
+            }
+        }
+        for (int r = 0; r < n2; ++r)
+            for (int c = 0; c < n2; ++c) Minv[((size_t)j * n2 + r) * n2 + c] = a[r * 2 * n2 + n2 + c];
+        free(a);
+    }
+}
+
+/* y = Minv x on the sites of parity p, 0 elsewhere. */
+static void coarse_block_mul(const int cdims[4], int nv, const or_cplx* Minv, int p, const or_cplx* x, or_cplx* y) {
+    long nc = or_volume(cdims);
+    int n2 = 2 * nv;
+    for (long j = 0; j < nc; ++j)
+        for (int a = 0; a < n2; ++a) {
+            or_cplx acc = 0;
+            if (coarse_parity(cdims, j) == p)
+                for (int b = 0; b < n2; ++b) acc += Minv[((size_t)j * n2 + a) * n2 + b] * x[(size_t)j * n2 + b];
+            y[(size_t)j * n2 + a] = acc;
+        }
+}
+
+/* Reduced operator on the odd coarse sites (section 2.5, applied to the coarse
+ * grid): y_o = (D_oo - D_oe D_ee^-1 D_eo) x_o; x and y are full coarse vectors
+ * whose even parts are ignored / zero. */
+static void coarse_dhat_fn(const void* ctx, const or_cplx* in, or_cplx* out) {
+    const coarse_ctx* c = (const coarse_ctx*)ctx;
+    long n = or_volume(c->cdims) * 2 * c->nv;
+    or_cplx* t = c->t;
+    or_cplx* u = c->t + n;
+    coarse_part(c->cdims, c->nv, c->Dc, c->mu_c, 0, NULL, in, t);        /* t_e = D_eo x_o */
+    coarse_block_mul(c->cdims, c->nv, c->Minv, 0, t, u);                /* u_e = D_ee^-1 t_e */
+    coarse_part(c->cdims, c->nv, c->Dc, c->mu_c, 1, in, NULL, out);      /* D_oo x_o */
+    coarse_part(c->cdims, c->nv, c->Dc, c->mu_c, 1, NULL, u, t);         /* D_oe u_e */
+    for (long i = 0; i < n; ++i) out[i] -= t[i];
+}
+
+void or_mg_coarse_dhat(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* x, or_cplx* y) {
+    long n = or_volume(cdims) * 2 * nv;
+    or_cplx* Minv = malloc(sizeof(or_cplx) * or_volume(cdims) * 4 * nv * nv);
+    or_cplx* t = malloc(sizeof(or_cplx) * 2 * n);
+    coarse_block_inverses(cdims, nv, Dc, mu_c, 0, Minv);
+    coarse_ctx c = {cdims, nv, Dc, mu_c, Minv, t};
+    coarse_dhat_fn(&c, x, y);
+    free(Minv);
+    free(t);
+}
+
+/* Even-odd preconditioned GMRES on the coarse grid (the paper's coarsest-grid
+ * solver, section 2.5): GMRES(restart) for the odd-site system
+ * Dhat x_o = b_o - D_oe D_ee^-1 b_e from x = 0, then x_e = D_ee^-1 (b_e - D_eo x_o).
+ * The full residual's even part vanishes and its odd part is the reduced
+ * residual, so the estimate is compared with tol ||b||. */
+int or_mg_coarse_gmres_eo(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* b, or_cplx* x,
+                          double tol, int restart, int max_restarts, or_report* rep) {
+    long nc = or_volume(cdims), n = nc * 2 * nv;
+    or_cplx* Minv = malloc(sizeof(or_cplx) * nc * 4 * nv * nv);
+    or_cplx* t = malloc(sizeof(or_cplx) * 2 * n);
+    or_cplx* bh = malloc(sizeof(or_cplx) * n);
+    or_cplx* u = malloc(sizeof(or_cplx) * n);
+    coarse_block_inverses(cdims, nv, Dc, mu_c, 0, Minv);
+    coarse_ctx c = {cdims, nv, Dc, mu_c, Minv, t};
+    /* bhat_o = b_o - D_oe D_ee^-1 b_e */
+    coarse_block_mul(cdims, nv, Minv, 0, b, u);
+    coarse_part(cdims, nv, Dc, mu_c, 1, NULL, u, bh);
+    for (long j = 0; j < nc; ++j)
+        for (int a = 0; a < 2 * nv; ++a) {
+            size_t i = (size_t)j * 2 * nv + a;
+            bh[i] = coarse_parity(cdims, j) == 1 ? b[i] - bh[i] : 0;
+        }
+    int rc = gmres_op(n, coarse_dhat_fn, &c, bh, x, tol, vnorm(b, n), restart, max_restarts, rep);
+    /* x_e = D_ee^-1 (b_e - D_eo x_o) */
+    coarse_part(cdims, nv, Dc, mu_c, 0, NULL, x, t);
+    for (long i = 0; i < n; ++i) t[i] = b[i] - t[i];
+    coarse_block_mul(cdims, nv, Minv, 0, t, u);
+    for (long j = 0; j < nc; ++j)
+        if (coarse_parity(cdims, j) == 0)
+            for (int a = 0; a < 2 * nv; ++a) x[(size_t)j * 2 * nv + a] = u[(size_t)j * 2 * nv + a];
+    free(Minv);
+    free(t);
+    free(bh);
+    free(u);
+    return rc;
+}
+
 /* Two-level preconditioner (eq. (multigrid_preconditioning) followed by
  * post-smoothing, no pre-smoothing): z = P D_c(mu, delta)^-1 P^+ r with the
  * coarse system solved by GMRES, then post_cycles SAP cycles on D z = r
@@ -1285,8 +1459,12 @@ void or_mg_precond(const or_op* op, const or_mg* mg, const or_cplx* r, or_cplx* 
     or_cplx* c = malloc(sizeof(or_cplx) * nc * n2);
     or_cplx* ec = malloc(sizeof(or_cplx) * nc * n2);
     or_mg_restrict(op->dims, mg->adims, mg->nv, mg->P, r, c);
-    or_mg_coarse_gmres(cd, mg->nv, mg->Dc, mg->delta * op->mu, c, ec, mg->coarse_tol, mg->coarse_restart,
-                       mg->coarse_max_restarts, NULL);
+    if (mg->coarse_eo)
+        or_mg_coarse_gmres_eo(cd, mg->nv, mg->Dc, mg->delta * op->mu, c, ec, mg->coarse_tol, mg->coarse_restart,
+                              mg->coarse_max_restarts, NULL);
+    else
+        or_mg_coarse_gmres(cd, mg->nv, mg->Dc, mg->delta * op->mu, c, ec, mg->coarse_tol, mg->coarse_restart,
+                           mg->coarse_max_restarts, NULL);
     or_mg_prolong(op->dims, mg->adims, mg->nv, mg->P, ec, z);
     if (mg->post_cycles > 0) or_sap_eo(op, mg->adims, mg->post_cycles, mg->mr_iters, 0, r, z);
     free(c);

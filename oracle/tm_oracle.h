@@ -138,6 +138,7 @@ typedef struct {
     int mr_iters;           /* MR steps per block solve */
     int setup_iters;        /* setup iterations (the first one is SAP only) */
     int setup_cycles;       /* SAP cycles per test vector in setup iteration 1 */
+    int coarse_eo;          /* 1: coarse GMRES on the even-odd reduced coarse system */
     or_cplx* P;             /* [nv][V][12], caller-allocated */
     or_cplx* Dc;            /* [nc][9][2nv][2nv], caller-allocated */
 } or_mg;
@@ -149,6 +150,12 @@ void or_mg_coarse_build(const or_op* op, const int adims[4], int nv, const or_cp
 void or_mg_coarse_apply(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* x, or_cplx* y);
 int or_mg_coarse_gmres(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* b, or_cplx* x,
                        double tol, int restart, int max_restarts, or_report* rep);
+/* Even-odd reduced coarse operator (coarse parity = sum of coarse coordinates mod 2,
+ * odd sites kept): y_o = (D_oo - D_oe D_ee^-1 D_eo) x_o; even parts ignored / zero. */
+void or_mg_coarse_dhat(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* x, or_cplx* y);
+/* As or_mg_coarse_gmres on the reduced system, then the even sites recovered. */
+int or_mg_coarse_gmres_eo(const int cdims[4], int nv, const or_cplx* Dc, double mu_c, const or_cplx* b, or_cplx* x,
+                          double tol, int restart, int max_restarts, or_report* rep);
 void or_mg_precond(const or_op* op, const or_mg* mg, const or_cplx* r, or_cplx* z);
 int or_fgmres_mg(const or_op* op, const or_mg* mg, const or_cplx* b, or_cplx* x, double tol, int restart,
                  int max_iters, or_report* rep);

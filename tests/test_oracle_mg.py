@@ -292,3 +292,63 @@ def test_setup_exposes_low_modes():
         Pd = dense_P(mg)
         fracs.append(np.linalg.norm(Pd.conj().T @ low) ** 2 / 6)
     assert fracs[1] > 0.3 and fracs[1] > 5 * fracs[0], fracs
+
+
+def even_coarse_mg():
+    # coarse extents 4, 2, 2, 2 (all even: every coarse neighbour has the other parity)
+    dims = (8, 4, 4, 4)
+    op = make_op(dims=dims, theta=(0.4, 0.0, 0.0, -0.6), shift=(0.02, -0.01), seed=9)
+    mg = oracle.MG(op, ADIMS, 3, delta=1.0)
+    mg.setup(random_vectors(dims, 3, seed=19))
+    cd = np.asarray(mg.cdims)
+    par = np.repeat(np.indices(mg.cdims).reshape(4, -1).sum(axis=0) % 2, 2 * mg.nv)
+    return op, mg, par
+
+
+def test_coarse_dhat_is_the_dense_schur_complement():
+    # section 2.5's reduction on the coarse grid: odd sites kept, D_oo - D_oe D_ee^-1 D_eo
+    op, mg, par = even_coarse_mg()
+    mu_c = 0.07
+    M = dense_coarse(mg, mu_c)
+    e, o = np.nonzero(par == 0)[0], np.nonzero(par == 1)[0]
+    S = M[np.ix_(o, o)] - M[np.ix_(o, e)] @ np.linalg.solve(M[np.ix_(e, e)], M[np.ix_(e, o)])
+    n = len(par)
+    got = np.zeros((len(o), len(o)), complex)
+    for k, col in enumerate(o):
+        x = np.zeros(n, complex)
+        x[col] = 1.0
+        y = mg.coarse_dhat(x, mu_c).reshape(-1)
+        assert np.abs(y[e]).max() == 0.0
+        got[:, k] = y[o]
+    assert np.abs(got - S).max() < 1e-12 * np.abs(S).max()
+
+
+def test_coarse_gmres_eo_matches_dense_solve():
+    op, mg, par = even_coarse_mg()
+    mu_c = 0.05
+    M = dense_coarse(mg, mu_c)
+    rng = np.random.default_rng(20)
+    b = rng.normal(size=len(M)) + 1j * rng.normal(size=len(M))
+    ref = np.linalg.solve(M, b)
+    x, rep = mg.coarse_gmres_eo(b, mu_c, 1e-13, int((par == 1).sum()), 2)
+    assert np.abs(x.reshape(-1) - ref).max() < 1e-10 * np.abs(ref).max()
+    # low accuracy: the estimate is the full system's true residual (its even part vanishes)
+    x, rep = mg.coarse_gmres_eo(b, mu_c, 0.1, 10, 5)
+    r = b - M @ x.reshape(-1)
+    assert np.abs(r[par == 0]).max() < 1e-12 * np.linalg.norm(b)
+    true = np.linalg.norm(r) / np.linalg.norm(b)
+    assert rep["met"] and true <= 0.1 * (1 + 1e-10) and abs(true - rep["rel_estimate"]) < 1e-10
+
+
+def test_two_level_with_even_odd_coarse_solve():
+    # with exact coarse solves the preconditioner does not depend on how the coarse system is solved
+    op, _, _ = even_coarse_mg()
+    v0 = random_vectors(op.dims, 3, seed=19)
+    out = []
+    for eo in (False, True):
+        mg = oracle.MG(op, ADIMS, 3, delta=3.0, coarse_tol=1e-14, coarse_restart=200, coarse_max_restarts=3,
+                       post_cycles=1, mr_iters=3, coarse_eo=eo)
+        mg.setup(v0)
+        r = random_vectors(op.dims, 1, seed=21)[0]
+        out.append(mg.precond(r).reshape(-1))
+    assert np.abs(out[0] - out[1]).max() < 1e-10 * np.abs(out[0]).max()

@@ -67,6 +67,10 @@ MUTATIONS = {
     "mg_prolong_half": ("int sg = q / 6;", "int sg = q / 9;"),
     # setup without the global orthonormalisation
     "mg_setup_no_orthonormalization": ("        mg_orthonormalize(n, nv, v);\n", "\n"),
+    # even-odd coarse reduction with + instead of - before the Schur term
+    "mg_eo_schur_sign": ("    for (long i = 0; i < n; ++i) out[i] -= t[i];\n}", "    for (long i = 0; i < n; ++i) out[i] += t[i];\n}"),
+    # even coarse sites recovered without the odd-site coupling
+    "mg_eo_recovery": ("    for (long i = 0; i < n; ++i) t[i] = b[i] - t[i];", "    for (long i = 0; i < n; ++i) t[i] = b[i];"),
 }
 
 
@@ -86,6 +90,8 @@ CATCHES = {
     "link_transposed": "test_oracle_operator.py::test_constant_nonabelian_links_plane_wave",
     "mg_aggregate_dot_conj": "test_oracle_mg.py::test_aggregate_basis_is_phase_fixed_qr",
     "mg_delta_ignored": "test_oracle_mg.py::test_unitary_prolongation_with_exact_coarse_solve_inverts_D",
+    "mg_eo_recovery": "test_oracle_mg.py::test_coarse_gmres_eo_matches_dense_solve",
+    "mg_eo_schur_sign": "test_oracle_mg.py::test_coarse_dhat_is_the_dense_schur_complement",
     "mg_gamma5c_sign": "test_oracle_mg.py::test_coarse_operator_galerkin_on_uneven_coarse_grid",
     "mg_no_post_smoothing": "test_oracle_mg.py::test_two_level_error_propagation",
     "mg_prolong_half": "test_oracle_mg.py::test_prolongation_commutes_with_gamma5",
