@@ -293,6 +293,10 @@ typedef struct {
     int coarse_max_restarts; /* >= 1 */
     int post_cycles;         /* SAP post-smoothing cycles (>= 0) */
     int mr_iters;            /* MR steps per block solve */
+    int coarse_eo;           /* 1: the coarse GMRES runs on the even-odd reduced coarse system (coarse
+                                parity = sum of the aggregate coordinates mod 2), the odd sites'
+                                Schur complement, with the even sites recovered from the even-site
+                                block inverses; 0: GMRES on the full coarse operator */
 } tm_mg_params;
 
 typedef struct {
@@ -306,8 +310,8 @@ typedef struct {
 
 /* Table 1 values where a two-level method has them: 4^4 blocks, N_v 28,
  * 5 setup iterations, delta 5.2, coarse GMRES(100) with at most 5 restarts to
- * 1e-1, 4 post-smoothing cycles, 3 MR steps; setup_cycles 4 (the paper says
- * "some steps"). */
+ * 1e-1 on the even-odd reduced system, 4 post-smoothing cycles, 3 MR steps;
+ * setup_cycles 4 (the paper gives no number for these SAP steps). */
 TM_API void tm_mg_params_default(tm_mg_params* p);
 /* Builds the two-level method for D(geom->mu[0]) (geom->nsys must be 1).  v0: the
  * N_v starting vectors (the setup's random draws), canonical complex128
@@ -327,7 +331,11 @@ TM_API int tm_mg_prolong(tm_mg* mg, int nsys, const void* c, void* e, const tm_o
 TM_API int tm_mg_coarse_apply(tm_mg* mg, int nsys, const double* mu_c, const void* x, void* y, const tm_opts* opts);
 /* GMRES(restart) for (D_c + i mu_c[k] Gamma5c) x_k = b_k from x = 0, stopping per system
  * when the residual estimate is <= tol ||b_k|| (tol 0: never) or after max_restarts
- * cycles; *iters (may be NULL) gets the largest step count. */
+ * cycles; *iters (may be NULL) gets the largest step count.  With the handle's
+ * coarse_eo the GMRES runs on the even-odd reduced system (the estimate is then that
+ * of the odd-site residual, which equals the full one) and the even sites follow from
+ * the block inverses, which the handle keeps for up to 4 coarse twists until the next
+ * setup; more distinct twists in one call are solved in runs of at most 4. */
 TM_API int tm_mg_coarse_solve(tm_mg* mg, int nsys, const double* mu_c, const void* b, void* x, double tol,
                               int restart, int max_restarts, int* iters, const tm_opts* opts);
 /* z = the two-level preconditioner applied to r, for geom->nsys systems with twists

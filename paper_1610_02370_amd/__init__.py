@@ -65,7 +65,7 @@ class MgParams(ctypes.Structure):
     _fields_ = [("block_dims", ctypes.c_int * 4), ("n_vec", ctypes.c_int), ("setup_iters", ctypes.c_int),
                 ("setup_cycles", ctypes.c_int), ("delta", ctypes.c_double), ("coarse_tol", ctypes.c_double),
                 ("coarse_restart", ctypes.c_int), ("coarse_max_restarts", ctypes.c_int),
-                ("post_cycles", ctypes.c_int), ("mr_iters", ctypes.c_int)]
+                ("post_cycles", ctypes.c_int), ("mr_iters", ctypes.c_int), ("coarse_eo", ctypes.c_int)]
 
 
 class MgInfo(ctypes.Structure):

@@ -45,6 +45,31 @@ hipError_t launch_mg_block_orthonormalize(const MgArgs& m, void* P, hipStream_t 
 // y_s = (Dc + i mu_c[s] Gamma5c) x_s, nsys <= kMaxSys; mu_c in device memory.
 hipError_t launch_mg_coarse_apply(const Geo& g, int nv, const float2* Dc, const double* mu_c, const float2* x,
                                   float2* y, int nsys, hipStream_t st);
+// General form: y_s = add_s + (Dc[j][0] + i mu_c[s] Gamma5c) x_self + hop_sign * sum_{t>=1} Dc[j][t] x_hop(nbr_t(j))
+// on the coarse sites of `parity` (coarse parity = sum of the tile coordinates mod 2; parity < 0: all
+// sites); a null input drops its terms, a null mu_c the twist.  Sites of the other parity get 0 when
+// zero_other is set and are left alone otherwise.  y may equal add, not x_self or x_hop.
+hipError_t launch_mg_coarse_part(const Geo& g, int nv, const float2* Dc, const double* mu_c, const float2* x_self,
+                                 const float2* x_hop, double hop_sign, const float2* add, int parity, bool zero_other,
+                                 float2* y, int nsys, hipStream_t st);
+// Minv[j >> 1] = (Dc[j][0] + i mu_c Gamma5c)^-1 (column-major, FP32; FP64 elimination) for the sites j of
+// `parity`; Minv holds nc / 2 matrices.  Needs an even innermost coarse extent.
+hipError_t launch_mg_block_inverse(const Geo& g, int nv, const float2* Dc, double mu_c, int parity, float2* Minv,
+                                   hipStream_t st);
+constexpr int kMgMaxInv = 4;  // inverse sets (distinct coarse twists) one call can use
+struct BlockMulArgs {
+    Geo g;
+    int nv;
+    const float2* sets[kMgMaxInv];
+    unsigned char sel[kMaxSys];  // system -> inverse set
+    int parity;
+    bool zero_other;  // other-parity sites: 0, or left alone
+    const float2* x;
+    float2* y;
+    int nsys;
+};
+// y_s = Minv_{sel[s]}[j >> 1] x_s at the coarse sites j of a.parity (y != x).
+hipError_t launch_mg_block_mul(const BlockMulArgs& a, hipStream_t st);
 // Transposes the stored stencil into complex128 [nc][9][2nv][2nv] row-major.
 hipError_t launch_mg_stencil_export(long long nc, int nv, const float2* Dc, void* out, hipStream_t st);
 // complex128 <-> FP32 coarse vectors (n complex per call)

@@ -321,15 +321,30 @@ __device__ inline long long coarse_nbr(const Geo& g, long long j, int t) {
     return out;
 }
 
+__device__ inline int coarse_parity(const Geo& g, long long j) {
+    int sum = 0;
+    for (int a = 3; a >= 0; --a) {
+        sum += (int)(j % g.nb[a]);
+        j /= g.nb[a];
+    }
+    return sum & 1;
+}
+
 // One workgroup per coarse site and group of kCoarseSys systems.  The 9 stencil
 // matrices of the site are 9 * n2 columns of n2 complex numbers, stored one after
 // the other; thread t takes the row pair (2p, 2p + 1) with p = t % nv of the columns
 // c = t / nv, t / nv + G, ... (G = 256 / nv column groups), so a wavefront reads
 // consecutive 16-byte pieces and every thread has its own stream of loads.  The
 // neighbours' x are staged in LDS; the column groups' partial sums meet there too.
+// General form: y = add + (self term + i mu_c Gamma5c) x_self + hop_sign * (8 neighbour terms) x_hop
+// on the coarse sites of `parity` (all sites when parity < 0); a null input drops its terms, a
+// null mu_c the twist.  The other parity's sites get 0 when zero_other is set, else stay as they are.
 __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, const float2* __restrict__ Dc,
                                                               const double* __restrict__ mu_c,
-                                                              const float2* __restrict__ x, float2* y, int nsys) {
+                                                              const float2* __restrict__ x_self,
+                                                              const float2* __restrict__ x_hop, float hop_sign,
+                                                              const float2* add, int parity, int zero_other,
+                                                              float2* y, int nsys) {
     // xs [9][ks][n2]; then [G][ks][n2] partial sums, ks = systems per workgroup (LDS sized by it)
     extern __shared__ float2 sh[];
     const int n2 = 2 * nv;
@@ -339,9 +354,23 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
     const int s0 = blockIdx.y * kCoarseSys;
     const int ns = min(kCoarseSys, nsys - s0);
     const int tid = threadIdx.x;
+    if (parity >= 0 && coarse_parity(g, j) != parity) {  // uniform over the workgroup
+        if (!zero_other) return;
+        for (int idx = tid; idx < ns * n2; idx += kThreads) {
+            const int k = idx / n2, r = idx - k * n2;
+            y[((size_t)(s0 + k) * nc + j) * n2 + r] = make_float2(0.f, 0.f);
+        }
+        return;
+    }
     for (int idx = tid; idx < 9 * ns * n2; idx += kThreads) {
         const int t = idx / (ns * n2), r = idx - t * ns * n2, k = r / n2, b = r - k * n2;
-        sh[(t * ks + k) * n2 + b] = x[((size_t)(s0 + k) * nc + coarse_nbr(g, j, t)) * n2 + b];
+        const float2* src = t == 0 ? x_self : x_hop;
+        float2 v = make_float2(0.f, 0.f);
+        if (src) {
+            v = src[((size_t)(s0 + k) * nc + coarse_nbr(g, j, t)) * n2 + b];
+            if (t > 0) v = make_float2(hop_sign * v.x, hop_sign * v.y);
+        }
+        sh[(t * ks + k) * n2 + b] = v;
     }
     __syncthreads();
     const int G = kThreads / nv;
@@ -351,9 +380,9 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
     for (int k = 0; k < kCoarseSys; ++k) acc0[k] = acc1[k] = make_float2(0.f, 0.f);
     if (grp < G) {
         const float4* A = reinterpret_cast<const float4*>(Dc + (size_t)j * 9 * n2 * n2);
-        const int ncol = 9 * n2;
+        const int c_lo = x_self ? 0 : n2, c_hi = x_hop ? 9 * n2 : n2;
 #pragma unroll 8
-        for (int c = grp; c < ncol; c += G) {
+        for (int c = c_lo + grp; c < c_hi; c += G) {
             const float4 mv = A[(size_t)c * nv + p];  // rows 2p, 2p + 1 of column c
             const float2* xs = sh + ((c / n2) * ks) * n2 + (c % n2);
 #pragma unroll
@@ -386,12 +415,127 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
             sum.y += v.y;
         }
         const size_t at = ((size_t)(s0 + k) * nc + j) * n2 + r;
-        const float2 xv = x[at];
-        const float tw = (float)mu_c[s0 + k] * (r < nv ? 1.f : -1.f);
-        sum.x -= tw * xv.y;
-        sum.y += tw * xv.x;
+        if (x_self && mu_c) {
+            const float2 xv = x_self[at];
+            const float tw = (float)mu_c[s0 + k] * (r < nv ? 1.f : -1.f);
+            sum.x -= tw * xv.y;
+            sum.y += tw * xv.x;
+        }
+        if (add) {
+            const float2 av = add[at];
+            sum.x += av.x;
+            sum.y += av.y;
+        }
         y[at] = sum;
     }
+}
+
+// (Dc[j][0] + i mu_c Gamma5c)^-1 at the coarse sites of `parity`, by Gauss-Jordan
+// elimination with partial pivoting in FP64 (augmented matrix in LDS); the result
+// goes to Minv[j >> 1] as FP32, column-major like the stencil (the innermost coarse extent is
+// even, so j >> 1 numbers the sites of one parity without gaps).
+__global__ void __launch_bounds__(kThreads) k_mg_block_inverse(Geo g, int nv, const float2* __restrict__ Dc,
+                                                               double mu_c, int parity, float2* Minv) {
+    extern __shared__ double2 aug[];  // [n2][2 n2] row-major
+    __shared__ double2 fac[64];
+    __shared__ int piv_s;
+    const long long j = blockIdx.x;
+    if (coarse_parity(g, j) != parity) return;  // uniform over the workgroup
+    const int n2 = 2 * nv, W = 2 * n2, tid = threadIdx.x;
+    const float2* A = Dc + (size_t)j * 9 * n2 * n2;
+    for (int idx = tid; idx < n2 * W; idx += kThreads) {
+        const int r = idx / W, c = idx - r * W;
+        double2 v = make_double2(0.0, 0.0);
+        if (c < n2) {
+            const float2 a = A[(size_t)c * n2 + r];
+            v = make_double2(a.x, a.y);
+            if (c == r) v.y += mu_c * (r < nv ? 1.0 : -1.0);
+        } else if (c - n2 == r) {
+            v.x = 1.0;
+        }
+        aug[idx] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < n2; ++k) {
+        if (tid < 64) {  // pivot: largest |a_rk| for r >= k, the first on ties
+            const int r = k + tid;
+            double val = -1.0;
+            int at = r;
+            if (r < n2) {
+                const double2 a = aug[r * W + k];
+                val = a.x * a.x + a.y * a.y;
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(val, off, 64);
+                const int oa = __shfl_xor(at, off, 64);
+                if (ov > val || (ov == val && oa < at)) {
+                    val = ov;
+                    at = oa;
+                }
+            }
+            if (tid == 0) piv_s = at;
+        }
+        __syncthreads();
+        const int piv = piv_s;
+        if (piv != k)
+            for (int c = tid; c < W; c += kThreads) {
+                const double2 t = aug[k * W + c];
+                aug[k * W + c] = aug[piv * W + c];
+                aug[piv * W + c] = t;
+            }
+        __syncthreads();
+        const double2 d = aug[k * W + k];
+        const double dn = d.x * d.x + d.y * d.y;
+        const double2 inv = make_double2(d.x / dn, -d.y / dn);
+        __syncthreads();
+        for (int c = tid; c < W; c += kThreads) {
+            const double2 a = aug[k * W + c];
+            aug[k * W + c] = make_double2(a.x * inv.x - a.y * inv.y, a.x * inv.y + a.y * inv.x);
+        }
+        for (int r = tid; r < n2; r += kThreads) fac[r] = r == k ? make_double2(0.0, 0.0) : aug[r * W + k];
+        __syncthreads();
+        for (int idx = tid; idx < n2 * W; idx += kThreads) {
+            const int r = idx / W, c = idx - r * W;
+            if (r == k) continue;
+            const double2 f = fac[r], p = aug[k * W + c];
+            const double2 a = aug[idx];
+            aug[idx] = make_double2(a.x - (f.x * p.x - f.y * p.y), a.y - (f.x * p.y + f.y * p.x));
+        }
+        __syncthreads();
+    }
+    float2* out = Minv + (size_t)(j >> 1) * n2 * n2;
+    for (int idx = tid; idx < n2 * n2; idx += kThreads) {
+        const int c = idx / n2, r = idx - c * n2;  // column-major
+        const double2 v = aug[r * W + n2 + c];
+        out[idx] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+// y_s = Minv_{sel[s]} x_s at the coarse sites of `parity` (the others get 0 when zero_other
+// is set, else stay as they are); one 64-thread workgroup per (site, system), one lane per row.
+__global__ void __launch_bounds__(64) k_mg_block_mul(BlockMulArgs a) {
+    __shared__ float2 xs[64];
+    const Geo& g = a.g;
+    const long long j = blockIdx.x;
+    const int sys = blockIdx.y, lane = threadIdx.x, n2 = 2 * a.nv;
+    const long long nc = g.V / g.Vb;
+    const size_t at = ((size_t)sys * nc + j) * n2;
+    if (coarse_parity(g, j) != a.parity) {
+        if (a.zero_other && lane < n2) a.y[at + lane] = make_float2(0.f, 0.f);
+        return;
+    }
+    if (lane < n2) xs[lane] = a.x[at + lane];
+    __syncthreads();
+    if (lane >= n2) return;
+    const float2* M = a.sets[a.sel[sys]] + (size_t)(j >> 1) * n2 * n2 + lane;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b = 0; b < n2; ++b) {
+        const float2 m = M[(size_t)b * n2], v = xs[b];
+        acc.x += m.x * v.x - m.y * v.y;
+        acc.y += m.x * v.y + m.y * v.x;
+    }
+    a.y[at + lane] = acc;
 }
 
 __global__ void k_mg_stencil_export(long long nc, int nv, const float2* __restrict__ Dc, double2* out) {
@@ -604,8 +748,9 @@ hipError_t launch_mg_block_orthonormalize(const MgArgs& m, void* P, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_mg_coarse_apply(const Geo& g, int nv, const float2* Dc, const double* mu_c, const float2* x,
-                                  float2* y, int nsys, hipStream_t st) {
+hipError_t launch_mg_coarse_part(const Geo& g, int nv, const float2* Dc, const double* mu_c, const float2* x_self,
+                                 const float2* x_hop, double hop_sign, const float2* add, int parity, bool zero_other,
+                                 float2* y, int nsys, hipStream_t st) {
     if (nv < 1 || nv > kMgMaxVec || nsys < 1 || nsys > kMaxSys) return hipErrorInvalidValue;
     const int n2 = 2 * nv, ks = nsys < kCoarseSys ? nsys : kCoarseSys;
     const size_t xs = (size_t)9 * ks * n2, red = (size_t)(kThreads / nv) * ks * n2;
@@ -616,7 +761,36 @@ hipError_t launch_mg_coarse_apply(const Geo& g, int nv, const float2* Dc, const 
         if (e != hipSuccess) return e;
     }
     const dim3 grid((unsigned)(g.V / g.Vb), (unsigned)((nsys + kCoarseSys - 1) / kCoarseSys));
-    hipLaunchKernelGGL(k_mg_coarse_apply, grid, dim3(kThreads), lds, st, g, nv, Dc, mu_c, x, y, nsys);
+    hipLaunchKernelGGL(k_mg_coarse_apply, grid, dim3(kThreads), lds, st, g, nv, Dc, mu_c, x_self, x_hop,
+                       (float)hop_sign, add, parity, (int)zero_other, y, nsys);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_coarse_apply(const Geo& g, int nv, const float2* Dc, const double* mu_c, const float2* x,
+                                  float2* y, int nsys, hipStream_t st) {
+    return launch_mg_coarse_part(g, nv, Dc, mu_c, x, x, 1.0, nullptr, -1, true, y, nsys, st);
+}
+
+hipError_t launch_mg_block_inverse(const Geo& g, int nv, const float2* Dc, double mu_c, int parity, float2* Minv,
+                                   hipStream_t st) {
+    if (nv < 1 || nv > kMgMaxVec || g.nb[3] % 2 != 0) return hipErrorInvalidValue;
+    const size_t lds = (size_t)(2 * nv) * (4 * nv) * sizeof(double2);  // at most 128 KiB
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_block_inverse),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_mg_block_inverse, dim3((unsigned)(g.V / g.Vb)), dim3(kThreads), lds, st, g, nv, Dc, mu_c,
+                       parity, Minv);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_block_mul(const BlockMulArgs& a, hipStream_t st) {
+    if (a.nv < 1 || a.nv > kMgMaxVec || a.nsys < 1 || a.nsys > kMaxSys || a.g.nb[3] % 2 != 0)
+        return hipErrorInvalidValue;
+    for (int s = 0; s < a.nsys; ++s)
+        if (a.sel[s] >= kMgMaxInv || !a.sets[a.sel[s]]) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mg_block_mul, dim3((unsigned)(a.g.V / a.g.Vb), a.nsys), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

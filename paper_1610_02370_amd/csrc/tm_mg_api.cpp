@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "../../include/tm.h"
@@ -37,6 +38,12 @@ struct tm_mg {
     tmsap::DeviceBuffer coarse;    // coarse vectors and the coarse Krylov basis
     tmsap::DeviceBuffer small;     // coefficients, norms, partial sums
     tmsap::DeviceBuffer fine;      // fine workspaces of setup and of the canonical entry points
+    // even-odd coarse solver: inverses of the even-site blocks, one set per coarse twist,
+    // valid until the stencil is rebuilt
+    tmsap::DeviceBuffer inv[tmsap::kMgMaxInv];
+    double inv_mu[tmsap::kMgMaxInv] = {};
+    bool inv_ok[tmsap::kMgMaxInv] = {};
+    unsigned long long inv_stamp[tmsap::kMgMaxInv] = {}, inv_clock = 0;
     double t_setup = 0;
     long long applications = 0, coarse_iters = 0;
     double t_coarse = 0;
@@ -136,32 +143,35 @@ int basis_dots(const float2* V, size_t vstride, int nv, const float2* w, size_t 
     return TM_OK;
 }
 
-}  // namespace
+// y = A x for the ns systems of one coarse solve (full coarse vectors)
+typedef std::function<int(const float2* x, float2* y)> CoarseOp;
 
-// GMRES(m) on the coarse operator for ns systems; b and x [ns][nc][n2] FP32
-// (x overwritten), mu_c host [ns].  Classical Gram-Schmidt applied twice; the
-// host solves the small least-squares problems.  Returns the largest number
-// of steps any system took in *iters.
-int mg_coarse_gmres(tm_mg* mg, int ns, const double* mu_c, const float2* b, float2* x, double tol, int m, int maxr,
-                    int* iters, hipStream_t st) {
+// Host copy of ||v_s|| for ns coarse vectors.
+int coarse_norms(tm_mg* mg, const float2* v, int ns, const SmallBufs& sb, double* out, hipStream_t st) {
+    const long long n = mg->nc * mg->n2;
+    int rc;
+    if ((rc = hc(mg_blas_norm2(v, (size_t)n, ns, n, sb.partials, sb.nrm, st), "norm"))) return rc;
+    if ((rc = hc(hipMemcpyAsync(out, sb.nrm, ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy"))) return rc;
+    if ((rc = hc(hipStreamSynchronize(st), "coarse solve"))) return rc;
+    for (int k = 0; k < ns; ++k) out[k] = std::sqrt(std::max(0.0, out[k]));
+    return TM_OK;
+}
+
+// GMRES(m) for A x = b over ns systems from x = 0; b and x [ns][nc][n2] FP32 (x
+// overwritten).  A system stops when its residual estimate is <= tol * bref[s]
+// (tol 0: never).  work holds (m + 2) ns coarse vectors (the basis and one more).
+// Classical Gram-Schmidt applied twice; the host solves the small least-squares
+// problems.  Returns the largest number of steps any system took in *iters.
+int gmres_core(tm_mg* mg, int ns, const CoarseOp& A, const double* bref, const float2* b, float2* x, float2* work,
+               double tol, int m, int maxr, const SmallBufs& sb, int* iters, hipStream_t st) {
     const long long n = mg->nc * mg->n2;
     const size_t vs = (size_t)n, vstride = (size_t)ns * n;
     int rc;
-    // coarse workspace: basis (m + 1 vectors of ns systems) and w
-    hipError_t e = mg->coarse.ensure(((size_t)(m + 2) * vstride) * sizeof(float2) + 2 * (size_t)ns * n * sizeof(float2));
-    if (e != hipSuccess) return hip_fail(e, "coarse Krylov basis");
-    float2* V = static_cast<float2*>(mg->coarse.ptr) + 2 * (size_t)ns * n;  // leaves room for the caller's c, e
+    float2* V = work;
     float2* w = V + (size_t)(m + 1) * vstride;
-    SmallBufs sb;
-    if ((rc = carve_small(mg, ns, m, n, sb))) return rc;
     std::vector<double> host(2 * 2 * (size_t)ns * (m + 1) + 4 * (size_t)ns);
-    if ((rc = hc(hipMemcpyAsync(sb.mu, mu_c, ns * sizeof(double), hipMemcpyHostToDevice, st), "copy"))) return rc;
     if ((rc = hc(blas_zero(x, (size_t)ns * n * sizeof(float2), st), "zero"))) return rc;
-    if ((rc = hc(mg_blas_norm2(b, vs, ns, n, sb.partials, sb.nrm, st), "norm"))) return rc;
-    std::vector<double> bn(ns), beta(ns), fh(ns);
-    if ((rc = hc(hipMemcpyAsync(host.data(), sb.nrm, ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy"))) return rc;
-    if ((rc = hc(hipStreamSynchronize(st), "coarse solve"))) return rc;
-    for (int k = 0; k < ns; ++k) bn[k] = std::sqrt(host[k]);
+    std::vector<double> bn(bref, bref + ns), beta(ns), fh(ns);
     std::vector<zc> H((size_t)ns * (m + 1) * m), sn((size_t)ns * m), gv((size_t)ns * (m + 1));
     std::vector<double> cs((size_t)ns * m);
     std::vector<int> kdim(ns);
@@ -175,9 +185,7 @@ int mg_coarse_gmres(tm_mg* mg, int ns, const double* mu_c, const float2* b, floa
                 return rc;
             if ((rc = hc(mg_blas_scale(b, sb.f, V, vs, ns, n, st), "copy"))) return rc;
         } else {
-            if ((rc = hc(launch_mg_coarse_apply(mg->g, mg->p.n_vec, (const float2*)mg->Dc.ptr, sb.mu, x, V, ns, st),
-                         "coarse operator")))
-                return rc;
+            if ((rc = A(x, V))) return rc;
             if ((rc = hc(mg_blas_sub_from(b, V, vs, ns, n, st), "residual"))) return rc;
         }
         if ((rc = hc(mg_blas_norm2(V, vs, ns, n, sb.partials, sb.nrm, st), "norm"))) return rc;
@@ -201,9 +209,7 @@ int mg_coarse_gmres(tm_mg* mg, int ns, const double* mu_c, const float2* b, floa
         int jdone = 0;
         for (int j = 0; j < m; ++j) {
             float2* vj = V + (size_t)j * vstride;
-            if ((rc = hc(launch_mg_coarse_apply(mg->g, mg->p.n_vec, (const float2*)mg->Dc.ptr, sb.mu, vj, w, ns, st),
-                         "coarse operator")))
-                return rc;
+            if ((rc = A(vj, w))) return rc;
             const int nb = j + 1;
             if ((rc = basis_dots(V, vstride, nb, w, vs, ns, n, sb.partials, sb.h1, m + 1, st))) return rc;
             if ((rc = basis_axpy(V, vstride, nb, sb.h1, m + 1, -1.0, w, vs, ns, n, st))) return rc;
@@ -301,6 +307,154 @@ int mg_coarse_gmres(tm_mg* mg, int ns, const double* mu_c, const float2* b, floa
     return TM_OK;
 }
 
+
+// Coarse floats a solve over ns systems with restart m needs after the caller's two
+// vectors c, e: the basis, w, and for the even-odd solver three more.
+size_t coarse_work_vectors(const tm_mg* mg, int m) { return (size_t)m + 2 + (mg->p.coarse_eo ? 3 : 0); }
+
+// Even-site block inverses for the twists mu_c[0..ns) (at most kMgMaxInv distinct):
+// cached sets are reused, missing ones computed; fills a.sets and a.sel.
+int ensure_inverses(tm_mg* mg, int ns, const double* mu_c, BlockMulArgs& a, hipStream_t st) {
+    bool used[kMgMaxInv] = {};
+    const int n2 = mg->n2;
+    for (int s = 0; s < ns; ++s) {
+        int k = 0;
+        while (k < kMgMaxInv && !(mg->inv_ok[k] && mg->inv_mu[k] == mu_c[s])) ++k;
+        if (k == kMgMaxInv) {  // a set not needed by this call: an empty one, else the least recently used
+            k = -1;
+            for (int q = 0; q < kMgMaxInv; ++q) {
+                if (used[q]) continue;
+                if (k < 0 || (!mg->inv_ok[q] && mg->inv_ok[k]) ||
+                    (mg->inv_ok[q] == mg->inv_ok[k] && mg->inv_stamp[q] < mg->inv_stamp[k]))
+                    k = q;
+            }
+            if (k < 0) return fail(TM_ERR_ARG, "more than %d distinct coarse twists in one coarse solve", kMgMaxInv);
+            hipError_t e = mg->inv[k].ensure((size_t)(mg->nc / 2) * n2 * n2 * sizeof(float2));
+            if (e != hipSuccess) return hip_fail(e, "coarse block inverses");
+            mg->inv_ok[k] = false;
+            int rc;
+            if ((rc = hc(launch_mg_block_inverse(mg->g, mg->p.n_vec, (const float2*)mg->Dc.ptr, mu_c[s], 0,
+                                                 static_cast<float2*>(mg->inv[k].ptr), st),
+                         "coarse block inverses")))
+                return rc;
+            mg->inv_ok[k] = true;
+            mg->inv_mu[k] = mu_c[s];
+        }
+        used[k] = true;
+        mg->inv_stamp[k] = ++mg->inv_clock;
+        a.sets[k] = static_cast<const float2*>(mg->inv[k].ptr);
+        a.sel[s] = (unsigned char)k;
+    }
+    return TM_OK;
+}
+
+// Even-odd preconditioned GMRES on the coarse grid (section 2.5's reduction, used as
+// the coarsest-grid solver in Table 1): GMRES(m) for the odd-site system
+// (D_oo - D_oe D_ee^-1 D_eo) x_o = b_o - D_oe D_ee^-1 b_e, then
+// x_e = D_ee^-1 (b_e - D_eo x_o).  The full residual's even part vanishes and its odd
+// part is the reduced residual, so the stop compares with tol ||b||.  Vectors keep the
+// full coarse layout with zero even parts; at most kMgMaxInv distinct twists.
+int coarse_gmres_eo(tm_mg* mg, int ns, const double* mu_c, const float2* b, float2* x, float2* work, double tol, int m,
+                    int maxr, int* iters, hipStream_t st) {
+    const long long n = mg->nc * mg->n2;
+    const Geo& g = mg->g;
+    const int nv = mg->p.n_vec;
+    const float2* Dc = static_cast<const float2*>(mg->Dc.ptr);
+    int rc;
+    BlockMulArgs a{};
+    a.g = g;
+    a.nv = nv;
+    a.nsys = ns;
+    a.parity = 0;
+    a.zero_other = false;
+    if ((rc = ensure_inverses(mg, ns, mu_c, a, st))) return rc;
+    SmallBufs sb;
+    if ((rc = carve_small(mg, ns, m, n, sb))) return rc;
+    if ((rc = hc(hipMemcpyAsync(sb.mu, mu_c, ns * sizeof(double), hipMemcpyHostToDevice, st), "copy"))) return rc;
+    float2* t = work + (size_t)(m + 2) * ns * n;
+    float2* u = t + (size_t)ns * n;
+    float2* bh = u + (size_t)ns * n;
+    std::vector<double> bref(ns);
+    if ((rc = coarse_norms(mg, b, ns, sb, bref.data(), st))) return rc;
+    // bh_o = b_o - D_oe D_ee^-1 b_e, bh_e = 0
+    a.x = b;
+    a.y = u;
+    if ((rc = hc(launch_mg_block_mul(a, st), "coarse block inverses"))) return rc;
+    if ((rc = hc(launch_mg_coarse_part(g, nv, Dc, nullptr, nullptr, u, -1.0, b, 1, true, bh, ns, st), "coarse operator")))
+        return rc;
+    const CoarseOp dhat = [&](const float2* in, float2* out) -> int {
+        int r;
+        // t_e = D_eo in_o; u_e = D_ee^-1 t_e; out_o = D_oo in_o - D_oe u_e, out_e = 0
+        if ((r = hc(launch_mg_coarse_part(g, nv, Dc, nullptr, nullptr, in, 1.0, nullptr, 0, false, t, ns, st),
+                    "coarse operator")))
+            return r;
+        BlockMulArgs am = a;
+        am.x = t;
+        am.y = u;
+        if ((r = hc(launch_mg_block_mul(am, st), "coarse block inverses"))) return r;
+        return hc(launch_mg_coarse_part(g, nv, Dc, sb.mu, in, u, -1.0, nullptr, 1, true, out, ns, st), "coarse operator");
+    };
+    if ((rc = gmres_core(mg, ns, dhat, bref.data(), bh, x, work, tol, m, maxr, sb, iters, st))) return rc;
+    // x_e = D_ee^-1 (b_e - D_eo x_o)
+    if ((rc = hc(launch_mg_coarse_part(g, nv, Dc, nullptr, nullptr, x, -1.0, b, 0, false, t, ns, st), "coarse operator")))
+        return rc;
+    a.x = t;
+    a.y = x;
+    return hc(launch_mg_block_mul(a, st), "coarse block inverses");
+}
+
+}  // namespace
+
+// Solves (D_c + i mu_c[s] Gamma5c) x_s = b_s for ns systems (b, x [ns][nc][n2] FP32,
+// x overwritten; mu_c host [ns]) by GMRES(m) on the full coarse operator or, when the
+// handle's coarse_eo is set, on the even-odd reduced one.  The workspace sits in the
+// handle's coarse buffer after 2 ns coarse vectors left to the caller.  Returns the
+// largest number of GMRES steps any system took in *iters.
+int mg_coarse_gmres(tm_mg* mg, int ns, const double* mu_c, const float2* b, float2* x, double tol, int m, int maxr,
+                    int* iters, hipStream_t st) {
+    const long long n = mg->nc * mg->n2;
+    int rc;
+    hipError_t e = mg->coarse.ensure((2 + coarse_work_vectors(mg, m)) * (size_t)ns * n * sizeof(float2));
+    if (e != hipSuccess) return hip_fail(e, "coarse Krylov basis");
+    float2* work = static_cast<float2*>(mg->coarse.ptr) + 2 * (size_t)ns * n;
+    if (mg->p.coarse_eo) {
+        // systems in runs of at most kMgMaxInv distinct twists
+        int most = 0;
+        for (int s0 = 0; s0 < ns;) {
+            std::vector<double> seen;
+            int s1 = s0;
+            while (s1 < ns) {
+                if (std::find(seen.begin(), seen.end(), mu_c[s1]) == seen.end()) {
+                    if ((int)seen.size() == kMgMaxInv) break;
+                    seen.push_back(mu_c[s1]);
+                }
+                ++s1;
+            }
+            int it = 0;
+            if ((rc = coarse_gmres_eo(mg, s1 - s0, mu_c + s0, b + (size_t)s0 * n, x + (size_t)s0 * n, work, tol, m, maxr,
+                                      &it, st)))
+                return rc;
+            most = std::max(most, it);
+            s0 = s1;
+        }
+        if (iters) *iters = most;
+        return TM_OK;
+    }
+    SmallBufs sb;
+    if ((rc = carve_small(mg, ns, m, n, sb))) return rc;
+    if ((rc = hc(hipMemcpyAsync(sb.mu, mu_c, ns * sizeof(double), hipMemcpyHostToDevice, st), "copy"))) return rc;
+    std::vector<double> bref(ns);
+    if ((rc = coarse_norms(mg, b, ns, sb, bref.data(), st))) return rc;
+    const Geo g = mg->g;
+    const int nv = mg->p.n_vec;
+    const float2* Dc = static_cast<const float2*>(mg->Dc.ptr);
+    const double* mud = sb.mu;
+    const CoarseOp full = [&](const float2* in, float2* out) -> int {
+        return hc(launch_mg_coarse_apply(g, nv, Dc, mud, in, out, ns, st), "coarse operator");
+    };
+    return gmres_core(mg, ns, full, bref.data(), b, x, work, tol, m, maxr, sb, iters, st);
+}
+
 // The two-level preconditioner on internal FP32 fields (tiled by the
 // aggregates): z = P D_c^-1 P^+ r, then post_cycles SAP cycles from z.
 int mg_apply(tm_mg* mg, DeviceState* ds, const SpinorBuf& r, const SpinorBuf& z, const double* mu, int ns,
@@ -309,7 +463,7 @@ int mg_apply(tm_mg* mg, DeviceState* ds, const SpinorBuf& r, const SpinorBuf& z,
     int rc;
     const long long n = mg->nc * mg->n2;
     const int m = mg->p.coarse_restart;
-    hipError_t e = mg->coarse.ensure(((size_t)(m + 2) * ns * n + 2 * (size_t)ns * n) * sizeof(float2));
+    hipError_t e = mg->coarse.ensure((2 + coarse_work_vectors(mg, m)) * (size_t)ns * n * sizeof(float2));
     if (e != hipSuccess) return hip_fail(e, "coarse vectors");
     float2* c = static_cast<float2*>(mg->coarse.ptr);
     float2* ec = c + (size_t)ns * n;
@@ -382,6 +536,7 @@ int build_coarse(tm_mg* mg, const GaugeDev& G, const void* v, void* W, int chunk
     const int nv = mg->p.n_vec, n2 = mg->n2;
     if ((rc = hc(hipMemcpyAsync(mg->P.ptr, v, (size_t)nv * mg->field, hipMemcpyDeviceToDevice, st), "copy"))) return rc;
     const MgArgs ma = margs(mg);
+    for (int k = 0; k < kMgMaxInv; ++k) mg->inv_ok[k] = false;  // the block inverses follow the stencil
     if ((rc = hc(launch_mg_block_orthonormalize(ma, mg->P.ptr, st), "aggregate orthonormalisation"))) return rc;
     const size_t fb = internal_bytes(mg->g, 1, P_F32);
     for (int t = 0; t < 9; ++t)
@@ -405,6 +560,7 @@ int check_params(const tm_geom* geom, const tm_mg_params* p, int tile[4]) {
         return fail(TM_ERR_ARG, "coarse_restart must be 1..128 and coarse_max_restarts >= 1");
     if (!(p->delta > 0) || !std::isfinite(p->delta) || !(p->coarse_tol >= 0) || !std::isfinite(p->coarse_tol))
         return fail(TM_ERR_ARG, "bad delta or coarse_tol");
+    if (p->coarse_eo != 0 && p->coarse_eo != 1) return fail(TM_ERR_ARG, "coarse_eo must be 0 or 1");
     return check_sap_blocks(geom, p->block_dims, tile);
 }
 
@@ -421,10 +577,14 @@ int mg_matches(const tm_mg* mg, const tm_geom* geom) {
     return check_device(mg);
 }
 
-size_t mg_workspace_held(const tm_mg* mg) { return mg->coarse.bytes + mg->small.bytes; }
+size_t mg_workspace_held(const tm_mg* mg) {
+    size_t b = mg->coarse.bytes + mg->small.bytes;
+    for (int k = 0; k < kMgMaxInv; ++k) b += mg->inv[k].bytes;
+    return b;
+}
 
 size_t mg_workspace_per_sys(const tm_mg* mg) {
-    return (size_t)(mg->p.coarse_restart + 4) * mg->nc * mg->n2 * sizeof(float2);
+    return (2 + coarse_work_vectors(mg, mg->p.coarse_restart)) * mg->nc * mg->n2 * sizeof(float2);
 }
 
 void mg_block_dims(const tm_mg* mg, int bd[4]) {
@@ -450,6 +610,7 @@ void tm_mg_params_default(tm_mg_params* p) {
     p->coarse_max_restarts = 5;
     p->post_cycles = 4;
     p->mr_iters = 3;
+    p->coarse_eo = 1;
 }
 
 int tm_mg_setup(const tm_geom* geom, const void* U, double kappa, double c_sw, const tm_mg_params* params,

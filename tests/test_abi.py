@@ -91,6 +91,7 @@ def test_table1_multigrid_defaults_match_library():
     assert p.coarse_restart == int(vals["coarse_restart"][0])
     assert p.coarse_max_restarts == int(vals["coarse_max_restarts"][0])
     assert p.coarse_tol == float(vals["coarse_relative_tolerance"][0])
+    assert vals["coarse_solver"][0] == "even_odd_gmres" and p.coarse_eo == 1
     sap = read_golden("table1_sap_defaults.txt")
     assert p.mr_iters == int(sap["block_mr_iterations"][0])
 
@@ -102,7 +103,7 @@ def test_two_level_setup_rejects_bad_input_on_host():
     dummy = ctypes.c_void_p(16)
     L = tm.lib()
     for kw, code in (({"n_vec": 0}, -1), ({"n_vec": 33}, -1), ({"coarse_restart": 129}, -1), ({"delta": 0.0}, -1),
-                     ({"block_dims": (4, 4, 4, 3)}, -2), ({"block_dims": (8, 4, 4, 4)}, -3)):
+                     ({"coarse_eo": 2}, -1), ({"block_dims": (4, 4, 4, 3)}, -2), ({"block_dims": (8, 4, 4, 4)}, -3)):
         p = tm.mg_params(**kw)
         rc = L.tm_mg_setup(ctypes.byref(g), dummy, 0.15, 1.0, ctypes.byref(p), dummy, ctypes.byref(h), ctypes.byref(o))
         assert rc == code, (kw, rc)

@@ -4,9 +4,10 @@ Both sides build the method from the same seeded starting vectors; nothing the
 GPU computes is fed to the oracle.  FP32 on the GPU against FP64:
   aggregate basis P, coarse stencil, restriction, coarse operator  1e-5
   prolongation                                                      1e-6
-  coarse GMRES, a fixed number of steps                             1e-4
+  coarse GMRES, a fixed number of steps (full or even-odd reduced)  1e-4
   two-level preconditioner (coarse solve + FP32 SAP post-smoothing) 5e-4
   setup with one two-level iteration                                2e-3
+The even-odd coarse solver's block inverses are FP64 eliminations rounded to FP32.
 The solve with the two-level preconditioner is checked on its FP64 true
 residual (oracle operator) and against the oracle's solution.
 """
@@ -43,7 +44,7 @@ def build(case, mu, seed=3, **kw):
     U = synth.gauge_field(dims, 0.6, seed=seed)
     v0 = synth.gaussian_spinor(dims, nv, seed=100 + seed)
     params = dict(block_dims=adims, n_vec=nv, setup_iters=0, setup_cycles=2, delta=2.0, coarse_tol=0.0,
-                  coarse_restart=8, coarse_max_restarts=2, post_cycles=2, mr_iters=3)
+                  coarse_restart=8, coarse_max_restarts=2, post_cycles=2, mr_iters=3, coarse_eo=0)
     params.update(kw)
     announce(f"two-level setup case={case} params={params}")
     g = tm.MG(dims, dev(U), KAPPA, mu, CSW, dev(v0), antiperiodic_t=ap, theta=theta, mu_shift=shift, **params)
@@ -51,7 +52,7 @@ def build(case, mu, seed=3, **kw):
     o = oracle.MG(op, adims, nv, delta=params["delta"], coarse_tol=params["coarse_tol"],
                   coarse_restart=params["coarse_restart"], coarse_max_restarts=params["coarse_max_restarts"],
                   post_cycles=params["post_cycles"], mr_iters=params["mr_iters"], setup_iters=params["setup_iters"],
-                  setup_cycles=params["setup_cycles"])
+                  setup_cycles=params["setup_cycles"], coarse_eo=bool(params["coarse_eo"]))
     o.setup(v0)
     return dims, U, g, o, op
 
@@ -59,6 +60,16 @@ def build(case, mu, seed=3, **kw):
 @pytest.fixture(scope="module", params=sorted(CASES))
 def built(request):
     return build(request.param, mu=0.01)
+
+
+# the even-odd coarse solver: the smallest and largest coarse rows (block inverses of 2x2 and of
+# 64x64, the latter with 128 KiB of LDS) and the largest coarse grid
+EO_CASES = ["4^4 aggregates", "2^4 aggregates, uneven coarse grid", "32 test vectors", "1 test vector"]
+
+
+@pytest.fixture(scope="module", params=EO_CASES)
+def built_eo(request):
+    return build(request.param, mu=0.01, coarse_eo=1)
 
 
 def test_basis_and_stencil(built):
@@ -128,6 +139,66 @@ def test_two_level_preconditioner(built):
         assert rel_err(z[k], ref) < 5e-4
 
 
+def test_coarse_eo_gmres_fixed_steps(built_eo):
+    # three systems, two twists: the second system with the first one's twist reuses its inverses
+    dims, U, g, o, op = built_eo
+    rng = np.random.default_rng(54)
+    mus = [0.05, -0.05, 0.05]
+    b = rng.normal(size=(3, o.nc, 2 * o.nv)) + 1j * rng.normal(size=(3, o.nc, 2 * o.nv))
+    x, it = g.coarse_solve(dev(b), mus, 0.0, 6, 3)
+    assert it == 18
+    x = host(x)
+    for k, m in enumerate(mus):
+        ref, rep = o.coarse_gmres_eo(b[k], m, 0.0, 6, 3)
+        assert rep["iters"] == 18
+        assert rel_err(x[k], ref) < 1e-4
+
+
+def test_coarse_eo_gmres_more_twists_than_inverse_sets(built_eo):
+    # five distinct twists: solved in runs of at most four, the cached inverse sets evicted in turn
+    dims, U, g, o, op = built_eo
+    rng = np.random.default_rng(55)
+    mus = [0.05, -0.05, 0.02, 0.0, 0.05, -0.03]
+    b = rng.normal(size=(6, o.nc, 2 * o.nv)) + 1j * rng.normal(size=(6, o.nc, 2 * o.nv))
+    x, it = g.coarse_solve(dev(b), mus, 0.0, 4, 2)
+    assert it == 8
+    x = host(x)
+    for k, m in enumerate(mus):
+        ref, _ = o.coarse_gmres_eo(b[k], m, 0.0, 4, 2)
+        assert rel_err(x[k], ref) < 1e-4
+
+
+def test_coarse_eo_gmres_to_tolerance(built_eo):
+    dims, U, g, o, op = built_eo
+    rng = np.random.default_rng(56)
+    b = rng.normal(size=(1, o.nc, 2 * o.nv)) + 1j * rng.normal(size=(1, o.nc, 2 * o.nv))
+    x, it = g.coarse_solve(dev(b), [-0.05], 1e-5, 64, 20)
+    x = host(x)[0]
+    # the full coarse system's residual (even sites from the recovery)
+    res = np.linalg.norm(b[0] - o.coarse_apply(x, -0.05)) / np.linalg.norm(b[0])
+    assert res < 5e-5
+    ref, _ = o.coarse_gmres(b[0], -0.05, 1e-12, 64, 40)
+    assert rel_err(x, ref) < 1e-3
+
+
+def test_two_level_preconditioner_eo(built_eo):
+    dims, U, g, o, op = built_eo
+    r = synth.gaussian_spinor(dims, 2, seed=57)
+    mus = [0.01, -0.01]
+    z = host(g.precond(dev(r), mus))
+    for k, m in enumerate(mus):
+        ref = o.precond(r[k], op.with_mu(m))
+        assert rel_err(z[k], ref) < 5e-4
+
+
+def test_setup_with_a_two_level_iteration_eo():
+    dims, U, g, o, op = build("4^4 aggregates", mu=0.01, seed=6, setup_iters=2, coarse_eo=1)
+    P, Dc = g.export()
+    P, Dc = host(P), host(Dc)
+    assert np.abs(P - o.P).max() < 2e-3 * np.abs(o.P).max()
+    assert np.abs(Dc - o.Dc).max() < 2e-3 * np.abs(o.Dc).max()
+
+
 def test_setup_with_a_two_level_iteration():
     # iteration 1 (SAP on the starting vectors) and iteration 2 (the two-level method of iteration 1)
     dims, U, g, o, op = build("4^4 aggregates", mu=0.01, seed=5, setup_iters=2)
@@ -145,14 +216,14 @@ def test_setup_with_a_two_level_iteration():
             assert np.abs(Q.conj() @ Q.T - np.eye(o.nv)).max() < 1e-5
 
 
-@pytest.mark.parametrize("form", ["flexible", "defect_correction"])
-def test_solve_with_two_level_preconditioner(form):
+@pytest.mark.parametrize("form,eo", [("flexible", 0), ("defect_correction", 0), ("defect_correction", 1)])
+def test_solve_with_two_level_preconditioner(form, eo):
     dims, U, g, o, op = build("4^4 aggregates", mu=0.01, seed=7, setup_iters=2, coarse_tol=0.1, coarse_restart=16,
-                              coarse_max_restarts=2)
+                              coarse_max_restarts=2, coarse_eo=eo)
     mus = [0.01, -0.01]
     b = synth.point_sources(dims, [(0, 0), (2, 1)])
     x = dev(np.zeros_like(b))
-    announce(f"two-level solve form={form}")
+    announce(f"two-level solve form={form} coarse_eo={eo}")
     rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, KAPPA, mus, CSW, 1e-10, storage="f32", antiperiodic_t=True,
                                  theta=THETA, mu_shift=SHIFT, mg=g, form=form, restart=16)
     assert rc == 0 and rep["converged"] == 2
