@@ -62,6 +62,8 @@ struct BlockMulArgs {
     int nv;
     const float2* sets[kMgMaxInv];
     unsigned char sel[kMaxSys];  // system -> inverse set
+    unsigned char order[kMaxSys];  // filled by the launcher: systems grouped by set,
+    int start[kMgMaxInv + 1];      // set q's at order[start[q] .. start[q + 1])
     int parity;
     bool zero_other;  // other-parity sites: 0, or left alone
     const float2* x;

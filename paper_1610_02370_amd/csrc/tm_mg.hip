@@ -134,7 +134,9 @@ __device__ inline float transpose_sum64(float (&v)[64]) {
 // Restriction of S systems per workgroup (one aggregate of at most NT sites).
 // Per site and test vector the 4 S partial sums (two spin halves, re / im, per
 // system) of 16 / S test vectors at a time go through one wave-level transpose
-// sum; the wave sums meet in LDS.
+// sum; the wave sums meet in LDS.  The workgroups of one aggregate's system
+// groups are consecutive in the grid, so the later ones find the aggregate's
+// part of P in cache.
 template <int S, int NT>
 __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __restrict__ x, size_t x_stride,
                                                       int nsys, float2* out, size_t base, size_t s_stride,
@@ -142,10 +144,11 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __rest
     constexpr int PER = 16 / S;  // test vectors per 64-value chunk
     extern __shared__ float red[];  // [waves][chunks][64]
     const Geo& g = m.g;
-    const int j = blockIdx.x, l = threadIdx.x;
+    const int G = (nsys + S - 1) / S;
+    const int j = blockIdx.x / G, l = threadIdx.x;
     const bool on = l < g.Vb;
     const long long s = (long long)j * g.Vb + l;
-    const int s0 = blockIdx.y * S;
+    const int s0 = (blockIdx.x - j * G) * S;
     const int ns = min(S, nsys - s0);
     const int lane = l & 63, w = l >> 6, nw = blockDim.x >> 6, nv = m.nv;
     const int nch = (nv + PER - 1) / PER;
@@ -203,9 +206,10 @@ __global__ void __launch_bounds__(NT) k_mg_prolong(MgArgs m, const float2* __res
                                                      size_t e_stride) {
     extern __shared__ float2 cs[];  // [S][2 nv]
     const Geo& g = m.g;
-    const int j = blockIdx.x, l = threadIdx.x, nv = m.nv, n2 = 2 * nv;
+    const int G = (nsys + S - 1) / S;  // system groups, consecutive in the grid per aggregate
+    const int j = blockIdx.x / G, l = threadIdx.x, nv = m.nv, n2 = 2 * nv;
     const long long nc = g.V / g.Vb;
-    const int s0 = blockIdx.y * S;
+    const int s0 = (blockIdx.x - j * G) * S;
     const int ns = min(S, nsys - s0);
     for (int idx = l; idx < ns * n2; idx += blockDim.x) {
         const int k = idx / n2, a = idx - k * n2;
@@ -339,6 +343,8 @@ __device__ inline int coarse_parity(const Geo& g, long long j) {
 // General form: y = add + (self term + i mu_c Gamma5c) x_self + hop_sign * (8 neighbour terms) x_hop
 // on the coarse sites of `parity` (all sites when parity < 0); a null input drops its terms, a
 // null mu_c the twist.  The other parity's sites get 0 when zero_other is set, else stay as they are.
+// With a parity the grid covers site pairs (2b, 2b + 1), one of each parity since the innermost
+// coarse extent is even: the workgroup computes its pair's site of `parity` (and zeroes the other).
 __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, const float2* __restrict__ Dc,
                                                               const double* __restrict__ mu_c,
                                                               const float2* __restrict__ x_self,
@@ -350,17 +356,20 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
     const int n2 = 2 * nv;
     const int ks = min(kCoarseSys, nsys);
     const long long nc = g.V / g.Vb;
-    const long long j = blockIdx.x;
     const int s0 = blockIdx.y * kCoarseSys;
     const int ns = min(kCoarseSys, nsys - s0);
     const int tid = threadIdx.x;
-    if (parity >= 0 && coarse_parity(g, j) != parity) {  // uniform over the workgroup
-        if (!zero_other) return;
-        for (int idx = tid; idx < ns * n2; idx += kThreads) {
-            const int k = idx / n2, r = idx - k * n2;
-            y[((size_t)(s0 + k) * nc + j) * n2 + r] = make_float2(0.f, 0.f);
+    long long j = blockIdx.x;
+    if (parity >= 0) {
+        const long long j0 = 2 * (long long)blockIdx.x;
+        j = coarse_parity(g, j0) == parity ? j0 : j0 + 1;
+        if (zero_other) {
+            const long long jo = 2 * j0 + 1 - j;
+            for (int idx = tid; idx < ns * n2; idx += kThreads) {
+                const int k = idx / n2, r = idx - k * n2;
+                y[((size_t)(s0 + k) * nc + jo) * n2 + r] = make_float2(0.f, 0.f);
+            }
         }
-        return;
     }
     for (int idx = tid; idx < 9 * ns * n2; idx += kThreads) {
         const int t = idx / (ns * n2), r = idx - t * ns * n2, k = r / n2, b = r - k * n2;
@@ -513,29 +522,49 @@ __global__ void __launch_bounds__(kThreads) k_mg_block_inverse(Geo g, int nv, co
 }
 
 // y_s = Minv_{sel[s]} x_s at the coarse sites of `parity` (the others get 0 when zero_other
-// is set, else stay as they are); one 64-thread workgroup per (site, system), one lane per row.
+// is set, else stay as they are).  One 64-lane workgroup per site pair (2b, 2b + 1), whose
+// site of `parity` has inverse b; one lane per row; the systems of one inverse set go in
+// chunks of kBlockMulSys, so each inverse is read from memory once per call.
+constexpr int kBlockMulSys = 8;
 __global__ void __launch_bounds__(64) k_mg_block_mul(BlockMulArgs a) {
-    __shared__ float2 xs[64];
+    __shared__ float2 xs[kBlockMulSys][64];
     const Geo& g = a.g;
-    const long long j = blockIdx.x;
-    const int sys = blockIdx.y, lane = threadIdx.x, n2 = 2 * a.nv;
+    const long long j0 = 2 * (long long)blockIdx.x;
+    const long long j = coarse_parity(g, j0) == a.parity ? j0 : j0 + 1;
+    const int lane = threadIdx.x, n2 = 2 * a.nv;
     const long long nc = g.V / g.Vb;
-    const size_t at = ((size_t)sys * nc + j) * n2;
-    if (coarse_parity(g, j) != a.parity) {
-        if (a.zero_other && lane < n2) a.y[at + lane] = make_float2(0.f, 0.f);
-        return;
+    if (a.zero_other && lane < n2) {
+        const long long jo = 2 * j0 + 1 - j;
+        for (int s = 0; s < a.nsys; ++s) a.y[((size_t)s * nc + jo) * n2 + lane] = make_float2(0.f, 0.f);
     }
-    if (lane < n2) xs[lane] = a.x[at + lane];
-    __syncthreads();
-    if (lane >= n2) return;
-    const float2* M = a.sets[a.sel[sys]] + (size_t)(j >> 1) * n2 * n2 + lane;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int b = 0; b < n2; ++b) {
-        const float2 m = M[(size_t)b * n2], v = xs[b];
-        acc.x += m.x * v.x - m.y * v.y;
-        acc.y += m.x * v.y + m.y * v.x;
+    for (int q = 0; q < kMgMaxInv; ++q) {
+        if (a.start[q] == a.start[q + 1]) continue;
+        const float2* M = a.sets[q] + (size_t)blockIdx.x * n2 * n2 + lane;
+        for (int c0 = a.start[q]; c0 < a.start[q + 1]; c0 += kBlockMulSys) {
+            const int cn = min(kBlockMulSys, a.start[q + 1] - c0);
+            __syncthreads();
+            if (lane < n2)
+                for (int k = 0; k < cn; ++k) xs[k][lane] = a.x[((size_t)a.order[c0 + k] * nc + j) * n2 + lane];
+            __syncthreads();
+            if (lane < n2) {
+                float2 acc[kBlockMulSys];
+#pragma unroll
+                for (int k = 0; k < kBlockMulSys; ++k) acc[k] = make_float2(0.f, 0.f);
+                for (int b = 0; b < n2; ++b) {
+                    const float2 m = M[(size_t)b * n2];
+#pragma unroll
+                    for (int k = 0; k < kBlockMulSys; ++k) {
+                        const float2 v = xs[k][b];
+                        acc[k].x += m.x * v.x - m.y * v.y;
+                        acc[k].y += m.x * v.y + m.y * v.x;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kBlockMulSys; ++k)
+                    if (k < cn) a.y[((size_t)a.order[c0 + k] * nc + j) * n2 + lane] = acc[k];
+            }
+        }
     }
-    a.y[at + lane] = acc;
 }
 
 __global__ void k_mg_stencil_export(long long nc, int nv, const float2* __restrict__ Dc, double2* out) {
@@ -718,7 +747,7 @@ hipError_t launch_mg_restrict(const MgArgs& m, const void* x, size_t x_stride, i
     const int S = nt <= 256 ? 4 : 1;
     const int nch = (m.nv + 16 / S - 1) / (16 / S);
     const size_t lds = (size_t)(nt / 64) * nch * 64 * sizeof(float);
-    const dim3 grid((unsigned)(m.g.V / m.g.Vb), (unsigned)((nsys + S - 1) / S));
+    const dim3 grid((unsigned)(m.g.V / m.g.Vb * ((nsys + S - 1) / S)));
     if (nt <= 256)
         hipLaunchKernelGGL((k_mg_restrict<4, 256>), grid, dim3(nt), lds, st, m, x, x_stride, nsys, out, base,
                            s_stride, j_stride);
@@ -733,7 +762,7 @@ hipError_t launch_mg_prolong(const MgArgs& m, const float2* c, int nsys, void* e
     if (nt > 1024 || m.nv < 1 || m.nv > kMgMaxVec || nsys < 1) return hipErrorInvalidValue;
     const int S = nt <= 256 ? 4 : 2;
     const size_t lds = (size_t)S * 2 * m.nv * sizeof(float2);
-    const dim3 grid((unsigned)(m.g.V / m.g.Vb), (unsigned)((nsys + S - 1) / S));
+    const dim3 grid((unsigned)(m.g.V / m.g.Vb * ((nsys + S - 1) / S)));
     if (nt <= 256)
         hipLaunchKernelGGL((k_mg_prolong<4, 256>), grid, dim3(nt), lds, st, m, c, nsys, e, e_stride);
     else
@@ -760,7 +789,9 @@ hipError_t launch_mg_coarse_part(const Geo& g, int nv, const float2* Dc, const d
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    const dim3 grid((unsigned)(g.V / g.Vb), (unsigned)((nsys + kCoarseSys - 1) / kCoarseSys));
+    if (parity >= 0 && g.nb[3] % 2 != 0) return hipErrorInvalidValue;
+    const long long nc = g.V / g.Vb;
+    const dim3 grid((unsigned)(parity >= 0 ? nc / 2 : nc), (unsigned)((nsys + kCoarseSys - 1) / kCoarseSys));
     hipLaunchKernelGGL(k_mg_coarse_apply, grid, dim3(kThreads), lds, st, g, nv, Dc, mu_c, x_self, x_hop,
                        (float)hop_sign, add, parity, (int)zero_other, y, nsys);
     return hipGetLastError();
@@ -788,9 +819,19 @@ hipError_t launch_mg_block_inverse(const Geo& g, int nv, const float2* Dc, doubl
 hipError_t launch_mg_block_mul(const BlockMulArgs& a, hipStream_t st) {
     if (a.nv < 1 || a.nv > kMgMaxVec || a.nsys < 1 || a.nsys > kMaxSys || a.g.nb[3] % 2 != 0)
         return hipErrorInvalidValue;
-    for (int s = 0; s < a.nsys; ++s)
-        if (a.sel[s] >= kMgMaxInv || !a.sets[a.sel[s]]) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mg_block_mul, dim3((unsigned)(a.g.V / a.g.Vb), a.nsys), dim3(64), 0, st, a);
+    BlockMulArgs k = a;  // systems grouped by inverse set
+    int pos = 0;
+    for (int q = 0; q < kMgMaxInv; ++q) {
+        k.start[q] = pos;
+        for (int s = 0; s < a.nsys; ++s)
+            if (a.sel[s] == q) {
+                if (!a.sets[q]) return hipErrorInvalidValue;
+                k.order[pos++] = (unsigned char)s;
+            }
+    }
+    k.start[kMgMaxInv] = pos;
+    if (pos != a.nsys) return hipErrorInvalidValue;  // a selector outside 0 .. kMgMaxInv - 1
+    hipLaunchKernelGGL(k_mg_block_mul, dim3((unsigned)(a.g.V / a.g.Vb / 2)), dim3(64), 0, st, k);
     return hipGetLastError();
 }
 
