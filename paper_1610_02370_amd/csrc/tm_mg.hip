@@ -131,12 +131,25 @@ __device__ inline float transpose_sum64(float (&v)[64]) {
     return v[0];
 }
 
+// Aggregate and system group of workgroup b when each aggregate has G system groups:
+// runs of 8 aggregates take 8 G consecutive workgroups, group-major, so the G
+// workgroups of one aggregate are 8 apart.  Workgroups are dealt to the 8 XCDs in
+// turn, so all of an aggregate's groups run at about the same time on one XCD and
+// the later ones find its part of P in that XCD's L2.
+__device__ inline void agg_group(int b, int G, long long nc, int& j, int& grp) {
+    constexpr int X = 8;
+    const int run = b / (X * G);
+    const int base = run * X;
+    const int width = (int)min((long long)X, nc - base);
+    const int within = b - run * X * G;
+    grp = within / width;
+    j = base + (within - grp * width);
+}
+
 // Restriction of S systems per workgroup (one aggregate of at most NT sites).
 // Per site and test vector the 4 S partial sums (two spin halves, re / im, per
 // system) of 16 / S test vectors at a time go through one wave-level transpose
-// sum; the wave sums meet in LDS.  The workgroups of one aggregate's system
-// groups are consecutive in the grid, so the later ones find the aggregate's
-// part of P in cache.
+// sum; the wave sums meet in LDS.
 template <int S, int NT>
 __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __restrict__ x, size_t x_stride,
                                                       int nsys, float2* out, size_t base, size_t s_stride,
@@ -144,11 +157,12 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __rest
     constexpr int PER = 16 / S;  // test vectors per 64-value chunk
     extern __shared__ float red[];  // [waves][chunks][64]
     const Geo& g = m.g;
-    const int G = (nsys + S - 1) / S;
-    const int j = blockIdx.x / G, l = threadIdx.x;
+    int j, grp;
+    agg_group(blockIdx.x, (nsys + S - 1) / S, g.V / g.Vb, j, grp);
+    const int l = threadIdx.x;
     const bool on = l < g.Vb;
     const long long s = (long long)j * g.Vb + l;
-    const int s0 = (blockIdx.x - j * G) * S;
+    const int s0 = grp * S;
     const int ns = min(S, nsys - s0);
     const int lane = l & 63, w = l >> 6, nw = blockDim.x >> 6, nv = m.nv;
     const int nch = (nv + PER - 1) / PER;
@@ -206,10 +220,11 @@ __global__ void __launch_bounds__(NT) k_mg_prolong(MgArgs m, const float2* __res
                                                      size_t e_stride) {
     extern __shared__ float2 cs[];  // [S][2 nv]
     const Geo& g = m.g;
-    const int G = (nsys + S - 1) / S;  // system groups, consecutive in the grid per aggregate
-    const int j = blockIdx.x / G, l = threadIdx.x, nv = m.nv, n2 = 2 * nv;
     const long long nc = g.V / g.Vb;
-    const int s0 = (blockIdx.x - j * G) * S;
+    int j, grp;
+    agg_group(blockIdx.x, (nsys + S - 1) / S, nc, j, grp);
+    const int l = threadIdx.x, nv = m.nv, n2 = 2 * nv;
+    const int s0 = grp * S;
     const int ns = min(S, nsys - s0);
     for (int idx = l; idx < ns * n2; idx += blockDim.x) {
         const int k = idx / n2, a = idx - k * n2;
