@@ -12,7 +12,9 @@ Printed on one JSON line:
   sap_sweep        the SAP half-sweep kernel alone, all systems in one launch,
                    event-timed on its stream: GB/s, site-updates/s
   roofline         the dominant kernel (SAP half-sweep) against its binding
-                   peak, with algorithmic bytes / flops per launch
+                   peak, with algorithmic bytes / flops per launch, and the
+                   FP32 FMA rate measured on the device without packed FP32
+                   (the ceiling these kernels can reach)
   solve            time per RHS of the batched mixed-precision solve vs the
                    plain FP64 single-RHS solve and the FP64 CG on the squared
                    even-odd reduced system, all to 1e-10
@@ -503,8 +505,12 @@ def main():
         kernel = "k_sap_half_eo"
     traffic = measured_traffic(kernel, args.workload)
     if wl["storage"] != "f64":
+        # the FP32 vector rate these kernels can reach (no packed FP32), measured on this device
+        fma = tm.tm_probe_fp32_fma()
+        log(f"FP32 FMA probe: {fma:.1f} TFLOP/s")
         roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                "measured_fp32_fma_tflops": fma, "frac_of_measured_fma": achieved_tflops / fma,
                 "kernel": kernel, "launches": launches, "avg_launch_ms": per_launch_s * 1e3,
                 "flops_per_launch": sap_flops / launches, "bytes_per_launch": sap_bytes / launches,
                 "hbm_GBps": achieved_gbps, "hbm_frac": achieved_gbps / HBM_PEAK_GBPS}

@@ -360,6 +360,18 @@ TM_API int tm_mg_precond(const tm_geom* geom, tm_mg* mg, const void* r, void* z,
 TM_API int tm_autotune_sap(const tm_geom* geom, const void* U, double kappa, double c_sw, int n_cycles, int mr_iters,
                            const tm_opts* opts, int best_block[4], int* best_sys_tile);
 
+/* ----------------------------------------------------------- measurement */
+/*
+ * Measured FP32 vector arithmetic ceiling of the current device, for roofline
+ * statements: a loop of independent FMA chains held in registers, 16
+ * workgroups of 256 threads per compute unit, compiled like every kernel of
+ * the library (without packed FP32 instructions).  Four launches on
+ * opts->stream (the first warms up); *tflops gets the best of the other three
+ * in TFLOP/s (an FMA counts 2).  Synchronises the stream; allocates nothing
+ * beyond the library's reduction scratch.
+ */
+TM_API int tm_probe_fp32_fma(double* tflops, const tm_opts* opts);
+
 #ifdef __cplusplus
 }
 #endif

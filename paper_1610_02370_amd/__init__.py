@@ -32,7 +32,7 @@ EXPORTS = (
     "tm_sap_smooth", "tm_solver_opts_default", "tm_fgmres_solve", "tm_spinor_bytes", "tm_spinor_import",
     "tm_spinor_export", "tm_spinor_import_range", "tm_spinor_export_range", "tm_autotune_sap", "tm_cg_solve",
     "tm_mg_params_default", "tm_mg_setup", "tm_mg_destroy", "tm_mg_get_info", "tm_mg_export", "tm_mg_restrict",
-    "tm_mg_prolong", "tm_mg_coarse_apply", "tm_mg_coarse_solve", "tm_mg_precond",
+    "tm_mg_prolong", "tm_mg_coarse_apply", "tm_mg_coarse_solve", "tm_mg_precond", "tm_probe_fp32_fma",
 )
 
 
@@ -91,6 +91,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(the library has no CPU fallback)")
+        # torch's HIP runtime goes in first: the library then binds to the same runtime (same
+        # soname) as the tensors and streams it is handed, instead of loading a second one
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         vp, P = ctypes.c_void_p, ctypes.POINTER
         L.tm_opts_default.argtypes = [P(Opts)]
@@ -129,6 +133,7 @@ def lib():
         L.tm_mg_precond.argtypes = [P(Geom), vp, vp, vp, P(Opts)]
         L.tm_autotune_sap.argtypes = [P(Geom), vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       P(Opts), P(ctypes.c_int), P(ctypes.c_int)]
+        L.tm_probe_fp32_fma.argtypes = [P(ctypes.c_double), P(Opts)]
         _lib = L
     return _lib
 
@@ -345,6 +350,14 @@ def tm_autotune_sap(dims, U, kappa: float, mu, c_sw: float, n_cycles: int, mr_it
     _check(lib().tm_autotune_sap(ctypes.byref(g), _canon(U, "U"), float(kappa), float(c_sw), int(n_cycles),
                                  int(mr_iters), ctypes.byref(o), best, ctypes.byref(tile)))
     return tuple(best), tile.value
+
+
+def tm_probe_fp32_fma(*, stream=None) -> float:
+    """Measured FP32 vector FMA ceiling of the current device in TFLOP/s (no packed FP32)."""
+    o = make_opts("f32", stream=stream)
+    out = ctypes.c_double()
+    _check(lib().tm_probe_fp32_fma(ctypes.byref(out), ctypes.byref(o)))
+    return out.value
 
 
 def mg_params(**kw) -> MgParams:
