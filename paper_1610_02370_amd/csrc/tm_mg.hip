@@ -455,16 +455,17 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
 }
 
 // (Dc[j][0] + i mu_c Gamma5c)^-1 at the coarse sites of `parity`, by Gauss-Jordan
-// elimination with partial pivoting in FP64 (augmented matrix in LDS); the result
-// goes to Minv[j >> 1] as FP32, column-major like the stencil (the innermost coarse extent is
-// even, so j >> 1 numbers the sites of one parity without gaps).
+// elimination with partial pivoting in FP64 (augmented matrix in LDS).  One workgroup
+// per site pair (2b, 2b + 1), for its site j of `parity`; the result goes to Minv[b]
+// (= Minv[j >> 1]) as FP32, column-major like the stencil (the innermost coarse extent
+// is even, so the pair holds one site of each parity).
 __global__ void __launch_bounds__(kThreads) k_mg_block_inverse(Geo g, int nv, const float2* __restrict__ Dc,
                                                                double mu_c, int parity, float2* Minv) {
     extern __shared__ double2 aug[];  // [n2][2 n2] row-major
     __shared__ double2 fac[64];
     __shared__ int piv_s;
-    const long long j = blockIdx.x;
-    if (coarse_parity(g, j) != parity) return;  // uniform over the workgroup
+    const long long j0 = 2 * (long long)blockIdx.x;
+    const long long j = coarse_parity(g, j0) == parity ? j0 : j0 + 1;
     const int n2 = 2 * nv, W = 2 * n2, tid = threadIdx.x;
     const float2* A = Dc + (size_t)j * 9 * n2 * n2;
     for (int idx = tid; idx < n2 * W; idx += kThreads) {
@@ -528,7 +529,7 @@ __global__ void __launch_bounds__(kThreads) k_mg_block_inverse(Geo g, int nv, co
         }
         __syncthreads();
     }
-    float2* out = Minv + (size_t)(j >> 1) * n2 * n2;
+    float2* out = Minv + (size_t)blockIdx.x * n2 * n2;
     for (int idx = tid; idx < n2 * n2; idx += kThreads) {
         const int c = idx / n2, r = idx - c * n2;  // column-major
         const double2 v = aug[r * W + n2 + c];
@@ -826,8 +827,8 @@ hipError_t launch_mg_block_inverse(const Geo& g, int nv, const float2* Dc, doubl
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_mg_block_inverse, dim3((unsigned)(g.V / g.Vb)), dim3(kThreads), lds, st, g, nv, Dc, mu_c,
-                       parity, Minv);
+    hipLaunchKernelGGL(k_mg_block_inverse, dim3((unsigned)(g.V / g.Vb / 2)), dim3(kThreads), lds, st, g, nv, Dc,
+                       mu_c, parity, Minv);
     return hipGetLastError();
 }
 
