@@ -662,9 +662,18 @@ int tm_mg_setup(const tm_geom* geom, const void* U, double kappa, double c_sw, c
     if ((e = mg->P.ensure((size_t)nv * mg->field)) != hipSuccess) return hip_fail(e, "basis P");
     if ((e = mg->Dc.ensure((size_t)mg->nc * 9 * mg->n2 * mg->n2 * sizeof(float2))) != hipSuccess)
         return hip_fail(e, "coarse stencil");
-    // fine workspace: the vectors, their next iterate, and the stencil-term chunk
-    const int chunk = std::min(mg->n2, 16);
+    // fine workspace: the vectors, their next iterate, and the stencil-term chunk; all 2 N_v
+    // columns of a term at once when the device has room (each restriction then reads P once
+    // per term), else 16 at a time
     const size_t vbytes = (size_t)nv * mg->field;
+    int chunk = std::min(mg->n2, 16);
+    {
+        size_t free_b = 0, total_b = 0;
+        const size_t coarse_ws = (2 + coarse_work_vectors(mg.get(), params->coarse_restart)) * (size_t)nv *
+                                 (size_t)(mg->nc * mg->n2) * sizeof(float2);
+        const size_t need = 2 * vbytes + (size_t)mg->n2 * mg->field + coarse_ws + (size_t(4) << 30);
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need <= free_b) chunk = mg->n2;
+    }
     if ((e = mg->fine.ensure(2 * vbytes + (size_t)chunk * mg->field)) != hipSuccess) return hip_fail(e, "setup workspace");
     char* vcur = static_cast<char*>(mg->fine.ptr);
     char* vnext = vcur + vbytes;
