@@ -95,5 +95,12 @@ hipError_t mg_blas_scale(const float2* x, const double* f, float2* y, size_t sys
                          hipStream_t st);
 // y_s = x_s - y_s
 hipError_t mg_blas_sub_from(const float2* x, float2* y, size_t sys_stride, int nsys, long long n, hipStream_t st);
+// Panels of vectors w_s = w + s * w_stride (s < nw <= 4) against one shared basis, each vector read once:
+// out[s * out_stride + i] = <v_i, w_s> for i < cnt <= 4
+hipError_t mg_blas_panel_dots(const float2* basis, size_t vec_stride, int cnt, const float2* w, size_t w_stride, int nw,
+                              long long n, double* partials, double2* out, int out_stride, hipStream_t st);
+// w_s -= sum_i coef[s * coef_stride + i] v_i for i < cnt <= 8
+hipError_t mg_blas_panel_axpy(const float2* basis, size_t vec_stride, int cnt, const double2* coef, int coef_stride,
+                              float2* w, size_t w_stride, int nw, long long n, hipStream_t st);
 
 }  // namespace tmsap

@@ -651,6 +651,95 @@ __global__ void __launch_bounds__(kThreads) k_cdots(const float2* __restrict__ b
 }
 
 // out values (per system, nval consecutive doubles) from the per-workgroup partials, summed in order
+// Panel products for Gram-Schmidt of fields that share one basis: out (s, i) = <v_i, w_s> for
+// i < cnt <= kPanelDots and s < nw <= kPanel, every basis and panel vector read once.
+constexpr int kPanel = 4;
+constexpr int kPanelDots = 4;
+constexpr int kPanelAxpy = 8;
+__global__ void __launch_bounds__(kThreads) k_pdots(const float2* __restrict__ basis, size_t vec_stride, int cnt,
+                                                    const float2* __restrict__ w, size_t w_stride, int nw,
+                                                    long long n, double* partials) {
+    constexpr int NA = 2 * kPanelDots * kPanel;
+    __shared__ double lds[(kThreads / 64) * NA];
+    const int nblk = gridDim.x;
+    double acc[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i] = 0;
+    const long long n4 = n / 2;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n4; e += (long long)nblk * kThreads) {
+        float4 wv[kPanel];
+#pragma unroll
+        for (int s = 0; s < kPanel; ++s)
+            wv[s] = s < nw ? reinterpret_cast<const float4*>(w + (size_t)s * w_stride)[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < kPanelDots; ++i) {
+            if (i < cnt) {
+                const float4 v = reinterpret_cast<const float4*>(basis + (size_t)i * vec_stride)[e];
+#pragma unroll
+                for (int s = 0; s < kPanel; ++s) {
+                    acc[2 * (s * kPanelDots + i)] += (double)(v.x * wv[s].x + v.y * wv[s].y + v.z * wv[s].z + v.w * wv[s].w);
+                    acc[2 * (s * kPanelDots + i) + 1] +=
+                        (double)(v.x * wv[s].y - v.y * wv[s].x + v.z * wv[s].w - v.w * wv[s].z);
+                }
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wvi = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const double v = wave_sum_d(acc[i]);
+        if (lane == 0) lds[wvi * NA + i] = v;
+    }
+    __syncthreads();
+    // partials laid out for k_reduce: value k = 2 i + re/im of panel vector s at ((s * 2 cnt + k) * nblk + block)
+    const int t = threadIdx.x;
+    if (t < 2 * cnt * nw) {
+        const int sv = t / (2 * cnt), k = t - sv * 2 * cnt;
+        double sum = 0;
+        for (int q = 0; q < kThreads / 64; ++q) sum += lds[q * NA + 2 * sv * kPanelDots + k];
+        partials[((size_t)sv * 2 * cnt + k) * nblk + blockIdx.x] = sum;
+    }
+}
+
+// w_s -= sum_i coef[s][i] v_i for s < nw <= kPanel, i < cnt <= kPanelAxpy (coef double2 at
+// coef + s * coef_stride + i); every basis vector read once for the whole panel.
+__global__ void __launch_bounds__(kThreads) k_paxpy(const float2* __restrict__ basis, size_t vec_stride, int cnt,
+                                                    const double2* __restrict__ coef, int coef_stride, float2* w,
+                                                    size_t w_stride, int nw, long long n) {
+    float cr[kPanel][kPanelAxpy], ci[kPanel][kPanelAxpy];
+#pragma unroll
+    for (int s = 0; s < kPanel; ++s)
+#pragma unroll
+        for (int i = 0; i < kPanelAxpy; ++i) {
+            const double2 c = (s < nw && i < cnt) ? coef[(size_t)s * coef_stride + i] : make_double2(0.0, 0.0);
+            cr[s][i] = -(float)c.x;
+            ci[s][i] = -(float)c.y;
+        }
+    const long long n4 = n / 2;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n4; e += (long long)gridDim.x * kThreads) {
+        float4 t[kPanel];
+#pragma unroll
+        for (int s = 0; s < kPanel; ++s)
+            t[s] = s < nw ? reinterpret_cast<const float4*>(w + (size_t)s * w_stride)[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < kPanelAxpy; ++i) {
+            if (i < cnt) {
+                const float4 v = reinterpret_cast<const float4*>(basis + (size_t)i * vec_stride)[e];
+#pragma unroll
+                for (int s = 0; s < kPanel; ++s) {
+                    t[s].x += cr[s][i] * v.x - ci[s][i] * v.y;
+                    t[s].y += cr[s][i] * v.y + ci[s][i] * v.x;
+                    t[s].z += cr[s][i] * v.z - ci[s][i] * v.w;
+                    t[s].w += cr[s][i] * v.w + ci[s][i] * v.z;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kPanel; ++s)
+            if (s < nw) reinterpret_cast<float4*>(w + (size_t)s * w_stride)[e] = t[s];
+    }
+}
+
 __global__ void k_reduce(const double* __restrict__ partials, int nval, int nblk, int nsys, double* out,
                          int out_stride) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -904,6 +993,25 @@ hipError_t mg_blas_scale(const float2* x, const double* f, float2* y, size_t sys
                          hipStream_t st) {
     if (n & 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cscale, dim3(mg_blas_blocks(n), nsys), dim3(kThreads), 0, st, x, f, y, sys_stride, n);
+    return hipGetLastError();
+}
+
+hipError_t mg_blas_panel_dots(const float2* basis, size_t vec_stride, int cnt, const float2* w, size_t w_stride, int nw,
+                              long long n, double* partials, double2* out, int out_stride, hipStream_t st) {
+    if (cnt < 1 || cnt > kPanelDots || nw < 1 || nw > kPanel || (n & 1)) return hipErrorInvalidValue;
+    const int nblk = mg_blas_blocks(n);
+    hipLaunchKernelGGL(k_pdots, dim3(nblk), dim3(kThreads), 0, st, basis, vec_stride, cnt, w, w_stride, nw, n, partials);
+    const int tot = 2 * cnt * nw;
+    hipLaunchKernelGGL(k_reduce, dim3((tot + 63) / 64), dim3(64), 0, st, partials, 2 * cnt, nblk, nw,
+                       reinterpret_cast<double*>(out), 2 * out_stride);
+    return hipGetLastError();
+}
+
+hipError_t mg_blas_panel_axpy(const float2* basis, size_t vec_stride, int cnt, const double2* coef, int coef_stride,
+                              float2* w, size_t w_stride, int nw, long long n, hipStream_t st) {
+    if (cnt < 1 || cnt > kPanelAxpy || nw < 1 || nw > kPanel || (n & 1)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_paxpy, dim3(mg_blas_blocks(n)), dim3(kThreads), 0, st, basis, vec_stride, cnt, coef,
+                       coef_stride, w, w_stride, nw, n);
     return hipGetLastError();
 }
 

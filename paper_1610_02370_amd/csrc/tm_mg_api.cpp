@@ -501,31 +501,51 @@ int mg_apply(tm_mg* mg, DeviceState* ds, const SpinorBuf& r, const SpinorBuf& z,
 
 namespace {
 
-// Orthonormalises nv FP32 fields over the whole lattice, in order (classical
-// Gram-Schmidt twice per vector).
+// Orthonormalises nv FP32 fields over the whole lattice, in order: block classical
+// Gram-Schmidt twice, in panels of 4 fields (each pass reads the earlier fields once
+// for the whole panel), then classical Gram-Schmidt twice inside the panel.  Same
+// result as Gram-Schmidt vector by vector, up to rounding.
 int orthonormalize_fields(tm_mg* mg, float2* v, int nv, hipStream_t st) {
+    constexpr int kPb = 4, kPd = 4, kPa = 8;  // panel width, basis vectors per dot / axpy pass
     const long long n = 12 * mg->g.V;  // complex entries of one field
     const size_t fs = mg->field / sizeof(float2);
     SmallBufs sb;
     int rc;
-    if ((rc = carve_small(mg, 1, kMgMaxVec, n, sb))) return rc;
-    for (int i = 0; i < nv; ++i) {
-        float2* vi = v + (size_t)i * fs;
-        if (i > 0) {
-            for (int pass = 0; pass < 2; ++pass) {
-                if ((rc = basis_dots(v, fs, i, vi, 0, 1, n, sb.partials, sb.h1, 0, st))) return rc;
-                if ((rc = basis_axpy(v, fs, i, sb.h1, 0, -1.0, vi, 0, 1, n, st))) return rc;
-            }
+    if ((rc = carve_small(mg, kPb, kMgMaxVec, n, sb))) return rc;
+    const int hs = kMgMaxVec + 1;  // coefficient stride per panel vector
+    for (int p0 = 0; p0 < nv; p0 += kPb) {
+        const int pb = std::min(kPb, nv - p0);
+        float2* W = v + (size_t)p0 * fs;
+        for (int pass = 0; pass < 2 && p0 > 0; ++pass) {
+            for (int i0 = 0; i0 < p0; i0 += kPd)
+                if ((rc = hc(mg_blas_panel_dots(v + (size_t)i0 * fs, fs, std::min(kPd, p0 - i0), W, fs, pb, n,
+                                                sb.partials, sb.h1 + i0, hs, st),
+                             "panel dots")))
+                    return rc;
+            for (int i0 = 0; i0 < p0; i0 += kPa)
+                if ((rc = hc(mg_blas_panel_axpy(v + (size_t)i0 * fs, fs, std::min(kPa, p0 - i0), sb.h1 + i0, hs, W,
+                                                fs, pb, n, st),
+                             "panel update")))
+                    return rc;
         }
-        if ((rc = hc(mg_blas_norm2(vi, 0, 1, n, sb.partials, sb.nrm, st), "norm"))) return rc;
-        double n2 = 0;
-        if ((rc = hc(hipMemcpyAsync(&n2, sb.nrm, sizeof(double), hipMemcpyDeviceToHost, st), "copy"))) return rc;
-        if ((rc = hc(hipStreamSynchronize(st), "orthonormalisation"))) return rc;
-        if (!std::isfinite(n2)) return fail(TM_ERR_NONFINITE, "non-finite test vector %d", i);
-        const double f = n2 > 0 ? 1.0 / std::sqrt(n2) : 0.0;
-        if ((rc = hc(hipMemcpyAsync(sb.f, &f, sizeof(double), hipMemcpyHostToDevice, st), "copy"))) return rc;
-        if ((rc = hc(mg_blas_scale(vi, sb.f, vi, 0, 1, n, st), "scale"))) return rc;
-        if ((rc = hc(hipStreamSynchronize(st), "orthonormalisation"))) return rc;
+        for (int i = p0; i < p0 + pb; ++i) {
+            float2* vi = v + (size_t)i * fs;
+            if (i > p0) {
+                for (int pass = 0; pass < 2; ++pass) {
+                    if ((rc = basis_dots(W, fs, i - p0, vi, 0, 1, n, sb.partials, sb.h1, 0, st))) return rc;
+                    if ((rc = basis_axpy(W, fs, i - p0, sb.h1, 0, -1.0, vi, 0, 1, n, st))) return rc;
+                }
+            }
+            if ((rc = hc(mg_blas_norm2(vi, 0, 1, n, sb.partials, sb.nrm, st), "norm"))) return rc;
+            double n2 = 0;
+            if ((rc = hc(hipMemcpyAsync(&n2, sb.nrm, sizeof(double), hipMemcpyDeviceToHost, st), "copy"))) return rc;
+            if ((rc = hc(hipStreamSynchronize(st), "orthonormalisation"))) return rc;
+            if (!std::isfinite(n2)) return fail(TM_ERR_NONFINITE, "non-finite test vector %d", i);
+            const double f = n2 > 0 ? 1.0 / std::sqrt(n2) : 0.0;
+            if ((rc = hc(hipMemcpyAsync(sb.f, &f, sizeof(double), hipMemcpyHostToDevice, st), "copy"))) return rc;
+            if ((rc = hc(mg_blas_scale(vi, sb.f, vi, 0, 1, n, st), "scale"))) return rc;
+            if ((rc = hc(hipStreamSynchronize(st), "orthonormalisation"))) return rc;
+        }
     }
     return TM_OK;
 }

@@ -191,8 +191,11 @@ def test_two_level_preconditioner_eo(built_eo):
         assert rel_err(z[k], ref) < 5e-4
 
 
-def test_setup_with_a_two_level_iteration_eo():
-    dims, U, g, o, op = build("4^4 aggregates", mu=0.01, seed=6, setup_iters=2, coarse_eo=1)
+@pytest.mark.parametrize("case", ["4^4 aggregates", "32 test vectors"])
+def test_setup_with_a_two_level_iteration_eo(case):
+    # 6 and 32 test vectors: the global orthonormalisation runs in panels of 4 (a partial last
+    # panel for 6, eight full ones for 32)
+    dims, U, g, o, op = build(case, mu=0.01, seed=6, setup_iters=2, coarse_eo=1)
     P, Dc = g.export()
     P, Dc = host(P), host(Dc)
     assert np.abs(P - o.P).max() < 2e-3 * np.abs(o.P).max()
