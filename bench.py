@@ -491,6 +491,10 @@ def main():
     two = None
     if not args.no_two_level and wl["storage"] == "f32":
         two = two_level_phase(wl, Ud, torch, tm, args.restart)
+    if two and cg:
+        two["speedup_per_rhs_over_cg"] = cg["s_per_rhs"] / two["s_per_rhs"]
+    if two and fp64:
+        two["speedup_per_rhs_over_fp64_1rhs"] = fp64["s_per_rhs"] / two["s_per_rhs"]
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     if cpu:
         log(f"CPU oracle: {cpu['value']:.3f} GB/s-equivalent on {cpu['cores']} threads")
