@@ -324,22 +324,6 @@ __global__ void __launch_bounds__(1024) k_mg_block_orthonormalize(MgArgs m, void
     }
 }
 
-// Coarse site one step along the stencil term t (tile grid, periodic).
-__device__ inline long long coarse_nbr(const Geo& g, long long j, int t) {
-    if (t == 0) return j;
-    int B[4];
-    long long r = j;
-    for (int a = 3; a >= 0; --a) {
-        B[a] = (int)(r % g.nb[a]);
-        r /= g.nb[a];
-    }
-    const int mu = (t - 1) % 4, a = axis_of(mu), dir = t <= 4 ? 1 : -1;
-    B[a] = (B[a] + dir + g.nb[a]) % g.nb[a];
-    long long out = 0;
-    for (int q = 0; q < 4; ++q) out = out * g.nb[q] + B[q];
-    return out;
-}
-
 __device__ inline int coarse_parity(const Geo& g, long long j) {
     int sum = 0;
     for (int a = 3; a >= 0; --a) {
@@ -373,28 +357,54 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
     const long long nc = g.V / g.Vb;
     const int s0 = blockIdx.y * kCoarseSys;
     const int ns = min(kCoarseSys, nsys - s0);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // one (term, system) row per wavefront
+    constexpr int kWaves = kThreads / 64;
     long long j = blockIdx.x;
     if (parity >= 0) {
         const long long j0 = 2 * (long long)blockIdx.x;
         j = coarse_parity(g, j0) == parity ? j0 : j0 + 1;
-        if (zero_other) {
+        if (zero_other && lane < n2) {
             const long long jo = 2 * j0 + 1 - j;
-            for (int idx = tid; idx < ns * n2; idx += kThreads) {
-                const int k = idx / n2, r = idx - k * n2;
-                y[((size_t)(s0 + k) * nc + jo) * n2 + r] = make_float2(0.f, 0.f);
-            }
+            for (int k = wave; k < ns; k += kWaves) y[((size_t)(s0 + k) * nc + jo) * n2 + lane] = make_float2(0.f, 0.f);
         }
     }
-    for (int idx = tid; idx < 9 * ns * n2; idx += kThreads) {
-        const int t = idx / (ns * n2), r = idx - t * ns * n2, k = r / n2, b = r - k * n2;
-        const float2* src = t == 0 ? x_self : x_hop;
-        float2 v = make_float2(0.f, 0.f);
-        if (src) {
-            v = src[((size_t)(s0 + k) * nc + coarse_nbr(g, j, t)) * n2 + b];
-            if (t > 0) v = make_float2(hop_sign * v.x, hop_sign * v.y);
+    // coordinates of j once; the 8 neighbours by one coordinate step each
+    int Bj[4];
+    {
+        int rem = (int)j;
+#pragma unroll
+        for (int a = 3; a >= 0; --a) {
+            Bj[a] = rem % g.nb[a];
+            rem /= g.nb[a];
         }
-        sh[(t * ks + k) * n2 + b] = v;
+    }
+    for (int tk = wave; tk < 9 * ns; tk += kWaves) {
+        const int t = tk / ns, k = tk - t * ns;
+        const float2* src = t == 0 ? x_self : x_hop;
+        if (lane < n2) {
+            float2 v = make_float2(0.f, 0.f);
+            if (src) {
+                int site = (int)j;
+                if (t > 0) {
+                    const int a = axis_of((t - 1) & 3), step = t <= 4 ? 1 : -1;
+                    site = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        int c = Bj[q];
+                        if (q == a) {
+                            c += step;
+                            if (c == g.nb[q]) c = 0;
+                            if (c < 0) c = g.nb[q] - 1;
+                        }
+                        site = site * g.nb[q] + c;
+                    }
+                }
+                v = src[((size_t)(s0 + k) * nc + site) * n2 + lane];
+                if (t > 0) v = make_float2(hop_sign * v.x, hop_sign * v.y);
+            }
+            sh[(t * ks + k) * n2 + lane] = v;
+        }
     }
     __syncthreads();
     const int G = kThreads / nv;
@@ -405,10 +415,19 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
     if (grp < G) {
         const float4* A = reinterpret_cast<const float4*>(Dc + (size_t)j * 9 * n2 * n2);
         const int c_lo = x_self ? 0 : n2, c_hi = x_hop ? 9 * n2 : n2;
+        // column c = t n2 + r: term t, component r, stepped without a division per column
+        const int dt = G / n2, dr = G - dt * n2;
+        int t = (c_lo + grp) / n2, r = c_lo + grp - t * n2;
 #pragma unroll 8
         for (int c = c_lo + grp; c < c_hi; c += G) {
             const float4 mv = A[(size_t)c * nv + p];  // rows 2p, 2p + 1 of column c
-            const float2* xs = sh + ((c / n2) * ks) * n2 + (c % n2);
+            const float2* xs = sh + (t * ks) * n2 + r;
+            t += dt;
+            r += dr;
+            if (r >= n2) {
+                r -= n2;
+                ++t;
+            }
 #pragma unroll
             for (int k = 0; k < kCoarseSys; ++k) {
                 if (k < ns) {
@@ -430,8 +449,8 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
                 sh[(grp * ks + k) * n2 + 2 * p + 1] = acc1[k];
             }
     __syncthreads();
-    for (int idx = tid; idx < ns * n2; idx += kThreads) {
-        const int k = idx / n2, r = idx - k * n2;
+    for (int k = wave; k < ns && lane < n2; k += kWaves) {
+        const int r = lane;
         float2 sum = make_float2(0.f, 0.f);
         for (int q = 0; q < G; ++q) {
             const float2 v = sh[(q * ks + k) * n2 + r];
