@@ -412,7 +412,7 @@ def main():
                     help="run a plain 1 GiB elementwise kernel before the timed region (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes in DESIGN.md)",
+        print("bench.py measures one GPU: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
