@@ -36,7 +36,7 @@ def op_for(dims, U, mu, ap=False):
                            mu_shift=SHIFT)
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-5), ("f16", 4e-3)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-5), ("f16", 4e-3), ("bf16", 2.5e-2)])
 def test_dirac_twisted(field, prec, tol):
     dims, U = field
     mus = [0.0009, -0.0009]
@@ -54,6 +54,7 @@ def test_dirac_twisted(field, prec, tol):
     ("f32", (4, 4, 2, 4), False, 2e-4),   # general shapes up to 256 sites
     ("f32", (4, 4, 4, 8), False, 2e-4),   # larger blocks
     ("f64", (4, 4, 4, 4), False, 1e-11),
+    ("f16", (4, 4, 4, 4), False, 2e-2),
     ("bf16", (4, 4, 4, 4), False, 6e-2),
     ("f32", (4, 4, 4, 4), True, 2e-4),    # even-odd block solves
     ("f64", (4, 4, 4, 4), True, 1e-11),
