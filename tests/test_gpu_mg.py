@@ -63,8 +63,9 @@ def built(request):
 
 
 # the even-odd coarse solver: the smallest and largest coarse rows (block inverses of 2x2 and of
-# 64x64, the latter with 128 KiB of LDS) and the largest coarse grid
-EO_CASES = ["4^4 aggregates", "2^4 aggregates, uneven coarse grid", "32 test vectors", "1 test vector"]
+# 64x64, the latter with 128 KiB of LDS), the largest coarse grid, and 512-site aggregates
+EO_CASES = ["4^4 aggregates", "2^4 aggregates, uneven coarse grid", "32 test vectors", "1 test vector",
+            "8x4^3 aggregates"]
 
 
 @pytest.fixture(scope="module", params=EO_CASES)
