@@ -4,6 +4,8 @@
 // One thread per site; spin projection to half spinors before the SU(3)
 // products; every field is read structure-of-arrays so a wavefront's loads
 // are contiguous.
+#include <type_traits>
+
 #include "tm_internal.h"
 
 namespace tmsap {
@@ -11,6 +13,18 @@ namespace tmsap {
 namespace {
 
 constexpr int kThreads = 256;
+
+// Link from its first two rows, stored as 12 reals (row-major, re/im pairs); third row rebuilt.
+template <class R>
+__device__ inline void link_from_rows(const R* u, Link<R>& L) {
+    L.u[0][0] = cmk(u[0], u[1]);
+    L.u[0][1] = cmk(u[2], u[3]);
+    L.u[0][2] = cmk(u[4], u[5]);
+    L.u[1][0] = cmk(u[6], u[7]);
+    L.u[1][1] = cmk(u[8], u[9]);
+    L.u[1][2] = cmk(u[10], u[11]);
+    complete_su3(L);
+}
 
 template <class Si, class So, class G, class C, class R>
 __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
@@ -22,6 +36,23 @@ __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
     tiled_neighbours(g, s, nf, nbk, &wrap, &par);
     Clover<R> A;
     load_clover<R, C>(a.clover, g.V, s, A);
+    // FP32 spinors and links: the 8 links of the site's hops (two rows each) are loaded once
+    // for all systems.  The other forms reload them per system: holding them takes the FP64
+    // and the FP16 / BF16 kernels to one wavefront per SIMD, which costs more than the loads.
+    constexpr bool kHold = std::is_same<Si, float>::value && std::is_same<G, float>::value &&
+                           std::is_same<R, float>::value;
+    R lr[kHold ? 8 : 1][12];
+    if constexpr (kHold) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const size_t b = (size_t)mu * 3 * g.V;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                Unit<G>::load(a.links, b + (size_t)q * g.V + s, &lr[2 * mu][4 * q]);
+                Unit<G>::load(a.links, b + (size_t)q * g.V + nbk[mu], &lr[2 * mu + 1][4 * q]);
+            }
+        }
+    }
     const size_t in_stride = (size_t)6 * g.V * Unit<Si>::bytes;
     const size_t out_stride = (size_t)6 * g.V * Unit<So>::bytes;
     for (int sys = 0; sys < a.nsys; ++sys) {
@@ -34,7 +65,10 @@ __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
         for (int mu = 0; mu < 4; ++mu) {
             Link<R> L;
             Spinor<R> p;
-            load_link<R, G>(a.links, g.V, s, mu, L);
+            if constexpr (kHold)
+                link_from_rows(lr[2 * mu], L);
+            else
+                load_link<R, G>(a.links, g.V, s, mu, L);
             load_spinor<R, Si>(in, isc, g.V, nf[mu], p);
             {  // boundary phase (1 for hops inside the lattice), branch-free: fewer registers
                 const bool w = wrap & (1u << mu);
@@ -43,7 +77,10 @@ __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
                 for (int i = 0; i < 12; ++i) p.v[i] = cmk(re * p.v[i].re - im * p.v[i].im, re * p.v[i].im + im * p.v[i].re);
             }
             hop_forward(mu, L, p, (R)1, acc);
-            load_link<R, G>(a.links, g.V, nbk[mu], mu, L);
+            if constexpr (kHold)
+                link_from_rows(lr[2 * mu + 1], L);
+            else
+                load_link<R, G>(a.links, g.V, nbk[mu], mu, L);
             load_spinor<R, Si>(in, isc, g.V, nbk[mu], p);
             {
                 const bool w = wrap & (16u << mu);
