@@ -59,7 +59,10 @@ __device__ inline void reduce_out(double* vals, int n, double* lds, double* part
 //   mode 3: t = w - sum_i c_i v_i; y <- fac[sys] t (w kept); out = ||t||^2
 // Arithmetic at the vectors' precision R (FP64 or FP32) per site; the sums
 // over sites accumulate in FP64.  Norms and dots are of the stored values.
-template <class P, int NV>
+// KEEP: the basis values loaded for the update stay in registers for the dots of mode 1
+// (with up to 4 FP32 vectors), instead of being loaded again after w is stored, which the
+// compiler has to assume may alias the basis.
+template <class P, int NV, bool KEEP = false>
 __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride, int nvec, VecRef w,
                                                  const double* __restrict__ coef, int coef_stride, int mode, VecRef y,
                                                  const double* __restrict__ fac, double* partials, long long V) {
@@ -76,6 +79,7 @@ __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride
     const char* w0 = static_cast<const char*>(w.data) + (size_t)sys * w.sys_stride;
     for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
         Spinor<R> wv;
+        Spinor<R> vk[KEEP ? NV : 1];
         load_spinor<R, P>(w0, nullptr, V, s, wv);
         if (mode != 0) {
 #pragma unroll
@@ -83,6 +87,7 @@ __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride
                 if (i < nvec) {
                     Spinor<R> v;
                     load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
+                    if constexpr (KEEP) vk[i] = v;
                     const cplx<R> c = cmk((R)cf[2 * i], (R)cf[2 * i + 1]);
 #pragma unroll
                     for (int k = 0; k < 12; ++k) wv.v[k] = wv.v[k] - c * v.v[k];
@@ -106,7 +111,10 @@ __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride
             for (int i = 0; i < NV; ++i) {
                 if (i < nvec) {
                     Spinor<R> v;
-                    load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
+                    if constexpr (KEEP)
+                        v = vk[i];
+                    else
+                        load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
                     R re = 0, im = 0;
 #pragma unroll
                     for (int k = 0; k < 12; ++k) {
@@ -287,7 +295,10 @@ hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, con
 #define TM_GS_LAUNCH(NVT)                                                                                          \
     TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL((k_gs<T, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, \
                                              cf, coef_stride, mode, y, fac, partials, V))
-    if (nvec <= 4) {
+    if (nvec <= 4 && mode == 1 && p == P_F32) {
+        hipLaunchKernelGGL((k_gs<float, 4, true>), grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, cf,
+                           coef_stride, mode, y, fac, partials, V);
+    } else if (nvec <= 4) {
         TM_GS_LAUNCH(4);
     } else if (nvec <= 8) {
         TM_GS_LAUNCH(8);
