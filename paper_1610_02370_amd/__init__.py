@@ -377,7 +377,10 @@ def mg_params(**kw) -> MgParams:
 class MG:
     """Two-level method (tm_mg_setup); `close()` (or garbage collection) frees it.
 
-    Coarse vectors are complex128 tensors [nsys, nc, 2 n_vec]; fine vectors [nsys, V, 4, 3]."""
+    Coarse vectors are complex128 tensors [nsys, nc, 2 n_vec]; fine vectors [nsys, V, 4, 3].
+    `params` override the library defaults (Table 1) by field name of tm_mg_params, e.g.
+    n_vec, setup_iters, delta, coarse_tol, coarse_eo (1: even-odd reduced coarse GMRES, the default;
+    0: GMRES on the full coarse operator)."""
 
     def __init__(self, dims, U, kappa: float, mu: float, c_sw: float, v0, *, antiperiodic_t: bool = False,
                  theta=None, mu_shift=None, stream=None, gauge_tag: int = 0, **params):
