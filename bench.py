@@ -9,17 +9,25 @@ with inputs resident in HBM when the timed region starts.
 Printed on one JSON line:
   value            SAP-sweep algorithmic bytes moved per second of whole-step
                    wall time (GB/s)
-  sap_sweep        the SAP half-sweep kernel alone, all systems in one launch,
-                   event-timed on its stream: GB/s, site-updates/s
+  sap_kernel_GBps  the SAP half-sweep kernel's own algorithmic bandwidth over
+                   the launches of the timed steps (event time on the solve's
+                   stream), and its fraction of the 8 TB/s HBM peak
+  sap_sweep_all_systems
+                   the SAP half-sweep kernel with every system of the workload
+                   in one launch, event-timed: GB/s, TFLOP/s, site-updates/s
+  sap_sweeps_32^3x64
+                   the same for the 32^3 x 64 configuration: the +-mu pair in
+                   FP32 and one system in FP64 (the HBM-bound case)
   roofline         the dominant kernel (SAP half-sweep) against its binding
                    peak, with algorithmic bytes / flops per launch, and the
                    FP32 FMA rate measured on the device without packed FP32
                    (the ceiling these kernels can reach)
   solve            time per RHS of the batched mixed-precision solve vs the
                    plain FP64 single-RHS solve and the FP64 CG on the squared
-                   even-odd reduced system, all to 1e-10
-  cpu_baseline     the FP64 CPU oracle's SAP on a bounded sample of the same
-                   workload, on the host cores
+                   even-odd reduced system, all to 1e-10 (the baselines' first
+                   call, which allocates their workspaces, reported apart)
+  cpu_baseline     the FP64 CPU oracle on bounded samples at 1 thread and all
+                   host threads (operator, SAP cycle, an 8^4 solve), CPU model
 """
 from __future__ import annotations
 
@@ -196,9 +204,10 @@ def make_inputs(wl, torch, tm, synth):
     return Ud, b, mus
 
 
-def sap_sweep_phase(wl, Ud, mus, torch, tm, reps):
+def sap_sweep_phase(wl, Ud, mus, torch, tm, reps, storage=None):
     """SAP cycles over all systems in one launch per half-sweep, event-timed on the stream."""
-    dims, storage = wl["dims"], wl["storage"]
+    dims = wl["dims"]
+    storage = storage or wl["storage"]
     nsys = len(mus)
     nbytes = tm.tm_spinor_bytes(dims, nsys, storage, layout_block=BLOCK)
     bi = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -231,15 +240,52 @@ def sap_sweep_phase(wl, Ud, mus, torch, tm, reps):
     flops_launch = V / 2 * sap_flops_per_site_cycle(nsys)
     del bi, xi
     torch.cuda.empty_cache()
+    gbps = bytes_launch / per_launch_s / 1e9
+    tflops = flops_launch / per_launch_s / 1e12
+    alu_peak = FP64_VECTOR_PEAK_TFLOPS if storage == "f64" else FP32_VECTOR_PEAK_TFLOPS
     return {
+        "dims_TZYX": list(dims),
+        "systems": nsys,
+        "storage": storage,
+        "kernel": sap_kernel_name(storage),
         "launches": launches,
         "ms_per_launch": per_launch_s * 1e3,
-        "GBps": bytes_launch / per_launch_s / 1e9,
-        "TFLOPs": flops_launch / per_launch_s / 1e12,
+        "GBps": gbps,
+        "hbm_frac": gbps / HBM_PEAK_GBPS,
+        "TFLOPs": tflops,
+        "alu_frac": tflops / alu_peak,
         "site_updates_per_s": V * nsys * reps / (ms * 1e-3),
         "bytes_per_launch": bytes_launch,
         "flops_per_launch": flops_launch,
     }
+
+
+def sap_kernel_name(storage: str, eo: bool = False) -> str:
+    if eo:
+        return "k_sap_half_eo"
+    if storage == "f64":
+        return "k_sap_half"
+    return "k_sap_half_44" if tuple(BLOCK) == (4, 4, 4, 4) else "k_sap_half_v2"
+
+
+def small_lattice_sweeps(torch, tm, synth, reps):
+    """SAP sweeps of the 32^3 x 64 configuration (eps 0.6, kappa 0.1394, mu +-0.001, c_sw 1.5):
+    the +-mu pair in FP32 and one system in FP64, the cases whose sweep the HBM bound can limit."""
+    wl = WORKLOADS["32^3x64_pm_f32"]
+    U = synth.gauge_field(wl["dims"], wl["eps"], seed=3)
+    Ud = torch.from_numpy(U).cuda()
+    del U
+    out = {}
+    out["32^3x64_pm_f32"] = sap_sweep_phase(wl, Ud, [wl["mu"], -wl["mu"]], torch, tm, reps)
+    tm.tm_gauge_release(Ud)
+    out["32^3x64_1sys_f64"] = sap_sweep_phase(wl, Ud, [wl["mu"]], torch, tm, reps, storage="f64")
+    tm.tm_gauge_release(Ud)
+    del Ud
+    torch.cuda.empty_cache()
+    for k, v in out.items():
+        log(f"SAP sweep {k}: {v['ms_per_launch']:.3f} ms/launch, {v['GBps']:.0f} GB/s "
+            f"({100 * v['hbm_frac']:.1f}% of HBM), {v['TFLOPs']:.1f} TFLOP/s")
+    return out
 
 
 def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False):
@@ -250,7 +296,21 @@ def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False):
     return rc, rep
 
 
-def fp64_baseline(wl, Ud, torch, tm):
+def timed_twice(fn, torch):
+    """(cold, warm) wall times of two identical calls: the first also allocates the workspaces, the
+    second is the steady state.  Both rebuild the gauge copies (gauge tag 0), as the timed
+    mixed-precision step does."""
+    times, res = [], None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return times[0], times[1], res
+
+
+def fp64_baseline(wl, Ud, torch, tm, restart=20):
     import numpy as np
 
     dims = wl["dims"]
@@ -259,15 +319,18 @@ def fp64_baseline(wl, Ud, torch, tm):
     s, c, sg = wl["sources"][0]
     b[0, 0, s, c] = 1.0
     x = torch.zeros_like(b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, rep = tm.tm_fgmres_solve(dims, Ud, b, x, wl["kappa"], [sg * wl["mu"]], wl["csw"], TOL, storage="f64",
-                                 form="flexible", restart=20, n_cycles=N_CYCLES, mr_iters=MR_ITERS, block_dims=BLOCK,
-                                 gauge_tag=0)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+
+    def run():
+        x.zero_()
+        return tm.tm_fgmres_solve(dims, Ud, b, x, wl["kappa"], [sg * wl["mu"]], wl["csw"], TOL, storage="f64",
+                                  form="flexible", restart=restart, n_cycles=N_CYCLES, mr_iters=MR_ITERS,
+                                  block_dims=BLOCK, gauge_tag=0)
+
+    cold, warm, (rc, rep) = timed_twice(run, torch)
+    tm.tm_gauge_release(Ud)
     del b, x
-    return {"s_per_rhs": dt, "iters": rep["iters"], "true_rel_res": rep["true_rel_res"][0], "status": rc}
+    return {"s_per_rhs": warm, "s_per_rhs_cold": cold, "iters": rep["iters"], "restart": restart,
+            "true_rel_res": rep["true_rel_res"][0], "status": rc}
 
 
 def cg_baseline(wl, Ud, torch, tm):
@@ -280,13 +343,17 @@ def cg_baseline(wl, Ud, torch, tm):
     s, c, sg = wl["sources"][0]
     b[0, 0, s, c] = 1.0
     x = torch.zeros_like(b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, rep = tm.tm_cg_solve(dims, Ud, b, x, wl["kappa"], [sg * wl["mu"]], wl["csw"], TOL, max_iters=100000)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+
+    def run():
+        x.zero_()
+        return tm.tm_cg_solve(dims, Ud, b, x, wl["kappa"], [sg * wl["mu"]], wl["csw"], TOL, max_iters=100000,
+                              gauge_tag=0)
+
+    cold, warm, (rc, rep) = timed_twice(run, torch)
+    tm.tm_gauge_release(Ud)
     del b, x
-    return {"s_per_rhs": dt, "iters": rep["iters"], "true_rel_res": rep["true_rel_res"][0], "status": rc}
+    return {"s_per_rhs": warm, "s_per_rhs_cold": cold, "iters": rep["iters"],
+            "true_rel_res": rep["true_rel_res"][0], "status": rc}
 
 
 # Two-level method (sections 2.3 - 2.6) with the library defaults (Table 1 where a two-level
@@ -351,41 +418,81 @@ def two_level_phase(wl, Ud, torch, tm, restart):
             "coarse_share": (info["t_coarse"] - before["t_coarse"]) / dt}
 
 
-def cpu_baseline(wl, target_s: float = 12.0):
-    """FP64 CPU oracle SAP cycles (4^4 blocks, 4 MR steps, one system) on a 16^3 x 32
-    sample of the workload (same eps, kappa, mu, c_sw), all host threads."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _rate(fn, sites: int, min_s: float):
+    """Site-updates per second of fn over at least min_s seconds (at least one call)."""
+    n, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s:
+            return sites * n / dt, n, dt
+
+
+def cpu_baseline(wl):
+    """The FP64 CPU oracle on bounded samples, at one host thread and at all of them:
+    operator applications and SAP cycles (4^4 blocks, 4 MR steps, one system) on a 16^4 lattice
+    with the workload's eps / kappa / mu / c_sw, and the FGMRES(20) + SAP solve to 1e-10 of the
+    8^4 run with the 32^3 x 64 configuration's parameters (eps 0.6, kappa 0.1394, mu 0.001,
+    c_sw 1.5, gauge seed 3, point source).  `value` is the all-thread SAP rate converted with the
+    GPU value's byte model."""
     import numpy as np
 
     import oracle
     from paper_1610_02370_amd import synth
 
-    dims = (32, 16, 16, 16)
-    U = synth.gauge_field(dims, wl["eps"], seed=5)
-    b = synth.gaussian_spinor(dims, 1, seed=105)[0].ravel()
-    op = oracle.Operator(dims, U, oracle.kappa_to_m(wl["kappa"]), wl["mu"], wl["csw"])
+    dims = (16, 16, 16, 16)
     V = int(np.prod(dims))
-    cycles = 0
+    U = synth.gauge_field(dims, wl["eps"], seed=5)
+    psi = synth.gaussian_spinor(dims, 1, seed=105)[0].ravel()
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(wl["kappa"]), wl["mu"], wl["csw"])
+    all_threads = oracle.num_threads()
+    rates = {}
+    for th in (1, all_threads):
+        oracle.set_num_threads(th)
+        d_rate, _, _ = _rate(lambda: op.apply(psi), V, 1.0)
+        s_rate, cyc, _ = _rate(lambda: op.sap(psi, BLOCK, 1, MR_ITERS), V, 2.0)
+        rates[th] = {"dirac_site_updates_per_s": d_rate, "sap_cycle_site_updates_per_s": s_rate,
+                     "sap_cycles_timed": cyc}
+    oracle.set_num_threads(all_threads)
+    # the 8^4 solve (configuration 3's parameters)
+    c3 = WORKLOADS["32^3x64_pm_f32"]
+    d8 = (8, 8, 8, 8)
+    U8 = synth.gauge_field(d8, c3["eps"], seed=3)
+    op8 = oracle.Operator(d8, U8, oracle.kappa_to_m(c3["kappa"]), c3["mu"], c3["csw"])
+    b8 = np.zeros((int(np.prod(d8)), 4, 3), np.complex128)
+    b8[0, 0, 0] = 1.0
     t0 = time.perf_counter()
-    x = np.zeros_like(b)
-    while True:
-        x = op.sap(b, BLOCK, 1, MR_ITERS, x0=x)
-        cycles += 1
-        dt = time.perf_counter() - t0
-        if dt >= target_s:
-            break
+    _, rep8 = op8.fgmres(b8.ravel(), TOL, restart=20, precond=True, bdims=BLOCK, n_cycles=N_CYCLES,
+                         mr_iters=MR_ITERS)
+    solve8_s = time.perf_counter() - t0
     nsys = len(wl["sources"])
     per_site_sys = sap_bytes_per_site_cycle(wl["storage"], nsys) / nsys
-    rate = V * cycles / dt  # site-updates per second (one system)
+    rate = rates[all_threads]["sap_cycle_site_updates_per_s"]
     return {
         "value": rate * per_site_sys / 1e9,
         "unit": "GB/s",
-        "cores": oracle.num_threads(),
+        "cores": all_threads,
         "kind": "oracle",
-        "sample": f"{cycles} SAP cycle(s), 4^4 blocks, {MR_ITERS} MR steps, 1 system, FP64, on a 16^3x32 lattice "
-                  f"with the workload's eps/kappa/mu/c_sw; bytes per site-update from the same algorithmic model "
-                  f"as the GPU value ({per_site_sys:.0f} B per site and system per cycle)",
+        "sample": f"SAP cycles (4^4 blocks, {MR_ITERS} MR steps, 1 system, FP64) on a 16^4 lattice with the "
+                  f"workload's eps/kappa/mu/c_sw, {all_threads} threads; bytes per site-update from the GPU "
+                  f"value's algorithmic model ({per_site_sys:.0f} B per site and system per cycle)",
+        "cpu_model": cpu_model(),
+        "threads": {"1": rates[1], str(all_threads): rates[all_threads]},
         "site_updates_per_s": rate,
-        "seconds": dt,
+        "solve_8^4_cfg3_params": {"seconds": solve8_s, "iters": rep8["iters"],
+                                  "true_rel_res": rep8["true_rel_res"], "threads": all_threads},
     }
 
 
@@ -400,7 +507,9 @@ def main():
     ap.add_argument("--sap-reps", type=int, default=10)
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--group", type=int, default=0)
-    ap.add_argument("--sweep", action="store_true", help="also time SAP cycles with every system in one launch")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the SAP sweeps (every system of the workload in one launch; 32^3x64 +-mu FP32 and "
+                         "1-system FP64)")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cg-baseline", action="store_true")
@@ -439,8 +548,8 @@ def main():
         print(json.dumps({"two_level": two_level_phase(wl, Ud, torch, tm, args.restart)}), flush=True)
         return
 
-    sweep = None
-    if args.sweep or args.sweep_only:
+    sweep, small_sweeps = None, None
+    if not args.no_sweep or args.sweep_only:
         sweep = sap_sweep_phase(wl, Ud, mus, torch, tm, args.sap_reps)
         log(f"SAP sweep ({nsys} systems per launch): {sweep['ms_per_launch']:.3f} ms/launch, "
             f"{sweep['GBps']:.0f} GB/s, {sweep['TFLOPs']:.1f} TFLOP/s")
@@ -448,6 +557,8 @@ def main():
         if args.sweep_only:
             print(json.dumps({"sap_sweep": sweep}), flush=True)
             return
+        if args.workload == "48^3x96_12rhs_f32":
+            small_sweeps = small_lattice_sweeps(torch, tm, synth, args.sap_reps)
 
     x = torch.zeros_like(b)
     for w in range(args.warmup):
@@ -483,13 +594,16 @@ def main():
     del x, b
     torch.cuda.empty_cache()
 
-    fp64 = None if args.no_fp64_baseline else fp64_baseline(wl, Ud, torch, tm)
+    # FGMRES(20) in FP64 does not fit next to 64^3 x 128 inputs: restart 8 there
+    fp64 = None if args.no_fp64_baseline else fp64_baseline(wl, Ud, torch, tm,
+                                                            restart=8 if V > 20_000_000 else 20)
     if fp64:
-        log(f"FP64 1-RHS solve: {fp64['s_per_rhs']:.2f}s iters {fp64['iters']} res {fp64['true_rel_res']:.2e}")
+        log(f"FP64 1-RHS solve: {fp64['s_per_rhs']:.2f}s (first call {fp64['s_per_rhs_cold']:.2f}s) "
+            f"iters {fp64['iters']} res {fp64['true_rel_res']:.2e}")
     cg = None if args.no_cg_baseline else cg_baseline(wl, Ud, torch, tm)
     if cg:
-        log(f"FP64 CG (even-odd normal equations) 1-RHS: {cg['s_per_rhs']:.2f}s iters {cg['iters']} "
-            f"res {cg['true_rel_res']:.2e}")
+        log(f"FP64 CG (even-odd normal equations) 1-RHS: {cg['s_per_rhs']:.2f}s (first call "
+            f"{cg['s_per_rhs_cold']:.2f}s) iters {cg['iters']} res {cg['true_rel_res']:.2e}")
     two = None
     if not args.no_two_level and wl["storage"] == "f32":
         two = two_level_phase(wl, Ud, torch, tm, args.restart)
@@ -505,10 +619,7 @@ def main():
     t_rhs = wall / args.steps / nsys
     achieved_gbps = sap_bytes / t_sap / 1e9
     achieved_tflops = sap_flops / t_sap / 1e12
-    kernel = ("k_sap_half_44" if tuple(BLOCK) == (4, 4, 4, 4) else "k_sap_half_v2") if wl["storage"] != "f64" \
-        else "k_sap_half"
-    if args.eo:
-        kernel = "k_sap_half_eo"
+    kernel = sap_kernel_name(wl["storage"], args.eo)
     traffic = measured_traffic(kernel, args.workload)
     if wl["storage"] != "f64":
         # the FP32 vector rate these kernels can reach (no packed FP32), measured on this device
@@ -542,16 +653,22 @@ def main():
                    "tol": TOL, "restart": args.restart,
                    "group": group, "parallelism": "single GPU"},
         "converged": ok,
+        "sap_kernel_GBps": achieved_gbps,
+        "sap_kernel_hbm_frac": achieved_gbps / HBM_PEAK_GBPS,
         "sap": {"GBps": achieved_gbps, "hbm_frac": achieved_gbps / HBM_PEAK_GBPS, "TFLOPs": achieved_tflops,
                 "site_updates_per_s": V * sys_cycles / t_sap, "share_of_step": t_sap / wall},
         "sap_sweep_all_systems": sweep,
+        "sap_sweeps_32^3x64": small_sweeps,
         "solve": {"s_per_rhs_mixed": t_rhs, "iters": max(r["iters"] for _, r in reps),
                   "outer": max(r["outer"] for _, r in reps),
                   "max_true_rel_res": max(max(r["true_rel_res"]) for _, r in reps),
                   "s_per_rhs_fp64_1rhs": fp64["s_per_rhs"] if fp64 else None,
+                  "s_per_rhs_fp64_1rhs_first_call": fp64["s_per_rhs_cold"] if fp64 else None,
+                  "fp64_restart": fp64["restart"] if fp64 else None,
                   "fp64_iters": fp64["iters"] if fp64 else None,
                   "speedup_per_rhs": (fp64["s_per_rhs"] / t_rhs) if fp64 else None,
                   "s_per_rhs_cg_fp64": cg["s_per_rhs"] if cg else None,
+                  "s_per_rhs_cg_fp64_first_call": cg["s_per_rhs_cold"] if cg else None,
                   "cg_iters": cg["iters"] if cg else None,
                   "speedup_per_rhs_over_cg": (cg["s_per_rhs"] / t_rhs) if cg else None},
         "two_level": two,

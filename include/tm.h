@@ -165,8 +165,13 @@ typedef struct {
     int max_iters;        /* cap on Arnoldi steps (per system, summed over restarts) */
     int n_cycles;         /* SAP cycles per preconditioner application */
     int mr_iters;         /* MR steps per block solve */
-    int block_dims[4];    /* SAP blocks; zeros = autotuned (or 4^4 when no tuning is cached) */
-    double inner_tol;     /* defect correction: relative tolerance of each inner solve */
+    int block_dims[4];    /* SAP blocks; zeros = the shape tm_autotune_sap cached for this problem in the
+                             file named by the TM_TUNE_CACHE environment variable, or 4^4 when that
+                             variable is unset or holds no entry (report->block_dims has the shape used) */
+    double inner_tol;     /* defect correction: relative tolerance of each system's inner solve,
+                             raised to 0.5 tol ||b_k|| / ||r_k|| (at most 0.5) when that is larger, so
+                             no system is solved further than its outer tolerance needs; a system
+                             already at tol gets no correction */
     int max_outer;        /* defect correction: cap on outer corrections */
     int group;            /* systems solved together (0 = all nsys) */
     tm_mg* mg;            /* NULL: SAP preconditioner.  Else the two-level method of this handle
@@ -193,6 +198,8 @@ typedef struct {
     long long sap_cycles;               /* SAP cycles launched (each over a whole group of systems) */
     long long sap_sys_cycles;           /* SAP cycles times the systems they carried */
     int group;                          /* systems solved together (after fitting device memory) */
+    int block_dims[4];                  /* Schwarz block shape the smoother used */
+    int sys_tile;                       /* SAP systems per workgroup used (0 = all of a group) */
 } tm_solve_report;
 
 /*
@@ -216,13 +223,16 @@ TM_API int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, vo
  * of t+z+y+x) and bhat = b_e - D_eo D_oo^-1 b_o, run in the least-squares form;
  * then x_o = D_oo^-1 (b_o - D_oe x_e).  The odd rows of b - D x vanish by
  * construction and the even rows are the reduced residual, so CG stops when
- * that residual is <= tol ||b|| per system; report->true_rel_res is then
- * recomputed as ||b - D x|| / ||b|| with the full operator.  FP64 throughout
+ * that (recursively updated) residual is <= tol ||b|| per system; then
+ * ||b - D x|| / ||b|| is recomputed with the full operator into
+ * report->true_rel_res, and a system counts as converged only when that true
+ * residual is <= tol: otherwise CG restarts from it (at most 3 restarts, all
+ * within max_iters steps).  FP64 throughout
  * (opts->storage TM_F64), canonical buffers, x in/out (the even-site part of x
  * is the initial guess).  Needs even dims (TM_ERR_DIMS) and at most 8 distinct
  * |mu| per call; systems are solved in groups that fit device memory
- * (report->group).  Returns TM_NOT_CONVERGED when max_iters CG steps did not
- * reach tol (x then holds the last iterate).
+ * (report->group).  Returns TM_NOT_CONVERGED when some system's true residual
+ * is still above tol (x then holds the last iterate).
  */
 TM_API int tm_cg_solve(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw,
                        double tol, int max_iters, const tm_opts* opts, tm_solve_report* report);
@@ -352,7 +362,8 @@ TM_API int tm_mg_precond(const tm_geom* geom, tm_mg* mg, const void* r, void* z,
  * *best_sys_tile.  The choice is stored in a text cache (path from the
  * TM_TUNE_CACHE environment variable, default ./tm_tune.txt) keyed by
  * (dims, nsys, storage, n_cycles, mr_iters); tm_fgmres_solve with block_dims
- * all zero uses a cached shape when one exists, else 4^4.  The objective is
+ * all zero uses a cached shape only when TM_TUNE_CACHE names the cache (and
+ * it holds an entry for the problem), else 4^4.  The objective is
  * smoother throughput only: the block shape also changes the preconditioner,
  * so a tuned shape can converge in a different number of iterations.
  * Allocates its own test vectors; U is read through the gauge cache.

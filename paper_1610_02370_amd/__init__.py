@@ -78,7 +78,8 @@ class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("converged", ctypes.c_int),
                 ("true_rel_res", ctypes.c_double * MAX_SYS), ("t_total", ctypes.c_double),
                 ("t_sap", ctypes.c_double), ("sap_cycles", ctypes.c_longlong),
-                ("sap_sys_cycles", ctypes.c_longlong), ("group", ctypes.c_int)]
+                ("sap_sys_cycles", ctypes.c_longlong), ("group", ctypes.c_int), ("block_dims", ctypes.c_int * 4),
+                ("sys_tile", ctypes.c_int)]
 
 
 _lib = None
@@ -189,12 +190,49 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _canon(t, what: str):
+def _expect(t, what: str, numel: int | None = None) -> None:
+    """A canonical complex128 tensor; numel, when given, is the element count the call implies."""
     import torch
 
     if t.dtype != torch.complex128:
         raise TypeError(f"{what} must be complex128 in the canonical layout")
+    if numel is not None and numel > 0 and t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} complex elements; the call's dims and systems imply {numel}")
+
+
+def _expect_bytes(t, nbytes: int, what: str) -> None:
+    """An internal-layout buffer holding at least nbytes."""
+    have = t.numel() * t.element_size()
+    if nbytes > 0 and have < nbytes:
+        raise ValueError(f"{what} holds {have} bytes; the internal layout of the call needs {nbytes}")
+
+
+def _canon(t, what: str, numel: int | None = None):
+    _expect(t, what, numel)
     return _ptr(t)
+
+
+def _internal(t, nbytes: int, what: str) -> ctypes.c_void_p:
+    _expect_bytes(t, nbytes, what)
+    return _ptr(t)
+
+
+def _volume(dims) -> int:
+    """Sites of dims, or 0 when a dimension is not positive (the library reports that error itself)."""
+    V = 1
+    for d in dims:
+        if int(d) <= 0:
+            return 0
+        V *= int(d)
+    return V
+
+
+def _spinor_numel(dims, nsys: int) -> int:
+    return nsys * _volume(dims) * 12
+
+
+def _link_numel(dims) -> int:
+    return _volume(dims) * 36
 
 
 def tm_init() -> None:
@@ -220,10 +258,18 @@ def tm_dirac_apply(dims, U, psi, kappa: float, mu, c_sw: float, out=None, *, sto
     o = make_opts(storage, stream=stream, io=io, layout_block=layout_block, gauge_tag=gauge_tag)
     if out is None:
         out = torch.empty_like(psi)
-    pin = _canon(psi, "psi") if io == "canonical" else _ptr(psi)
-    pout = _canon(out, "out") if io == "canonical" else _ptr(out)
-    _check(lib().tm_dirac_apply(ctypes.byref(g), _canon(U, "U"), pin, pout, float(kappa), float(c_sw),
-                                ctypes.byref(o)))
+    _expect(U, "U", _link_numel(dims))
+    if io == "canonical":
+        n = _spinor_numel(dims, g.nsys)
+        _expect(psi, "psi", n)
+        _expect(out, "out", n)
+        pin, pout = _ptr(psi), _ptr(out)
+    else:
+        n = _spinor_bytes(g, o)
+        _expect_bytes(psi, n, "psi")
+        _expect_bytes(out, n, "out")
+        pin, pout = _ptr(psi), _ptr(out)
+    _check(lib().tm_dirac_apply(ctypes.byref(g), _ptr(U), pin, pout, float(kappa), float(c_sw), ctypes.byref(o)))
     return out
 
 
@@ -239,9 +285,16 @@ def tm_sap_smooth(dims, U, b, x, kappa: float, mu, c_sw: float, block_dims, n_cy
     o.sys_tile = int(sys_tile)
     o.sap_eo = int(bool(eo))
     bd = (ctypes.c_int * 4)(*[int(v) for v in block_dims])
-    pb = _canon(b, "b") if io == "canonical" else _ptr(b)
-    px = _canon(x, "x") if io == "canonical" else _ptr(x)
-    _check(lib().tm_sap_smooth(ctypes.byref(g), _canon(U, "U"), pb, px, float(kappa), float(c_sw), bd,
+    _expect(U, "U", _link_numel(dims))
+    if io == "canonical":
+        n = _spinor_numel(dims, g.nsys)
+        _expect(b, "b", n)
+        _expect(x, "x", n)
+    else:
+        n = _spinor_bytes(g, o)
+        _expect_bytes(b, n, "b")
+        _expect_bytes(x, n, "x")
+    _check(lib().tm_sap_smooth(ctypes.byref(g), _ptr(U), _ptr(b), _ptr(x), float(kappa), float(c_sw), bd,
                                int(n_cycles), int(mr_iters), ctypes.byref(o)))
     return x
 
@@ -273,14 +326,18 @@ def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *,
     if mg is not None:
         s.mg = mg.handle
     rep = Report()
-    rc = _check(lib().tm_fgmres_solve(ctypes.byref(g), _canon(U, "U"), _canon(b, "b"), _canon(x, "x"), float(kappa),
-                                      float(c_sw), float(tol), ctypes.byref(s), ctypes.byref(o), ctypes.byref(rep)),
+    n = _spinor_numel(dims, g.nsys)
+    _expect(U, "U", _link_numel(dims))
+    _expect(b, "b", n)
+    _expect(x, "x", n)
+    rc = _check(lib().tm_fgmres_solve(ctypes.byref(g), _ptr(U), _ptr(b), _ptr(x), float(kappa), float(c_sw),
+                                      float(tol), ctypes.byref(s), ctypes.byref(o), ctypes.byref(rep)),
                 allow_not_converged=True)
     n = g.nsys
     return rc, {"iters": rep.iters, "outer": rep.outer, "converged": rep.converged,
                 "true_rel_res": [rep.true_rel_res[k] for k in range(n)], "t_total": rep.t_total,
                 "t_sap": rep.t_sap, "sap_cycles": rep.sap_cycles, "sap_sys_cycles": rep.sap_sys_cycles,
-                "group": rep.group}
+                "group": rep.group, "block_dims": tuple(rep.block_dims), "sys_tile": rep.sys_tile}
 
 
 def tm_cg_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, max_iters: int = 100000,
@@ -289,25 +346,36 @@ def tm_cg_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *, max
     g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts("f64", stream=stream, gauge_tag=gauge_tag)
     rep = Report()
-    rc = _check(lib().tm_cg_solve(ctypes.byref(g), _canon(U, "U"), _canon(b, "b"), _canon(x, "x"), float(kappa),
-                                  float(c_sw), float(tol), int(max_iters), ctypes.byref(o), ctypes.byref(rep)))
+    n = _spinor_numel(dims, g.nsys)
+    _expect(U, "U", _link_numel(dims))
+    _expect(b, "b", n)
+    _expect(x, "x", n)
+    rc = _check(lib().tm_cg_solve(ctypes.byref(g), _ptr(U), _ptr(b), _ptr(x), float(kappa), float(c_sw), float(tol),
+                                  int(max_iters), ctypes.byref(o), ctypes.byref(rep)),
+                allow_not_converged=True)
     n = len(list(mu))
     return rc, {"iters": rep.iters, "converged": rep.converged,
                 "true_rel_res": [rep.true_rel_res[k] for k in range(n)], "t_total": rep.t_total, "group": rep.group}
+
+
+def _spinor_bytes(g: Geom, o: Opts) -> int:
+    return int(lib().tm_spinor_bytes(ctypes.byref(g), ctypes.byref(o)))
 
 
 def tm_spinor_bytes(dims, nsys: int, storage: str, layout_block=None) -> int:
     """Bytes of an internal buffer (host-side arithmetic, no GPU call)."""
     g = make_geom(dims, [0.0] * nsys)
     o = make_opts(storage, stream=False, io="internal", layout_block=layout_block)
-    return int(lib().tm_spinor_bytes(ctypes.byref(g), ctypes.byref(o)))
+    return _spinor_bytes(g, o)
 
 
 def tm_spinor_import(dims, canon, internal, *, storage: str, layout_block=None, stream=None):
     nsys = canon.shape[0]
     g = make_geom(dims, [0.0] * nsys)
     o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
-    _check(lib().tm_spinor_import(ctypes.byref(g), _canon(canon, "canon"), _ptr(internal), ctypes.byref(o)))
+    _expect(canon, "canon", _spinor_numel(dims, nsys))
+    _expect_bytes(internal, _spinor_bytes(g, o), "internal")
+    _check(lib().tm_spinor_import(ctypes.byref(g), _ptr(canon), _ptr(internal), ctypes.byref(o)))
     return internal
 
 
@@ -315,7 +383,9 @@ def tm_spinor_export(dims, internal, canon, *, storage: str, layout_block=None, 
     nsys = canon.shape[0]
     g = make_geom(dims, [0.0] * nsys)
     o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
-    _check(lib().tm_spinor_export(ctypes.byref(g), _ptr(internal), _canon(canon, "canon"), ctypes.byref(o)))
+    _expect(canon, "canon", _spinor_numel(dims, nsys))
+    _expect_bytes(internal, _spinor_bytes(g, o), "internal")
+    _check(lib().tm_spinor_export(ctypes.byref(g), _ptr(internal), _ptr(canon), ctypes.byref(o)))
     return canon
 
 
@@ -324,8 +394,11 @@ def tm_spinor_import_range(dims, canon, internal, nsys: int, first: int, *, stor
     """canon ([count][V][4][3]) -> systems first..first+count-1 of an internal buffer of nsys systems."""
     g = make_geom(dims, [0.0] * nsys)
     o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
-    _check(lib().tm_spinor_import_range(ctypes.byref(g), _canon(canon, "canon"), _ptr(internal), int(first),
-                                        int(canon.shape[0]), ctypes.byref(o)))
+    count = int(canon.shape[0])
+    _expect(canon, "canon", _spinor_numel(dims, count))
+    _expect_bytes(internal, _spinor_bytes(g, o), "internal")
+    _check(lib().tm_spinor_import_range(ctypes.byref(g), _ptr(canon), _ptr(internal), int(first), count,
+                                        ctypes.byref(o)))
     return internal
 
 
@@ -334,8 +407,11 @@ def tm_spinor_export_range(dims, internal, canon, nsys: int, first: int, *, stor
     """Systems first..first+count-1 of an internal buffer of nsys systems -> canon ([count][V][4][3])."""
     g = make_geom(dims, [0.0] * nsys)
     o = make_opts(storage, stream=stream, io="internal", layout_block=layout_block)
-    _check(lib().tm_spinor_export_range(ctypes.byref(g), _ptr(internal), _canon(canon, "canon"), int(first),
-                                        int(canon.shape[0]), ctypes.byref(o)))
+    count = int(canon.shape[0])
+    _expect(canon, "canon", _spinor_numel(dims, count))
+    _expect_bytes(internal, _spinor_bytes(g, o), "internal")
+    _check(lib().tm_spinor_export_range(ctypes.byref(g), _ptr(internal), _ptr(canon), int(first), count,
+                                        ctypes.byref(o)))
     return canon
 
 
@@ -347,7 +423,8 @@ def tm_autotune_sap(dims, U, kappa: float, mu, c_sw: float, n_cycles: int, mr_it
     o.sap_eo = int(bool(eo))
     best = (ctypes.c_int * 4)()
     tile = ctypes.c_int()
-    _check(lib().tm_autotune_sap(ctypes.byref(g), _canon(U, "U"), float(kappa), float(c_sw), int(n_cycles),
+    _check(lib().tm_autotune_sap(ctypes.byref(g), _canon(U, "U", _link_numel(dims)), float(kappa), float(c_sw),
+                                 int(n_cycles),
                                  int(mr_iters), ctypes.byref(o), best, ctypes.byref(tile)))
     return tuple(best), tile.value
 
@@ -391,8 +468,10 @@ class MG:
         g = make_geom(dims, [float(mu)], antiperiodic_t, theta, mu_shift)
         o = make_opts("f32", stream=stream, gauge_tag=gauge_tag)
         h = ctypes.c_void_p()
-        _check(lib().tm_mg_setup(ctypes.byref(g), _canon(U, "U"), float(kappa), float(c_sw),
-                                 ctypes.byref(self.params), _canon(v0, "v0"), ctypes.byref(h), ctypes.byref(o)))
+        _expect(U, "U", _link_numel(dims))
+        _expect(v0, "v0", _spinor_numel(dims, self.params.n_vec))
+        _check(lib().tm_mg_setup(ctypes.byref(g), _ptr(U), float(kappa), float(c_sw), ctypes.byref(self.params),
+                                 _ptr(v0), ctypes.byref(h), ctypes.byref(o)))
         self.handle = h
         self.n_vec = self.params.n_vec
         self.cdims = tuple(d // b for d, b in zip(self.dims, self.params.block_dims))
@@ -439,7 +518,8 @@ class MG:
 
         ns = r.shape[0]
         c = torch.empty((ns, self.nc, 2 * self.n_vec), dtype=torch.complex128, device=r.device)
-        _check(lib().tm_mg_restrict(self.handle, ns, _canon(r, "r"), _ptr(c), ctypes.byref(self._opts(stream))))
+        _check(lib().tm_mg_restrict(self.handle, ns, _canon(r, "r", _spinor_numel(self.dims, ns)), _ptr(c),
+                                    ctypes.byref(self._opts(stream))))
         return c
 
     def prolong(self, c, stream=None):
@@ -450,7 +530,8 @@ class MG:
         for d in self.dims:
             V *= d
         e = torch.empty((ns, V, 4, 3), dtype=torch.complex128, device=c.device)
-        _check(lib().tm_mg_prolong(self.handle, ns, _canon(c, "c"), _ptr(e), ctypes.byref(self._opts(stream))))
+        _check(lib().tm_mg_prolong(self.handle, ns, _canon(c, "c", ns * self.nc * 2 * self.n_vec), _ptr(e),
+                                   ctypes.byref(self._opts(stream))))
         return e
 
     def coarse_apply(self, x, mu_c, stream=None):
@@ -459,7 +540,7 @@ class MG:
         ns = x.shape[0]
         mus = (ctypes.c_double * ns)(*[float(m) for m in mu_c])
         y = torch.empty_like(x)
-        _check(lib().tm_mg_coarse_apply(self.handle, ns, mus, _canon(x, "x"), _ptr(y),
+        _check(lib().tm_mg_coarse_apply(self.handle, ns, mus, _canon(x, "x", ns * self.nc * 2 * self.n_vec), _ptr(y),
                                         ctypes.byref(self._opts(stream))))
         return y
 
@@ -470,7 +551,8 @@ class MG:
         mus = (ctypes.c_double * ns)(*[float(m) for m in mu_c])
         x = torch.empty_like(b)
         it = ctypes.c_int(0)
-        _check(lib().tm_mg_coarse_solve(self.handle, ns, mus, _canon(b, "b"), _ptr(x), float(tol), int(restart),
+        _check(lib().tm_mg_coarse_solve(self.handle, ns, mus, _canon(b, "b", ns * self.nc * 2 * self.n_vec), _ptr(x),
+                                        float(tol), int(restart),
                                         int(max_restarts), ctypes.byref(it), ctypes.byref(self._opts(stream))))
         return x, it.value
 
@@ -479,6 +561,7 @@ class MG:
 
         g = make_geom(self.dims, mu, self.antiperiodic_t, self.theta, self.mu_shift)
         z = torch.empty_like(r)
-        _check(lib().tm_mg_precond(ctypes.byref(g), self.handle, _canon(r, "r"), _ptr(z),
+        _check(lib().tm_mg_precond(ctypes.byref(g), self.handle, _canon(r, "r", _spinor_numel(self.dims, g.nsys)),
+                                   _ptr(z),
                                    ctypes.byref(self._opts(stream))))
         return z

@@ -5,9 +5,11 @@
 // Run in the least-squares form: r = bhat - Dhat x_e is the reduced residual
 // and s = Dhat^+ r the residual of the normal equations.  With
 // x_o = D_oo^-1 (b_o - D_oe x_e) the odd rows of b - D x vanish and the even
-// rows equal r, so ||r|| <= tol ||b|| is the stopping test on the true
-// residual.  All systems of a group advance together; a converged system
-// takes zero steps from then on.
+// rows equal r, so ||r|| <= tol ||b|| is the stopping test.  r is updated
+// recursively; the returned status rests on the true residual b - D x
+// recomputed with the full operator, and CG restarts from it when rounding
+// left it above tol.  All systems of a group advance together; a converged
+// system takes zero steps from then on.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -182,100 +184,112 @@ int tm_cg_solve(const tm_geom* geom, const void* U, const void* b, void* x, doub
         char* xcan = (char*)x + g0 * canon_sys;
         if ((rc = hchk(launch_parity_import(g, ns, bcan, be, bo, flag, st), "import b"))) return rc;
         if ((rc = hchk(launch_parity_import(g, ns, xcan, xe, t, flag, st), "import x"))) return rc;
-        // ||b||^2
-        if ((rc = norm2(c, be, bn1)) || (rc = norm2(c, bo, bn2))) return rc;
-        // r = bhat - Dhat x_e with bhat = b_e - H_eo D_oo^-1 b_o
-        ParityArgs a0 = base_args(c, 1);
-        a0.in_add = bo;
-        a0.do_inv = 1;
-        a0.out = t;
-        if ((rc = hchk(launch_parity_op(a0, st), "reduced rhs"))) return rc;
-        ParityArgs a1 = base_args(c, 0);
-        a1.in_add = be;
-        a1.in_hop = t;
-        a1.hop_sign = -1.0;
-        a1.out = r;
-        if ((rc = hchk(launch_parity_op(a1, st), "reduced rhs"))) return rc;
-        if ((rc = dhat(c, xe, t, q, false))) return rc;
-        if ((rc = hchk(launch_axpby(q, mone, r, one, ns, (long long)fd / ns, st), "axpby"))) return rc;
-        // s = Dhat^+ r, p = s, gamma = ||s||^2
-        if ((rc = dhat(c, r, t, s, true))) return rc;
-        if ((rc = hchk(launch_axpby(s, one, p, zero, ns, (long long)fd / ns, st), "axpby"))) return rc;
-        if ((rc = norm2(c, s, gam))) return rc;
-        if ((rc = norm2(c, r, rr))) return rc;
-        if ((rc = hchk(hipMemcpyAsync(host.data(), bn1, 2 * kMaxSys * sizeof(double), hipMemcpyDeviceToHost, st),
-                       "copy")))
-            return rc;
-        if ((rc = hchk(hipMemcpyAsync(host.data() + 2 * kMaxSys, rr, ns * sizeof(double), hipMemcpyDeviceToHost, st),
-                       "copy")))
-            return rc;
-        unsigned hflag = 0;
-        if ((rc = hchk(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st), "copy"))) return rc;
-        if ((rc = hchk(hipStreamSynchronize(st), "CG setup"))) return rc;
-        if (hflag) return fail(TM_ERR_NONFINITE, "b or x holds NaN or Inf");
+        // Each pass runs CG from the current x_e on the recomputed reduced residual, then forms x_o and
+        // the true residual b - D x with the full operator.  A system is converged when that true
+        // residual is <= tol ||b||; one whose recursively updated residual met tol while the true one
+        // did not (rounding drift) goes through another pass, at most 3 more, within max_iters steps.
         std::vector<double> bnorm(ns);
         std::vector<int> iters(ns, 0);
-        unsigned long long frozen = 0;
-        for (int k = 0; k < ns; ++k) {
-            bnorm[k] = std::sqrt(host[k] + host[kMaxSys + k]);
-            const double rk = std::sqrt(std::max(0.0, host[2 * kMaxSys + k]));
-            if (!std::isfinite(rk)) return fail(TM_ERR_NONFINITE, "non-finite CG residual");
-            if (rk <= tol * bnorm[k]) frozen |= 1ull << k;
-        }
+        unsigned long long met = 0;  // systems whose true residual is <= tol
         const unsigned long long all = ns == 64 ? ~0ull : ((1ull << ns) - 1);
         int it = 0;
-        while (frozen != all && it < max_iters) {
-            if ((rc = dhat(c, p, t, q, false))) return rc;
-            if ((rc = norm2(c, q, qq))) return rc;
-            if ((rc = hchk(launch_cg_scalars(0, ns, frozen, gam, qq, alpha, nalpha, st), "scalars"))) return rc;
-            if ((rc = hchk(launch_axpby(p, alpha, xe, one, ns, (long long)fd / ns, st), "axpby"))) return rc;
-            if ((rc = hchk(launch_axpby(q, nalpha, r, one, ns, (long long)fd / ns, st), "axpby"))) return rc;
-            if ((rc = norm2(c, r, rr))) return rc;
-            if ((rc = hchk(hipMemcpyAsync(host.data(), rr, ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy")))
-                return rc;
+        for (int pass = 0;; ++pass) {
+            // ||b||^2 (the closing residual of a pass reuses these scalars)
+            if ((rc = norm2(c, be, bn1)) || (rc = norm2(c, bo, bn2))) return rc;
+            // r = bhat - Dhat x_e with bhat = b_e - H_eo D_oo^-1 b_o
+            ParityArgs a0 = base_args(c, 1);
+            a0.in_add = bo;
+            a0.do_inv = 1;
+            a0.out = t;
+            if ((rc = hchk(launch_parity_op(a0, st), "reduced rhs"))) return rc;
+            ParityArgs a1 = base_args(c, 0);
+            a1.in_add = be;
+            a1.in_hop = t;
+            a1.hop_sign = -1.0;
+            a1.out = r;
+            if ((rc = hchk(launch_parity_op(a1, st), "reduced rhs"))) return rc;
+            if ((rc = dhat(c, xe, t, q, false))) return rc;
+            if ((rc = hchk(launch_axpby(q, mone, r, one, ns, (long long)fd / ns, st), "axpby"))) return rc;
+            // s = Dhat^+ r, p = s, gamma = ||s||^2
             if ((rc = dhat(c, r, t, s, true))) return rc;
-            if ((rc = norm2(c, s, gnew))) return rc;
-            if ((rc = hchk(launch_cg_scalars(1, ns, frozen, gam, gnew, beta, nullptr, st), "scalars"))) return rc;
-            if ((rc = hchk(launch_axpby(s, one, p, beta, ns, (long long)fd / ns, st), "axpby"))) return rc;
-            if ((rc = hchk(hipStreamSynchronize(st), "CG step"))) return rc;
-            ++it;
+            if ((rc = hchk(launch_axpby(s, one, p, zero, ns, (long long)fd / ns, st), "axpby"))) return rc;
+            if ((rc = norm2(c, s, gam))) return rc;
+            if ((rc = norm2(c, r, rr))) return rc;
+            if ((rc = hchk(hipMemcpyAsync(host.data(), bn1, 2 * kMaxSys * sizeof(double), hipMemcpyDeviceToHost, st),
+                           "copy")))
+                return rc;
+            if ((rc = hchk(hipMemcpyAsync(host.data() + 2 * kMaxSys, rr, ns * sizeof(double), hipMemcpyDeviceToHost, st),
+                           "copy")))
+                return rc;
+            unsigned hflag = 0;
+            if ((rc = hchk(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st), "copy"))) return rc;
+            if ((rc = hchk(hipStreamSynchronize(st), "CG setup"))) return rc;
+            if (hflag) return fail(TM_ERR_NONFINITE, "b or x holds NaN or Inf");
+            unsigned long long frozen = met;
             for (int k = 0; k < ns; ++k) {
-                if ((frozen >> k) & 1ull) continue;
-                ++iters[k];
-                const double rk = std::sqrt(std::max(0.0, host[k]));
-                if (!std::isfinite(host[k])) return fail(TM_ERR_NONFINITE, "non-finite CG residual");
+                bnorm[k] = std::sqrt(host[k] + host[kMaxSys + k]);
+                const double rk = std::sqrt(std::max(0.0, host[2 * kMaxSys + k]));
+                if (!std::isfinite(rk)) return fail(TM_ERR_NONFINITE, "non-finite CG residual");
                 if (rk <= tol * bnorm[k]) frozen |= 1ull << k;
             }
-        }
-        // x_o = D_oo^-1 (b_o - H_oe x_e), then back to the canonical layout
-        ParityArgs a2 = base_args(c, 1);
-        a2.in_add = bo;
-        a2.in_hop = xe;
-        a2.hop_sign = -1.0;
-        a2.do_inv = 1;
-        a2.out = t;
-        if ((rc = hchk(launch_parity_op(a2, st), "odd sites"))) return rc;
-        if ((rc = hchk(launch_parity_export(g, ns, xe, t, xcan, st), "export x"))) return rc;
+            while (frozen != all && it < max_iters) {
+                if ((rc = dhat(c, p, t, q, false))) return rc;
+                if ((rc = norm2(c, q, qq))) return rc;
+                if ((rc = hchk(launch_cg_scalars(0, ns, frozen, gam, qq, alpha, nalpha, st), "scalars"))) return rc;
+                if ((rc = hchk(launch_axpby(p, alpha, xe, one, ns, (long long)fd / ns, st), "axpby"))) return rc;
+                if ((rc = hchk(launch_axpby(q, nalpha, r, one, ns, (long long)fd / ns, st), "axpby"))) return rc;
+                if ((rc = norm2(c, r, rr))) return rc;
+                if ((rc = hchk(hipMemcpyAsync(host.data(), rr, ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy")))
+                    return rc;
+                if ((rc = dhat(c, r, t, s, true))) return rc;
+                if ((rc = norm2(c, s, gnew))) return rc;
+                if ((rc = hchk(launch_cg_scalars(1, ns, frozen, gam, gnew, beta, nullptr, st), "scalars"))) return rc;
+                if ((rc = hchk(launch_axpby(s, one, p, beta, ns, (long long)fd / ns, st), "axpby"))) return rc;
+                if ((rc = hchk(hipStreamSynchronize(st), "CG step"))) return rc;
+                ++it;
+                for (int k = 0; k < ns; ++k) {
+                    if ((frozen >> k) & 1ull) continue;
+                    ++iters[k];
+                    const double rk = std::sqrt(std::max(0.0, host[k]));
+                    if (!std::isfinite(host[k])) return fail(TM_ERR_NONFINITE, "non-finite CG residual");
+                    if (rk <= tol * bnorm[k]) frozen |= 1ull << k;
+                }
+            }
+            // x_o = D_oo^-1 (b_o - H_oe x_e), then back to the canonical layout
+            ParityArgs a2 = base_args(c, 1);
+            a2.in_add = bo;
+            a2.in_hop = xe;
+            a2.hop_sign = -1.0;
+            a2.do_inv = 1;
+            a2.out = t;
+            if ((rc = hchk(launch_parity_op(a2, st), "odd sites"))) return rc;
+            if ((rc = hchk(launch_parity_export(g, ns, xe, t, xcan, st), "export x"))) return rc;
 
-        // true residual b - D x with the full operator
-        if ((h = ds->io.ensure(3 * ffield * ns)) != hipSuccess) return hip_fail(h, "residual workspace");
-        SpinorBuf fb = wrap_internal(ds->io.ptr, g, ns, P_F64);
-        SpinorBuf fx = wrap_internal((char*)ds->io.ptr + ffield * ns, g, ns, P_F64);
-        SpinorBuf fr = wrap_internal((char*)ds->io.ptr + 2 * ffield * ns, g, ns, P_F64);
-        if ((rc = hchk(launch_spinor_import(g, fb, bcan, flag, st), "import"))) return rc;
-        if ((rc = hchk(launch_spinor_import(g, fx, xcan, flag, st), "import"))) return rc;
-        if ((rc = run_dirac(g, *G, fx, fr, c.mu, ns, P_F64, st))) return rc;
-        if ((rc = hchk(blas_residual(P_F64, vec_ref(fb, g.V), vec_ref(fr, g.V), vec_ref(fr, g.V), c.partials, bn1, ns,
-                                     g.V, st),
-                       "residual")))
-            return rc;
-        if ((rc = hchk(hipMemcpyAsync(host.data(), bn1, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy")))
-            return rc;
-        if ((rc = hchk(hipStreamSynchronize(st), "residual"))) return rc;
+            // true residual b - D x with the full operator
+            if ((h = ds->io.ensure(3 * ffield * ns)) != hipSuccess) return hip_fail(h, "residual workspace");
+            SpinorBuf fb = wrap_internal(ds->io.ptr, g, ns, P_F64);
+            SpinorBuf fx = wrap_internal((char*)ds->io.ptr + ffield * ns, g, ns, P_F64);
+            SpinorBuf fr = wrap_internal((char*)ds->io.ptr + 2 * ffield * ns, g, ns, P_F64);
+            if ((rc = hchk(launch_spinor_import(g, fb, bcan, flag, st), "import"))) return rc;
+            if ((rc = hchk(launch_spinor_import(g, fx, xcan, flag, st), "import"))) return rc;
+            if ((rc = run_dirac(g, *G, fx, fr, c.mu, ns, P_F64, st))) return rc;
+            if ((rc = hchk(blas_residual(P_F64, vec_ref(fb, g.V), vec_ref(fr, g.V), vec_ref(fr, g.V), c.partials, bn1, ns,
+                                         g.V, st),
+                           "residual")))
+                return rc;
+            if ((rc = hchk(hipMemcpyAsync(host.data(), bn1, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy")))
+                return rc;
+            if ((rc = hchk(hipStreamSynchronize(st), "residual"))) return rc;
+            met = 0;
+            for (int k = 0; k < ns; ++k) {
+                const double rel = host[2 * k + 1] > 0 ? std::sqrt(host[2 * k] / host[2 * k + 1]) : 0.0;
+                rep.true_rel_res[g0 + k] = rel;
+                if (rel <= tol) met |= 1ull << k;
+            }
+            if (met == all || it >= max_iters || pass >= 3) break;
+        }
         for (int k = 0; k < ns; ++k) {
-            const double rel = host[2 * k + 1] > 0 ? std::sqrt(host[2 * k] / host[2 * k + 1]) : 0.0;
-            rep.true_rel_res[g0 + k] = rel;
-            const bool ok = ((frozen >> k) & 1ull) != 0;
+            const bool ok = ((met >> k) & 1ull) != 0;
             rep.converged += ok;
             all_conv &= ok;
             rep.iters = std::max(rep.iters, iters[k]);

@@ -88,9 +88,10 @@ template <> struct Unit<bf16> {
     }
 };
 
-// FP16 spinors carry one FP32 scale per site and system (max |component|):
-// without it a unit-norm field on a large lattice falls below FP16's normal
-// range.  Other storage types carry no scale.
+// FP16 spinors carry one FP32 scale per site and system (the power of two
+// just above the largest |component|, see store_spinor): without it a
+// unit-norm field on a large lattice falls below FP16's normal range.  Other
+// storage types carry no scale.
 template <class S> struct HasScale { static constexpr bool value = false; };
 template <> struct HasScale<f16> { static constexpr bool value = true; };
 
@@ -522,9 +523,24 @@ __device__ inline void load_spinor(const void* base, const float* scale, long lo
     }
 }
 
+// FP16 scale of a site: the power of two 2^e with m = f 2^e, f in [0.5, 1),
+// for the largest |component| m (0 for a zero site).  Scaling by 2^-e is an
+// exponent shift (ldexp), exact and finite for every finite m, subnormal FP32
+// included, where a reciprocal 1/m would overflow below about 2.9e-39; the
+// scaled components lie in (-1, 1).
+__device__ inline int fp16_site_exponent(float m, float* scale) {
+    if (!(m > 0.f)) {
+        *scale = 0.f;
+        return 0;
+    }
+    int e;
+    (void)frexpf(m, &e);
+    *scale = ldexpf(1.0f, e);
+    return e;
+}
+
 template <class R, class S>
 __device__ inline void store_spinor(void* base, float* scale, long long V, long long s, const Spinor<R>& p) {
-    R inv = (R)1;
     if constexpr (HasScale<S>::value) {
         float m = 0.f;
 #pragma unroll
@@ -532,13 +548,24 @@ __device__ inline void store_spinor(void* base, float* scale, long long V, long 
             m = fmaxf(m, fabsf((float)p.v[i].re));
             m = fmaxf(m, fabsf((float)p.v[i].im));
         }
-        scale[s] = m;
-        inv = m > 0.f ? (R)(1.0f / m) : (R)0;
-    }
+        float sc;
+        const int e = fp16_site_exponent(m, &sc);
+        scale[s] = sc;
+        const bool zero = sc == 0.f;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        R u[4] = {inv * p.v[2 * k].re, inv * p.v[2 * k].im, inv * p.v[2 * k + 1].re, inv * p.v[2 * k + 1].im};
-        Unit<S>::store(base, (size_t)k * V + s, u);
+        for (int k = 0; k < 6; ++k) {
+            float u[4] = {(float)p.v[2 * k].re, (float)p.v[2 * k].im, (float)p.v[2 * k + 1].re,
+                          (float)p.v[2 * k + 1].im};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u[q] = zero ? u[q] * 0.f : ldexpf(u[q], -e);  // NaN stays NaN
+            Unit<S>::store(base, (size_t)k * V + s, u);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            R u[4] = {p.v[2 * k].re, p.v[2 * k].im, p.v[2 * k + 1].re, p.v[2 * k + 1].im};
+            Unit<S>::store(base, (size_t)k * V + s, u);
+        }
     }
 }
 

@@ -181,11 +181,11 @@ struct CoreResult {
     bool conv[kMaxSys];
 };
 
-// FGMRES(m) for D x = rhs, x in/out, all vectors at c.vp.  Stops per system at
-// ||rhs - D x|| <= tol ||rhs|| (residual recomputed at every restart at the
+// FGMRES(m) for D x = rhs, x in/out, all vectors at c.vp.  Stops per system k at
+// ||rhs - D x|| <= tol[k] ||rhs|| (residual recomputed at every restart at the
 // operator's precision) or when max_iters Arnoldi steps were taken.
-int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, double tol, int max_iters,
-                CoreResult& out) {
+int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const double* tol,
+                int max_iters, CoreResult& out) {
     const long long V = c.g.V;
     const int ns = c.nsys, m = K.m;
     int rc;
@@ -204,7 +204,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
         for (int k = 0; k < ns; ++k) {
             const double rel = bnorm[k] > 0 ? std::sqrt(rn2[k]) / bnorm[k] : 0.0;
             out.rel[k] = rel;
-            out.conv[k] = rel <= tol;
+            out.conv[k] = rel <= tol[k];
             frozen[k] = out.conv[k];
             any |= !out.conv[k];
         }
@@ -334,7 +334,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                 gk[j + 1] = -std::conj(snk[j]) * gk[j];
                 gk[j] = csk[j] * gk[j];
                 kdim[k] = j + 1;
-                const bool done = std::abs(gk[j + 1]) <= tol * bnorm[k] || hn == 0.0;
+                const bool done = std::abs(gk[j + 1]) <= tol[k] * bnorm[k] || hn == 0.0;
                 if (done) frozen[k] = 1;
                 all_frozen &= (bool)frozen[k];
             }
@@ -574,7 +574,8 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
             c.op = op64;
             c.op_compute = P_F64;
             Krylov K = carve_krylov(p, g, ns, m, vp, sp);
-            if ((rc = fgmres_core(c, K, bb, xx, false, tol, so->max_iters, res))) return rc;
+            std::vector<double> tols(ns, tol);
+            if ((rc = fgmres_core(c, K, bb, xx, false, tols.data(), so->max_iters, res))) return rc;
             for (int k = 0; k < ns; ++k) {
                 rep.true_rel_res[g0 + k] = res.rel[k];
                 rep.iters = std::max(rep.iters, res.iters[k]);
@@ -620,13 +621,22 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                 c.vp = P_F32;
                 c.op = op32;
                 c.op_compute = P_F32;
-                double itol = so->inner_tol;
-                // never ask the inner solve for more than the outer tolerance needs
-                for (int k = 0; k < ns; ++k)
-                    if (rn2[k] > 0 && bn2[k] > 0) itol = std::max(itol, 0.5 * tol * std::sqrt(bn2[k] / rn2[k]));
-                itol = std::min(itol, 0.5);
+                // each system's own inner tolerance: inner_tol, relaxed to what its outer
+                // tolerance still needs (never below 0.5 tol ||b_k|| / ||r_k||); a system that
+                // has already converged takes tolerance 1, which its zero start meets, so it is
+                // frozen at once and its x is left as it is
+                std::vector<double> itol(ns, so->inner_tol);
+                for (int k = 0; k < ns; ++k) {
+                    if (rep.true_rel_res[g0 + k] <= tol) {
+                        itol[k] = 1.0;
+                        continue;
+                    }
+                    if (rn2[k] > 0 && bn2[k] > 0)
+                        itol[k] = std::max(itol[k], 0.5 * tol * std::sqrt(bn2[k] / rn2[k]));
+                    itol[k] = std::min(itol[k], 0.5);
+                }
                 if ((rc = hcheck(blas_zero(c32.data, internal_bytes(g, ns, P_F32), st), "zero"))) return rc;
-                if ((rc = fgmres_core(c, K, r32, c32, true, itol, so->max_iters - maxit, res))) return rc;
+                if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res))) return rc;
                 for (int k = 0; k < ns; ++k) iters[k] += res.iters[k];
                 if ((rc = hcheck(blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st),
                                  "accumulate")))
@@ -644,6 +654,8 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
         if ((rc = hcheck(launch_spinor_export(g, xx, xcan, st), "export x"))) return rc;
         if ((rc = hcheck(hipStreamSynchronize(st), "export"))) return rc;
     }
+    for (int a = 0; a < 4; ++a) rep.block_dims[a] = bd[a];
+    rep.sys_tile = c.sys_tile;
     rep.t_sap = c.t_sap;
     rep.sap_cycles = c.sap_cycles;
     rep.sap_sys_cycles = c.sap_sys_cycles;

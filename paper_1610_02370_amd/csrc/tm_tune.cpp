@@ -169,6 +169,10 @@ Timing time_config(DeviceState* ds, const tm_geom* geom, const void* U, double k
 }  // namespace
 
 bool tune_lookup(const tm_geom* geom, int storage, int n_cycles, int mr_iters, int eo, int block[4], int* sys_tile) {
+    // solves consult a cache only when the caller names one: the same call then gives the
+    // same block shape (and preconditioner) whatever the working directory holds
+    const char* named = std::getenv("TM_TUNE_CACHE");
+    if (!named || !*named) return false;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     FILE* f = std::fopen(cache_path().c_str(), "r");
     if (!f) return false;

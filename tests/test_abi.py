@@ -119,3 +119,42 @@ def test_two_level_setup_rejects_bad_input_on_host():
     g2 = tm.make_geom((8, 8, 8, 8), [0.01, -0.01])
     assert L.tm_mg_setup(ctypes.byref(g2), dummy, 0.15, 1.0, ctypes.byref(p), dummy, ctypes.byref(h),
                          ctypes.byref(o)) == -1
+
+
+def test_binding_checks_buffer_sizes_before_any_library_call():
+    # a buffer smaller or larger than dims and the number of systems imply is refused on the host (a kernel
+    # would otherwise read or write past it); the tensors here are host tensors, so a call whose sizes are
+    # right stops at the device check instead
+    import torch
+
+    dims = (4, 4, 4, 8)
+    V = 4 * 4 * 4 * 8
+    U = torch.zeros((V, 4, 3, 3), dtype=torch.complex128)
+    psi = torch.zeros((2, V, 4, 3), dtype=torch.complex128)
+    with pytest.raises(ValueError, match="U has"):
+        tm.tm_dirac_apply(dims, U[: V // 2], psi, 0.15, [0.1, -0.1], 1.0, stream=False)
+    with pytest.raises(ValueError, match="psi has"):
+        tm.tm_dirac_apply(dims, U, psi, 0.15, [0.1, -0.1, 0.2], 1.0, stream=False)
+    with pytest.raises(ValueError, match="b has"):
+        tm.tm_sap_smooth(dims, U, psi[:1], psi[1:].clone(), 0.15, [0.1, -0.1], 1.0, (2, 2, 2, 2), 1, 1, stream=False)
+    with pytest.raises(ValueError, match="x has"):
+        tm.tm_fgmres_solve(dims, U, psi, psi[:1].clone(), 0.15, [0.1, -0.1], 1.0, 1e-10, stream=False)
+    with pytest.raises(ValueError, match="b has"):
+        tm.tm_cg_solve(dims, U, psi, psi.clone(), 0.15, [0.1], 1.0, 1e-10, stream=False)
+    need = tm.tm_spinor_bytes(dims, 2, "f16", layout_block=(2, 2, 2, 2))
+    small = torch.zeros(need - 1, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="internal holds"):
+        tm.tm_spinor_import(dims, psi, small, storage="f16", layout_block=(2, 2, 2, 2), stream=False)
+    with pytest.raises(ValueError, match="b holds"):
+        tm.tm_sap_smooth(dims, U, small, small, 0.15, [0.1, -0.1], 1.0, (2, 2, 2, 2), 1, 1, storage="f16",
+                         io="internal", stream=False)
+    with pytest.raises(ValueError, match="canon has"):
+        tm.tm_spinor_import_range(dims, psi[:, : V // 2].contiguous(), torch.zeros(need, dtype=torch.uint8), 2, 0,
+                                  storage="f16",
+                                  layout_block=(2, 2, 2, 2), stream=False)
+    # sizes right: only the device check is left
+    with pytest.raises(ValueError, match="live on the GPU"):
+        tm.tm_dirac_apply(dims, U, psi, 0.15, [0.1, -0.1], 1.0, stream=False)
+    with pytest.raises(ValueError, match="live on the GPU"):
+        tm.tm_spinor_import(dims, psi, torch.zeros(need, dtype=torch.uint8), storage="f16",
+                            layout_block=(2, 2, 2, 2), stream=False)

@@ -1,11 +1,7 @@
 """GPU operator parity: tm_dirac_apply (HIP) against the FP64 CPU oracle.
 
-Tolerances (norm-wise relative error per application):
-  f64  1e-13  rounding of reordered FP64 sums only
-  f32  1e-5   the per-application bound for FP32 storage and compute
-  f16  4e-3   links and spinors rounded to FP16 (2^-11 relative to the site
-              maximum / link entry), about 8 hops' worth of such errors
-  bf16 2.5e-2 same with BF16's 2^-9 unit roundoff
+Each application is checked norm-wise and per site against the error model of
+gpu_util (f64 1e-13, f32 1e-5, f16 2e-3, bf16 1.5e-2).
 """
 import numpy as np
 import pytest
@@ -14,11 +10,12 @@ import oracle
 import paper_1610_02370_amd as tm
 from paper_1610_02370_amd import synth
 
-from gpu_util import announce, dev, host, rel_err
+from gpu_util import TOL as ERR_TOL
+from gpu_util import announce, check_close, dev, host, rel_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-13, "f32": 1e-5, "f16": 4e-3, "bf16": 2.5e-2}
+TOL = ERR_TOL["dirac"]
 
 CASES = [
     # dims, eps, kappa, mus, csw, antiperiodic; dims chosen so tiles are mixed
@@ -50,7 +47,7 @@ def test_dirac_matches_oracle(fields, case, prec):
     out = tm.tm_dirac_apply(dims, dev(U), dev(psi), kappa, mus, csw, storage=prec, antiperiodic_t=ap)
     got = host(out)
     for i in range(len(mus)):
-        assert rel_err(got[i], ref[i]) < TOL[prec], (i, rel_err(got[i], ref[i]))
+        check_close(got[i], ref[i], "dirac", prec, f"case {case} {dims} system {i}")
 
 
 def test_dirac_internal_io_roundtrip(fields):
@@ -72,6 +69,36 @@ def test_dirac_internal_io_roundtrip(fields):
         tm.tm_spinor_export(dims, a, back, storage=prec)
         if prec == "f64":
             assert np.array_equal(host(back), psi)
+
+
+def test_fp16_scale_subnormal_and_zero_sites():
+    # FP16 storage scales each site by a power of two: a site whose largest component is an FP32
+    # subnormal (about 1e-40, where a reciprocal scale would overflow) and an all-zero site must
+    # come back finite, the first within FP16 rounding of its own size, the second exactly zero
+    import torch
+
+    dims = (4, 4, 4, 4)
+    rng = np.random.default_rng(11)
+    psi = rng.normal(size=(1, 256, 4, 3)) + 1j * rng.normal(size=(1, 256, 4, 3))
+    psi[0, 1] *= 1e-40          # FP32 subnormal band
+    psi[0, 2] *= 3e-39          # just below the smallest normal FP32 number
+    psi[0, 3] = 0.0             # zero site
+    psi[0, 4] *= 1e30           # large site: FP16 alone would overflow
+    announce("fp16 storage: subnormal, zero and large sites")
+    nbytes = tm.tm_spinor_bytes(dims, 1, "f16")
+    a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    tm.tm_spinor_import(dims, dev(psi), a, storage="f16")
+    back = host(tm.tm_spinor_export(dims, a, dev(np.zeros_like(psi)), storage="f16"))
+    assert np.isfinite(back).all()
+    assert np.array_equal(back[0, 3], psi[0, 3])
+    for s in range(256):
+        if s == 3:
+            continue
+        m = np.abs(np.concatenate([psi[0, s].real.ravel(), psi[0, s].imag.ravel()])).max()
+        err = np.abs(np.concatenate([(back[0, s] - psi[0, s]).real.ravel(), (back[0, s] - psi[0, s]).imag.ravel()]))
+        # one FP16 rounding (2^-11 of the power-of-two scale, which is < 2 m), plus the FP32 subnormal
+        # spacing 2^-149 for the tiny sites
+        assert err.max() <= 2.0 ** -11 * 2 * m + 2.0 ** -149, (s, err.max(), m)
 
 
 def test_dirac_gamma5_hermiticity_on_gpu(fields):

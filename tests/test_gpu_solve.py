@@ -164,3 +164,30 @@ def test_16x16x16x16_twelve_sources_defect_correction():
     for k in (0, 4, 11):
         r = b[k].reshape(-1, 4, 3) - op.apply(xg[k])
         assert np.linalg.norm(r) / np.linalg.norm(b[k]) <= TOL * RES_SLACK
+
+
+def test_defect_correction_tolerance_per_system(cfg_8888):
+    # Each system's inner solve runs to its own tolerance: a system started from its converged
+    # solution next to one started from zero leaves the first untouched and gives the second the
+    # same iterations as a solve of it alone (a group-wide tolerance would let the converged system
+    # relax the other's inner solves).
+    dims, kappa, mu, csw, U, op = cfg_8888
+    announce("defect correction: converged system next to a fresh one")
+    b = synth.all_point_sources(dims)[:2]
+    mus = [mu, -mu]
+    kw = dict(storage="f32", form="defect_correction", restart=8, n_cycles=3, mr_iters=4, block_dims=(4, 4, 4, 4))
+    x = dev(np.zeros_like(b))
+    rc, rep_pair = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, mus, csw, TOL, **kw)
+    assert rc == 0, rep_pair
+    xs = host(x)
+    alone = dev(np.zeros_like(b[1:]))
+    rc, rep_alone = tm.tm_fgmres_solve(dims, dev(U), dev(b[1:]), alone, kappa, mus[1:], csw, TOL, **kw)
+    assert rc == 0, rep_alone
+    x = dev(np.stack([xs[0], np.zeros_like(xs[1])]))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, mus, csw, TOL, **kw)
+    assert rc == 0, rep
+    got = host(x)
+    assert np.array_equal(got[0], xs[0])
+    assert rep["iters"] == rep_alone["iters"] and rep["outer"] == rep_alone["outer"], (rep, rep_alone)
+    assert np.abs(got[1] - host(alone)[0]).max() <= 1e-12 * np.abs(got[1]).max()
+    check_solutions(op, dims, b, got, mus, TOL)
