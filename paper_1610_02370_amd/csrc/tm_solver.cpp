@@ -183,9 +183,10 @@ struct CoreResult {
 
 // FGMRES(m) for D x = rhs, x in/out, all vectors at c.vp.  Stops per system k at
 // ||rhs - D x|| <= tol[k] ||rhs|| (residual recomputed at every restart at the
-// operator's precision) or when max_iters Arnoldi steps were taken.
+// operator's precision) or when max_iters Arnoldi steps were taken.  Systems
+// in the `skip` mask are frozen from the start and keep x as it is.
 int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const double* tol,
-                int max_iters, CoreResult& out) {
+                int max_iters, CoreResult& out, unsigned long long skip = 0) {
     const long long V = c.g.V;
     const int ns = c.nsys, m = K.m;
     int rc;
@@ -204,7 +205,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
         for (int k = 0; k < ns; ++k) {
             const double rel = bnorm[k] > 0 ? std::sqrt(rn2[k]) / bnorm[k] : 0.0;
             out.rel[k] = rel;
-            out.conv[k] = rel <= tol[k];
+            out.conv[k] = rel <= tol[k] || ((skip >> k) & 1ull);
             frozen[k] = out.conv[k];
             any |= !out.conv[k];
         }
@@ -623,20 +624,29 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                 c.op_compute = P_F32;
                 // each system's own inner tolerance: inner_tol, relaxed to what its outer
                 // tolerance still needs (never below 0.5 tol ||b_k|| / ||r_k||); a system that
-                // has already converged takes tolerance 1, which its zero start meets, so it is
-                // frozen at once and its x is left as it is
+                // has already converged is skipped (frozen in every restart cycle, its x left
+                // as it is)
                 std::vector<double> itol(ns, so->inner_tol);
+                unsigned long long skip = 0;
                 for (int k = 0; k < ns; ++k) {
                     if (rep.true_rel_res[g0 + k] <= tol) {
-                        itol[k] = 1.0;
+                        skip |= 1ull << k;
                         continue;
                     }
                     if (rn2[k] > 0 && bn2[k] > 0)
                         itol[k] = std::max(itol[k], 0.5 * tol * std::sqrt(bn2[k] / rn2[k]));
                     itol[k] = std::min(itol[k], 0.5);
                 }
+                if (verbose()) {
+                    for (int k = 0; k < ns; ++k)
+                        std::fprintf(stderr, "[tm]   system %d: true residual %.6e, inner tolerance %.3e%s\n",
+                                     g0 + k, rep.true_rel_res[g0 + k], itol[k],
+                                     ((skip >> k) & 1ull) ? " (converged, skipped)" : "");
+                    std::fflush(stderr);
+                }
                 if ((rc = hcheck(blas_zero(c32.data, internal_bytes(g, ns, P_F32), st), "zero"))) return rc;
-                if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res))) return rc;
+                if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res, skip)))
+                    return rc;
                 for (int k = 0; k < ns; ++k) iters[k] += res.iters[k];
                 if ((rc = hcheck(blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st),
                                  "accumulate")))
