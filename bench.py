@@ -122,7 +122,7 @@ def sap_flops_per_site_cycle(nsys: int, mr: int = MR_ITERS) -> float:
 
 
 SAP_SOURCES = ("paper_1610_02370_amd/csrc/tm_sap.hip", "paper_1610_02370_amd/csrc/tm_device.h",
-               "paper_1610_02370_amd/csrc/tm_internal.h")
+               "paper_1610_02370_amd/csrc/tm_internal.h", "paper_1610_02370_amd/csrc/tm_sap_index.h")
 
 
 def sap_source_hash() -> str:

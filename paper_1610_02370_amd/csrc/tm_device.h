@@ -172,7 +172,7 @@ __host__ __device__ inline long long coords_site(const Geo& g, const int c[4]) {
 // sites.  In-tile neighbours are s plus a fixed stride; across a tile face the
 // local coordinate wraps and the tile index steps (with the lattice's
 // periodic wrap).
-__device__ inline void tiled_neighbours(const Geo& g, long long s, int nf[4], int nbk[4], unsigned* wrap,
+__host__ __device__ inline void tiled_neighbours(const Geo& g, long long s, int nf[4], int nbk[4], unsigned* wrap,
                                         int* parity) {
     const unsigned su = (unsigned)s;
     const unsigned Vb = (unsigned)g.Vb;

@@ -13,6 +13,7 @@
 #include <cstdlib>
 
 #include "tm_internal.h"
+#include "tm_sap_index.h"
 
 namespace tmsap {
 
@@ -933,62 +934,24 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
     const Geo& g = a.g;
     const int l = threadIdx.x;  // 256 threads, all sites active
 
-    const int half3 = g.nb[3] >> 1;
-    int j = blockIdx.x;
-    const int k3 = j % half3;
-    j /= half3;
-    const int B2 = j % g.nb[2];
-    j /= g.nb[2];
-    const int B1 = j % g.nb[1];
-    const int B0 = j / g.nb[1];
-    const int B3 = 2 * k3 + ((a.colour + B0 + B1 + B2) & 1);
-    const int Bc[4] = {B0, B1, B2, B3};
-    const long long blk = (((long long)B0 * g.nb[1] + B1) * g.nb[2] + B2) * g.nb[3] + B3;
-    const long long s = blk * 256 + l;
-    const int Lc[4] = {l >> 6, (l >> 4) & 3, (l >> 2) & 3, l & 3};
-
+    // block, site, in-block neighbours and halo duty (tm_sap_index.h, checked on the host)
+    S44Site ix;
+    s44_setup(g, a.colour, blockIdx.x, l, ix);
+    const long long s = ix.s;
+    int Lc[4], str[4], fsrc[4], bsrc[4];
     bool fin[4], bin[4];
-    int str[4], fsrc[4], bsrc[4];
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const int ax = axis_of(mu);
-        str[mu] = 1 << (2 * (3 - ax));
-        fin[mu] = Lc[ax] < 3;
-        bin[mu] = Lc[ax] > 0;
-        int p = 0;
-        for (int q = 0; q < 4; ++q)
-            if (q != ax) p = p * 4 + Lc[q];
-        // forward source: in-block neighbour or the upper-face halo entry; backward likewise
-        fsrc[mu] = fin[mu] ? l + str[mu] : ax * 64 + p;
-        bsrc[mu] = bin[mu] ? l - str[mu] : ax * 64 + p;
+    for (int q = 0; q < 4; ++q) {
+        Lc[q] = ix.L[q];
+        str[q] = ix.str[q];
+        fsrc[q] = ix.fsrc[q];
+        bsrc[q] = ix.bsrc[q];
+        fin[q] = ix.fin[q];
+        bin[q] = ix.bin[q];
     }
-
-    // this thread's halo duties: axis = wave, position = lane
-    const int wax = __builtin_amdgcn_readfirstlane(l >> 6);
-    const int hp = l & 63;
-    int up_site, dn_site;
-    bool up_wrap, dn_wrap;  // the staged hop crosses the lattice boundary
-    {
-        int c[4];
-        int p = hp;
-        for (int q = 3; q >= 0; --q) {
-            if (q == wax) continue;
-            c[q] = p & 3;
-            p >>= 2;
-        }
-        for (int q = 0; q < 4; ++q)
-            if (q != wax) c[q] += Bc[q] * 4;
-        c[wax] = Bc[wax] * 4 + 4;
-        bool wrap = false;
-        if (c[wax] >= g.d[wax]) { c[wax] -= g.d[wax]; wrap = true; }
-        up_site = (int)coords_site(g, c);
-        up_wrap = wrap;
-        c[wax] = Bc[wax] * 4 - 1;
-        wrap = false;
-        if (c[wax] < 0) { c[wax] += g.d[wax]; wrap = true; }
-        dn_site = (int)coords_site(g, c);
-        dn_wrap = wrap;
-    }
+    const int wax = __builtin_amdgcn_readfirstlane(ix.wax);
+    const int up_site = (int)ix.up_site, dn_site = (int)ix.dn_site;
+    const bool up_wrap = ix.up_wrap, dn_wrap = ix.dn_wrap;
     const int wmu = wax == 0 ? 0 : 4 - wax;
     Link<float> Ldn;  // U_mu(site below the lower face)
     load_link<float, G>(a.links, g.V, dn_site, wmu, Ldn);
