@@ -153,6 +153,29 @@ TM_API int tm_dirac_apply(const tm_geom* geom, const void* U, const void* psi, v
 TM_API int tm_sap_smooth(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw,
                   const int block_dims[4], int n_cycles, int mr_iters, const tm_opts* opts);
 
+/*
+ * tm_sap_smooth for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and errors as tm_sap_smooth (sap_eo must be 0), and the
+ * same kernels; it calls no hipMalloc, hipFree or other allocating routine.
+ * The gauge copy, the clover term, the internal copies of canonical b and x
+ * and the validation flags live in a fixed device array of
+ * TM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; the gauge copy is rebuilt and validated on every
+ * call (one stream synchronisation).  A call whose links + clover (+ b and x
+ * for canonical io) need more than the array returns TM_ERR_ARG before any
+ * device work: at FP32 storage that is V * (480 + 192 nsys) bytes with
+ * canonical buffers, V * 480 with internal ones (FP64: twice that; FP16 /
+ * BF16: V * (384 + 104 nsys)), so e.g. 16^4 sites with 2 systems at FP32.
+ * Every call on a device shares that device's array and leaves its contents
+ * there: calls that overlap on one device race.  tm_init sets the array up
+ * for the current device; otherwise the first call on a device does.
+ */
+#define TM_NOALLOC_SCRATCH_BYTES (64ull * 1024ull * 1024ull)
+TM_API int tm_sap_smooth_noalloc(const tm_geom* geom, const void* U, const void* b, void* x, double kappa,
+                                 double c_sw, const int block_dims[4], int n_cycles, int mr_iters,
+                                 const tm_opts* opts);
+
 /* ---------------------------------------------------------------- solves */
 #define TM_SOLVE_FLEXIBLE 0          /* FP64 FGMRES, SAP at opts->storage */
 #define TM_SOLVE_DEFECT_CORRECTION 1 /* FP64 residual loop around an FP32 FGMRES+SAP solve */

@@ -33,6 +33,7 @@ EXPORTS = (
     "tm_spinor_export", "tm_spinor_import_range", "tm_spinor_export_range", "tm_autotune_sap", "tm_cg_solve",
     "tm_mg_params_default", "tm_mg_setup", "tm_mg_destroy", "tm_mg_get_info", "tm_mg_export", "tm_mg_restrict",
     "tm_mg_prolong", "tm_mg_coarse_apply", "tm_mg_coarse_solve", "tm_mg_precond", "tm_probe_fp32_fma",
+    "tm_sap_smooth_noalloc",
 )
 
 
@@ -109,6 +110,7 @@ def lib():
         L.tm_dirac_apply.argtypes = [P(Geom), vp, vp, vp, ctypes.c_double, ctypes.c_double, P(Opts)]
         L.tm_sap_smooth.argtypes = [P(Geom), vp, vp, vp, ctypes.c_double, ctypes.c_double, P(ctypes.c_int),
                                     ctypes.c_int, ctypes.c_int, P(Opts)]
+        L.tm_sap_smooth_noalloc.argtypes = L.tm_sap_smooth.argtypes
         L.tm_fgmres_solve.argtypes = [P(Geom), vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       P(SolverOpts), P(Opts), P(Report)]
         L.tm_spinor_bytes.argtypes = [P(Geom), P(Opts)]
@@ -280,6 +282,21 @@ def tm_sap_smooth(dims, U, b, x, kappa: float, mu, c_sw: float, block_dims, n_cy
     """x <- SAP(b, x): n_cycles red-black cycles, mr_iters MR steps per block (x is in/out).
 
     eo: even-odd preconditioned block solves (MR on the odd-site Schur complement)."""
+    return _sap(lib().tm_sap_smooth, dims, U, b, x, kappa, mu, c_sw, block_dims, n_cycles, mr_iters, storage,
+                antiperiodic_t, stream, io, theta, mu_shift, gauge_tag, sys_tile, eo)
+
+
+def tm_sap_smooth_noalloc(dims, U, b, x, kappa: float, mu, c_sw: float, block_dims, n_cycles: int, mr_iters: int,
+                          *, storage: str = "f64", antiperiodic_t: bool = False, stream=None, io: str = "canonical",
+                          theta=None, mu_shift=None, sys_tile: int = 0):
+    """tm_sap_smooth without device allocation: the library's fixed per-GPU scratch array holds the
+    gauge copy, clover and internal b / x (TMError TM_ERR_ARG when the problem does not fit)."""
+    return _sap(lib().tm_sap_smooth_noalloc, dims, U, b, x, kappa, mu, c_sw, block_dims, n_cycles, mr_iters,
+                storage, antiperiodic_t, stream, io, theta, mu_shift, 0, sys_tile, False)
+
+
+def _sap(fn, dims, U, b, x, kappa, mu, c_sw, block_dims, n_cycles, mr_iters, storage, antiperiodic_t, stream, io,
+         theta, mu_shift, gauge_tag, sys_tile, eo):
     g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts(storage, stream=stream, io=io, layout_block=block_dims, gauge_tag=gauge_tag)
     o.sys_tile = int(sys_tile)
@@ -294,8 +311,8 @@ def tm_sap_smooth(dims, U, b, x, kappa: float, mu, c_sw: float, block_dims, n_cy
         n = _spinor_bytes(g, o)
         _expect_bytes(b, n, "b")
         _expect_bytes(x, n, "x")
-    _check(lib().tm_sap_smooth(ctypes.byref(g), _ptr(U), _ptr(b), _ptr(x), float(kappa), float(c_sw), bd,
-                               int(n_cycles), int(mr_iters), ctypes.byref(o)))
+    _check(fn(ctypes.byref(g), _ptr(U), _ptr(b), _ptr(x), float(kappa), float(c_sw), bd, int(n_cycles),
+              int(mr_iters), ctypes.byref(o)))
     return x
 
 

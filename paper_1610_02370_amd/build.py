@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtmsap.so")
 
-SOURCES = ["tm_layout.hip", "tm_dirac.hip", "tm_sap.hip", "tm_blas.hip", "tm_api.cpp", "tm_solver.cpp", "tm_tune.cpp", "tm_cg.hip", "tm_cg_solver.cpp", "tm_mg.hip", "tm_mg_api.cpp", "tm_probe.hip"]
+SOURCES = ["tm_layout.hip", "tm_dirac.hip", "tm_sap.hip", "tm_blas.hip", "tm_api.cpp", "tm_solver.cpp", "tm_tune.cpp", "tm_cg.hip", "tm_cg_solver.cpp", "tm_mg.hip", "tm_mg_api.cpp", "tm_probe.hip", "tm_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -428,7 +428,8 @@ void tm_opts_default(tm_opts* o) {
 
 int tm_init(void) {
     int err = TM_OK;
-    return device_state(&err) ? TM_OK : err;
+    if (!device_state(&err)) return err;
+    return noalloc_scratch(nullptr);
 }
 
 int tm_finalize(void) {

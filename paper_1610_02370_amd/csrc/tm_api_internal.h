@@ -81,6 +81,10 @@ int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf
 int run_dirac(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu, int nsys,
               Prec compute, hipStream_t st);
 
+// Device address of the current device's fixed scratch array of the no-allocation entry point
+// (tm_noalloc.hip), looked up once per device; out may be NULL (set-up only).
+int noalloc_scratch(void** out);
+
 // ---- two-level method (tm_mg_api.cpp)
 // z = the handle's two-level preconditioner applied to r: FP32 internal fields
 // of ns systems tiled by the handle's aggregates (the handle holds its gauge copy).
