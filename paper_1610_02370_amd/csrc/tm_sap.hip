@@ -11,6 +11,7 @@
 // independent; the colour-to-colour dependency is the launch boundary.
 #include <cstddef>
 #include <cstdlib>
+#include <type_traits>
 
 #include "tm_internal.h"
 #include "tm_sap_index.h"
@@ -906,7 +907,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
 // wave).  Every site then takes exactly one forward and one backward hop per
 // direction from either the in-block exchange or these halo buffers, so the
 // residual b - D x costs one full stencil with no idle lanes for the faces.
-struct S44Shared {
+struct alignas(16) S44Shared {
     float xs[24 * kV2];      // in-block spinors, [6][site] float4
     float gb[4 * 12 * kV2];  // in-block backward products, [mu][3][site] float4
     float hf[24 * kV2];      // upper-face halo spinors, [6][axis*64 + pos] float4
@@ -915,6 +916,48 @@ struct S44Shared {
 };
 static_assert(offsetof(S44Shared, xs) == offsetof(V2Shared, xs) && offsetof(S44Shared, gb) == offsetof(V2Shared, gb),
               "the exchange helpers address S44Shared through its V2Shared prefix");
+
+// With FP32 storage the next system's b and x of the block's own sites are
+// copied into LDS by the memory unit while the current system's MR steps run
+// (global_load_lds, 16 bytes per lane, no registers), in the field layout
+// [6 units][site] float4.  Each wave copies and later reads only its own 64
+// sites, so no workgroup barrier guards the buffers.
+struct alignas(16) S44SharedPrefetch : S44Shared {
+    float pb[24 * kV2];  // next system's b
+    float px[24 * kV2];  // next system's x
+};
+static_assert(sizeof(S44SharedPrefetch) <= 160 * 1024, "LDS of one workgroup");
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Issues this wave's copies of system sys: b at the block's sites, x there when
+// `with_x`, and when `with_face` the x of the site just above the block's upper
+// face that this lane stages (into hf; the staging lane applies the boundary
+// phase once the copy has landed).
+__device__ inline void s44_prefetch(S44SharedPrefetch& sm, const SapArgs& a, int sys, int site, int l, bool with_x,
+                                    bool with_face, int up_site) {
+    const int w = __builtin_amdgcn_readfirstlane(l >> 6);
+    // uniform base per unit + one 32-bit byte offset per lane (a system's FP32 field is under 4 GiB)
+    const size_t stride = (size_t)6 * a.g.V * 16;
+    const char* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
+    const char* xx = reinterpret_cast<const char*>(a.x) + sys * stride;
+    const unsigned own_off = (unsigned)site * 16u;
+    const unsigned face_off = (unsigned)up_site * 16u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const size_t unit = (size_t)k * a.g.V * 16;
+        __builtin_amdgcn_global_load_lds(bb + unit + own_off, (lds_void*)&sm.pb[(k * kV2 + 64 * w) * 4], 16, 0, 0);
+        if (with_x)
+            __builtin_amdgcn_global_load_lds(xx + unit + own_off, (lds_void*)&sm.px[(k * kV2 + 64 * w) * 4], 16, 0,
+                                             0);
+        if (with_face)
+            __builtin_amdgcn_global_load_lds(xx + unit + face_off, (lds_void*)&sm.hf[(k * kV2 + 64 * w) * 4], 16, 0,
+                                             0);
+    }
+}
+
+// s_waitcnt lgkmcnt(0) with the other counters left free (gfx9 encoding)
+constexpr int kWaitLgkm0 = 0xC07F;
 
 template <int MU>
 __device__ inline void s44_stage_backward(const Link<float>& L, const Spinor<float>& p, float sg, float* hb, int j) {
@@ -929,7 +972,9 @@ __device__ inline void s44_stage_backward(const Link<float>& L, const Spinor<flo
 
 template <class S, class G, class C>
 __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
-    __shared__ S44Shared sm;
+    constexpr bool kPre = std::is_same<S, float>::value;  // prefetch the next system's b and x
+    typedef typename std::conditional<kPre, S44SharedPrefetch, S44Shared>::type Shared;
+    __shared__ Shared sm;
     V2Shared& sx = *reinterpret_cast<V2Shared*>(&sm);
     const Geo& g = a.g;
     const int l = threadIdx.x;  // 256 threads, all sites active
@@ -953,6 +998,15 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
     const int up_site = (int)ix.up_site, dn_site = (int)ix.dn_site;
     const bool up_wrap = ix.up_wrap, dn_wrap = ix.dn_wrap;
     const int wmu = wax == 0 ? 0 : 4 - wax;
+    const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
+    const int sys_begin = blockIdx.y * a.sys_tile;
+    const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
+    const bool own = !a.own_zero;
+    const bool halo = !(a.own_zero && a.halo_zero);
+    if constexpr (kPre) {
+        if (sys_begin < sys_end) s44_prefetch(sm, a, sys_begin, (int)s, l, own, halo, up_site);
+    }
+
     Link<float> Ldn;  // U_mu(site below the lower face)
     load_link<float, G>(a.links, g.V, dn_site, wmu, Ldn);
 
@@ -964,12 +1018,6 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
 #pragma unroll
     for (int i = 0; i < 72; ++i) A.a[i] *= -2.f;
 
-    const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
-    const int sys_begin = blockIdx.y * a.sys_tile;
-    const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
-    const bool own = !a.own_zero;
-    const bool halo = !(a.own_zero && a.halo_zero);
-
     for (int sys = sys_begin; sys < sys_end; ++sys) {
         const float mu_tw = (float)(a.mu[sys] + g.mu_shift[(Lc[0] + Lc[1] + Lc[2] + Lc[3]) & 1]);
         const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
@@ -978,19 +1026,38 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
         float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
 
         Spinor<float> r, e;
-        load_spinor<float, S>(bb, bsc, g.V, s, r);
 #pragma unroll
         for (int i = 0; i < 12; ++i) e.v[i] = cmk(0.f, 0.f);
+        if constexpr (kPre) {
+            // this system's b, x and upper-face x were copied into LDS during the previous one
+            __builtin_amdgcn_s_waitcnt(0);
+            v2_get_spinor(sm.pb, l, r);
+            if (own) v2_get_spinor(sm.px, l, e);
+            if (halo && up_wrap) {  // the copied face spinor still lacks the boundary phase
+                Spinor<float> hu;
+                v2_get_spinor(sm.hf, l, hu);
+                apply_bc(g, wmu, +1, hu);
+                v2_put_spinor(sm.hf, l, hu);
+            }
+        } else {
+            load_spinor<float, S>(bb, bsc, g.V, s, r);
+        }
         if (halo) {
             // ---- r = b - D x: one full stencil from the in-block exchange and the halo buffers
-            if (own) load_spinor<float, S>(xx, xsc, g.V, s, e);
-            Spinor<float> hu, hd;
-            load_spinor<float, S>(xx, xsc, g.V, up_site, hu);
-            load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
-            v2_push(sx, l, true, fin, Uo, e);
-            if (up_wrap) apply_bc(g, wmu, +1, hu);
+            Spinor<float> hd;
+            if constexpr (kPre) {
+                load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
+                v2_push(sx, l, true, fin, Uo, e);
+            } else {
+                if (own) load_spinor<float, S>(xx, xsc, g.V, s, e);
+                Spinor<float> hu;
+                load_spinor<float, S>(xx, xsc, g.V, up_site, hu);
+                load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
+                v2_push(sx, l, true, fin, Uo, e);
+                if (up_wrap) apply_bc(g, wmu, +1, hu);
+                v2_put_spinor(sm.hf, l, hu);
+            }
             if (dn_wrap) apply_bc(g, wmu, -1, hd);
-            v2_put_spinor(sm.hf, l, hu);
             switch (wax) {
                 case 0: s44_stage_backward<0>(Ldn, hd, 1.f, sm.hb, l); break;
                 case 1: s44_stage_backward<3>(Ldn, hd, 1.f, sm.hb, l); break;
@@ -1035,6 +1102,12 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] + 0.5f * acc.v[i];
             __syncthreads();
+        }
+        if constexpr (kPre) {
+            // every wave has read this system's pb, px (its own sites) and hf (after the barrier
+            // above): the next system's copies may land during the MR steps
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+            if (sys + 1 < sys_end) s44_prefetch(sm, a, sys + 1, (int)s, l, own, halo, up_site);
         }
 
         // ---- minimal residual on D_BB with q = -2 D_BB rho

@@ -69,5 +69,11 @@ def check_close(got, ref, kind, prec, label, tol=None):
     return ne, se
 
 
+def log_solve(label, prec, oracle_rel, tol, iters=None):
+    """Records a solve's true relative residual as recomputed by the oracle (the bound is tol)."""
+    log_error({"kind": "solve", "prec": prec, "case": label, "norm": float(oracle_rel), "site": None, "bound": tol,
+               "iters": iters})
+
+
 def announce(msg):
     print(msg, flush=True)

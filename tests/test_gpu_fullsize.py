@@ -26,7 +26,7 @@ import paper_1610_02370_amd as tm
 from paper_1610_02370_amd import synth
 
 from gpu_util import TOL as ERR_TOL
-from gpu_util import announce, check_close, host, rel_err
+from gpu_util import announce, check_close, host, log_solve, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -229,7 +229,9 @@ def test_solve_32x64_pm_mu_whole_lattice_residual(lattice_32x64):
     op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), 0.0, csw)
     for k, m in enumerate(mus):
         r = b[k].reshape(-1, 4, 3) - op.with_mu(m).apply(xg[k])
-        assert np.linalg.norm(r) / np.linalg.norm(b[k]) <= 1.05e-10
+        rel = np.linalg.norm(r) / np.linalg.norm(b[k])
+        log_solve(f"32^3x64 +-mu flexible system {k} (oracle, whole lattice)", "f32", rel, 1e-10, rep["iters"])
+        assert rel <= 1.05e-10
     del x
     tm.tm_finalize()
     torch.cuda.empty_cache()
@@ -341,6 +343,10 @@ def test_solve_64x128_pm_mu_16bit_defect_correction(lattice_64x128, prec):
     sites = [int(lex(dims, np.mod(c, dims))) for c in near] + [int(v) for v in rng.integers(0, V, 12)]
     worst = sampled_residual_check(dims, U, x, kappa, csw, mus, 0, [(0, 0), (0, 0)], sites)
     announce(f"  oracle residual at {len(sites)} sampled sites: max {worst:.2e}")
+    for k in range(2):
+        log_solve(f"64^3x128 +-mu defect correction system {k} (library FP64 residual; oracle at sampled sites "
+                  f"max {worst:.2e}; group {rep['group']}, {rep['t_total']:.1f} s)", prec, rep["true_rel_res"][k],
+                  1e-10, rep["iters"])
     del Ud, b, x
     tm.tm_finalize()
     torch.cuda.empty_cache()

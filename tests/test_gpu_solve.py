@@ -14,7 +14,7 @@ import oracle
 import paper_1610_02370_amd as tm
 from paper_1610_02370_amd import synth
 
-from gpu_util import announce, dev, host
+from gpu_util import announce, dev, host, log_solve
 
 pytestmark = pytest.mark.gpu
 
@@ -45,6 +45,7 @@ def test_4x4x4x4_solve_against_dense_lu(cfg_4444, form, storage):
     xg = host(x)[0].ravel()
     r = b[0].ravel() - op.apply(xg)
     rel = np.linalg.norm(r) / np.linalg.norm(b)
+    log_solve(f"4^4 {form}", storage, rel, TOL, rep["iters"])
     assert rel <= TOL * RES_SLACK, rel
     assert abs(rep["true_rel_res"][0] - rel) <= 0.05 * TOL
     # sigma_min >= |mu| bounds the error; the dense solution confirms it
@@ -71,10 +72,11 @@ def cfg_8888():
     return dims, kappa, mu, csw, U, op
 
 
-def check_solutions(op, dims, b, x, mus, tol):
+def check_solutions(op, dims, b, x, mus, tol, label="", prec=""):
     for k, m in enumerate(mus):
         r = b[k].ravel() - op.with_mu(m).apply(x[k].ravel())
         rel = np.linalg.norm(r) / np.linalg.norm(b[k])
+        log_solve(f"{label} {dims} system {k}", prec, rel, tol)
         assert rel <= tol * RES_SLACK, (k, rel)
 
 
@@ -89,7 +91,7 @@ def test_8x8x8x8_point_source_pm_mu(cfg_8888, form, storage):
     rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, mus, csw, TOL, storage=storage, form=form,
                                  restart=16, n_cycles=4, mr_iters=4, block_dims=(4, 4, 4, 4))
     assert rc == 0 and rep["converged"] == 2, rep
-    check_solutions(op, dims, b, host(x), mus, TOL)
+    check_solutions(op, dims, b, host(x), mus, TOL, f"8^4 +-mu {form}", storage)
 
 
 def test_8x8x8x8_twelve_sources_grouped(cfg_8888):
@@ -102,7 +104,7 @@ def test_8x8x8x8_twelve_sources_grouped(cfg_8888):
     rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, mus, csw, TOL, storage="f32",
                                  form="defect_correction", restart=12, group=5)
     assert rc == 0 and rep["converged"] == 12, rep
-    check_solutions(op, dims, b, host(x), mus, TOL)
+    check_solutions(op, dims, b, host(x), mus, TOL, "8^4 twelve sources groups of 5", "f32")
 
 
 def test_nonzero_initial_guess_and_antiperiodic():
@@ -116,7 +118,7 @@ def test_nonzero_initial_guess_and_antiperiodic():
     rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, TOL, storage="f32",
                                  antiperiodic_t=True, block_dims=(2, 2, 2, 4))
     assert rc == 0
-    check_solutions(op, dims, b, host(x), [mu], TOL)
+    check_solutions(op, dims, b, host(x), [mu], TOL, "nonzero guess antiperiodic", "f32")
 
 
 def test_solver_error_paths(cfg_4444):
