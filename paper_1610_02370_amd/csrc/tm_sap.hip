@@ -31,6 +31,15 @@ bool sap_v1_forced() {
     return forced == 1;
 }
 
+bool sap_44a_forced() {
+    static int forced = -1;
+    if (forced < 0) {
+        const char* e = getenv("TM_SAP_KERNEL");
+        forced = (e && e[0] == '4' && e[1] == '4' && e[2] == 'a') ? 1 : 0;
+    }
+    return forced == 1;
+}
+
 bool sap_v2_forced() {
     static int forced = -1;
     if (forced < 0) {
@@ -1143,6 +1152,204 @@ __global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
     }
 }
 
+// Sum of three values over the four waves of a 256-thread workgroup; the
+// wave totals are written as one float4 each and read back together.
+__device__ inline void block_sum3_w4(float* red, float& a, float& b, float& c) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    float4* r4 = reinterpret_cast<float4*>(red);
+    if ((threadIdx.x & 63) == 0) r4[threadIdx.x >> 6] = make_float4(a, b, c, 0.f);
+    __syncthreads();
+    const float4 p0 = r4[0], p1 = r4[1], p2 = r4[2], p3 = r4[3];
+    a = (p0.x + p1.x) + (p2.x + p3.x);
+    b = (p0.y + p1.y) + (p2.y + p3.y);
+    c = (p0.z + p1.z) + (p2.z + p3.z);
+}
+
+// Upper-face halo of direction MU: h = upper - B_MU lower of the spinor just
+// above the face, times the boundary phase when that hop crosses the lattice
+// edge, stored in the layout [3][axis*64 + pos] float4 at entry j.
+template <int MU>
+__device__ inline void s44_stage_forward(const Geo& g, const Spinor<float>& p, bool wrap, float* dst, int j) {
+    Half<float> h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<float> b0, b1;
+        apply_B(MU, p.v[6 + c], p.v[9 + c], b0, b1);
+        h.h[0][c] = p.v[c] - b0;
+        h.h[1][c] = p.v[3 + c] - b1;
+    }
+    if (wrap) {
+        const cplx<float> ph = cmk((float)g.bcr[MU], (float)g.bci[MU]);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h.h[s][c] = ph * h.h[s][c];
+    }
+    v2_put_half(dst, 0, j, h);
+}
+
+// ---------------------------------------------------------------------------
+// The 4^4 half-sweep at two workgroups per compute unit (two waves per SIMD,
+// so that one workgroup's LDS waits, barriers and loads overlap the other's
+// arithmetic).  LDS is only the exchange buffers (xs, gb: 72 KiB):
+//   * the lower-face halo products go into gb slots that no site fills: on
+//     direction mu the 64 upper-face sites have no in-block +mu neighbour, and
+//     the product for the site below the lower face of a column is kept in the
+//     slot of that column's upper-face site;
+//   * the upper-face halo is taken in a second pass of the residual: once every
+//     in-block hop has read xs, each wave stages its axis's 64 projected half
+//     spinors h = (1 - gamma_mu) psi there, and the face sites finish their
+//     forward hops from them.
+// Arithmetic and MR steps are those of k_sap_half_44.
+template <class S, class G, class C>
+__global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))) k_sap_half_44w(SapArgs a) {
+    __shared__ V2Shared sm;
+    const Geo& g = a.g;
+    const int l = threadIdx.x;  // 256 threads, all sites active
+
+    S44Site ix;
+    s44_setup(g, a.colour, blockIdx.x, l, ix);
+    const long long s = ix.s;
+    int Lc[4], str[4], fsrc[4], bcol[4];
+    bool fin[4], bin[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Lc[q] = ix.L[q];
+        str[q] = ix.str[q];
+        fsrc[q] = ix.fsrc[q];
+        bcol[q] = ix.bcol[q];
+        fin[q] = ix.fin[q];
+        bin[q] = ix.bin[q];
+    }
+    const int wax = __builtin_amdgcn_readfirstlane(ix.wax);
+    const int up_site = (int)ix.up_site, dn_site = (int)ix.dn_site, top = ix.top;
+    const bool up_wrap = ix.up_wrap, dn_wrap = ix.dn_wrap;
+    const int wmu = wax == 0 ? 0 : 4 - wax;
+    const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
+    const int sys_begin = blockIdx.y * a.sys_tile;
+    const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
+    const bool own = !a.own_zero;
+    const bool halo = !(a.own_zero && a.halo_zero);
+    float* hb = sm.gb + wmu * 3 * kV2 * 4;  // this wave's lower-face products, direction wmu
+
+    Link<float> Uo[4];
+    Clover<float> A;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) load_link<float, G>(a.links, g.V, s, mu, Uo[mu]);
+    load_clover<float, C>(a.clover, g.V, s, A);
+#pragma unroll
+    for (int i = 0; i < 72; ++i) A.a[i] *= -2.f;
+
+    for (int sys = sys_begin; sys < sys_end; ++sys) {
+        const float mu_tw = (float)(a.mu[sys] + g.mu_shift[(Lc[0] + Lc[1] + Lc[2] + Lc[3]) & 1]);
+        const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
+        void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
+        const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
+        float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
+
+        Spinor<float> r, e;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) e.v[i] = cmk(0.f, 0.f);
+        load_spinor<float, S>(bb, bsc, g.V, s, r);
+        if (halo) {
+            // ---- r = b - D x.  Pass 1: in-block hops and the lower-face halo.
+            if (own) load_spinor<float, S>(xx, xsc, g.V, s, e);
+            {
+                Spinor<float> hd;
+                Link<float> Ldn;  // U_mu(site below the lower face), mu = wmu
+                load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
+                load_link<float, G>(a.links, g.V, dn_site, wmu, Ldn);
+                v2_push(sm, l, true, fin, Uo, e);
+                if (dn_wrap) apply_bc(g, wmu, -1, hd);
+                switch (wax) {
+                    case 0: s44_stage_backward<0>(Ldn, hd, 1.f, hb, top); break;
+                    case 1: s44_stage_backward<3>(Ldn, hd, 1.f, hb, top); break;
+                    case 2: s44_stage_backward<2>(Ldn, hd, 1.f, hb, top); break;
+                    default: s44_stage_backward<1>(Ldn, hd, 1.f, hb, top); break;
+                }
+            }
+            __syncthreads();
+            Spinor<float> acc;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                __builtin_amdgcn_sched_barrier(0);
+                if (fin[mu]) {
+                    Half<float> h, gg;
+                    project_forward_lds(sm.xs, mu, l + str[mu], h);
+                    su3_mul(Uo[mu], h, gg);
+                    forward_accumulate(mu, gg, acc);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                Half<float> gg;
+                v2_get_half(sm.gb, mu, bcol[mu], gg);
+                backward_accumulate(mu, gg, acc);
+            }
+            __syncthreads();
+            // ---- pass 2: the upper-face halo, staged in xs
+            {
+                Spinor<float> hu;
+                load_spinor<float, S>(xx, xsc, g.V, up_site, hu);
+                switch (wax) {
+                    case 0: s44_stage_forward<0>(g, hu, up_wrap, sm.xs, l); break;
+                    case 1: s44_stage_forward<3>(g, hu, up_wrap, sm.xs, l); break;
+                    case 2: s44_stage_forward<2>(g, hu, up_wrap, sm.xs, l); break;
+                    default: s44_stage_forward<1>(g, hu, up_wrap, sm.xs, l); break;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                if (!fin[mu]) {
+                    Half<float> h, gg;
+                    v2_get_half(sm.xs, 0, fsrc[mu], h);
+                    su3_mul(Uo[mu], h, gg);
+                    forward_accumulate(mu, gg, acc);
+                }
+            }
+            // r = b + (acc - 2 A x) / 2
+            if (own) clover_acc(A, -2.f * mu_tw, e, acc);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] + 0.5f * acc.v[i];
+            __syncthreads();
+        }
+
+        // ---- minimal residual on D_BB with q = -2 D_BB rho
+        Spinor<float>& rho = r;
+        for (int it = 0; it < a.mr_iters; ++it) {
+            v2_push(sm, l, true, fin, Uo, rho);
+            __syncthreads();
+            Spinor<float> q;
+            float qr_re = 0.f, qr_im = 0.f, qq = 0.f;
+#pragma unroll
+            for (int i = 0; i < 12; ++i) q.v[i] = cmk(0.f, 0.f);
+            v2_pull(sm, l, fin, bin, str, Uo, q);
+            clover_acc(A, -2.f * mu_tw, rho, q);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
+                qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
+                qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
+            }
+            block_sum3_w4(sm.red, qr_re, qr_im, qq);
+            if (qq >= min_normal<float>()) {
+                const float inv = __builtin_amdgcn_rcpf(qq);
+                const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
+                const cplx<float> beta = cmk(-2.f * alpha.re, -2.f * alpha.im);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    e.v[i] = cmad(beta, rho.v[i], e.v[i]);
+                    rho.v[i] = rho.v[i] - alpha * q.v[i];
+                }
+            }
+        }
+        store_spinor<float, S>(xx, xsc, g.V, s, e);
+    }
+}
+
 template <class S, class G, class C, class R>
 hipError_t run(const SapArgs& a, hipStream_t st) {
     const int nt = (a.g.Vb + 63) & ~63;
@@ -1176,7 +1383,9 @@ hipError_t run(const SapArgs& a, hipStream_t st) {
     if constexpr (sizeof(R) == 4) {
         if (nt <= kV2 && !sap_v1_forced()) {
             const bool is44 = a.g.lb[0] == 4 && a.g.lb[1] == 4 && a.g.lb[2] == 4 && a.g.lb[3] == 4;
-            if (is44 && !sap_v2_forced())
+            if (is44 && !sap_v2_forced() && !sap_44a_forced())
+                hipLaunchKernelGGL((k_sap_half_44w<S, G, C>), grid, dim3(nt), 0, st, a);
+            else if (is44 && !sap_v2_forced())
                 hipLaunchKernelGGL((k_sap_half_44<S, G, C>), grid, dim3(nt), 0, st, a);
             else
                 hipLaunchKernelGGL((k_sap_half_v2<S, G, C>), grid, dim3(nt), 0, st, a);

@@ -24,9 +24,12 @@ struct S44Site {
     int str[4];        // local-index stride of direction mu
     int fsrc[4];       // forward source: local index (fin) or upper-halo entry axis*64 + position
     int bsrc[4];       // backward source: local index (bin) or lower-halo entry axis*64 + position
+    int bcol[4];       // backward source inside the block: local index (bin) or, for a lower-face
+                       // site, the upper-face site of its column, whose product slot holds the halo
     int parity;        // (t + z + y + x) mod 2 of the global coordinates
     // halo duty of the thread: array axis wax (= wave), face position hp (= lane)
     int wax, wmu, hp;
+    int top;           // local index of the upper-face site (on axis wax) of position hp's column
     long long up_site, dn_site;  // sites just above / below the block on axis wax at position hp
     bool up_wrap, dn_wrap;       // those hops cross the lattice boundary
 };
@@ -70,6 +73,7 @@ __host__ __device__ inline void s44_setup(const Geo& g, int colour, long long j,
             if (q != ax) p = p * 4 + t.L[q];
         t.fsrc[mu] = t.fin[mu] ? l + t.str[mu] : ax * 64 + p;
         t.bsrc[mu] = t.bin[mu] ? l - t.str[mu] : ax * 64 + p;
+        t.bcol[mu] = t.bin[mu] ? l - t.str[mu] : l + 3 * t.str[mu];
     }
     t.wax = l >> 6;
     t.wmu = t.wax == 0 ? 0 : 4 - t.wax;
@@ -77,11 +81,13 @@ __host__ __device__ inline void s44_setup(const Geo& g, int colour, long long j,
     // face position hp: lexicographic over the axes other than wax, the last one fastest
     int up[4], dn[4];
     int p = t.hp;
+    t.top = 0;
 #pragma unroll
     for (int q = 3; q >= 0; --q) {
         const bool on = q == t.wax;
         up[q] = on ? 0 : (p & 3);
         p = on ? p : p >> 2;
+        t.top += (on ? 3 : up[q]) << (2 * (3 - q));
     }
     t.up_wrap = false;
     t.dn_wrap = false;

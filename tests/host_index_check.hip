@@ -132,6 +132,7 @@ static void check_s44(const Geo& g) {
                         CHECK(h.wmu == mu, "upper halo direction");
                     }
                     if (t.bin[mu]) {
+                        CHECK(t.bcol[mu] == t.bsrc[mu], "in-block backward column source j=%lld l=%d mu=%d", j, l, mu);
                         int cn[4];
                         coords_of(g, t.blk * 256 + t.bsrc[mu], cn);
                         for (int q = 0; q < 4; ++q) CHECK(cn[q] == b[q], "in-block backward j=%lld l=%d mu=%d", j, l, mu);
@@ -144,6 +145,14 @@ static void check_s44(const Geo& g) {
                         for (int q = 0; q < 4; ++q) CHECK(cn[q] == b[q], "lower halo site j=%lld l=%d mu=%d", j, l, mu);
                         CHECK(h.dn_wrap == (c[a] == 0), "lower halo wrap j=%lld l=%d mu=%d", j, l, mu);
                         CHECK(h.wmu == mu, "lower halo direction");
+                        // the halo product's slot in the block: the column's upper-face site, which
+                        // has no in-block +mu neighbour and so never writes that slot itself
+                        CHECK(t.bcol[mu] == h.top, "lower halo slot j=%lld l=%d mu=%d", j, l, mu);
+                        S44Site o;
+                        s44_setup(g, colour, j, t.bcol[mu], o);
+                        CHECK(!o.fin[mu], "lower halo slot is an upper-face site j=%lld l=%d mu=%d", j, l, mu);
+                        for (int q = 0; q < 4; ++q)
+                            CHECK(o.L[q] == (q == a ? 3 : t.L[q]), "lower halo slot column j=%lld l=%d mu=%d", j, l, mu);
                     }
                 }
             }
