@@ -31,15 +31,6 @@ bool sap_v1_forced() {
     return forced == 1;
 }
 
-bool sap_44a_forced() {
-    static int forced = -1;
-    if (forced < 0) {
-        const char* e = getenv("TM_SAP_KERNEL");
-        forced = (e && e[0] == '4' && e[1] == '4' && e[2] == 'a') ? 1 : 0;
-    }
-    return forced == 1;
-}
-
 bool sap_v2_forced() {
     static int forced = -1;
     if (forced < 0) {
@@ -907,67 +898,8 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// FP32 half-sweep specialised to 4^4 blocks (the paper's level-1 Schwarz
-// block).  Each of the four waves owns one axis: at the start of a system it
-// copies the 64 spinors above the block's upper face on that axis into LDS,
-// and forms the 64 backward hop products U_mu(y)^+ (1 + gamma_mu) psi(y) of
-// the sites y below the lower face (link loaded once per launch, mu fixed per
-// wave).  Every site then takes exactly one forward and one backward hop per
-// direction from either the in-block exchange or these halo buffers, so the
-// residual b - D x costs one full stencil with no idle lanes for the faces.
-struct alignas(16) S44Shared {
-    float xs[24 * kV2];      // in-block spinors, [6][site] float4
-    float gb[4 * 12 * kV2];  // in-block backward products, [mu][3][site] float4
-    float hf[24 * kV2];      // upper-face halo spinors, [6][axis*64 + pos] float4
-    float hb[12 * kV2];      // lower-face halo products, [3][axis*64 + pos] float4
-    float red[64];
-};
-static_assert(offsetof(S44Shared, xs) == offsetof(V2Shared, xs) && offsetof(S44Shared, gb) == offsetof(V2Shared, gb),
-              "the exchange helpers address S44Shared through its V2Shared prefix");
-
-// With FP32 storage the next system's b and x of the block's own sites are
-// copied into LDS by the memory unit while the current system's MR steps run
-// (global_load_lds, 16 bytes per lane, no registers), in the field layout
-// [6 units][site] float4.  Each wave copies and later reads only its own 64
-// sites, so no workgroup barrier guards the buffers.
-struct alignas(16) S44SharedPrefetch : S44Shared {
-    float pb[24 * kV2];  // next system's b
-    float px[24 * kV2];  // next system's x
-};
-static_assert(sizeof(S44SharedPrefetch) <= 160 * 1024, "LDS of one workgroup");
-
-typedef __attribute__((address_space(3))) void lds_void;
-
-// Issues this wave's copies of system sys: b at the block's sites, x there when
-// `with_x`, and when `with_face` the x of the site just above the block's upper
-// face that this lane stages (into hf; the staging lane applies the boundary
-// phase once the copy has landed).
-__device__ inline void s44_prefetch(S44SharedPrefetch& sm, const SapArgs& a, int sys, int site, int l, bool with_x,
-                                    bool with_face, int up_site) {
-    const int w = __builtin_amdgcn_readfirstlane(l >> 6);
-    // uniform base per unit + one 32-bit byte offset per lane (a system's FP32 field is under 4 GiB)
-    const size_t stride = (size_t)6 * a.g.V * 16;
-    const char* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
-    const char* xx = reinterpret_cast<const char*>(a.x) + sys * stride;
-    const unsigned own_off = (unsigned)site * 16u;
-    const unsigned face_off = (unsigned)up_site * 16u;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const size_t unit = (size_t)k * a.g.V * 16;
-        __builtin_amdgcn_global_load_lds(bb + unit + own_off, (lds_void*)&sm.pb[(k * kV2 + 64 * w) * 4], 16, 0, 0);
-        if (with_x)
-            __builtin_amdgcn_global_load_lds(xx + unit + own_off, (lds_void*)&sm.px[(k * kV2 + 64 * w) * 4], 16, 0,
-                                             0);
-        if (with_face)
-            __builtin_amdgcn_global_load_lds(xx + unit + face_off, (lds_void*)&sm.hf[(k * kV2 + 64 * w) * 4], 16, 0,
-                                             0);
-    }
-}
-
-// s_waitcnt lgkmcnt(0) with the other counters left free (gfx9 encoding)
-constexpr int kWaitLgkm0 = 0xC07F;
-
+// Lower-face halo product of direction MU: U_MU(y)^+ (1 + gamma_MU) psi(y) of the
+// site y just below the face, stored in the layout [3][site] float4 at entry j.
 template <int MU>
 __device__ inline void s44_stage_backward(const Link<float>& L, const Spinor<float>& p, float sg, float* hb, int j) {
     Half<float> g;
@@ -977,179 +909,6 @@ __device__ inline void s44_stage_backward(const Link<float>& L, const Spinor<flo
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         h4[k * kV2 + j] = make_float4(sg * v[2 * k].re, sg * v[2 * k].im, sg * v[2 * k + 1].re, sg * v[2 * k + 1].im);
-}
-
-template <class S, class G, class C>
-__global__ void __launch_bounds__(kV2) k_sap_half_44(SapArgs a) {
-    constexpr bool kPre = std::is_same<S, float>::value;  // prefetch the next system's b and x
-    typedef typename std::conditional<kPre, S44SharedPrefetch, S44Shared>::type Shared;
-    __shared__ Shared sm;
-    V2Shared& sx = *reinterpret_cast<V2Shared*>(&sm);
-    const Geo& g = a.g;
-    const int l = threadIdx.x;  // 256 threads, all sites active
-
-    // block, site, in-block neighbours and halo duty (tm_sap_index.h, checked on the host)
-    S44Site ix;
-    s44_setup(g, a.colour, blockIdx.x, l, ix);
-    const long long s = ix.s;
-    int Lc[4], str[4], fsrc[4], bsrc[4];
-    bool fin[4], bin[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        Lc[q] = ix.L[q];
-        str[q] = ix.str[q];
-        fsrc[q] = ix.fsrc[q];
-        bsrc[q] = ix.bsrc[q];
-        fin[q] = ix.fin[q];
-        bin[q] = ix.bin[q];
-    }
-    const int wax = __builtin_amdgcn_readfirstlane(ix.wax);
-    const int up_site = (int)ix.up_site, dn_site = (int)ix.dn_site;
-    const bool up_wrap = ix.up_wrap, dn_wrap = ix.dn_wrap;
-    const int wmu = wax == 0 ? 0 : 4 - wax;
-    const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
-    const int sys_begin = blockIdx.y * a.sys_tile;
-    const int sys_end = min(a.nsys, sys_begin + a.sys_tile);
-    const bool own = !a.own_zero;
-    const bool halo = !(a.own_zero && a.halo_zero);
-    if constexpr (kPre) {
-        if (sys_begin < sys_end) s44_prefetch(sm, a, sys_begin, (int)s, l, own, halo, up_site);
-    }
-
-    Link<float> Ldn;  // U_mu(site below the lower face)
-    load_link<float, G>(a.links, g.V, dn_site, wmu, Ldn);
-
-    Link<float> Uo[4];
-    Clover<float> A;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) load_link<float, G>(a.links, g.V, s, mu, Uo[mu]);
-    load_clover<float, C>(a.clover, g.V, s, A);
-#pragma unroll
-    for (int i = 0; i < 72; ++i) A.a[i] *= -2.f;
-
-    for (int sys = sys_begin; sys < sys_end; ++sys) {
-        const float mu_tw = (float)(a.mu[sys] + g.mu_shift[(Lc[0] + Lc[1] + Lc[2] + Lc[3]) & 1]);
-        const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
-        void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
-        const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
-        float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
-
-        Spinor<float> r, e;
-#pragma unroll
-        for (int i = 0; i < 12; ++i) e.v[i] = cmk(0.f, 0.f);
-        if constexpr (kPre) {
-            // this system's b, x and upper-face x were copied into LDS during the previous one
-            __builtin_amdgcn_s_waitcnt(0);
-            v2_get_spinor(sm.pb, l, r);
-            if (own) v2_get_spinor(sm.px, l, e);
-            if (halo && up_wrap) {  // the copied face spinor still lacks the boundary phase
-                Spinor<float> hu;
-                v2_get_spinor(sm.hf, l, hu);
-                apply_bc(g, wmu, +1, hu);
-                v2_put_spinor(sm.hf, l, hu);
-            }
-        } else {
-            load_spinor<float, S>(bb, bsc, g.V, s, r);
-        }
-        if (halo) {
-            // ---- r = b - D x: one full stencil from the in-block exchange and the halo buffers
-            Spinor<float> hd;
-            if constexpr (kPre) {
-                load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
-                v2_push(sx, l, true, fin, Uo, e);
-            } else {
-                if (own) load_spinor<float, S>(xx, xsc, g.V, s, e);
-                Spinor<float> hu;
-                load_spinor<float, S>(xx, xsc, g.V, up_site, hu);
-                load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
-                v2_push(sx, l, true, fin, Uo, e);
-                if (up_wrap) apply_bc(g, wmu, +1, hu);
-                v2_put_spinor(sm.hf, l, hu);
-            }
-            if (dn_wrap) apply_bc(g, wmu, -1, hd);
-            switch (wax) {
-                case 0: s44_stage_backward<0>(Ldn, hd, 1.f, sm.hb, l); break;
-                case 1: s44_stage_backward<3>(Ldn, hd, 1.f, sm.hb, l); break;
-                case 2: s44_stage_backward<2>(Ldn, hd, 1.f, sm.hb, l); break;
-                default: s44_stage_backward<1>(Ldn, hd, 1.f, sm.hb, l); break;
-            }
-            __syncthreads();
-            Spinor<float> acc;
-#pragma unroll
-            for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu) {
-                Half<float> h, gg;
-                {
-                    Spinor<float> p;
-                    v2_get_spinor(fin[mu] ? sm.xs : sm.hf, fsrc[mu], p);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        cplx<float> b0, b1;
-                        apply_B(mu, p.v[6 + c], p.v[9 + c], b0, b1);
-                        h.h[0][c] = p.v[c] - b0;
-                        h.h[1][c] = p.v[3 + c] - b1;
-                    }
-                }
-                su3_mul(Uo[mu], h, gg);
-                forward_accumulate(mu, gg, acc);
-                {
-                    const float4* src = reinterpret_cast<const float4*>(bin[mu] ? sm.gb : sm.hb);
-                    const int base = bin[mu] ? mu * 3 * kV2 : 0;
-                    cplx<float>* v = &gg.h[0][0];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const float4 t = src[base + k * kV2 + bsrc[mu]];
-                        v[2 * k] = cmk(t.x, t.y);
-                        v[2 * k + 1] = cmk(t.z, t.w);
-                    }
-                }
-                backward_accumulate(mu, gg, acc);
-            }
-            // r = b + (acc - 2 A x) / 2
-            if (own) clover_acc(A, -2.f * mu_tw, e, acc);
-#pragma unroll
-            for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] + 0.5f * acc.v[i];
-            __syncthreads();
-        }
-        if constexpr (kPre) {
-            // every wave has read this system's pb, px (its own sites) and hf (after the barrier
-            // above): the next system's copies may land during the MR steps
-            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-            if (sys + 1 < sys_end) s44_prefetch(sm, a, sys + 1, (int)s, l, own, halo, up_site);
-        }
-
-        // ---- minimal residual on D_BB with q = -2 D_BB rho
-        Spinor<float>& rho = r;
-        for (int it = 0; it < a.mr_iters; ++it) {
-            v2_push(sx, l, true, fin, Uo, rho);
-            __syncthreads();
-            Spinor<float> q;
-            float qr_re = 0.f, qr_im = 0.f, qq = 0.f;
-#pragma unroll
-            for (int i = 0; i < 12; ++i) q.v[i] = cmk(0.f, 0.f);
-            v2_pull(sx, l, fin, bin, str, Uo, q);
-            clover_acc(A, -2.f * mu_tw, rho, q);
-#pragma unroll
-            for (int i = 0; i < 12; ++i) {
-                qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
-                qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
-                qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
-            }
-            block_sum3(sm.red, qr_re, qr_im, qq);
-            if (qq >= min_normal<float>()) {
-                const float inv = __builtin_amdgcn_rcpf(qq);
-                const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
-                const cplx<float> beta = cmk(-2.f * alpha.re, -2.f * alpha.im);
-#pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    e.v[i] = cmad(beta, rho.v[i], e.v[i]);
-                    rho.v[i] = rho.v[i] - alpha * q.v[i];
-                }
-            }
-        }
-        store_spinor<float, S>(xx, xsc, g.V, s, e);
-    }
 }
 
 // Sum of three values over the four waves of a 256-thread workgroup; the
@@ -1191,20 +950,27 @@ __device__ inline void s44_stage_forward(const Geo& g, const Spinor<float>& p, b
 }
 
 // ---------------------------------------------------------------------------
-// The 4^4 half-sweep at two workgroups per compute unit (two waves per SIMD,
+// FP32 half-sweep specialised to 4^4 blocks (the paper's level-1 Schwarz
+// block): one site per thread, links and clover held in registers for all
+// systems of the launch, two workgroups per compute unit (two waves per SIMD,
 // so that one workgroup's LDS waits, barriers and loads overlap the other's
-// arithmetic).  LDS is only the exchange buffers (xs, gb: 72 KiB):
-//   * the lower-face halo products go into gb slots that no site fills: on
+// arithmetic).  LDS holds only the exchange buffers xs and gb (72 KiB).  Wave w
+// also owns array axis w of the halo: its lane p forms, at face position p, the
+// backward hop product U_mu(y)^+ (1 + gamma_mu) psi(y) of the site y below the
+// block's lower face and the projected half spinor (1 - gamma_mu) psi of the
+// site above its upper face.
+//   * The lower-face products go into gb slots that no site fills: on
 //     direction mu the 64 upper-face sites have no in-block +mu neighbour, and
-//     the product for the site below the lower face of a column is kept in the
-//     slot of that column's upper-face site;
-//   * the upper-face halo is taken in a second pass of the residual: once every
-//     in-block hop has read xs, each wave stages its axis's 64 projected half
-//     spinors h = (1 - gamma_mu) psi there, and the face sites finish their
-//     forward hops from them.
-// Arithmetic and MR steps are those of k_sap_half_44.
+//     the product for the site below a column's lower face is kept in the slot
+//     of that column's upper-face site.
+//   * The upper-face halo is taken in a second pass of the residual: once every
+//     in-block hop has read xs, the waves stage the projected halves there and
+//     the face sites finish their forward hops from them.
+// Every site takes each of its eight hops once, so the residual b - D x costs
+// one stencil plus the halo staging; the MR steps exchange rho through xs and
+// gb with two barriers per step.
 template <class S, class G, class C>
-__global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))) k_sap_half_44w(SapArgs a) {
+__global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))) k_sap_half_44(SapArgs a) {
     __shared__ V2Shared sm;
     const Geo& g = a.g;
     const int l = threadIdx.x;  // 256 threads, all sites active
@@ -1252,7 +1018,7 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
         Spinor<float> r, e;
 #pragma unroll
         for (int i = 0; i < 12; ++i) e.v[i] = cmk(0.f, 0.f);
-        load_spinor<float, S>(bb, bsc, g.V, s, r);
+        if (!halo) load_spinor<float, S>(bb, bsc, g.V, s, r);
         if (halo) {
             // ---- r = b - D x.  Pass 1: in-block hops and the lower-face halo.
             if (own) load_spinor<float, S>(xx, xsc, g.V, s, e);
@@ -1312,6 +1078,9 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
             }
             // r = b + (acc - 2 A x) / 2
             if (own) clover_acc(A, -2.f * mu_tw, e, acc);
+            // b only now: loaded earlier it would stay live through both passes and push
+            // other values out of registers (this kernel has no room to spare at 2 waves/SIMD)
+            load_spinor<float, S>(bb, bsc, g.V, s, r);
 #pragma unroll
             for (int i = 0; i < 12; ++i) r.v[i] = r.v[i] + 0.5f * acc.v[i];
             __syncthreads();
@@ -1383,9 +1152,7 @@ hipError_t run(const SapArgs& a, hipStream_t st) {
     if constexpr (sizeof(R) == 4) {
         if (nt <= kV2 && !sap_v1_forced()) {
             const bool is44 = a.g.lb[0] == 4 && a.g.lb[1] == 4 && a.g.lb[2] == 4 && a.g.lb[3] == 4;
-            if (is44 && !sap_v2_forced() && !sap_44a_forced())
-                hipLaunchKernelGGL((k_sap_half_44w<S, G, C>), grid, dim3(nt), 0, st, a);
-            else if (is44 && !sap_v2_forced())
+            if (is44 && !sap_v2_forced())
                 hipLaunchKernelGGL((k_sap_half_44<S, G, C>), grid, dim3(nt), 0, st, a);
             else
                 hipLaunchKernelGGL((k_sap_half_v2<S, G, C>), grid, dim3(nt), 0, st, a);
