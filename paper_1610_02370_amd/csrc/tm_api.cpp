@@ -159,6 +159,8 @@ Geo make_geo(const tm_geom* geom, const int tile[4]) {
             g.bcr[mu] = (mu == 0 && geom->antiperiodic_t) ? -1.0 : 1.0;
             g.bci[mu] = 0.0;
         }
+        g.bcrf[mu] = (float)g.bcr[mu];
+        g.bcif[mu] = (float)g.bci[mu];
     }
     g.mu_shift[0] = geom->mu_shift[0];
     g.mu_shift[1] = geom->mu_shift[1];

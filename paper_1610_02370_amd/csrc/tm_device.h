@@ -135,6 +135,8 @@ struct Geo {
     double bcr[4], bci[4];  // boundary phase of a forward hop across the lattice boundary along mu
                             // (a backward one takes the conjugate): exp(i theta_mu), -1 for
                             // antiperiodic t
+    float bcrf[4], bcif[4]; // the same phases rounded to FP32 on the host (FP32 kernels read these
+                            // as scalar operands instead of converting per lane)
     double mu_shift[2];     // added to the twisted mass on even / odd sites
 };
 
@@ -311,7 +313,14 @@ template <class R> struct Spinor {
 // (dir = +1 forward, -1 backward).
 template <class R>
 __device__ inline void apply_bc(const Geo& g, int mu, int dir, Spinor<R>& p) {
-    const R re = (R)g.bcr[mu], im = dir > 0 ? (R)g.bci[mu] : -(R)g.bci[mu];
+    R re, im;
+    if constexpr (sizeof(R) == 4) {
+        re = g.bcrf[mu];
+        im = dir > 0 ? g.bcif[mu] : -g.bcif[mu];
+    } else {
+        re = (R)g.bcr[mu];
+        im = dir > 0 ? (R)g.bci[mu] : -(R)g.bci[mu];
+    }
 #pragma unroll
     for (int i = 0; i < 12; ++i) p.v[i] = cmk(re * p.v[i].re - im * p.v[i].im, re * p.v[i].im + im * p.v[i].re);
 }

@@ -940,7 +940,7 @@ __device__ inline void s44_stage_forward(const Geo& g, const Spinor<float>& p, b
         h.h[1][c] = p.v[3 + c] - b1;
     }
     if (wrap) {
-        const cplx<float> ph = cmk((float)g.bcr[MU], (float)g.bci[MU]);
+        const cplx<float> ph = cmk(g.bcrf[MU], g.bcif[MU]);
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -975,23 +975,24 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
     const Geo& g = a.g;
     const int l = threadIdx.x;  // 256 threads, all sites active
 
+    // block (the same for the whole workgroup), then the thread's site, in-block
+    // neighbours and halo duty (tm_sap_index.h, checked on the host)
+    int B[4];
+    s44_block(g, a.colour, blockIdx.x, B);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) B[q] = __builtin_amdgcn_readfirstlane(B[q]);
+    const long long blk = s44_block_index(g, B);
     S44Site ix;
-    s44_setup(g, a.colour, blockIdx.x, l, ix);
-    const long long s = ix.s;
-    int Lc[4], str[4], fsrc[4], bcol[4];
+    s44_lane(g, B, blk, l, ix);
+    int str[4];
     bool fin[4], bin[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        Lc[q] = ix.L[q];
         str[q] = ix.str[q];
-        fsrc[q] = ix.fsrc[q];
-        bcol[q] = ix.bcol[q];
         fin[q] = ix.fin[q];
         bin[q] = ix.bin[q];
     }
     const int wax = __builtin_amdgcn_readfirstlane(ix.wax);
-    const int up_site = (int)ix.up_site, dn_site = (int)ix.dn_site, top = ix.top;
-    const bool up_wrap = ix.up_wrap, dn_wrap = ix.dn_wrap;
     const int wmu = wax == 0 ? 0 : 4 - wax;
     const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
     const int sys_begin = blockIdx.y * a.sys_tile;
@@ -1003,13 +1004,29 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
     Link<float> Uo[4];
     Clover<float> A;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) load_link<float, G>(a.links, g.V, s, mu, Uo[mu]);
-    load_clover<float, C>(a.clover, g.V, s, A);
+    for (int mu = 0; mu < 4; ++mu) load_link<float, G>(a.links, g.V, ix.s, mu, Uo[mu]);
+    load_clover<float, C>(a.clover, g.V, ix.s, A);
 #pragma unroll
     for (int i = 0; i < 72; ++i) A.a[i] *= -2.f;
 
     for (int sys = sys_begin; sys < sys_end; ++sys) {
-        const float mu_tw = (float)(a.mu[sys] + g.mu_shift[(Lc[0] + Lc[1] + Lc[2] + Lc[3]) & 1]);
+        // The per-thread indices used outside the MR steps are recomputed for every system from
+        // an index the compiler cannot see through: held across the MR steps they would be
+        // spilled to scratch memory (the MR steps need every register at two waves per SIMD).
+        int lx = l;
+        asm volatile("" : "+v"(lx));
+        S44Site hx;
+        s44_lane(g, B, blk, lx, hx);
+        const long long s = hx.s;
+        const int up_site = (int)hx.up_site, dn_site = (int)hx.dn_site, top = hx.top;
+        const bool up_wrap = hx.up_wrap, dn_wrap = hx.dn_wrap;
+        int fsrc[4], bcol[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            fsrc[q] = hx.fsrc[q];
+            bcol[q] = hx.bcol[q];
+        }
+        const float mu_tw = (float)(a.mu[sys] + g.mu_shift[hx.parity]);
         const void* bb = reinterpret_cast<const char*>(a.b) + sys * stride;
         void* xx = reinterpret_cast<char*>(a.x) + sys * stride;
         const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;

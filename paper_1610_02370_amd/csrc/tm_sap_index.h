@@ -46,12 +46,21 @@ __host__ __device__ inline void s44_block(const Geo& g, int colour, long long j,
     B[3] = 2 * k3 + ((colour + B[0] + B[1] + B[2]) & 1);
 }
 
-// Every loop is unrolled and every array index a compile-time constant after
-// unrolling (the run-time axis wax enters only through comparisons), so the
-// struct lives in registers.
-__host__ __device__ inline void s44_setup(const Geo& g, int colour, long long j, int l, S44Site& t) {
-    s44_block(g, colour, j, t.B);
-    t.blk = (((long long)t.B[0] * g.nb[1] + t.B[1]) * g.nb[2] + t.B[2]) * g.nb[3] + t.B[3];
+// Tiled-layout index of global coordinates c on 4^4 tiles (shifts and masks;
+// the general coords_site divides by the tile extents).
+__host__ __device__ inline long long s44_site_of(const Geo& g, const int c[4]) {
+    const long long blk = (((long long)(c[0] >> 2) * g.nb[1] + (c[1] >> 2)) * g.nb[2] + (c[2] >> 2)) * g.nb[3] + (c[3] >> 2);
+    return blk * 256 + (((c[0] & 3) * 4 + (c[1] & 3)) * 4 + (c[2] & 3)) * 4 + (c[3] & 3);
+}
+
+// The thread's part of the setup, given the block coordinates B (the same for
+// the whole workgroup) and its block index blk.  Every loop is unrolled and
+// every array index a compile-time constant after unrolling (the run-time axis
+// wax enters only through comparisons), so the struct lives in registers.
+__host__ __device__ inline void s44_lane(const Geo& g, const int B[4], long long blk, int l, S44Site& t) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) t.B[a] = B[a];
+    t.blk = blk;
     t.s = t.blk * 256 + l;
     t.L[0] = l >> 6;
     t.L[1] = (l >> 4) & 3;
@@ -108,8 +117,19 @@ __host__ __device__ inline void s44_setup(const Geo& g, int colour, long long j,
         up[q] = u;
         dn[q] = d;
     }
-    t.up_site = coords_site(g, up);
-    t.dn_site = coords_site(g, dn);
+    t.up_site = s44_site_of(g, up);
+    t.dn_site = s44_site_of(g, dn);
+}
+
+// Block index of block coordinates B.
+__host__ __device__ inline long long s44_block_index(const Geo& g, const int B[4]) {
+    return (((long long)B[0] * g.nb[1] + B[1]) * g.nb[2] + B[2]) * g.nb[3] + B[3];
+}
+
+__host__ __device__ inline void s44_setup(const Geo& g, int colour, long long j, int l, S44Site& t) {
+    int B[4];
+    s44_block(g, colour, j, B);
+    s44_lane(g, B, s44_block_index(g, B), l, t);
 }
 
 }  // namespace tmsap
