@@ -116,6 +116,10 @@ hipError_t run(const DiracArgs& a, hipStream_t st) {
 //   FP16/BF16 input with FP32 output, links, clover and compute.
 hipError_t launch_dirac(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_p, Prec clover_p, Prec compute,
                         hipStream_t st) {
+    if (compute == P_F32) {  // 4^4 tiles: the tiled kernel of tm_sap.hip
+        const hipError_t e = launch_dirac_44(a, in_p, out_p, link_p, clover_p, st);
+        if (e != hipErrorNotSupported) return e;
+    }
 #define TM_CASE(PI, PO, PL, PC, PR, TI, TO, TL, TC, TR)                                      \
     if (in_p == PI && out_p == PO && link_p == PL && clover_p == PC && compute == PR) \
         return run<TI, TO, TL, TC, TR>(a, st);

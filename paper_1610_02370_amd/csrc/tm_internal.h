@@ -146,6 +146,10 @@ hipError_t launch_dirac(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_p, 
                         hipStream_t st);
 
 // ---- smoother (tm_sap.hip)
+// The operator on 4^4 tiles with FP32 arithmetic (tm_sap.hip); hipErrorNotSupported for other
+// tiles or precision combinations, which launch_dirac then runs in its generic kernel.
+hipError_t launch_dirac_44(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_p, Prec clover_p,
+                           hipStream_t st);
 hipError_t launch_sap_half(const SapArgs& a, Prec spinor_p, Prec link_p, Prec clover_p, Prec compute,
                            hipStream_t st);
 bool sap_supported(Prec spinor_p, Prec link_p, Prec clover_p, Prec compute);

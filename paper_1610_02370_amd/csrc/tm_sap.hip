@@ -949,6 +949,81 @@ __device__ inline void s44_stage_forward(const Geo& g, const Spinor<float>& p, b
     v2_put_half(dst, 0, j, h);
 }
 
+// The hop part of D on one 4^4 block for one system: acc = the sum over the eight
+// hops of the spinor field x (unscaled; D adds -1/2 acc), e holding x at this
+// thread's own site and xx the whole field (FP32 arithmetic, storage S).  Wave
+// w stages axis w's halo: the backward product of the site below the lower face
+// into the slot of its column's upper-face site, and, once the in-block hops
+// have read xs, the projected half spinor of the site above the upper face into
+// xs.  Starts by writing LDS (the caller must have passed a barrier since the
+// last reads of xs and gb) and ends after the last reads, without a barrier.
+// k_sap_half_44 takes the same steps written out in its residual: called there,
+// the compiler allocates that kernel's registers differently and spills one
+// more address per system, which cost 3 % of its time.
+template <class S, class G>
+__device__ __attribute__((always_inline)) inline void s44_stencil(V2Shared& sm, const Geo& g, const void* links, const void* xx, const float* xsc,
+                                   int l, const Link<float> Uo[4], const bool fin[4], const int str[4],
+                                   const S44Site& hx, int wax, int wmu, const Spinor<float>& e,
+                                   Spinor<float>& acc) {
+    const int up_site = (int)hx.up_site, dn_site = (int)hx.dn_site, top = hx.top;
+    const bool up_wrap = hx.up_wrap, dn_wrap = hx.dn_wrap;
+    float* hb = sm.gb + wmu * 3 * kV2 * 4;  // this wave's lower-face products, direction wmu
+    // pass 1: in-block hops and the lower-face halo
+    {
+        Spinor<float> hd;
+        Link<float> Ldn;  // U_mu(site below the lower face), mu = wmu
+        load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
+        load_link<float, G>(links, g.V, dn_site, wmu, Ldn);
+        v2_push(sm, l, true, fin, Uo, e);
+        if (dn_wrap) apply_bc(g, wmu, -1, hd);
+        switch (wax) {
+            case 0: s44_stage_backward<0>(Ldn, hd, 1.f, hb, top); break;
+            case 1: s44_stage_backward<3>(Ldn, hd, 1.f, hb, top); break;
+            case 2: s44_stage_backward<2>(Ldn, hd, 1.f, hb, top); break;
+            default: s44_stage_backward<1>(Ldn, hd, 1.f, hb, top); break;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (fin[mu]) {
+            Half<float> h, gg;
+            project_forward_lds(sm.xs, mu, l + str[mu], h);
+            su3_mul(Uo[mu], h, gg);
+            forward_accumulate(mu, gg, acc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        Half<float> gg;
+        v2_get_half(sm.gb, mu, hx.bcol[mu], gg);
+        backward_accumulate(mu, gg, acc);
+    }
+    __syncthreads();
+    // pass 2: the upper-face halo, staged in xs
+    {
+        Spinor<float> hu;
+        load_spinor<float, S>(xx, xsc, g.V, up_site, hu);
+        switch (wax) {
+            case 0: s44_stage_forward<0>(g, hu, up_wrap, sm.xs, l); break;
+            case 1: s44_stage_forward<3>(g, hu, up_wrap, sm.xs, l); break;
+            case 2: s44_stage_forward<2>(g, hu, up_wrap, sm.xs, l); break;
+            default: s44_stage_forward<1>(g, hu, up_wrap, sm.xs, l); break;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        if (!fin[mu]) {
+            Half<float> h, gg;
+            v2_get_half(sm.xs, 0, hx.fsrc[mu], h);
+            su3_mul(Uo[mu], h, gg);
+            forward_accumulate(mu, gg, acc);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP32 half-sweep specialised to 4^4 blocks (the paper's level-1 Schwarz
 // block): one site per thread, links and clover held in registers for all
@@ -1136,6 +1211,87 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// The operator out = D x on a lattice tiled in 4^4 blocks, FP32 arithmetic:
+// one workgroup per block (every block, both colours), the block's stencil
+// formed as in the residual of the half-sweep above (s44_stencil: links and
+// clover in registers for all systems, the exchange and the halo in LDS), two
+// workgroups per compute unit.  The generic k_dirac gathers its eight
+// neighbours per thread from memory and holds its links at one wavefront per
+// SIMD.
+template <class Si, class So, class G, class C>
+__global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dirac_44(DiracArgs a) {
+    __shared__ V2Shared sm;
+    const Geo& g = a.g;
+    const int l = threadIdx.x;
+
+    int B[4];
+    {
+        long long t = blockIdx.x;  // block index, lexicographic over the block grid
+        B[3] = (int)(t % g.nb[3]);
+        t /= g.nb[3];
+        B[2] = (int)(t % g.nb[2]);
+        t /= g.nb[2];
+        B[1] = (int)(t % g.nb[1]);
+        B[0] = (int)(t / g.nb[1]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) B[q] = __builtin_amdgcn_readfirstlane(B[q]);
+    const long long blk = s44_block_index(g, B);
+    S44Site ix;
+    s44_lane(g, B, blk, l, ix);
+    int str[4];
+    bool fin[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        str[q] = ix.str[q];
+        fin[q] = ix.fin[q];
+    }
+    const int wax = __builtin_amdgcn_readfirstlane(ix.wax);
+    const int wmu = wax == 0 ? 0 : 4 - wax;
+    const size_t in_stride = (size_t)6 * g.V * Unit<Si>::bytes;
+    const size_t out_stride = (size_t)6 * g.V * Unit<So>::bytes;
+
+    Link<float> Uo[4];
+    Clover<float> A;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) load_link<float, G>(a.links, g.V, ix.s, mu, Uo[mu]);
+    load_clover<float, C>(a.clover, g.V, ix.s, A);
+#pragma unroll
+    for (int i = 0; i < 72; ++i) A.a[i] *= -2.f;
+
+    for (int sys = 0; sys < a.nsys; ++sys) {
+        // indices used outside the stencil's own loops recomputed per system (see k_sap_half_44)
+        int lx = l;
+        asm volatile("" : "+v"(lx));
+        S44Site hx;
+        s44_lane(g, B, blk, lx, hx);
+        const long long s = hx.s;
+        const float mu_tw = (float)(a.mu[sys] + g.mu_shift[hx.parity]);
+        const void* in = reinterpret_cast<const char*>(a.in) + sys * in_stride;
+        const float* isc = a.in_scale ? a.in_scale + (size_t)sys * g.V : nullptr;
+
+        Spinor<float> e, acc;
+        load_spinor<float, Si>(in, isc, g.V, s, e);
+        s44_stencil<Si, G>(sm, g, a.links, in, isc, l, Uo, fin, str, hx, wax, wmu, e, acc);
+        // out = (A + twist) x - acc / 2, from acc - 2 (A + twist) x
+        clover_acc(A, -2.f * mu_tw, e, acc);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) acc.v[i] = -0.5f * acc.v[i];
+        store_spinor<float, So>(reinterpret_cast<char*>(a.out) + sys * out_stride,
+                                a.out_scale ? a.out_scale + (size_t)sys * g.V : nullptr, g.V, s, acc);
+        __syncthreads();  // every read of xs and gb done before the next system's push
+    }
+}
+
+template <class Si, class So, class G, class C>
+hipError_t run_dirac_44(const DiracArgs& a, hipStream_t st) {
+    const long long nblocks = (long long)a.g.nb[0] * a.g.nb[1] * a.g.nb[2] * a.g.nb[3];
+    hipLaunchKernelGGL((k_dirac_44<Si, So, G, C>), dim3((unsigned)nblocks), dim3(kV2), 0, st, a);
+    return hipGetLastError();
+}
+
 template <class S, class G, class C, class R>
 hipError_t run(const SapArgs& a, hipStream_t st) {
     const int nt = (a.g.Vb + 63) & ~63;
@@ -1204,6 +1360,23 @@ hipError_t launch_sap_half(const SapArgs& a, Prec sp, Prec lp, Prec cp, Prec r, 
     if (sp == P_F16 && lp == P_F16 && cp == P_F32 && r == P_F32) return run<f16, f16, float, float>(a, st);
     if (sp == P_BF16 && lp == P_BF16 && cp == P_F32 && r == P_F32) return run<bf16, bf16, float, float>(a, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_dirac_44(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_p, Prec clover_p,
+                           hipStream_t st) {
+    const bool is44 = a.g.lb[0] == 4 && a.g.lb[1] == 4 && a.g.lb[2] == 4 && a.g.lb[3] == 4;
+    if (!is44 || sap_v1_forced() || sap_v2_forced()) return hipErrorNotSupported;
+    if (in_p == P_F32 && out_p == P_F32 && link_p == P_F32 && clover_p == P_F32)
+        return run_dirac_44<float, float, float, float>(a, st);
+    if (in_p == P_F16 && out_p == P_F16 && link_p == P_F16 && clover_p == P_F32)
+        return run_dirac_44<f16, f16, f16, float>(a, st);
+    if (in_p == P_BF16 && out_p == P_BF16 && link_p == P_BF16 && clover_p == P_F32)
+        return run_dirac_44<bf16, bf16, bf16, float>(a, st);
+    if (in_p == P_F16 && out_p == P_F32 && link_p == P_F32 && clover_p == P_F32)
+        return run_dirac_44<f16, float, float, float>(a, st);
+    if (in_p == P_BF16 && out_p == P_F32 && link_p == P_F32 && clover_p == P_F32)
+        return run_dirac_44<bf16, float, float, float>(a, st);
+    return hipErrorNotSupported;
 }
 
 }  // namespace tmsap

@@ -23,6 +23,9 @@ CASES = [
     ((8, 6, 4, 10), 0.5, 0.1632, [0.003], 1.5, False),
     ((4, 4, 4, 4), 0.3, 0.16, [0.01, -0.01], 0.0, True),
     ((6, 4, 8, 4), 0.6, 0.1373, [0.0009, -0.0009, 0.0009], 1.5, False),
+    # 4^4 tiles (the tiled FP32 kernel): 2, 3, 1, 2 blocks per axis, so one axis has an odd
+    # count and along y the block is its own neighbour
+    ((8, 12, 4, 8), 0.55, 0.15, [0.004, -0.004, 0.01], 1.2, True),
 ]
 
 
