@@ -1053,7 +1053,7 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
     // block (the same for the whole workgroup), then the thread's site, in-block
     // neighbours and halo duty (tm_sap_index.h, checked on the host)
     int B[4];
-    s44_block(g, a.colour, blockIdx.x, B);
+    s44_block(g, a.colour, xcd_swizzle(blockIdx.x, gridDim.x), B);
 #pragma unroll
     for (int q = 0; q < 4; ++q) B[q] = __builtin_amdgcn_readfirstlane(B[q]);
     const long long blk = s44_block_index(g, B);
@@ -1228,7 +1228,7 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     int B[4];
     {
-        long long t = blockIdx.x;  // block index, lexicographic over the block grid
+        long long t = xcd_swizzle(blockIdx.x, gridDim.x);  // block index, lexicographic over the block grid
         B[3] = (int)(t % g.nb[3]);
         t /= g.nb[3];
         B[2] = (int)(t % g.nb[2]);

@@ -162,7 +162,22 @@ static void check_s44(const Geo& g) {
     }
 }
 
+// xcd_swizzle is a permutation of [0, n) that keeps the workgroups of one XCD
+// (j mod 8 equal) on consecutive block numbers.
+static void check_swizzle() {
+    for (long long n = 1; n <= 200; ++n) {
+        std::vector<char> hit(n, 0);
+        for (long long j = 0; j < n; ++j) {
+            const long long b = xcd_swizzle(j, n);
+            CHECK(b >= 0 && b < n && !hit[b], "swizzle n=%lld j=%lld", n, j);
+            if (b >= 0 && b < n) hit[b] = 1;
+            if (j + 8 < n) CHECK(xcd_swizzle(j + 8, n) == b + 1, "swizzle neighbours n=%lld j=%lld", n, j);
+        }
+    }
+}
+
 int main() {
+    check_swizzle();
     // lattices (T, Z, Y, X) and tiles; the last three have several blocks per axis, unequal extents
     const int cases[][8] = {
         {8, 8, 8, 8, 4, 4, 4, 4},    {8, 8, 8, 16, 4, 4, 4, 4},   {16, 8, 16, 24, 4, 4, 4, 4},
