@@ -168,6 +168,15 @@ __host__ __device__ inline long long coords_site(const Geo& g, const int c[4]) {
     return blk * g.Vb + l;
 }
 
+// Workgroups are dealt to the eight XCDs round-robin (workgroup j to XCD j mod 8),
+// and each XCD has its own L2.  This bijection of [0, n) gives the workgroups of
+// one XCD consecutive block numbers, so that neighbouring blocks, which read the
+// same face spinors, run at the same time on the same L2.
+__host__ __device__ inline long long xcd_swizzle(long long j, long long n) {
+    const long long q = n / 8, r = n % 8, x = j % 8, p = j / 8;
+    return x * q + (x < r ? x : r) + p;
+}
+
 // The 8 neighbours of site s in the tiled layout, s +- mu (periodic), the
 // hops that cross the lattice boundary (bit mu forward, bit 4+mu backward) and
 // the parity of s.  32-bit arithmetic: the library limits the volume to 2^29

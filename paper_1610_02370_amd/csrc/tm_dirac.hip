@@ -29,7 +29,8 @@ __device__ inline void link_from_rows(const R* u, Link<R>& L) {
 template <class Si, class So, class G, class C, class R>
 __global__ void __launch_bounds__(kThreads) k_dirac(DiracArgs a) {
     const Geo& g = a.g;
-    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // workgroups of one XCD on consecutive tiles (their neighbours' spinors and links share an L2)
+    long long s = xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     int nf[4], nbk[4], par;
     unsigned wrap;

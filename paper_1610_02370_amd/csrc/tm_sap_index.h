@@ -34,15 +34,6 @@ struct S44Site {
     bool up_wrap, dn_wrap;       // those hops cross the lattice boundary
 };
 
-// Workgroups are dealt to the eight XCDs round-robin (workgroup j to XCD j mod 8),
-// and each XCD has its own L2.  This bijection of [0, n) gives the workgroups of
-// one XCD consecutive block numbers, so that neighbouring blocks, which read the
-// same face spinors, run at the same time on the same L2.
-__host__ __device__ inline long long xcd_swizzle(long long j, long long n) {
-    const long long q = n / 8, r = n % 8, x = j % 8, p = j / 8;
-    return x * q + (x < r ? x : r) + p;
-}
-
 // Block coordinates of workgroup j in the half-sweep of `colour` (g.nb[3] even).
 __host__ __device__ inline void s44_block(const Geo& g, int colour, long long j, int B[4]) {
     const int half3 = g.nb[3] >> 1;
