@@ -32,7 +32,9 @@
  * to validate the links); with a nonzero tag it reuses the copy made for the
  * same (U pointer, tag, dims, kappa, c_sw, precision, tile), so the caller
  * must change the tag, or call tm_gauge_release(U), whenever the contents at
- * U change.  tm_finalize() frees everything the library allocated.
+ * U change.  A new nonzero tag with the same U pointer rebuilds that
+ * pointer's older copy of the same shape in place (no new allocation).
+ * tm_finalize() frees everything the library allocated.
  *
  * Streams: all work is enqueued on opts->stream (NULL = the null stream).
  * tm_dirac_apply and tm_sap_smooth return after enqueueing (the caller

@@ -194,6 +194,9 @@ int get_gauge(DeviceState* ds, const Geo& g, const void* U, double kappa, double
             slot = &e;
             break;
         }
+        // a new tag for the same field buffer: its contents changed, so the stale copy is rebuilt
+        // in place rather than kept beside a new one
+        if (tag != 0 && e.tag != 0 && e.U == U && e.last_call != ds->call_id && !slot) slot = &e;
     }
     if (!slot) {
         // keep the cache small: at most 8 entries per device, evicting the

@@ -138,3 +138,28 @@ def test_dirac_error_paths(fields):
     with pytest.raises(tm.TMError) as e:
         tm.tm_dirac_apply(dims, dev(U), t, kappa, mus, csw, t)
     assert e.value.code == -1
+
+
+def test_gauge_tag_rebuilds_the_same_buffer_in_place(fields):
+    # a new tag for the same U buffer after its contents changed: the library rebuilds that
+    # buffer's cached copy (in place) and every later call with the new tag uses the new field
+    dims, eps, kappa, mus, csw, ap = CASES[3]
+    U1, psi, ref1 = fields[3]
+    U2 = synth.gauge_field(dims, eps, seed=99)
+    op2 = oracle.Operator(dims, U2, oracle.kappa_to_m(kappa), 0.0, csw, antiperiodic_t=ap)
+    ref2 = np.stack([op2.with_mu(m).apply(psi[i]).reshape(-1, 4, 3) for i, m in enumerate(mus)])
+    announce("gauge tag: same buffer, new contents, new tag")
+    Ud = dev(U1)
+    for prec in ("f32", "f64"):
+        got = host(tm.tm_dirac_apply(dims, Ud, dev(psi), kappa, mus, csw, storage=prec, antiperiodic_t=ap,
+                                     gauge_tag=5))
+        for i in range(len(mus)):
+            check_close(got[i], ref1[i], "dirac", prec, f"tag 5 field 1 system {i}")
+    Ud.copy_(dev(U2))
+    for rep in range(2):  # the first call rebuilds, the second reuses the rebuilt copy
+        for prec in ("f32", "f64"):
+            got = host(tm.tm_dirac_apply(dims, Ud, dev(psi), kappa, mus, csw, storage=prec, antiperiodic_t=ap,
+                                         gauge_tag=6))
+            for i in range(len(mus)):
+                check_close(got[i], ref2[i], "dirac", prec, f"tag 6 field 2 call {rep} system {i}")
+    tm.tm_gauge_release(Ud)
