@@ -232,9 +232,26 @@ int get_gauge(DeviceState* ds, const Geo& g, const void* U, double kappa, double
     if ((h = hipMemsetAsync(stats, 0, 2 * sizeof(unsigned), st)) != hipSuccess) return hip_fail(h, "memset");
     if ((h = launch_link_ingest(g, link_p, U, slot->dev.links, stats, st)) != hipSuccess)
         return hip_fail(h, "link ingest");
+    // an FP32 clover is the FP64 one rounded: converted from an FP64 copy of the same field,
+    // parameters and tiling made or used in this call, else built
+    const GaugeEntry* c64 = nullptr;
+    if (cl_p == P_F32)
+        for (auto& ep : ds->gauge) {
+            const GaugeEntry& e = *ep;
+            if (&e != slot && e.U == U && e.last_call == ds->call_id && e.dev.clover_prec == P_F64 &&
+                e.kappa == kappa && e.csw == csw && std::memcmp(e.g.d, g.d, sizeof g.d) == 0 &&
+                std::memcmp(e.g.lb, g.lb, sizeof g.lb) == 0) {
+                c64 = &e;
+                break;
+            }
+        }
     const double m4 = 1.0 / (2.0 * kappa);
-    if ((h = launch_clover_build(g, cl_p, U, m4, csw, slot->dev.clover, st)) != hipSuccess)
+    if (c64) {
+        if ((h = launch_clover_to_f32(g, c64->dev.clover, slot->dev.clover, st)) != hipSuccess)
+            return hip_fail(h, "clover conversion");
+    } else if ((h = launch_clover_build(g, cl_p, U, m4, csw, slot->dev.clover, st)) != hipSuccess) {
         return hip_fail(h, "clover build");
+    }
     unsigned host[2];
     if ((h = hipMemcpyAsync(host, stats, sizeof host, hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hip_fail(h, "stats copy");

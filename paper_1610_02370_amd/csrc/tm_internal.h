@@ -129,6 +129,8 @@ hipError_t launch_cg_scalars(int mode, int nsys, unsigned long long frozen, doub
 
 // ---- layout kernels (tm_layout.hip)
 hipError_t launch_link_ingest(const Geo& g, Prec G, const void* Ucanon, void* links, unsigned* stats, hipStream_t st);
+// FP32 clover [18][V] units from the FP64 one (FP64 [18][V] double4 units) of the same geometry.
+hipError_t launch_clover_to_f32(const Geo& g, const void* clover64, void* clover32, hipStream_t st);
 hipError_t launch_clover_build(const Geo& g, Prec C, const void* Ucanon, double m4, double csw, void* clover,
                                hipStream_t st);
 hipError_t launch_spinor_import(const Geo& g, const SpinorBuf& dst, const void* canon, unsigned* flag,

@@ -217,6 +217,16 @@ __global__ void __launch_bounds__(kThreads) k_clover_build(Geo g, const double* 
     for (int k = 0; k < 18; ++k) Unit<C>::store(clover, (size_t)k * g.V + s, packed + 4 * k);
 }
 
+// FP32 clover from the FP64 one of the same field: the build rounds its FP64
+// result once at the store, so this rounding gives the same values.
+__global__ void __launch_bounds__(kThreads) k_clover_to_f32(long long n_units, const double* __restrict__ src,
+                                                            float* dst) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_units) return;
+    const double4 a = reinterpret_cast<const double4*>(src)[i];
+    reinterpret_cast<float4*>(dst)[i] = make_float4((float)a.x, (float)a.y, (float)a.z, (float)a.w);
+}
+
 // ------------------------------------------------------------ spinors
 // canonical [nsys][V][12] complex128 -> internal
 template <class S>
@@ -371,6 +381,13 @@ hipError_t launch_clover_build(const Geo& g, Prec C, const void* Ucanon, double 
     if (C == P_F16 || C == P_BF16) return hipErrorInvalidValue;
     TM_DISPATCH_PREC(C, T, hipLaunchKernelGGL(k_clover_build<T>, dim3(grid_for(g.V)), dim3(kThreads), 0, st, g,
                                               (const double*)Ucanon, m4, csw, clover));
+    return hipGetLastError();
+}
+
+hipError_t launch_clover_to_f32(const Geo& g, const void* clover64, void* clover32, hipStream_t st) {
+    const long long n = 18 * g.V;
+    hipLaunchKernelGGL(k_clover_to_f32, dim3(grid_for(n)), dim3(kThreads), 0, st, n,
+                       static_cast<const double*>(clover64), static_cast<float*>(clover32));
     return hipGetLastError();
 }
 
