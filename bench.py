@@ -49,8 +49,10 @@ WORKLOADS = {
     # name: dims (T,Z,Y,X), eps, kappa, mu, csw, systems (list of (spin, colour, mu sign)), storage
     "48^3x96_12rhs_f32": dict(dims=(96, 48, 48, 48), eps=0.6, kappa=0.1373, mu=0.0009, csw=1.5,
                               sources=[(s, c, 1) for s in range(4) for c in range(3)], storage="f32"),
+    # solved as stated for this configuration: FP64 FGMRES(20) preconditioned directly by the FP32
+    # SAP (the other workloads use defect correction, whose FP64 state is what fits in memory)
     "32^3x64_pm_f32": dict(dims=(64, 32, 32, 32), eps=0.6, kappa=0.1394, mu=0.001, csw=1.5,
-                           sources=[(0, 0, 1), (0, 0, -1)], storage="f32"),
+                           sources=[(0, 0, 1), (0, 0, -1)], storage="f32", form="flexible", restart=20),
     # 12 point sources x both flavours; the canonical complex128 buffers of 24 systems (309 GB for b
     # and x) do not fit beside the solver, so the solves go in calls of one +-mu pair (chunk 2)
     "64^3x128_24sys_f16": dict(dims=(128, 64, 64, 64), eps=0.6, kappa=0.1373, mu=0.0009, csw=1.5,
@@ -292,7 +294,7 @@ def small_lattice_sweeps(torch, tm, synth, reps):
     return out
 
 
-def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False, tag=0):
+def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False, tag=0, form="defect_correction"):
     """Every system of the workload solved to TOL, in calls of b.shape[0] systems (point sources
     set in b at the start of each call); returns the worst status and the merged report.  All
     calls of the step pass gauge tag `tag`: with 0 each call rebuilds the gauge copies, with a tag
@@ -307,7 +309,7 @@ def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False, tag=0):
             b[k, 0, s, c] = 1.0
         x.zero_()
         rc, rep = tm.tm_fgmres_solve(wl["dims"], Ud, b[:n], x[:n], wl["kappa"], mus[c0:c0 + n], wl["csw"], TOL,
-                                     storage=wl["storage"], form="defect_correction", restart=restart,
+                                     storage=wl["storage"], form=form, restart=restart,
                                      n_cycles=N_CYCLES, mr_iters=MR_ITERS, block_dims=BLOCK, group=group,
                                      gauge_tag=tag, eo=eo)
         rc_all = max(rc_all, rc)
@@ -534,7 +536,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="48^3x96_12rhs_f32", choices=sorted(WORKLOADS))
     ap.add_argument("--sap-reps", type=int, default=10)
-    ap.add_argument("--restart", type=int, default=8)
+    ap.add_argument("--restart", type=int, default=None,
+                    help="FGMRES restart length (default: the workload's, else 8)")
+    ap.add_argument("--form", choices=["defect_correction", "flexible"], default=None,
+                    help="solver form (default: the workload's, else defect_correction)")
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the SAP sweeps (every system of the workload in one launch; 32^3x64 +-mu FP32 and "
@@ -562,6 +567,9 @@ def main():
     from paper_1610_02370_amd import synth
 
     wl = WORKLOADS[args.workload]
+    if args.restart is None:
+        args.restart = wl.get("restart", 8)
+    form = args.form or wl.get("form", "defect_correction")
     torch.cuda.set_device(0)
     Ud, b, mus = make_inputs(wl, torch, tm, synth)
     nsys = len(mus)
@@ -596,14 +604,14 @@ def main():
     chunked = b_chunk < nsys
     step_tag = (lambda k: 1000 + k) if chunked else (lambda k: 0)
     for w in range(args.warmup):
-        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group, args.eo, step_tag(w))
+        rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group, args.eo, step_tag(w), form)
         log(f"warmup {w}: status {rc} iters {rep['iters']} outer {rep['outer']} t {rep['t_total']:.2f}s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
     for s in range(args.steps):
         rc, rep = solve_step(wl, Ud, b, mus, x, torch, tm, args.restart, args.group, args.eo,
-                             step_tag(args.warmup + s))
+                             step_tag(args.warmup + s), form)
         reps.append((rc, rep))
         log(f"step {s}: status {rc} iters {rep['iters']} outer {rep['outer']} group {rep['group']} "
             f"sap {rep['t_sap']:.2f}s total {rep['t_total']:.2f}s max res {max(rep['true_rel_res']):.2e}")
@@ -687,7 +695,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "dims_TZYX": list(dims), "systems": nsys, "block": list(BLOCK),
                    "n_cycles": N_CYCLES, "mr_iters": MR_ITERS, "block_solve": "even-odd MR" if args.eo else "MR",
-                   "tol": TOL, "restart": args.restart, "systems_per_call": b_chunk,
+                   "tol": TOL, "solver_form": form, "restart": args.restart, "systems_per_call": b_chunk,
                    "group": group, "parallelism": "single GPU"},
         "converged": ok,
         "sap_kernel_GBps": achieved_gbps,
