@@ -474,10 +474,11 @@ def _rate(fn, sites: int, min_s: float):
 def cpu_baseline(wl):
     """The FP64 CPU oracle on bounded samples, at one host thread and at all of them:
     operator applications and SAP cycles (4^4 blocks, 4 MR steps, one system) on a 16^4 lattice
-    with the workload's eps / kappa / mu / c_sw, and the FGMRES(20) + SAP solve to 1e-10 of the
+    with the workload's eps / kappa / mu / c_sw; the same two rates on the 32^3 x 64 lattice with
+    that configuration's parameters (all threads); and the FGMRES(20) + SAP solve to 1e-10 of the
     8^4 run with the 32^3 x 64 configuration's parameters (eps 0.6, kappa 0.1394, mu 0.001,
-    c_sw 1.5, gauge seed 3, point source).  `value` is the all-thread SAP rate converted with the
-    GPU value's byte model."""
+    c_sw 1.5, gauge seed 3, point source).  `value` is the all-thread SAP rate at 16^4 converted
+    with the GPU value's byte model."""
     import numpy as np
 
     import oracle
@@ -497,8 +498,16 @@ def cpu_baseline(wl):
         rates[th] = {"dirac_site_updates_per_s": d_rate, "sap_cycle_site_updates_per_s": s_rate,
                      "sap_cycles_timed": cyc}
     oracle.set_num_threads(all_threads)
-    # the 8^4 solve (configuration 3's parameters)
     c3 = WORKLOADS["32^3x64_pm_f32"]
+    # the 32^3 x 64 lattice itself (all threads): one operator application, one SAP cycle
+    V3 = int(np.prod(c3["dims"]))
+    U3 = synth.gauge_field(c3["dims"], c3["eps"], seed=3)
+    psi3 = synth.gaussian_spinor(c3["dims"], 1, seed=103)[0].ravel()
+    op3 = oracle.Operator(c3["dims"], U3, oracle.kappa_to_m(c3["kappa"]), c3["mu"], c3["csw"])
+    d3_rate, _, _ = _rate(lambda: op3.apply(psi3), V3, 1.0)
+    s3_rate, cyc3, _ = _rate(lambda: op3.sap(psi3, BLOCK, 1, MR_ITERS), V3, 1.0)
+    del U3, psi3, op3
+    # the 8^4 solve (configuration 3's parameters)
     d8 = (8, 8, 8, 8)
     U8 = synth.gauge_field(d8, c3["eps"], seed=3)
     op8 = oracle.Operator(d8, U8, oracle.kappa_to_m(c3["kappa"]), c3["mu"], c3["csw"])
@@ -522,6 +531,8 @@ def cpu_baseline(wl):
         "cpu_model": cpu_model(),
         "threads": {"1": rates[1], str(all_threads): rates[all_threads]},
         "site_updates_per_s": rate,
+        "lattice_32^3x64": {"dirac_site_updates_per_s": d3_rate, "sap_cycle_site_updates_per_s": s3_rate,
+                            "sap_cycles_timed": cyc3, "threads": all_threads},
         "solve_8^4_cfg3_params": {"seconds": solve8_s, "iters": rep8["iters"],
                                   "true_rel_res": rep8["true_rel_res"], "threads": all_threads},
     }
