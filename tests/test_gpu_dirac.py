@@ -163,3 +163,23 @@ def test_gauge_tag_rebuilds_the_same_buffer_in_place(fields):
             for i in range(len(mus)):
                 check_close(got[i], ref2[i], "dirac", prec, f"tag 6 field 2 call {rep} system {i}")
     tm.tm_gauge_release(Ud)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_dirac_64_systems_match_single_calls(prec):
+    # the tiled FP32 operator loops over every system of the call inside each workgroup; the
+    # largest batch the ABI allows gives, system by system, the bits of one-system calls
+    dims = (8, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.5, seed=61)
+    mus = [0.002 * (k - 32) for k in range(64)]
+    psi = synth.gaussian_spinor(dims, len(mus), seed=161)
+    announce(f"dirac 64 systems vs single calls, {prec}")
+    Ud = dev(U)
+    allsys = host(tm.tm_dirac_apply(dims, Ud, dev(psi), 0.15, mus, 1.2, storage=prec))
+    for k in (0, 1, 31, 32, 63):
+        one = host(tm.tm_dirac_apply(dims, Ud, dev(psi[k:k + 1]), 0.15, [mus[k]], 1.2, storage=prec))
+        assert np.array_equal(allsys[k], one[0]), k
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(0.15), 0.0, 1.2)
+    for k in (0, 63):
+        ref = op.with_mu(mus[k]).apply(psi[k]).reshape(-1, 4, 3)
+        check_close(allsys[k], ref, "dirac", prec, f"64 systems, system {k}")
