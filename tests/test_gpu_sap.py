@@ -118,3 +118,26 @@ def test_sap_blocks_with_vanishing_residual(prec, bd, tiny):
     op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), mu, csw)
     ref = op.sap(b[0], bd, 2, 4).reshape(-1, 4, 3)
     check_close(got, ref, "sap", prec, f"vanishing residual block {bd} tiny {tiny}")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_sap_without_mr_steps_leaves_x(prec):
+    # zero MR steps: every block's correction is zero, so x comes back as stored (rounded once to
+    # the storage precision) whatever the number of cycles; several systems run through the 4^4
+    # kernel's system loop with no MR step between one system's residual and the next one's
+    dims, bd = (8, 8, 8, 8), (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, seed=41)
+    mus = [0.003, -0.003, 0.01]
+    b = synth.gaussian_spinor(dims, len(mus), seed=141)
+    x0 = synth.gaussian_spinor(dims, len(mus), seed=241)
+    announce(f"sap with mr_iters 0, {prec}")
+    Ud = dev(U)
+    outs = []
+    for cyc in (1, 3):
+        x = dev(x0)
+        tm.tm_sap_smooth(dims, Ud, dev(b), x, 0.16, mus, 1.5, bd, cyc, 0, storage=prec)
+        outs.append(host(x))
+    assert np.array_equal(outs[0], outs[1])
+    bound = 1e-6 if prec == "f32" else 1e-3
+    for i in range(len(mus)):
+        assert rel_err(outs[0][i], x0[i]) < bound, i
