@@ -33,9 +33,24 @@ int blas_max_vec();
 hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, const VecRef& w, const double* coef,
                    int coef_stride, int mode, const VecRef& y, const double* fac, double* partials, double* out,
                    int accumulate, int nsys, long long V, hipStream_t st);
-// s[k] = 1/sqrt(hn_k[2 nvec] - sum_i hn_k[i]^2) for the mode-1 output hn (2 nvec + 1 values per system):
-// the norm after the second projection by Pythagoras; 0 for bit k of `off` set or a vanishing norm.
-hipError_t blas_pythagoras(const double* hn, int nvec, int nsys, unsigned long long off, double* s, hipStream_t st);
+// Classical Gram-Schmidt with delayed reorthogonalisation, two sweeps over the basis per Arnoldi
+// step.  Basis vectors v_0..v_{nb-1} (orthonormal) at basis.data + i*vec_stride; u is the lagged
+// direction (projected once), w the new operator output; FP64 or FP32, no scales.
+// Dots: out[sys*(4 nb + 4) + ...] = (<v_i, u>, <v_i, w>)_i as complex pairs, then <u, u>, <u, w>
+// (complex), <w, w>.
+hipError_t blas_dgs_dots(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, const VecRef& w,
+                         double* partials, double* out, int nsys, long long V, hipStream_t st);
+// Coefficients of the update from those dots (coef: 4 nb + 4 values per system; rep: beta, h, s
+// per system, with beta = ||u - V V^H u||, h = <v_nb, w> for v_nb = (u - V V^H u) / beta, s the
+// scale of the next direction); nb = 0 means u is v_0 itself.  Systems with bit k of `off` set
+// get zero coefficients; beta = 0 flags u in the span of the basis.  nsys <= 64.
+hipError_t blas_dgs_coef(const double* d, int nb, int nsys, unsigned long long off, double* coef, double* rep,
+                         hipStream_t st);
+// Update: u <- (u - V c) / beta when write_u (the finished basis vector v_nb), y <- s (w - V a -
+// h v_nb) (the next direction); out[sys] = (||u||^2 or 0, ||y||^2) of the stored values.
+hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, int write_u,
+                           const VecRef& w, const VecRef& y, const double* coef, double* partials, double* out,
+                           int nsys, long long V, hipStream_t st);
 // y = a[sys] x
 hipError_t blas_scale(Prec pi, Prec po, const VecRef& x, const double* a, const VecRef& y, int nsys, long long V,
                       hipStream_t st);

@@ -59,10 +59,7 @@ __device__ inline void reduce_out(double* vals, int n, double* lds, double* part
 //   mode 3: t = w - sum_i c_i v_i; y <- fac[sys] t (w kept); out = ||t||^2
 // Arithmetic at the vectors' precision R (FP64 or FP32) per site; the sums
 // over sites accumulate in FP64.  Norms and dots are of the stored values.
-// KEEP: the basis values loaded for the update stay in registers for the dots of mode 1
-// (with up to 4 FP32 vectors), instead of being loaded again after w is stored, which the
-// compiler has to assume may alias the basis.
-template <class P, int NV, bool KEEP = false>
+template <class P, int NV>
 __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride, int nvec, VecRef w,
                                                  const double* __restrict__ coef, int coef_stride, int mode, VecRef y,
                                                  const double* __restrict__ fac, double* partials, long long V) {
@@ -79,7 +76,6 @@ __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride
     const char* w0 = static_cast<const char*>(w.data) + (size_t)sys * w.sys_stride;
     for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
         Spinor<R> wv;
-        Spinor<R> vk[KEEP ? NV : 1];
         load_spinor<R, P>(w0, nullptr, V, s, wv);
         if (mode != 0) {
 #pragma unroll
@@ -87,7 +83,6 @@ __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride
                 if (i < nvec) {
                     Spinor<R> v;
                     load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
-                    if constexpr (KEEP) vk[i] = v;
                     const cplx<R> c = cmk((R)cf[2 * i], (R)cf[2 * i + 1]);
 #pragma unroll
                     for (int k = 0; k < 12; ++k) wv.v[k] = wv.v[k] - c * v.v[k];
@@ -111,10 +106,7 @@ __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride
             for (int i = 0; i < NV; ++i) {
                 if (i < nvec) {
                     Spinor<R> v;
-                    if constexpr (KEEP)
-                        v = vk[i];
-                    else
-                        load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
+                    load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
                     R re = 0, im = 0;
 #pragma unroll
                     for (int k = 0; k < 12; ++k) {
@@ -136,17 +128,209 @@ __global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride
     reduce_out<2 * NV + 1>(acc, n, lds, partials, sys, nblk);
 }
 
-// s[k] = 1 / sqrt(||w'||^2 - sum_i |h_i|^2): the norm of w' - V h by Pythagoras
-// (V orthonormal), from the mode-1 output hn = [h (2 nvec), ||w'||^2] per
-// system; 0 for systems in `off` (frozen) or when the difference vanishes.
-__global__ void k_pythagoras(const double* hn, int nvec, int nsys, unsigned long long off, double* s) {
+// Classical Gram-Schmidt with delayed reorthogonalisation: two sweeps over the
+// basis per Arnoldi step.  At step j the basis holds v_0..v_{j-1} (orthonormal)
+// and, in slot j, u: the previous step's new direction, projected once and
+// scaled to about unit norm.  w = D z_j.
+//
+// Dots sweep over basis vectors [i0, i0 + n): per system 4 n values
+// (<v_i, u>, <v_i, w>) as complex pairs, and with `head` 4 more: <u, u>,
+// <u, w> (complex), <w, w>.
+template <class P, int NV>
+__global__ void __launch_bounds__(kThreads) k_dgs_dots(VecRef basis, size_t vec_stride, int i0, int n, VecRef u,
+                                                       VecRef w, int head, double* partials, long long V) {
+    typedef typename std::conditional<std::is_same<P, double>::value, double, float>::type R;
+    __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
+    const int sys = blockIdx.y;
+    const int nblk = gridDim.x;
+    double acc[4 * NV + 4];
+#pragma unroll
+    for (int i = 0; i < 4 * NV + 4; ++i) acc[i] = 0;
+    const char* b0 = static_cast<const char*>(basis.data) + (size_t)sys * basis.sys_stride + (size_t)i0 * vec_stride;
+    const char* u0 = static_cast<const char*>(u.data) + (size_t)sys * u.sys_stride;
+    const char* w0 = static_cast<const char*>(w.data) + (size_t)sys * w.sys_stride;
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
+        Spinor<R> uv, wv;
+        load_spinor<R, P>(u0, nullptr, V, s, uv);
+        load_spinor<R, P>(w0, nullptr, V, s, wv);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < n) {
+                Spinor<R> v;
+                load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
+                R cr = 0, ci = 0, ar = 0, ai = 0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    cr += v.v[k].re * uv.v[k].re + v.v[k].im * uv.v[k].im;
+                    ci += v.v[k].re * uv.v[k].im - v.v[k].im * uv.v[k].re;
+                    ar += v.v[k].re * wv.v[k].re + v.v[k].im * wv.v[k].im;
+                    ai += v.v[k].re * wv.v[k].im - v.v[k].im * wv.v[k].re;
+                }
+                acc[4 * i] += (double)cr;
+                acc[4 * i + 1] += (double)ci;
+                acc[4 * i + 2] += (double)ar;
+                acc[4 * i + 3] += (double)ai;
+            }
+        }
+        if (head) {
+            R uu = 0, uwr = 0, uwi = 0, ww = 0;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                uu += uv.v[k].re * uv.v[k].re + uv.v[k].im * uv.v[k].im;
+                uwr += uv.v[k].re * wv.v[k].re + uv.v[k].im * wv.v[k].im;
+                uwi += uv.v[k].re * wv.v[k].im - uv.v[k].im * wv.v[k].re;
+                ww += wv.v[k].re * wv.v[k].re + wv.v[k].im * wv.v[k].im;
+            }
+            acc[4 * NV] += (double)uu;
+            acc[4 * NV + 1] += (double)uwr;
+            acc[4 * NV + 2] += (double)uwi;
+            acc[4 * NV + 3] += (double)ww;
+        }
+    }
+    // the head values follow the n dot pairs
+#pragma unroll
+    for (int i = 0; i < 4 * NV; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (head && i == 4 * n + t) acc[i] = acc[4 * NV + t];
+    reduce_out<4 * NV + 4>(acc, 4 * n + (head ? 4 : 0), lds, partials, sys, nblk);
+}
+
+// Coefficients of the update sweep, one thread per system, from the dots d
+// (ds values per system: the 4 nb dot values of v_0..v_{nb-1}, then <u, u>,
+// <u, w>, <w, w>).  With c_i = <v_i, u> and a_i = <v_i, w>:
+//   beta = sqrt(<u, u> - sum |c_i|^2)            (u - V c has no cancellation: u is already
+//                                                 orthogonal to V up to rounding)
+//   v_j  = (u - sum c_i v_i) / beta
+//   h    = <v_j, w> = (<u, w> - sum conj(c_i) a_i) / beta
+//   w'   = w - sum a_i v_i - h v_j = w - e u - sum (a_i - c_i e) v_i,   e = h / beta
+//   s    = 1 / sqrt(<w, w> - sum |a_i|^2 - |h|^2), the norm of w' by Pythagoras, floored at
+//          1e-6 <w, w> (only a scale for the next direction s w'; its exact norm is
+//          returned by the update sweep)
+// At the first step of a cycle (nb == 0) u is v_0 itself: beta = 1, v_j is not rewritten.
+// coef per system (cstride): [1/beta, s e (complex), s, (c_i / beta, s (a_i - c_i e)) complex
+// pairs]; rep per system: [beta, h (complex), s].  Frozen systems (bit set in `off`) and a
+// vanishing beta (u in the span of the basis: the previous column ends the Krylov space) get
+// zero coefficients and beta 0.
+__global__ void k_dgs_coef(const double* d, int ds, int nb, int nsys, unsigned long long off, double* coef,
+                           int cstride, double* rep) {
     const int k = threadIdx.x;
     if (k >= nsys) return;
-    const double* h = hn + (size_t)k * (2 * nvec + 1);
-    double t = h[2 * nvec];
-    const double w2 = t;
-    for (int i = 0; i < 2 * nvec; ++i) t -= h[i] * h[i];
-    s[k] = ((off >> k) & 1ull) || !(t > 1e-28 * w2) || !(t > 0) ? 0.0 : 1.0 / sqrt(t);
+    const double* dk = d + (size_t)k * ds;
+    double* ck = coef + (size_t)k * cstride;
+    double* rk = rep + (size_t)k * 4;
+    for (int i = 0; i < 4 + 4 * nb; ++i) ck[i] = 0.0;
+    for (int i = 0; i < 4; ++i) rk[i] = 0.0;
+    if ((off >> k) & 1ull) return;
+    const double uu = dk[4 * nb], uwr = dk[4 * nb + 1], uwi = dk[4 * nb + 2], ww = dk[4 * nb + 3];
+    double beta = 1.0, hr = uwr, hi = uwi;
+    if (nb > 0) {
+        double t = uu;
+        for (int i = 0; i < nb; ++i) t -= dk[4 * i] * dk[4 * i] + dk[4 * i + 1] * dk[4 * i + 1];
+        if (!(uu > 0) || !(t > 1e-28 * uu)) return;
+        beta = sqrt(t);
+        for (int i = 0; i < nb; ++i) {
+            const double cr = dk[4 * i], ci = dk[4 * i + 1], ar = dk[4 * i + 2], ai = dk[4 * i + 3];
+            hr -= cr * ar + ci * ai;
+            hi -= cr * ai - ci * ar;
+        }
+        hr /= beta;
+        hi /= beta;
+    }
+    const double er = hr / beta, ei = hi / beta;
+    double est = ww - hr * hr - hi * hi;
+    for (int i = 0; i < nb; ++i) est -= dk[4 * i + 2] * dk[4 * i + 2] + dk[4 * i + 3] * dk[4 * i + 3];
+    const double s = ww > 0 ? 1.0 / sqrt(fmax(est, 1e-6 * ww)) : 0.0;
+    ck[0] = nb > 0 ? 1.0 / beta : 0.0;
+    ck[1] = s * er;
+    ck[2] = s * ei;
+    ck[3] = s;
+    for (int i = 0; i < nb; ++i) {
+        const double cr = dk[4 * i], ci = dk[4 * i + 1], ar = dk[4 * i + 2], ai = dk[4 * i + 3];
+        ck[4 + 4 * i] = cr / beta;
+        ck[4 + 4 * i + 1] = ci / beta;
+        ck[4 + 4 * i + 2] = s * (ar - (cr * er - ci * ei));
+        ck[4 + 4 * i + 3] = s * (ai - (cr * ei + ci * er));
+    }
+    rk[0] = beta;
+    rk[1] = hr;
+    rk[2] = hi;
+    rk[3] = s;
+}
+
+// Update sweep with the coefficients of k_dgs_coef (per system at coef + sys * cstride):
+//   t = u / beta - sum_i (c_i / beta) v_i      written over u when write_u; ||t||^2
+//   y = s w - (s e) u - sum_i s (a_i - c_i e) v_i   written to y;           ||y||^2
+// (2 values per system: ||t||^2, ||y||^2; the first is 0 without write_u).
+template <class P, int NV>
+__global__ void __launch_bounds__(kThreads) k_dgs_update(VecRef basis, size_t vec_stride, int nb, VecRef u,
+                                                         int write_u, VecRef w, VecRef y,
+                                                         const double* __restrict__ coef, int cstride,
+                                                         double* partials, long long V) {
+    typedef typename std::conditional<std::is_same<P, double>::value, double, float>::type R;
+    __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
+    const int sys = blockIdx.y;
+    const int nblk = gridDim.x;
+    const double* cf = coef + (size_t)sys * cstride;
+    const R bu = (R)cf[0], sw = (R)cf[3];
+    const cplx<R> ew = cmk((R)cf[1], (R)cf[2]);
+    const char* b0 = static_cast<const char*>(basis.data) + (size_t)sys * basis.sys_stride;
+    char* u0 = static_cast<char*>(u.data) + (size_t)sys * u.sys_stride;
+    const char* w0 = static_cast<const char*>(w.data) + (size_t)sys * w.sys_stride;
+    char* y0 = static_cast<char*>(y.data) + (size_t)sys * y.sys_stride;
+    double acc[2] = {0, 0};
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
+        Spinor<R> tv, yv;
+        load_spinor<R, P>(u0, nullptr, V, s, tv);
+        load_spinor<R, P>(w0, nullptr, V, s, yv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            yv.v[k] = sw * yv.v[k] - ew * tv.v[k];
+            tv.v[k] = bu * tv.v[k];
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nb) {
+                Spinor<R> v;
+                load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
+                const cplx<R> pv = cmk((R)cf[4 + 4 * i], (R)cf[4 + 4 * i + 1]);
+                const cplx<R> qw = cmk((R)cf[4 + 4 * i + 2], (R)cf[4 + 4 * i + 3]);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    tv.v[k] = tv.v[k] - pv * v.v[k];
+                    yv.v[k] = yv.v[k] - qw * v.v[k];
+                }
+            }
+        }
+        if (write_u) {
+            store_spinor<R, P>(u0, nullptr, V, s, tv);
+            R n2 = 0;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) n2 += tv.v[k].re * tv.v[k].re + tv.v[k].im * tv.v[k].im;
+            acc[0] += (double)n2;
+        }
+        store_spinor<R, P>(y0, nullptr, V, s, yv);
+        R n2 = 0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) n2 += yv.v[k].re * yv.v[k].re + yv.v[k].im * yv.v[k].im;
+        acc[1] += (double)n2;
+    }
+    reduce_out<2>(acc, 2, lds, partials, sys, nblk);
+}
+
+// out[sys*stride + off + i] = sum over blocks of value sys*n + i (fixed order).
+__global__ void k_reduce_strided(const double* partials, int nblk, int n, int stride, int off, double* out) {
+    __shared__ double lds[kThreads];
+    const int v = blockIdx.x;
+    double t = 0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) t += partials[(size_t)v * nblk + b];
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)(v / n) * stride + off + v % n] = lds[0];
 }
 
 // out[sys*n + i] = sum over blocks (fixed order), optionally added to out.
@@ -295,10 +479,7 @@ hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, con
 #define TM_GS_LAUNCH(NVT)                                                                                          \
     TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL((k_gs<T, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, \
                                              cf, coef_stride, mode, y, fac, partials, V))
-    if (nvec <= 4 && mode == 1 && p == P_F32) {
-        hipLaunchKernelGGL((k_gs<float, 4, true>), grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, cf,
-                           coef_stride, mode, y, fac, partials, V);
-    } else if (nvec <= 4) {
+    if (nvec <= 4) {
         TM_GS_LAUNCH(4);
     } else if (nvec <= 8) {
         TM_GS_LAUNCH(8);
@@ -315,8 +496,67 @@ hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, con
     return hipGetLastError();
 }
 
-hipError_t blas_pythagoras(const double* hn, int nvec, int nsys, unsigned long long off, double* s, hipStream_t st) {
-    hipLaunchKernelGGL(k_pythagoras, dim3(1), dim3(64), 0, st, hn, nvec, nsys, off, s);
+hipError_t blas_dgs_dots(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, const VecRef& w,
+                        double* partials, double* out, int nsys, long long V, hipStream_t st) {
+    if (nb < 0 || nb > kMaxVec - 1 || (p != P_F64 && p != P_F32)) return hipErrorInvalidValue;
+    const int nblk = blas_blocks(V);
+    const int chunk = p == P_F32 ? 8 : 4;  // FP64 spinors take twice the registers
+    const int ds = 4 * nb + 4;
+    dim3 grid(nblk, nsys);
+    for (int i0 = 0;; i0 += chunk) {
+        const int n = nb - i0 < chunk ? nb - i0 : chunk;
+        const int head = i0 + n == nb;
+        if (p == P_F32)
+            hipLaunchKernelGGL((k_dgs_dots<float, 8>), grid, dim3(kThreads), 0, st, basis, vec_stride, i0, n, u, w,
+                               head, partials, V);
+        else
+            hipLaunchKernelGGL((k_dgs_dots<double, 4>), grid, dim3(kThreads), 0, st, basis, vec_stride, i0, n, u, w,
+                               head, partials, V);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int nv = 4 * n + (head ? 4 : 0);
+        hipLaunchKernelGGL(k_reduce_strided, dim3(nsys * nv), dim3(kThreads), 0, st, partials, nblk, nv, ds, 4 * i0,
+                           out);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (head) break;
+    }
+    return hipSuccess;
+}
+
+hipError_t blas_dgs_coef(const double* d, int nb, int nsys, unsigned long long off, double* coef, double* rep,
+                         hipStream_t st) {
+    if (nb < 0 || nb > kMaxVec - 1 || nsys > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dgs_coef, dim3(1), dim3(64), 0, st, d, 4 * nb + 4, nb, nsys, off, coef, 4 * nb + 4, rep);
+    return hipGetLastError();
+}
+
+hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, int write_u,
+                           const VecRef& w, const VecRef& y, const double* coef, double* partials, double* out,
+                           int nsys, long long V, hipStream_t st) {
+    if (nb < 0 || nb > kMaxVec - 1 || (p != P_F64 && p != P_F32)) return hipErrorInvalidValue;
+    const int nblk = blas_blocks(V);
+    dim3 grid(nblk, nsys);
+    const int cs = 4 * nb + 4;
+#define TM_DGS_LAUNCH(NVT)                                                                                       \
+    if (p == P_F32)                                                                                             \
+        hipLaunchKernelGGL((k_dgs_update<float, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nb, u,  \
+                           write_u, w, y, coef, cs, partials, V);                                               \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_dgs_update<double, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nb, u, \
+                           write_u, w, y, coef, cs, partials, V)
+    if (nb <= 4) {
+        TM_DGS_LAUNCH(4);
+    } else if (nb <= 8) {
+        TM_DGS_LAUNCH(8);
+    } else if (nb <= 16) {
+        TM_DGS_LAUNCH(16);
+    } else {
+        TM_DGS_LAUNCH(kMaxVec - 1);
+    }
+#undef TM_DGS_LAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(2 * nsys), dim3(kThreads), 0, st, partials, nblk, 2 * nsys, out, 0);
     return hipGetLastError();
 }
 

@@ -61,13 +61,14 @@ struct Pinned {
 
 // Device scratch of one solve (carved from the device's reduction buffer).
 struct Scratch {
-    double* h1;        // [nsys][kMaxVec][2]
-    double* h2;        // [nsys][kMaxVec][2]
-    double* nrm;       // [nsys]
     double* inv;       // [nsys]
     double* ones;      // [nsys]
     double* y;         // [nsys][kMaxVec][2]
     double* res;       // [nsys][2]
+    double* dots;      // [nsys][4 kMaxVec] Gram-Schmidt dots
+    double* coef;      // [nsys][4 kMaxVec] update coefficients
+    double* rep;       // [nsys][4] beta, h, s
+    double* nrm2;      // [nsys][2] norms of the update sweep
     double* partials;  // [nsys * 2 * kMaxVec][blocks]
 };
 
@@ -191,10 +192,41 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
     const int ns = c.nsys, m = K.m;
     int rc;
     std::vector<double> rn2(ns), bn2(ns), bnorm(ns);
-    std::vector<zc> H((size_t)ns * (m + 1) * m), sn((size_t)ns * m), gv((size_t)ns * (m + 1));
-    std::vector<double> cs((size_t)ns * m);
+    // per system: the Hessenberg columns as formed (Hraw) and after the Givens rotations (R), the
+    // rotations, and the rotated right-hand side g
+    std::vector<zc> Hraw((size_t)ns * (m + 1) * m), R((size_t)ns * (m + 1) * m), sn((size_t)ns * m),
+        gv((size_t)ns * (m + 1)), gsave(ns);
+    std::vector<double> cs((size_t)ns * m), sprev(ns);
     std::vector<int> kdim(ns);
     std::vector<char> frozen(ns);
+    // rotate column j of system k by the rotations of columns < j, form the rotation of column j
+    // and apply it to g (g_j, g_{j+1})
+    auto commit = [&](int k, int j) {
+        const zc* Hk = &Hraw[(size_t)k * (m + 1) * m];
+        zc* Rk = &R[(size_t)k * (m + 1) * m];
+        double* csk = &cs[(size_t)k * m];
+        zc* snk = &sn[(size_t)k * m];
+        zc* gk = &gv[(size_t)k * (m + 1)];
+        for (int i = 0; i <= j + 1; ++i) Rk[i * m + j] = Hk[i * m + j];
+        for (int i = 0; i < j; ++i) {
+            const zc a = Rk[i * m + j], b2 = Rk[(i + 1) * m + j];
+            Rk[i * m + j] = csk[i] * a + snk[i] * b2;
+            Rk[(i + 1) * m + j] = -std::conj(snk[i]) * a + csk[i] * b2;
+        }
+        const zc a = Rk[j * m + j], b2 = Rk[(j + 1) * m + j];
+        const double t = std::sqrt(std::norm(a) + std::norm(b2));
+        if (std::abs(a) == 0.0) {
+            csk[j] = 0.0;
+            snk[j] = 1.0;
+        } else {
+            csk[j] = std::abs(a) / t;
+            snk[j] = (a / std::abs(a)) * std::conj(b2) / t;
+        }
+        Rk[j * m + j] = csk[j] * a + snk[j] * b2;
+        Rk[(j + 1) * m + j] = 0.0;
+        gk[j + 1] = -std::conj(snk[j]) * gk[j];
+        gk[j] = csk[j] * gk[j];
+    };
     for (int k = 0; k < ns; ++k) out.iters[k] = 0;
     SpinorBuf V0 = K.Vb(c, 0);
     if ((rc = residual(c, rhs, x, x_zero, V0, rn2.data(), bn2.data()))) return rc;
@@ -224,14 +256,16 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             return rc;
         int jdone = 0;
         for (int j = 0; j < m && steps < max_iters; ++j) {
-            const SpinorBuf vj = K.Vb(c, j);
+            // slot j: v_0 at the first step, afterwards the direction u_j of the previous step,
+            // orthogonalised once; it becomes v_j in this step's update sweep
+            const SpinorBuf uj = K.Vb(c, j);
             const SpinorBuf zj = K.Zb(c, j);
-            SpinorBuf src = vj;
+            SpinorBuf src = uj;
             if (K.convert) {
-                if ((rc = hcheck(launch_spinor_convert(c.g, vj, K.vS, c.st), "convert"))) return rc;
+                if ((rc = hcheck(launch_spinor_convert(c.g, uj, K.vS, c.st), "convert"))) return rc;
                 src = K.vS;
             }
-            // z_j = SAP(v_j) from a zero guess; w = D z_j
+            // z_j = SAP(u_j) from a zero guess; w = D z_j
             if ((rc = hcheck(hipEventRecord(c.ev[0], c.st), "event"))) return rc;
             if (c.mg)
                 rc = mg_apply(c.mg, c.ds, src, zj, c.mu, ns, c.st);
@@ -242,40 +276,35 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             c.sap_cycles += c.n_cycles;
             c.sap_sys_cycles += (long long)c.n_cycles * ns;
             if ((rc = run_dirac(c.g, *c.op, zj, K.w, c.mu, ns, c.op_compute, c.st))) return rc;
-            // classical Gram-Schmidt, twice, in three passes: h1 = V^H w; w -= V h1 with h2 = V^H w and
-            // ||w||^2; v_{j+1} = (w - V h2) s with s = 1 / sqrt(||w||^2 - |h2|^2) (Pythagoras), which
-            // also returns ||w - V h2||^2 to check the normalisation
-            const VecRef basis = vec_ref(K.Vb(c, 0), V), wr = vec_ref(K.w, V);
-            const SpinorBuf vn = K.Vb(c, j + 1);
-            const int nv = j + 1;
+            // classical Gram-Schmidt with delayed reorthogonalisation: one sweep for the dots of
+            // v_0..v_{j-1} with u_j and w (and <u,u>, <u,w>, <w,w>), then one sweep that finishes
+            // v_j = (u_j - V V^H u_j) / beta and writes u_{j+1} = s (w - V_j V_j^H w), projected
+            // once; its second projection is the first part of the next step
+            const VecRef basis = vec_ref(K.Vb(c, 0), V), wr = vec_ref(K.w, V), ur = vec_ref(uj, V);
+            const SpinorBuf un = K.Vb(c, j + 1);
             unsigned long long off = 0;
             for (int k = 0; k < ns; ++k)
                 if (frozen[k]) off |= 1ull << k;
-            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, nullptr, 0, 0, wr, nullptr, c.sc.partials,
-                                     c.sc.h1, 0, ns, V, c.st),
+            if ((rc = hcheck(blas_dgs_dots(c.vp, basis, K.vstride, j, ur, wr, c.sc.partials, c.sc.dots, ns, V, c.st),
                              "gs")))
                 return rc;
-            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h1, 2 * nv, 1, wr, nullptr, c.sc.partials,
-                                     c.sc.h2, 0, ns, V, c.st),
+            if ((rc = hcheck(blas_dgs_coef(c.sc.dots, j, ns, off, c.sc.coef, c.sc.rep, c.st), "gs"))) return rc;
+            if ((rc = hcheck(blas_dgs_update(c.vp, basis, K.vstride, j, ur, j > 0, wr, vec_ref(un, V), c.sc.coef,
+                                             c.sc.partials, c.sc.nrm2, ns, V, c.st),
                              "gs")))
                 return rc;
-            if ((rc = hcheck(blas_pythagoras(c.sc.h2, nv, ns, off, c.sc.inv, c.st), "gs"))) return rc;
-            if ((rc = hcheck(blas_gs(c.vp, basis, K.vstride, nv, wr, c.sc.h2, 2 * nv + 1, 3, vec_ref(vn, V),
-                                     c.sc.inv, c.sc.partials, c.sc.nrm, 0, ns, V, c.st),
-                             "gs")))
+            const int ds = 4 * j + 4;
+            const size_t nd = (size_t)ns * ds;
+            double* st_d = c.hstage;
+            double* st_rep = st_d + nd;
+            double* st_n = st_rep + 4 * (size_t)ns;
+            if ((rc = hcheck(hipMemcpyAsync(st_d, c.sc.dots, nd * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
                 return rc;
-            const size_t nh1 = (size_t)ns * nv * 2, nh2 = (size_t)ns * (2 * nv + 1);
-            double* st_h1 = c.hstage;
-            double* st_h2 = st_h1 + nh1;
-            double* st_nrm = st_h2 + nh2;
-            double* st_s = st_nrm + ns;
-            if ((rc = hcheck(hipMemcpyAsync(st_h1, c.sc.h1, nh1 * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
+            if ((rc = hcheck(hipMemcpyAsync(st_rep, c.sc.rep, 4 * ns * sizeof(double), hipMemcpyDeviceToHost, c.st),
+                             "copy")))
                 return rc;
-            if ((rc = hcheck(hipMemcpyAsync(st_h2, c.sc.h2, nh2 * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
-                return rc;
-            if ((rc = hcheck(hipMemcpyAsync(st_nrm, c.sc.nrm, ns * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
-                return rc;
-            if ((rc = hcheck(hipMemcpyAsync(st_s, c.sc.inv, ns * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
+            if ((rc = hcheck(hipMemcpyAsync(st_n, c.sc.nrm2, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, c.st),
+                             "copy")))
                 return rc;
             if ((rc = hcheck(hipStreamSynchronize(c.st), "arnoldi step"))) return rc;
             float ms = 0;
@@ -283,7 +312,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             ++steps;
             // a non-finite Hessenberg entry (an overflow in the preconditioner
             // or the operator) would otherwise read as a breakdown
-            for (size_t i = 0; i < nh1 + nh2 + 2 * (size_t)ns; ++i)
+            for (size_t i = 0; i < nd + 6 * (size_t)ns; ++i)
                 if (!std::isfinite(c.hstage[i]))
                     return fail(TM_ERR_NONFINITE, "non-finite value in the Arnoldi step %d (preconditioned vector)",
                                 steps);
@@ -291,49 +320,47 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             std::vector<double> fix(ns, 1.0);
             for (int k = 0; k < ns; ++k) {
                 if (frozen[k]) continue;
-                ++out.iters[k];
-                zc* Hk = &H[(size_t)k * (m + 1) * m];
-                for (int i = 0; i < nv; ++i) {
-                    const double* a = st_h1 + ((size_t)k * nv + i) * 2;
-                    const double* b2 = st_h2 + (size_t)k * (2 * nv + 1) + 2 * i;
-                    Hk[i * m + j] = zc(a[0] + b2[0], a[1] + b2[1]);
-                }
-                // v_{j+1} = (w - V h2) s, so h_{j+1,j} = 1/s keeps the Arnoldi relation exact; when the
-                // Pythagorean norm was off (cancellation), v_{j+1} is rescaled to unit norm
-                const double sk = st_s[k], t2 = std::max(0.0, st_nrm[k]);
-                double hn = 0.0;
-                if (sk > 0 && t2 > 0) {
-                    const double ratio = sk * std::sqrt(t2);  // ||v_{j+1}||
-                    if (std::fabs(ratio - 1.0) > 1e-4) {
-                        fix[k] = 1.0 / ratio;
-                        rescale = true;
-                        hn = std::sqrt(t2);
-                    } else {
-                        hn = 1.0 / sk;
-                    }
-                }
-                Hk[(j + 1) * m + j] = hn;
-                double* csk = &cs[(size_t)k * m];
-                zc* snk = &sn[(size_t)k * m];
+                const double* dk = st_d + (size_t)k * ds;
+                const double* rk = st_rep + 4 * (size_t)k;
+                const double* nk = st_n + 2 * (size_t)k;
+                zc* Hk = &Hraw[(size_t)k * (m + 1) * m];
                 zc* gk = &gv[(size_t)k * (m + 1)];
-                for (int i = 0; i < j; ++i) {
-                    const zc a = Hk[i * m + j], b2 = Hk[(i + 1) * m + j];
-                    Hk[i * m + j] = csk[i] * a + snk[i] * b2;
-                    Hk[(i + 1) * m + j] = -std::conj(snk[i]) * a + csk[i] * b2;
+                double f = 1.0;  // ||v_j|| as written
+                if (j > 0) {
+                    // finish column j-1: w_{j-1} = V h + u_j / s_{j-1} with u_j = V c + beta v_j
+                    const double beta = rk[0], sj = sprev[k];
+                    gk[j - 1] = gsave[k];  // undo the provisional rotation of column j-1
+                    for (int i = 0; i < j; ++i) Hk[i * m + j - 1] += zc(dk[4 * i], dk[4 * i + 1]) / sj;
+                    if (beta == 0.0) {
+                        // u_j lies in the span of v_0..v_{j-1}: column j-1 closes the Krylov space
+                        Hk[j * m + j - 1] = 0.0;
+                        commit(k, j - 1);
+                        kdim[k] = j;
+                        frozen[k] = 1;
+                        continue;
+                    }
+                    // v_j = (u_j - V c) / beta with beta by Pythagoras; when that norm was off
+                    // (cancellation), v_j is rescaled to unit norm
+                    const double nv = std::sqrt(std::max(0.0, nk[0]));
+                    if (nv > 0 && std::fabs(nv - 1.0) > 1e-4) {
+                        f = nv;
+                        fix[k] = 1.0 / nv;
+                        rescale = true;
+                    }
+                    Hk[j * m + j - 1] = beta * f / sj;
+                    commit(k, j - 1);
                 }
-                const zc a = Hk[j * m + j], b2 = Hk[(j + 1) * m + j];
-                const double t = std::sqrt(std::norm(a) + std::norm(b2));
-                if (std::abs(a) == 0.0) {
-                    csk[j] = 0.0;
-                    snk[j] = 1.0;
-                } else {
-                    csk[j] = std::abs(a) / t;
-                    snk[j] = (a / std::abs(a)) * std::conj(b2) / t;
-                }
-                Hk[j * m + j] = csk[j] * a + snk[j] * b2;
-                Hk[(j + 1) * m + j] = 0.0;
-                gk[j + 1] = -std::conj(snk[j]) * gk[j];
-                gk[j] = csk[j] * gk[j];
+                ++out.iters[k];
+                // provisional column j (its second projection comes with the next step):
+                // w_j = V_{j-1} a + h v_j + u_{j+1} / s
+                for (int i = 0; i < j; ++i) Hk[i * m + j] = zc(dk[4 * i + 2], dk[4 * i + 3]);
+                Hk[j * m + j] = zc(rk[1], rk[2]) * f;
+                const double s = rk[3];
+                const double hn = s > 0 ? std::sqrt(std::max(0.0, nk[1])) / s : 0.0;
+                Hk[(j + 1) * m + j] = hn;
+                sprev[k] = s;
+                gsave[k] = gk[j];
+                commit(k, j);
                 kdim[k] = j + 1;
                 const bool done = std::abs(gk[j + 1]) <= tol[k] * bnorm[k] || hn == 0.0;
                 if (done) frozen[k] = 1;
@@ -357,22 +384,20 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                 if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st),
                                  "copy")))
                     return rc;
-                if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(vn, V), c.sc.inv, vec_ref(vn, V), ns, V, c.st),
-                                 "scale")))
-                    return rc;
+                if ((rc = hcheck(blas_scale(c.vp, c.vp, ur, c.sc.inv, ur, ns, V, c.st), "scale"))) return rc;
             }
             if (all_frozen) break;
         }
         // x += Z y, y = R^-1 g per system (zero beyond its Krylov dimension)
         std::vector<double> yh((size_t)ns * jdone * 2, 0.0);
         for (int k = 0; k < ns; ++k) {
-            const zc* Hk = &H[(size_t)k * (m + 1) * m];
+            const zc* Rk = &R[(size_t)k * (m + 1) * m];
             const zc* gk = &gv[(size_t)k * (m + 1)];
             std::vector<zc> y(kdim[k]);
             for (int i = kdim[k] - 1; i >= 0; --i) {
                 zc t = gk[i];
-                for (int q = i + 1; q < kdim[k]; ++q) t -= Hk[i * m + q] * y[q];
-                y[i] = t / Hk[i * m + i];
+                for (int q = i + 1; q < kdim[k]; ++q) t -= Rk[i * m + q] * y[q];
+                y[i] = t / Rk[i * m + i];
             }
             for (int i = 0; i < kdim[k]; ++i) {
                 yh[((size_t)k * jdone + i) * 2] = y[i].real();
@@ -400,19 +425,20 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
 int carve_scratch(Ctx& c) {
     const int nblk = blas_blocks(c.g.V);
     const size_t nvals = (size_t)c.nsys * 2 * blas_max_vec();
-    const size_t doubles = 2 * nvals + 4 * c.nsys + nvals + 2 * c.nsys + nvals * nblk + 64;
+    const size_t doubles = 3 * c.nsys + nvals + 2 * c.nsys + 4 * nvals + 6 * c.nsys + nvals * nblk + 64;
     hipError_t e = c.ds->red.ensure(doubles * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "solver scratch");
     double* p = (double*)c.ds->red.ptr;
-    c.sc.h1 = p; p += nvals;
-    c.sc.h2 = p; p += nvals;
-    c.sc.nrm = p; p += c.nsys;
     c.sc.inv = p; p += c.nsys;
     c.sc.ones = p; p += c.nsys;
     c.sc.y = p; p += nvals;
     c.sc.res = p; p += 2 * c.nsys;
+    c.sc.dots = p; p += 2 * nvals;
+    c.sc.coef = p; p += 2 * nvals;
+    c.sc.rep = p; p += 4 * c.nsys;
+    c.sc.nrm2 = p; p += 2 * c.nsys;
     c.sc.partials = p;
-    const size_t stage = 2 * nvals + c.nsys + 32, hinv = c.nsys + 32, hy = nvals + 32;
+    const size_t stage = 2 * nvals + 8 * c.nsys + 32, hinv = c.nsys + 32, hy = nvals + 32;
     e = c.host.ensure(stage + hinv + hy);
     if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
     c.hstage = c.host.p;
