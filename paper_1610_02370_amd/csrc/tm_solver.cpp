@@ -185,9 +185,13 @@ struct CoreResult {
 // FGMRES(m) for D x = rhs, x in/out, all vectors at c.vp.  Stops per system k at
 // ||rhs - D x|| <= tol[k] ||rhs|| (residual recomputed at every restart at the
 // operator's precision) or when max_iters Arnoldi steps were taken.  Systems
-// in the `skip` mask are frozen from the start and keep x as it is.
+// in the `skip` mask are frozen from the start and keep x as it is.  With
+// trust_estimate, a cycle in which every system met its tolerance by the
+// least-squares residual estimate ends the solve without recomputing the
+// residual (out.rel then holds the estimates): for inner solves whose caller
+// computes the true residual next.
 int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const double* tol,
-                int max_iters, CoreResult& out, unsigned long long skip = 0) {
+                int max_iters, CoreResult& out, unsigned long long skip = 0, bool trust_estimate = false) {
     const long long V = c.g.V;
     const int ns = c.nsys, m = K.m;
     int rc;
@@ -389,6 +393,8 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             if (all_frozen) break;
         }
         // x += Z y, y = R^-1 g per system (zero beyond its Krylov dimension)
+        bool by_estimate = trust_estimate;
+        for (int k = 0; k < ns; ++k) by_estimate &= (bool)frozen[k];
         std::vector<double> yh((size_t)ns * jdone * 2, 0.0);
         for (int k = 0; k < ns; ++k) {
             const zc* Rk = &R[(size_t)k * (m + 1) * m];
@@ -415,6 +421,14 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                                           c.sc.y, ns, V, c.st),
                              "x update")))
                 return rc;
+        }
+        if (by_estimate) {
+            for (int k = 0; k < ns; ++k) {
+                if (((skip >> k) & 1ull) || bnorm[k] == 0) continue;
+                out.rel[k] = std::abs(gv[(size_t)k * (m + 1) + kdim[k]]) / bnorm[k];
+                out.conv[k] = true;
+            }
+            return TM_OK;
         }
         x_zero = false;
         if ((rc = residual(c, rhs, x, false, V0, rn2.data(), bn2.data()))) return rc;
@@ -596,13 +610,24 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
         if ((rc = hcheck(hipStreamSynchronize(st), "import"))) return rc;
         if (hflag) return fail(TM_ERR_NONFINITE, "b or x holds NaN or Inf");
 
+        // a zero starting vector (every system of the group) makes the first residual b itself
+        if ((rc = hcheck(blas_gs(P_F64, vec_ref(xx, V), 0, 0, vec_ref(xx, V), nullptr, 0, 2, vec_ref(xx, V), nullptr,
+                                 c.sc.partials, c.sc.res, 0, ns, V, st),
+                         "norm")))
+            return rc;
+        if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy")))
+            return rc;
+        if ((rc = hcheck(hipStreamSynchronize(st), "norm"))) return rc;
+        bool x_zero = true;
+        for (int k = 0; k < ns; ++k) x_zero &= c.hstage[k] == 0.0;
+
         CoreResult res;
         if (!dc) {
             c.op = op64;
             c.op_compute = P_F64;
             Krylov K = carve_krylov(p, g, ns, m, vp, sp);
             std::vector<double> tols(ns, tol);
-            if ((rc = fgmres_core(c, K, bb, xx, false, tols.data(), so->max_iters, res))) return rc;
+            if ((rc = fgmres_core(c, K, bb, xx, x_zero, tols.data(), so->max_iters, res))) return rc;
             for (int k = 0; k < ns; ++k) {
                 rep.true_rel_res[g0 + k] = res.rel[k];
                 rep.iters = std::max(rep.iters, res.iters[k]);
@@ -622,11 +647,29 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
             int outer = 0;
             bool done = false;
             for (;;) {
-                // FP64 residual of the current iterate
+                // FP64 residual of the current iterate (b itself for a zero start: then the
+                // inner solve's right-hand side is converted from b)
                 c.vp = P_F64;
                 c.op = op64;
                 c.op_compute = P_F64;
-                if ((rc = residual(c, bb, xx, false, rr, rn2.data(), bn2.data()))) return rc;
+                const bool r_is_b = x_zero && outer == 0;
+                if (r_is_b) {
+                    if ((rc = hcheck(blas_gs(P_F64, vec_ref(bb, V), 0, 0, vec_ref(bb, V), nullptr, 0, 2,
+                                             vec_ref(bb, V), nullptr, c.sc.partials, c.sc.res, 0, ns, V, st),
+                                     "norm")))
+                        return rc;
+                    if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, ns * sizeof(double), hipMemcpyDeviceToHost,
+                                                    st),
+                                     "copy")))
+                        return rc;
+                    if ((rc = hcheck(hipStreamSynchronize(st), "norm"))) return rc;
+                    for (int k = 0; k < ns; ++k) {
+                        rn2[k] = bn2[k] = c.hstage[k];
+                        if (!std::isfinite(rn2[k])) return fail(TM_ERR_NONFINITE, "non-finite residual of system %d", k);
+                    }
+                } else if ((rc = residual(c, bb, xx, false, rr, rn2.data(), bn2.data()))) {
+                    return rc;
+                }
                 done = true;
                 for (int k = 0; k < ns; ++k) {
                     const double rel = bn2[k] > 0 ? std::sqrt(rn2[k] / bn2[k]) : 0.0;
@@ -644,7 +687,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                 }
                 if (done || outer >= so->max_outer || maxit >= so->max_iters) break;
                 // inner FP32 solve of D c = r to inner_tol, then x += c
-                if ((rc = hcheck(launch_spinor_convert(g, rr, r32, st), "convert"))) return rc;
+                if ((rc = hcheck(launch_spinor_convert(g, r_is_b ? bb : rr, r32, st), "convert"))) return rc;
                 c.vp = P_F32;
                 c.op = op32;
                 c.op_compute = P_F32;
@@ -671,7 +714,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                     std::fflush(stderr);
                 }
                 if ((rc = hcheck(blas_zero(c32.data, internal_bytes(g, ns, P_F32), st), "zero"))) return rc;
-                if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res, skip)))
+                if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res, skip, true)))
                     return rc;
                 for (int k = 0; k < ns; ++k) iters[k] += res.iters[k];
                 if ((rc = hcheck(blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st),
