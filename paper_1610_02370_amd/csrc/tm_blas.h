@@ -54,9 +54,10 @@ hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int n
 // y = a[sys] x
 hipError_t blas_scale(Prec pi, Prec po, const VecRef& x, const double* a, const VecRef& y, int nsys, long long V,
                       hipStream_t st);
-// x += sum_i y[sys][i] z_i  (z_i at z.data + i*zvec_stride, scales at z.scale + i*zscale_stride)
+// x += sum_i y[sys][i] z_i  (z_i at z.data + i*zvec_stride, scales at z.scale + i*zscale_stride);
+// with overwrite != 0, x = sum_i y[sys][i] z_i and x is not read
 hipError_t blas_xupdate(Prec px, Prec pz, const VecRef& x, const VecRef& z, size_t zvec_stride, size_t zscale_stride,
-                        int nvec, const double* y, int nsys, long long V, hipStream_t st);
+                        int nvec, const double* y, int overwrite, int nsys, long long V, hipStream_t st);
 // r = b - ax, out[sys] = (||r||^2, ||b||^2)
 hipError_t blas_residual(Prec p, const VecRef& b, const VecRef& ax, const VecRef& r, double* partials, double* out,
                          int nsys, long long V, hipStream_t st);

@@ -363,14 +363,20 @@ __global__ void __launch_bounds__(kThreads) k_scale(VecRef x, const double* a, V
     }
 }
 
-// x += sum_i y_i z_i, y complex per (sys, i) from device memory
+// x += sum_i y_i z_i (x = sum_i y_i z_i with `overwrite`: x is not read), y complex per
+// (sys, i) from device memory
 template <class Px, class Pz>
 __global__ void __launch_bounds__(kThreads) k_xupdate(VecRef x, VecRef z, size_t zvec_stride, size_t zscale_stride,
-                                                      int nvec, const double* y, long long V) {
+                                                      int nvec, const double* y, int overwrite, long long V) {
     const int sys = blockIdx.y;
     for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)gridDim.x * kThreads) {
         Spinor<double> xv;
-        ld<Px>(x, sys, V, s, xv);
+        if (overwrite) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) xv.v[k] = cmk(0.0, 0.0);
+        } else {
+            ld<Px>(x, sys, V, s, xv);
+        }
         for (int i = 0; i < nvec; ++i) {
             VecRef zi = z;
             zi.data = static_cast<char*>(z.data) + i * zvec_stride;
@@ -569,11 +575,11 @@ hipError_t blas_scale(Prec pi, Prec po, const VecRef& x, const double* a, const 
 }
 
 hipError_t blas_xupdate(Prec px, Prec pz, const VecRef& x, const VecRef& z, size_t zvec_stride, size_t zscale_stride,
-                        int nvec, const double* y, int nsys, long long V, hipStream_t st) {
+                        int nvec, const double* y, int overwrite, int nsys, long long V, hipStream_t st) {
     dim3 grid(blas_blocks(V), nsys);
     TM_DISPATCH_VEC(px, Tx, TM_DISPATCH_VEC(pz, Tz, hipLaunchKernelGGL((k_xupdate<Tx, Tz>), grid, dim3(kThreads), 0,
                                                                         st, x, z, zvec_stride, zscale_stride, nvec, y,
-                                                                        V)));
+                                                                        overwrite, V)));
     return hipGetLastError();
 }
 

@@ -139,15 +139,14 @@ Krylov carve_krylov(char*& p, const Geo& g, int nsys, int m, Prec vp, Prec sp) {
     return k;
 }
 
-// r = rhs - D x (or r = rhs when x is zero); host gets ||r||^2 and ||rhs||^2.
+// r = rhs - D x; host gets ||r||^2 and ||rhs||^2.  When x is zero the residual is rhs
+// itself: r is not written, only the norm of rhs is taken.
 int residual(Ctx& c, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const SpinorBuf& r, double* rn2,
              double* bn2) {
     const long long V = c.g.V;
     int rc;
     if (x_zero) {
-        if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(rhs, V), c.sc.ones, vec_ref(r, V), c.nsys, V, c.st), "copy")))
-            return rc;
-        if ((rc = hcheck(blas_gs(c.vp, vec_ref(r, V), 0, 0, vec_ref(r, V), nullptr, 0, 2, vec_ref(r, V), nullptr,
+        if ((rc = hcheck(blas_gs(c.vp, vec_ref(rhs, V), 0, 0, vec_ref(rhs, V), nullptr, 0, 2, vec_ref(rhs, V), nullptr,
                                  c.sc.partials, c.sc.res, 0,
                                  c.nsys, V, c.st),
                          "norm")))
@@ -180,18 +179,23 @@ struct CoreResult {
     int iters[kMaxSys];
     double rel[kMaxSys];
     bool conv[kMaxSys];
+    bool accumulated;  // the solution was added to x_acc (x left as it was)
 };
 
 // FGMRES(m) for D x = rhs, x in/out, all vectors at c.vp.  Stops per system k at
 // ||rhs - D x|| <= tol[k] ||rhs|| (residual recomputed at every restart at the
 // operator's precision) or when max_iters Arnoldi steps were taken.  Systems
-// in the `skip` mask are frozen from the start and keep x as it is.  With
-// trust_estimate, a cycle in which every system met its tolerance by the
-// least-squares residual estimate ends the solve without recomputing the
-// residual (out.rel then holds the estimates): for inner solves whose caller
-// computes the true residual next.
+// in the `skip` mask are frozen from the start and keep x as it is.  x_zero:
+// x is taken as zero and its contents are not read.  With trust_estimate, a
+// cycle in which every system met its tolerance by the least-squares residual
+// estimate ends the solve without recomputing the residual (out.rel then holds
+// the estimates): for inner solves whose caller computes the true residual
+// next.  With x_acc (FP64, same systems), a solve from zero that ends that way
+// in its first cycle adds its solution to *x_acc instead of writing x
+// (out.accumulated).
 int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const double* tol,
-                int max_iters, CoreResult& out, unsigned long long skip = 0, bool trust_estimate = false) {
+                int max_iters, CoreResult& out, unsigned long long skip = 0, bool trust_estimate = false,
+                const SpinorBuf* x_acc = nullptr) {
     const long long V = c.g.V;
     const int ns = c.nsys, m = K.m;
     int rc;
@@ -232,8 +236,10 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
         gk[j] = csk[j] * gk[j];
     };
     for (int k = 0; k < ns; ++k) out.iters[k] = 0;
+    out.accumulated = false;
     SpinorBuf V0 = K.Vb(c, 0);
     if ((rc = residual(c, rhs, x, x_zero, V0, rn2.data(), bn2.data()))) return rc;
+    bool r_in_rhs = x_zero;  // the residual is rhs itself until x changes
     for (int k = 0; k < ns; ++k) bnorm[k] = std::sqrt(bn2[k]);
     int steps = 0;
     for (;;) {
@@ -256,8 +262,11 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
         }
         if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st), "copy")))
             return rc;
-        if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(V0, V), c.sc.inv, vec_ref(V0, V), ns, V, c.st), "scale")))
+        if ((rc = hcheck(blas_scale(c.vp, c.vp, vec_ref(r_in_rhs ? rhs : V0, V), c.sc.inv, vec_ref(V0, V), ns, V,
+                                    c.st),
+                         "scale")))
             return rc;
+        r_in_rhs = false;
         int jdone = 0;
         for (int j = 0; j < m && steps < max_iters; ++j) {
             // slot j: v_0 at the first step, afterwards the direction u_j of the previous step,
@@ -417,10 +426,17 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                 return rc;
             const SpinorBuf z0 = K.Zb(c, 0);
             const size_t zscale_stride = K.zstride / sizeof(float);
-            if ((rc = hcheck(blas_xupdate(c.vp, c.sp, vec_ref(x, V), vec_ref(z0, V), K.zstride, zscale_stride, jdone,
-                                          c.sc.y, ns, V, c.st),
-                             "x update")))
+            out.accumulated = x_acc && x_zero && by_estimate;
+            if (out.accumulated) {
+                if ((rc = hcheck(blas_xupdate(P_F64, c.sp, vec_ref(*x_acc, V), vec_ref(z0, V), K.zstride,
+                                              zscale_stride, jdone, c.sc.y, 0, ns, V, c.st),
+                                 "x update")))
+                    return rc;
+            } else if ((rc = hcheck(blas_xupdate(c.vp, c.sp, vec_ref(x, V), vec_ref(z0, V), K.zstride, zscale_stride,
+                                                 jdone, c.sc.y, x_zero, ns, V, c.st),
+                                    "x update"))) {
                 return rc;
+            }
         }
         if (by_estimate) {
             for (int k = 0; k < ns; ++k) {
@@ -432,6 +448,13 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
         }
         x_zero = false;
         if ((rc = residual(c, rhs, x, false, V0, rn2.data(), bn2.data()))) return rc;
+    }
+    if (x_zero) {
+        // no cycle ran: the solution is zero
+        if (x_acc)
+            out.accumulated = true;
+        else if ((rc = hcheck(blas_zero(x.data, internal_bytes(c.g, ns, c.vp), c.st), "zero")))
+            return rc;
     }
     return TM_OK;
 }
@@ -713,11 +736,12 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                                      ((skip >> k) & 1ull) ? " (converged, skipped)" : "");
                     std::fflush(stderr);
                 }
-                if ((rc = hcheck(blas_zero(c32.data, internal_bytes(g, ns, P_F32), st), "zero"))) return rc;
-                if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res, skip, true)))
+                if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res, skip, true,
+                                      &xx)))
                     return rc;
                 for (int k = 0; k < ns; ++k) iters[k] += res.iters[k];
-                if ((rc = hcheck(blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st),
+                if (!res.accumulated &&
+                    (rc = hcheck(blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st),
                                  "accumulate")))
                     return rc;
                 ++outer;
