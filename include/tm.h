@@ -207,10 +207,12 @@ typedef struct {
                              this call's U, kappa and c_sw: a handle set up for other ones still
                              gives solutions to tol (FGMRES admits any preconditioner), only in
                              more iterations */
+    int x_in;             /* 1: x holds the starting vector; 0: the solve starts from zero and x is
+                             output only (its contents are not read) */
 } tm_solver_opts;
 
 /* restart 20, max_iters 2000, 4 cycles, 4 MR steps, 4^4 blocks, flexible form,
- * inner_tol 1e-6, max_outer 50, group 0, no two-level method. */
+ * inner_tol 1e-6, max_outer 50, group 0, no two-level method, x_in 1. */
 TM_API void tm_solver_opts_default(tm_solver_opts* sopts);
 
 typedef struct {
@@ -234,7 +236,8 @@ typedef struct {
  * a fixed linear map).  TM_SOLVE_FLEXIBLE keeps the Krylov basis in FP64 and
  * runs SAP at opts->storage; TM_SOLVE_DEFECT_CORRECTION repeats
  * r = b - D x (FP64), an FP32 FGMRES+SAP solve of D c = r to inner_tol, and
- * x += c (the mixed-precision solver of section 3.1).  x is in/out.  Returns
+ * x += c (the mixed-precision solver of section 3.1).  x is in/out (output
+ * only with sopts->x_in 0).  Returns
  * TM_OK when every system converged, TM_NOT_CONVERGED otherwise (report
  * filled; x holds the last iterate).  report may be NULL.
  */

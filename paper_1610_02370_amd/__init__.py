@@ -59,7 +59,7 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("n_cycles", ctypes.c_int), ("mr_iters", ctypes.c_int), ("block_dims", ctypes.c_int * 4),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("group", ctypes.c_int),
-                ("mg", ctypes.c_void_p)]
+                ("mg", ctypes.c_void_p), ("x_in", ctypes.c_int)]
 
 
 class MgParams(ctypes.Structure):
@@ -318,13 +318,14 @@ def _sap(fn, dims, U, b, x, kappa, mu, c_sw, block_dims, n_cycles, mr_iters, sto
 
 def solver_opts(form: str = "flexible", restart: int = 20, max_iters: int = 2000, n_cycles: int = 4,
                 mr_iters: int = 4, block_dims=(4, 4, 4, 4), inner_tol: float = 1e-6, max_outer: int = 50,
-                group: int = 0) -> SolverOpts:
+                group: int = 0, x_in: bool = True) -> SolverOpts:
     s = SolverOpts()
     lib().tm_solver_opts_default(ctypes.byref(s))
     s.form = FORMS[form]
     s.restart, s.max_iters, s.n_cycles, s.mr_iters = int(restart), int(max_iters), int(n_cycles), int(mr_iters)
     s.block_dims = (ctypes.c_int * 4)(*[int(v) for v in (block_dims or (0, 0, 0, 0))])
     s.inner_tol, s.max_outer, s.group = float(inner_tol), int(max_outer), int(group)
+    s.x_in = int(bool(x_in))
     return s
 
 
@@ -334,7 +335,8 @@ def tm_fgmres_solve(dims, U, b, x, kappa: float, mu, c_sw: float, tol: float, *,
                     eo: bool = False, mg: "MG | None" = None, **solver_kw):
     """Solve D(mu_k) x_k = b_k to a true relative residual tol; returns (status, report dict).
 
-    mg: a two-level handle (MG) whose method preconditions FGMRES instead of SAP."""
+    mg: a two-level handle (MG) whose method preconditions FGMRES instead of SAP.
+    x_in=False (a solver option): the solve starts from zero and x is output only."""
     g = make_geom(dims, mu, antiperiodic_t, theta, mu_shift)
     o = make_opts(storage, stream=stream, gauge_tag=gauge_tag)
     o.sys_tile = int(sys_tile)

@@ -518,6 +518,7 @@ void tm_solver_opts_default(tm_solver_opts* s) {
     s->inner_tol = 1e-6;
     s->max_outer = 50;
     s->group = 0;
+    s->x_in = 1;
 }
 
 int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, double kappa, double c_sw, double tol,
@@ -627,22 +628,28 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
         unsigned* flag = (unsigned*)ds->stats.ptr + 2;
         if ((rc = hcheck(hipMemsetAsync(flag, 0, sizeof(unsigned), st), "memset"))) return rc;
         if ((rc = hcheck(launch_spinor_import(g, bb, bcan, flag, st), "import b"))) return rc;
-        if ((rc = hcheck(launch_spinor_import(g, xx, xcan, flag, st), "import x"))) return rc;
+        if (so->x_in && (rc = hcheck(launch_spinor_import(g, xx, xcan, flag, st), "import x"))) return rc;
         unsigned hflag = 0;
         if ((rc = hcheck(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st), "copy"))) return rc;
         if ((rc = hcheck(hipStreamSynchronize(st), "import"))) return rc;
         if (hflag) return fail(TM_ERR_NONFINITE, "b or x holds NaN or Inf");
 
-        // a zero starting vector (every system of the group) makes the first residual b itself
-        if ((rc = hcheck(blas_gs(P_F64, vec_ref(xx, V), 0, 0, vec_ref(xx, V), nullptr, 0, 2, vec_ref(xx, V), nullptr,
-                                 c.sc.partials, c.sc.res, 0, ns, V, st),
-                         "norm")))
-            return rc;
-        if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy")))
-            return rc;
-        if ((rc = hcheck(hipStreamSynchronize(st), "norm"))) return rc;
+        // a zero starting vector (every system of the group) makes the first residual b itself;
+        // without x_in the FP64 iterate starts as zeros
         bool x_zero = true;
-        for (int k = 0; k < ns; ++k) x_zero &= c.hstage[k] == 0.0;
+        if (so->x_in) {
+            if ((rc = hcheck(blas_gs(P_F64, vec_ref(xx, V), 0, 0, vec_ref(xx, V), nullptr, 0, 2, vec_ref(xx, V),
+                                     nullptr, c.sc.partials, c.sc.res, 0, ns, V, st),
+                             "norm")))
+                return rc;
+            if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, ns * sizeof(double), hipMemcpyDeviceToHost, st),
+                             "copy")))
+                return rc;
+            if ((rc = hcheck(hipStreamSynchronize(st), "norm"))) return rc;
+            for (int k = 0; k < ns; ++k) x_zero &= c.hstage[k] == 0.0;
+        } else if ((rc = hcheck(blas_zero(xx.data, internal_bytes(g, ns, P_F64), st), "zero"))) {
+            return rc;
+        }
 
         CoreResult res;
         if (!dc) {

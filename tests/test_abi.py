@@ -39,6 +39,10 @@ def test_host_only_calls():
     assert n16 == 3 * 6 * 4096 * 8 + 3 * 4096 * 4
     s = tm.solver_opts()
     assert (s.restart, s.n_cycles, s.mr_iters, tuple(s.block_dims)) == (20, 4, 4, (4, 4, 4, 4))
+    # the library's own defaults, down to the last field of the struct (x is read by default)
+    raw = tm.SolverOpts()
+    tm.lib().tm_solver_opts_default(ctypes.byref(raw))
+    assert raw.x_in == 1 and raw.mg is None and raw.inner_tol == 1e-6
     # the FMA probe rejects a missing output before it touches a device
     o = tm.make_opts("f32", stream=False)
     assert tm.lib().tm_probe_fp32_fma(None, ctypes.byref(o)) == -1

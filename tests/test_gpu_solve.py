@@ -121,6 +121,26 @@ def test_nonzero_initial_guess_and_antiperiodic():
     check_solutions(op, dims, b, host(x), [mu], TOL, "nonzero guess antiperiodic", "f32")
 
 
+@pytest.mark.parametrize("form", ["flexible", "defect_correction"])
+def test_zero_start_without_reading_x(form):
+    # x_in=False: x is output only, so NaNs in it change nothing; the result equals the solve
+    # from an x of zeros bit for bit (both start from the zero vector)
+    dims, kappa, mu, csw = (8, 4, 4, 8), 0.1394, 0.01, 1.5
+    U = synth.gauge_field(dims, 0.6, seed=3)
+    b = synth.gaussian_spinor(dims, 2, seed=104)
+    announce(f"solve from zero without reading x, {form}")
+    kw = dict(storage="f32", form=form, restart=8, block_dims=(2, 2, 2, 4))
+    x0 = dev(np.zeros_like(b))
+    rc0, rep0 = tm.tm_fgmres_solve(dims, dev(U), dev(b), x0, kappa, [mu, -mu], csw, TOL, **kw)
+    xn = dev(np.full_like(b, np.nan))
+    rc1, rep1 = tm.tm_fgmres_solve(dims, dev(U), dev(b), xn, kappa, [mu, -mu], csw, TOL, x_in=False, **kw)
+    assert rc0 == 0 and rc1 == 0
+    assert rep0["iters"] == rep1["iters"] and rep0["outer"] == rep1["outer"]
+    assert np.array_equal(host(x0), host(xn))
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), mu, csw)
+    check_solutions(op, dims, b, host(xn), [mu, -mu], TOL, f"zero start {form}", "f32")
+
+
 def test_solver_error_paths(cfg_4444):
     dims, kappa, mu, csw, U, b, op, xs = cfg_4444
     announce("solve error paths")
