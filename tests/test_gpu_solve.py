@@ -64,6 +64,30 @@ def test_4x4x4x4_oracle_fgmres_agrees(cfg_4444):
     assert np.linalg.norm(host(x)[0].ravel() - xo) < 1e-9 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_long_cycles_against_dense_lu(cfg_4444, storage):
+    # FGMRES(22) with one SAP cycle of one MR step: cycles run to their full length, so the
+    # Gram-Schmidt sweeps see every basis size up to 22 (dots in several sweeps of at most 8
+    # FP32 or 4 FP64 vectors, updates over up to 22 vectors)
+    dims, kappa, mu, csw, U, b, op, xs = cfg_4444
+    announce(f"solve 4^4 restart 22, weak smoother, {storage}")
+    b2 = np.concatenate([b, b])
+    x = dev(np.zeros_like(b2))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b2), x, kappa, [mu, -mu], csw, TOL, storage=storage,
+                                 form="flexible", restart=22, n_cycles=1, mr_iters=1, block_dims=(2, 2, 2, 2),
+                                 max_iters=400)
+    assert rc == 0 and rep["converged"] == 2, rep
+    assert rep["iters"] > 22, rep  # at least one full cycle and a restart
+    xg = host(x)
+    for k, m in enumerate([mu, -mu]):
+        ref = np.linalg.solve(op.with_mu(m).dense(), b[0].ravel())
+        r = b[0].ravel() - op.with_mu(m).apply(xg[k].ravel())
+        rel = np.linalg.norm(r) / np.linalg.norm(b)
+        log_solve(f"4^4 restart 22 system {k}", storage, rel, TOL, rep["iters"])
+        assert rel <= TOL * RES_SLACK, (k, rel)
+        assert np.linalg.norm(xg[k].ravel() - ref) / np.linalg.norm(ref) < 1e-8
+
+
 @pytest.fixture(scope="module")
 def cfg_8888():
     dims, eps, kappa, mu, csw = (8, 8, 8, 8), 0.5, 0.1632, 0.003, 1.5
