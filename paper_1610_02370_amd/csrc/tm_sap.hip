@@ -189,14 +189,54 @@ __device__ inline void gen_site_setup(const Geo& g, int colour, int l, bool acti
     }
 }
 
+// Links of the block's sites staged in LDS (the FP64 kernel: a workgroup per
+// block, one per CU): the two stored rows of each link as 3 units of 4 reals,
+// [mu][unit][site]; the third row is rebuilt on use, as from memory.
+template <class R, class G>
+__device__ inline void lk_stage(const void* links, long long V, long long s, R* lk, int nt, int l) {
+#pragma unroll
+    for (int u = 0; u < 12; ++u) {
+        R v[4];
+        Unit<G>::load(links, (size_t)(u / 3) * 3 * V + (size_t)(u % 3) * V + s, v);
+        R* d = lk + ((size_t)u * nt + l) * 4;
+        d[0] = v[0];
+        d[1] = v[1];
+        d[2] = v[2];
+        d[3] = v[3];
+    }
+}
+
+template <class R>
+__device__ inline void lk_get(const R* lk, int nt, int mu, int n, Link<R>& L) {
+    const R* p0 = lk + ((size_t)(3 * mu) * nt + n) * 4;
+    const R* p1 = p0 + (size_t)nt * 4;
+    const R* p2 = p1 + (size_t)nt * 4;
+    L.u[0][0] = cmk(p0[0], p0[1]);
+    L.u[0][1] = cmk(p0[2], p0[3]);
+    L.u[0][2] = cmk(p1[0], p1[1]);
+    L.u[1][0] = cmk(p1[2], p1[3]);
+    L.u[1][1] = cmk(p2[0], p2[1]);
+    L.u[1][2] = cmk(p2[2], p2[3]);
+    complete_su3(L);
+}
+
+// Own link (mu) of local site l, from LDS when the links are staged there.
+template <bool LC, class R, class G>
+__device__ inline void own_link(const SapArgs& a, const R* lk, int nt, long long s, int l, int mu, Link<R>& L) {
+    if constexpr (LC)
+        lk_get(lk, nt, mu, l, L);
+    else
+        load_link<R, G>(a.links, a.g.V, s, mu, L);
+}
+
 // r = b - D x on the block for one system: diagonal and in-block hops from
 // LDS, hops from the neighbouring blocks straight from memory.  When x is
 // still zero on this colour only the halo hops remain; xv returns the old x
 // (zero when it was not read).  Contains barriers: every thread calls it.
-template <class S, class G, class R>
+template <class S, class G, class R, bool LC = false>
 __device__ inline void gen_residual(const SapArgs& a, const GenSite<R>& t, const Clover<R>& A, R mu_tw, bool active,
                                     R* sh, int nt, int l, const void* bb, const float* bsc, const void* xx,
-                                    const float* xsc, Spinor<R>& r, Spinor<R>& xv) {
+                                    const float* xsc, Spinor<R>& r, Spinor<R>& xv, const R* lk = nullptr) {
     const Geo& g = a.g;
 #pragma unroll
     for (int i = 0; i < 12; ++i) xv.v[i] = cmk<R>(0, 0);
@@ -219,7 +259,7 @@ __device__ inline void gen_residual(const SapArgs& a, const GenSite<R>& t, const
             Link<R> Lk;
             Spinor<R> p;
             if (t.nlf[mu] < 0 || own) {
-                load_link<R, G>(a.links, g.V, t.s, mu, Lk);
+                own_link<LC, R, G>(a, lk, nt, t.s, l, mu, Lk);
                 if (t.nlf[mu] >= 0) {
                     lds_get(sh, nt, t.nlf[mu], p);
                 } else {
@@ -231,7 +271,7 @@ __device__ inline void gen_residual(const SapArgs& a, const GenSite<R>& t, const
             if (t.nlb[mu] >= 0) {
                 if (own) {
                     lds_get(sh, nt, t.nlb[mu], p);
-                    load_link<R, G>(a.links, g.V, t.s0 + t.nlb[mu], mu, Lk);
+                    own_link<LC, R, G>(a, lk, nt, t.s0 + t.nlb[mu], t.nlb[mu], mu, Lk);
                     hop_backward(mu, Lk, p, (R)1, acc);
                 }
             } else {
@@ -253,30 +293,42 @@ __device__ inline void gen_residual(const SapArgs& a, const GenSite<R>& t, const
     if (own) __syncthreads();
 }
 
-// acc = sum over in-block neighbours of the hop terms (before the factor
-// -1/2) of the block vector held in LDS.
-template <class G, class R>
-__device__ inline void gen_block_hops(const SapArgs& a, const GenSite<R>& t, const R* sh, int nt, Spinor<R>& acc) {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc.v[i] = cmk<R>(0, 0);
+// acc += f * (sum over in-block neighbours of the hop terms) of the block
+// vector held in LDS.
+template <class G, class R, bool LC = false>
+__device__ inline void gen_block_hops_add(const SapArgs& a, const GenSite<R>& t, const R* sh, int nt, int l, R f,
+                                          Spinor<R>& acc, const R* lk = nullptr) {
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         Link<R> Lk;
         Spinor<R> p;
         if (t.nlf[mu] >= 0) {  // in-block hops never cross the lattice boundary
-            load_link<R, G>(a.links, a.g.V, t.s, mu, Lk);
+            own_link<LC, R, G>(a, lk, nt, t.s, l, mu, Lk);
             lds_get(sh, nt, t.nlf[mu], p);
-            hop_forward(mu, Lk, p, (R)1, acc);
+            hop_forward(mu, Lk, p, f, acc);
         }
         if (t.nlb[mu] >= 0) {
-            load_link<R, G>(a.links, a.g.V, t.s0 + t.nlb[mu], mu, Lk);
+            own_link<LC, R, G>(a, lk, nt, t.s0 + t.nlb[mu], t.nlb[mu], mu, Lk);
             lds_get(sh, nt, t.nlb[mu], p);
-            hop_backward(mu, Lk, p, (R)1, acc);
+            hop_backward(mu, Lk, p, f, acc);
         }
     }
 }
 
-template <class S, class G, class C, class R, int MAXT>
+// acc = sum over in-block neighbours of the hop terms (before the factor
+// -1/2) of the block vector held in LDS.
+template <class G, class R, bool LC = false>
+__device__ inline void gen_block_hops(const SapArgs& a, const GenSite<R>& t, const R* sh, int nt, int l,
+                                      Spinor<R>& acc, const R* lk = nullptr) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc.v[i] = cmk<R>(0, 0);
+    gen_block_hops_add<G, R, LC>(a, t, sh, nt, l, (R)1, acc, lk);
+}
+
+// LC: the block's links are staged in LDS once per workgroup (48 nt reals after
+// the exchange and reduction space) and every own or in-block link is read from
+// there; only the backward links of the halo hops come from memory.
+template <class S, class G, class C, class R, int MAXT, bool LC = false>
 __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Geo& g = a.g;
@@ -285,11 +337,16 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
     const bool active = l < g.Vb;
     R* sh = reinterpret_cast<R*>(smem_raw);
     R* red = sh + 24 * nt;
+    R* lk = LC ? red + 64 : nullptr;
     GenSite<R> t;
     gen_site_setup(g, a.colour, l, active, t);
 
     Clover<R> A;
     if (active) load_clover<R, C>(a.clover, g.V, t.s, A);
+    if constexpr (LC) {
+        if (active) lk_stage<R, G>(a.links, g.V, t.s, lk, nt, l);
+        __syncthreads();
+    }
 
     const size_t stride = (size_t)6 * g.V * Unit<S>::bytes;
     const int sys_begin = blockIdx.y * a.sys_tile;
@@ -302,25 +359,22 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
         const float* bsc = a.b_scale ? a.b_scale + (size_t)sys * g.V : nullptr;
         float* xsc = a.x_scale ? a.x_scale + (size_t)sys * g.V : nullptr;
 
-        Spinor<R> r, xv;
-        gen_residual<S, G, R>(a, t, A, mu_tw, active, sh, nt, l, bb, bsc, xx, xsc, r, xv);
+        Spinor<R> xv, rho;
+        gen_residual<S, G, R, LC>(a, t, A, mu_tw, active, sh, nt, l, bb, bsc, xx, xsc, rho, xv, lk);
 
-        // ---- minimal residual on D_BB from e = 0
-        Spinor<R> e, rho = r;
-#pragma unroll
-        for (int i = 0; i < 12; ++i) e.v[i] = cmk<R>(0, 0);
+        // ---- minimal residual on D_BB from a zero correction, added to x as it goes
+        // (x_new = x + sum_k alpha_k rho_k; no separate correction vector)
         for (int it = 0; it < a.mr_iters; ++it) {
             if (active) lds_put(sh, nt, l, rho);
             __syncthreads();
             Spinor<R> q;
             R qr_re = 0, qr_im = 0, qq = 0;
             if (active) {
-                Spinor<R> acc;
-                gen_block_hops<G, R>(a, t, sh, nt, acc);
+                // q = (A + twist) rho - 1/2 (in-block hops of rho)
                 clover_apply(A, mu_tw, rho, q);
+                gen_block_hops_add<G, R, LC>(a, t, sh, nt, l, (R)-0.5, q, lk);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
-                    q.v[i] = q.v[i] - (R)0.5 * acc.v[i];
                     qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
                     qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
                     qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
@@ -331,17 +385,13 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
                 const cplx<R> alpha = cmk(qr_re / qq, qr_im / qq);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
-                    e.v[i] = cmad(alpha, rho.v[i], e.v[i]);
+                    xv.v[i] = cmad(alpha, rho.v[i], xv.v[i]);
                     rho.v[i] = rho.v[i] - alpha * q.v[i];
                 }
             }
         }
 
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < 12; ++i) e.v[i] = e.v[i] + xv.v[i];
-            store_spinor<R, S>(xx, xsc, g.V, t.s, e);
-        }
+        if (active) store_spinor<R, S>(xx, xsc, g.V, t.s, xv);
     }
 }
 
@@ -398,7 +448,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
             e.v[i] = cmk<R>(0, 0);
         }
         if (odd) {
-            gen_block_hops<G, R>(a, t, sh, nt, acc);
+            gen_block_hops<G, R>(a, t, sh, nt, l, acc);
 #pragma unroll
             for (int i = 0; i < 12; ++i) rho.v[i] = r.v[i] + (R)0.5 * acc.v[i];
         }
@@ -412,7 +462,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) tv.v[i] = cmk<R>(0, 0);
             if (even) {
-                gen_block_hops<G, R>(a, t, sh, nt, acc);
+                gen_block_hops<G, R>(a, t, sh, nt, l, acc);
                 Spinor<R> u;
 #pragma unroll
                 for (int i = 0; i < 12; ++i) u.v[i] = (R)-0.5 * acc.v[i];
@@ -425,7 +475,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
             Spinor<R> q;
             R qr_re = 0, qr_im = 0, qq = 0;
             if (odd) {
-                gen_block_hops<G, R>(a, t, sh, nt, acc);
+                gen_block_hops<G, R>(a, t, sh, nt, l, acc);
                 clover_apply(A, mu_tw, rho, q);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) {
@@ -451,7 +501,7 @@ __global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
         if (active) lds_put(sh, nt, l, e);
         __syncthreads();
         if (even) {
-            gen_block_hops<G, R>(a, t, sh, nt, acc);
+            gen_block_hops<G, R>(a, t, sh, nt, l, acc);
             Spinor<R> v;
 #pragma unroll
             for (int i = 0; i < 12; ++i) v.v[i] = r.v[i] + (R)0.5 * acc.v[i];
@@ -1329,6 +1379,20 @@ hipError_t run(const SapArgs& a, hipStream_t st) {
                 hipLaunchKernelGGL((k_sap_half_44<S, G, C>), grid, dim3(nt), 0, st, a);
             else
                 hipLaunchKernelGGL((k_sap_half_v2<S, G, C>), grid, dim3(nt), 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (sizeof(R) == 8) {
+        // FP64: one workgroup per CU either way (registers), so the block's links fit in LDS
+        // beside the exchange buffer for blocks of up to 256 sites
+        const size_t lds_lc = lds + (size_t)48 * nt * sizeof(R);
+        if (nt <= 256 && lds_lc <= (size_t)max_lds) {
+            const void* fl = reinterpret_cast<const void*>(&k_sap_half<S, G, C, R, 256, true>);
+            if (lds_lc > 65536) {
+                e = hipFuncSetAttribute(fl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_lc);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL((k_sap_half<S, G, C, R, 256, true>), grid, dim3(nt), lds_lc, st, a);
             return hipGetLastError();
         }
     }
