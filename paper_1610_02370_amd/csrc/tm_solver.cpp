@@ -242,14 +242,17 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
     bool r_in_rhs = x_zero;  // the residual is rhs itself until x changes
     for (int k = 0; k < ns; ++k) bnorm[k] = std::sqrt(bn2[k]);
     int steps = 0;
+    // systems whose preconditioned direction vanished (a zero pivot in the first column of a
+    // cycle: no progress possible) are not cycled again; they end unconverged
+    unsigned long long stalled = 0;
     for (;;) {
         bool any = false;
         for (int k = 0; k < ns; ++k) {
             const double rel = bnorm[k] > 0 ? std::sqrt(rn2[k]) / bnorm[k] : 0.0;
             out.rel[k] = rel;
             out.conv[k] = rel <= tol[k] || ((skip >> k) & 1ull);
-            frozen[k] = out.conv[k];
-            any |= !out.conv[k];
+            frozen[k] = out.conv[k] || ((stalled >> k) & 1ull);
+            any |= !frozen[k];
         }
         if (!any || steps >= max_iters) break;
         // v0 = r / beta
@@ -408,13 +411,22 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
         for (int k = 0; k < ns; ++k) {
             const zc* Rk = &R[(size_t)k * (m + 1) * m];
             const zc* gk = &gv[(size_t)k * (m + 1)];
-            std::vector<zc> y(kdim[k]);
-            for (int i = kdim[k] - 1; i >= 0; --i) {
+            // a zero pivot comes from a zero preconditioned direction: the columns from there on
+            // add nothing, so the solution uses the ones before it
+            int kd = kdim[k];
+            for (int i = 0; i < kd; ++i)
+                if (std::abs(Rk[i * m + i]) == 0.0) {
+                    kd = i;
+                    if (i == 0) stalled |= 1ull << k;
+                    break;
+                }
+            std::vector<zc> y(kd);
+            for (int i = kd - 1; i >= 0; --i) {
                 zc t = gk[i];
-                for (int q = i + 1; q < kdim[k]; ++q) t -= Rk[i * m + q] * y[q];
+                for (int q = i + 1; q < kd; ++q) t -= Rk[i * m + q] * y[q];
                 y[i] = t / Rk[i * m + i];
             }
-            for (int i = 0; i < kdim[k]; ++i) {
+            for (int i = 0; i < kd; ++i) {
                 yh[((size_t)k * jdone + i) * 2] = y[i].real();
                 yh[((size_t)k * jdone + i) * 2 + 1] = y[i].imag();
             }
@@ -442,7 +454,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             for (int k = 0; k < ns; ++k) {
                 if (((skip >> k) & 1ull) || bnorm[k] == 0) continue;
                 out.rel[k] = std::abs(gv[(size_t)k * (m + 1) + kdim[k]]) / bnorm[k];
-                out.conv[k] = true;
+                out.conv[k] = out.rel[k] <= tol[k] && !((stalled >> k) & 1ull);
             }
             return TM_OK;
         }
@@ -701,11 +713,16 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                     return rc;
                 }
                 done = true;
+                // stagnation: a correction that left every unconverged system's residual no
+                // smaller (a preconditioner that returns zero) ends the loop unconverged
+                bool stagnant = outer > 0;
                 for (int k = 0; k < ns; ++k) {
                     const double rel = bn2[k] > 0 ? std::sqrt(rn2[k] / bn2[k]) : 0.0;
+                    if (rel > tol && rel < rep.true_rel_res[g0 + k]) stagnant = false;
                     rep.true_rel_res[g0 + k] = rel;
                     done &= rel <= tol;
                 }
+                if (done) stagnant = false;
                 int maxit = 0;
                 for (int k = 0; k < ns; ++k) maxit = std::max(maxit, iters[k]);
                 if (verbose()) {
@@ -715,7 +732,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                                  g0, g0 + ns - 1, outer, worst, maxit);
                     std::fflush(stderr);
                 }
-                if (done || outer >= so->max_outer || maxit >= so->max_iters) break;
+                if (done || stagnant || outer >= so->max_outer || maxit >= so->max_iters) break;
                 // inner FP32 solve of D c = r to inner_tol, then x += c
                 if ((rc = hcheck(launch_spinor_convert(g, r_is_b ? bb : rr, r32, st), "convert"))) return rc;
                 c.vp = P_F32;

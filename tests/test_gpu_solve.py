@@ -165,6 +165,22 @@ def test_zero_start_without_reading_x(form):
     check_solutions(op, dims, b, host(xn), [mu, -mu], TOL, f"zero start {form}", "f32")
 
 
+@pytest.mark.parametrize("form", ["flexible", "defect_correction"])
+def test_zero_preconditioner_ends_unconverged(cfg_4444, form):
+    # no MR steps: SAP returns zero, every Arnoldi column vanishes; the solve must end unconverged
+    # with x finite and untouched (no division by the zero pivot), without running to max_iters
+    dims, kappa, mu, csw, U, b, op, xs = cfg_4444
+    announce(f"solve with a zero preconditioner, {form}")
+    x = dev(np.zeros_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, [mu], csw, TOL, storage="f32", form=form,
+                                 restart=8, n_cycles=2, mr_iters=0, block_dims=(2, 2, 2, 2), max_iters=400)
+    assert rc == 1 and rep["converged"] == 0, rep
+    assert rep["iters"] <= 2, rep
+    xg = host(x)
+    assert np.isfinite(xg).all() and not xg.any()
+    assert abs(rep["true_rel_res"][0] - 1.0) < 1e-12
+
+
 def test_solver_error_paths(cfg_4444):
     dims, kappa, mu, csw, U, b, op, xs = cfg_4444
     announce("solve error paths")
