@@ -23,16 +23,9 @@ inline VecRef vec_ref(const SpinorBuf& b, long long V) {
 int blas_blocks(long long V);
 int blas_max_vec();
 
-// Gram-Schmidt passes over basis vectors 0..nvec-1 (vector i at basis.data + i*vec_stride, FP64 or FP32, no
-// scales; nvec < kMaxVec); coefficients per system at coef + sys*coef_stride as (re, im) pairs:
-//   mode 0: out[sys] = (<v_i, w>)_i                                   (2 nvec values)
-//   mode 1: w -= sum_i coef_i v_i, then out[sys] = (<v_i, w>)_i, ||w||^2  (2 nvec + 1 values)
-//   mode 2: w -= sum_i coef_i v_i, then out[sys] = ||w||^2
-//   mode 3: t = w - sum_i coef_i v_i; y = fac[sys] t (w unchanged); out[sys] = ||t||^2
-// Values per system are contiguous in out; accumulate != 0 adds to out.
-hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, const VecRef& w, const double* coef,
-                   int coef_stride, int mode, const VecRef& y, const double* fac, double* partials, double* out,
-                   int accumulate, int nsys, long long V, hipStream_t st);
+// out[sys] = ||x_sys||^2 (FP64 or FP32 fields, no scales; the sum over sites in FP64)
+hipError_t blas_norm2(Prec p, const VecRef& x, double* partials, double* out, int nsys, long long V,
+                      hipStream_t st);
 // Classical Gram-Schmidt with delayed reorthogonalisation, two sweeps over the basis per Arnoldi
 // step.  Basis vectors v_0..v_{nb-1} (orthonormal) at basis.data + i*vec_stride; u is the lagged
 // direction (projected once), w the new operator output; FP64 or FP32, no scales.
@@ -58,9 +51,10 @@ hipError_t blas_scale(Prec pi, Prec po, const VecRef& x, const double* a, const 
 // with overwrite != 0, x = sum_i y[sys][i] z_i and x is not read
 hipError_t blas_xupdate(Prec px, Prec pz, const VecRef& x, const VecRef& z, size_t zvec_stride, size_t zscale_stride,
                         int nvec, const double* y, int overwrite, int nsys, long long V, hipStream_t st);
-// r = b - ax, out[sys] = (||r||^2, ||b||^2)
+// r = b - ax (b, ax at p; r at pr, which is p or, from FP64, FP32: the FP64 difference rounded
+// once), out[sys] = (||r||^2, ||b||^2) of the FP64 values
 hipError_t blas_residual(Prec p, const VecRef& b, const VecRef& ax, const VecRef& r, double* partials, double* out,
-                         int nsys, long long V, hipStream_t st);
+                         int nsys, long long V, hipStream_t st, Prec pr);
 // x += c
 hipError_t blas_accumulate(Prec px, Prec pc, const VecRef& x, const VecRef& c, int nsys, long long V, hipStream_t st);
 // zero a buffer with a kernel (bytes a multiple of 16)

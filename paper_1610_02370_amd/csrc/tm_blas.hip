@@ -1,7 +1,7 @@
-// Vector kernels of the Krylov solvers on internal spinor fields: fused
-// classical Gram-Schmidt passes (w -= V h followed by the next dot products
-// or the norm in the same sweep), norms, scaling, the solution update
-// x += Z y, residual b - Dx and precision-changing accumulations.  Every
+// Vector kernels of the Krylov solvers on internal spinor fields: classical
+// Gram-Schmidt with delayed reorthogonalisation (a dots sweep and an update
+// sweep per Arnoldi step), norms, scaling, the solution update x += Z y,
+// residual b - Dx and precision-changing accumulations.  Every
 // inner product accumulates in FP64; per-workgroup partials are summed by a
 // second kernel in a fixed order, so results do not depend on scheduling.
 #include "tm_blas.h"
@@ -51,81 +51,24 @@ __device__ inline void reduce_out(double* vals, int n, double* lds, double* part
     }
 }
 
-// Gram-Schmidt passes over basis vectors v_0..v_{nvec-1} (nvec <= NV), w and
-// the coefficients c (per system at coef + sys * coef_stride, complex pairs):
-//   mode 0: out = <v_i, w>                                   (2 nvec values)
-//   mode 1: w <- w - sum_i c_i v_i; out = <v_i, w>, ||w||^2  (2 nvec + 1 values)
-//   mode 2: w <- w - sum_i c_i v_i; out = ||w||^2            (1 value)
-//   mode 3: t = w - sum_i c_i v_i; y <- fac[sys] t (w kept); out = ||t||^2
-// Arithmetic at the vectors' precision R (FP64 or FP32) per site; the sums
-// over sites accumulate in FP64.  Norms and dots are of the stored values.
-template <class P, int NV>
-__global__ void __launch_bounds__(kThreads) k_gs(VecRef basis, size_t vec_stride, int nvec, VecRef w,
-                                                 const double* __restrict__ coef, int coef_stride, int mode, VecRef y,
-                                                 const double* __restrict__ fac, double* partials, long long V) {
+// out = ||x||^2 per system: values at the vectors' precision R (FP64 or FP32) per site, the sum
+// over sites in FP64.
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_norm2(VecRef x, double* partials, long long V) {
     typedef typename std::conditional<std::is_same<P, double>::value, double, float>::type R;
     __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
     const int sys = blockIdx.y;
-    const int nblk = gridDim.x;
-    double acc[2 * NV + 1];
+    const char* x0 = static_cast<const char*>(x.data) + (size_t)sys * x.sys_stride;
+    double acc[1] = {0};
+    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)gridDim.x * kThreads) {
+        Spinor<R> v;
+        load_spinor<R, P>(x0, nullptr, V, s, v);
+        R n2 = 0;
 #pragma unroll
-    for (int i = 0; i < 2 * NV + 1; ++i) acc[i] = 0;
-    const double* cf = coef + (size_t)sys * coef_stride;
-    const R f = mode == 3 ? (R)fac[sys] : (R)1;
-    const char* b0 = static_cast<const char*>(basis.data) + (size_t)sys * basis.sys_stride;
-    const char* w0 = static_cast<const char*>(w.data) + (size_t)sys * w.sys_stride;
-    for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
-        Spinor<R> wv;
-        load_spinor<R, P>(w0, nullptr, V, s, wv);
-        if (mode != 0) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                if (i < nvec) {
-                    Spinor<R> v;
-                    load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
-                    const cplx<R> c = cmk((R)cf[2 * i], (R)cf[2 * i + 1]);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) wv.v[k] = wv.v[k] - c * v.v[k];
-                }
-            }
-            if (mode == 3) {
-                Spinor<R> t;
-#pragma unroll
-                for (int k = 0; k < 12; ++k) t.v[k] = f * wv.v[k];
-                store_spinor<R, P>(static_cast<char*>(y.data) + (size_t)sys * y.sys_stride, nullptr, V, s, t);
-            } else {
-                store_spinor<R, P>(const_cast<char*>(w0), nullptr, V, s, wv);
-            }
-            R n2 = 0;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) n2 += wv.v[k].re * wv.v[k].re + wv.v[k].im * wv.v[k].im;
-            acc[2 * NV] += (double)n2;
-        }
-        if (mode <= 1) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                if (i < nvec) {
-                    Spinor<R> v;
-                    load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
-                    R re = 0, im = 0;
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        re += v.v[k].re * wv.v[k].re + v.v[k].im * wv.v[k].im;
-                        im += v.v[k].re * wv.v[k].im - v.v[k].im * wv.v[k].re;
-                    }
-                    acc[2 * i] += (double)re;
-                    acc[2 * i + 1] += (double)im;
-                }
-            }
-        }
+        for (int k = 0; k < 12; ++k) n2 += v.v[k].re * v.v[k].re + v.v[k].im * v.v[k].im;
+        acc[0] += (double)n2;
     }
-    // move the norm next to the dots (mode 1) or to the front (modes 2, 3)
-    const int pos = mode == 1 ? 2 * nvec : 0;
-#pragma unroll
-    for (int i = 0; i < 2 * NV; ++i)
-        if (mode >= 1 && i == pos) acc[i] = acc[2 * NV];
-    const int n = mode == 0 ? 2 * nvec : (mode == 1 ? 2 * nvec + 1 : 1);
-    reduce_out<2 * NV + 1>(acc, n, lds, partials, sys, nblk);
+    reduce_out<1>(acc, 1, lds, partials, sys, gridDim.x);
 }
 
 // Classical Gram-Schmidt with delayed reorthogonalisation: two sweeps over the
@@ -391,8 +334,9 @@ __global__ void __launch_bounds__(kThreads) k_xupdate(VecRef x, VecRef z, size_t
     }
 }
 
-// r = b - ax (r may alias ax), partial ||r||^2 and ||b||^2 (2 values per system)
-template <class P>
+// r = b - ax (r may alias ax when Pr is P), computed in FP64 and stored at Pr; partial ||r||^2
+// and ||b||^2 of the FP64 values (2 values per system)
+template <class P, class Pr = P>
 __global__ void __launch_bounds__(kThreads) k_residual(VecRef b, VecRef ax, VecRef r, double* partials, long long V) {
     __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
     const int sys = blockIdx.y;
@@ -407,7 +351,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(VecRef b, VecRef ax, VecR
             acc[0] += av.v[k].re * av.v[k].re + av.v[k].im * av.v[k].im;
             acc[1] += bv.v[k].re * bv.v[k].re + bv.v[k].im * bv.v[k].im;
         }
-        st<P>(r, sys, V, s, av);
+        st<Pr>(r, sys, V, s, av);
     }
     reduce_out<2>(acc, 2, lds, partials, sys, gridDim.x);
 }
@@ -473,32 +417,18 @@ int blas_max_vec() { return kMaxVec; }
         default: { typedef bf16 T; __VA_ARGS__; break; }      \
     }
 
-hipError_t blas_gs(Prec p, const VecRef& basis, size_t vec_stride, int nvec, const VecRef& w, const double* coef,
-                   int coef_stride, int mode, const VecRef& y, const double* fac, double* partials, double* out,
-                   int accumulate, int nsys, long long V, hipStream_t st) {
-    if (nvec > kMaxVec - 1 || (p != P_F64 && p != P_F32) || mode < 0 || mode > 3) return hipErrorInvalidValue;
-    if (mode != 0 && nvec > 0 && !coef) return hipErrorInvalidValue;
+hipError_t blas_norm2(Prec p, const VecRef& x, double* partials, double* out, int nsys, long long V,
+                      hipStream_t st) {
+    if (p != P_F64 && p != P_F32) return hipErrorInvalidValue;
     const int nblk = blas_blocks(V);
     dim3 grid(nblk, nsys);
-    static const double zero[1] = {0.0};
-    const double* cf = coef ? coef : zero;
-#define TM_GS_LAUNCH(NVT)                                                                                          \
-    TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL((k_gs<T, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nvec, w, \
-                                             cf, coef_stride, mode, y, fac, partials, V))
-    if (nvec <= 4) {
-        TM_GS_LAUNCH(4);
-    } else if (nvec <= 8) {
-        TM_GS_LAUNCH(8);
-    } else if (nvec <= 16) {
-        TM_GS_LAUNCH(16);
-    } else {
-        TM_GS_LAUNCH(kMaxVec - 1);
-    }
-#undef TM_GS_LAUNCH
+    if (p == P_F32)
+        hipLaunchKernelGGL(k_norm2<float>, grid, dim3(kThreads), 0, st, x, partials, V);
+    else
+        hipLaunchKernelGGL(k_norm2<double>, grid, dim3(kThreads), 0, st, x, partials, V);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nval = nsys * (mode == 0 ? 2 * nvec : (mode == 1 ? 2 * nvec + 1 : 1));
-    hipLaunchKernelGGL(k_reduce, dim3(nval), dim3(kThreads), 0, st, partials, nblk, nval, out, accumulate);
+    hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(kThreads), 0, st, partials, nblk, nsys, out, 0);
     return hipGetLastError();
 }
 
@@ -584,10 +514,16 @@ hipError_t blas_xupdate(Prec px, Prec pz, const VecRef& x, const VecRef& z, size
 }
 
 hipError_t blas_residual(Prec p, const VecRef& b, const VecRef& ax, const VecRef& r, double* partials, double* out,
-                         int nsys, long long V, hipStream_t st) {
+                         int nsys, long long V, hipStream_t st, Prec pr) {
     const int nblk = blas_blocks(V);
     dim3 grid(nblk, nsys);
-    TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL(k_residual<T>, grid, dim3(kThreads), 0, st, b, ax, r, partials, V));
+    if (pr == p) {
+        TM_DISPATCH_VEC(p, T, hipLaunchKernelGGL(k_residual<T>, grid, dim3(kThreads), 0, st, b, ax, r, partials, V));
+    } else if (p == P_F64 && pr == P_F32) {
+        hipLaunchKernelGGL((k_residual<double, float>), grid, dim3(kThreads), 0, st, b, ax, r, partials, V);
+    } else {
+        return hipErrorInvalidValue;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3(2 * nsys), dim3(kThreads), 0, st, partials, nblk, 2 * nsys, out, 0);

@@ -91,7 +91,7 @@ VecRef compact_ref(double* p, long long half) {
 // out[sys] = ||v_sys||^2
 int norm2(const CgCtx& c, double* v, double* out) {
     const VecRef r = compact_ref(v, c.half);
-    return hchk(blas_gs(P_F64, r, 0, 0, r, nullptr, 0, 2, r, nullptr, c.partials, out, 0, c.ns, c.half, c.st), "norm");
+    return hchk(blas_norm2(P_F64, r, c.partials, out, c.ns, c.half, c.st), "norm");
 }
 
 }  // namespace
@@ -274,7 +274,7 @@ int tm_cg_solve(const tm_geom* geom, const void* U, const void* b, void* x, doub
             if ((rc = hchk(launch_spinor_import(g, fx, xcan, flag, st), "import"))) return rc;
             if ((rc = run_dirac(g, *G, fx, fr, c.mu, ns, P_F64, st))) return rc;
             if ((rc = hchk(blas_residual(P_F64, vec_ref(fb, g.V), vec_ref(fr, g.V), vec_ref(fr, g.V), c.partials, bn1, ns,
-                                         g.V, st),
+                                         g.V, st, P_F64),
                            "residual")))
                 return rc;
             if ((rc = hchk(hipMemcpyAsync(host.data(), bn1, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy")))

@@ -140,16 +140,14 @@ Krylov carve_krylov(char*& p, const Geo& g, int nsys, int m, Prec vp, Prec sp) {
 }
 
 // r = rhs - D x; host gets ||r||^2 and ||rhs||^2.  When x is zero the residual is rhs
-// itself: r is not written, only the norm of rhs is taken.
+// itself: r is not written, only the norm of rhs is taken.  With rout, r holds D x and the
+// residual goes to rout instead (at rout's precision: FP64 rounded once to FP32).
 int residual(Ctx& c, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const SpinorBuf& r, double* rn2,
-             double* bn2) {
+             double* bn2, const SpinorBuf* rout = nullptr) {
     const long long V = c.g.V;
     int rc;
     if (x_zero) {
-        if ((rc = hcheck(blas_gs(c.vp, vec_ref(rhs, V), 0, 0, vec_ref(rhs, V), nullptr, 0, 2, vec_ref(rhs, V), nullptr,
-                                 c.sc.partials, c.sc.res, 0,
-                                 c.nsys, V, c.st),
-                         "norm")))
+        if ((rc = hcheck(blas_norm2(c.vp, vec_ref(rhs, V), c.sc.partials, c.sc.res, c.nsys, V, c.st), "norm")))
             return rc;
         if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, c.nsys * sizeof(double), hipMemcpyDeviceToHost, c.st),
                          "copy")))
@@ -159,8 +157,9 @@ int residual(Ctx& c, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, cons
         return TM_OK;
     }
     if ((rc = run_dirac(c.g, *c.op, x, r, c.mu, c.nsys, c.op_compute, c.st))) return rc;
-    if ((rc = hcheck(blas_residual(c.vp, vec_ref(rhs, V), vec_ref(r, V), vec_ref(r, V), c.sc.partials, c.sc.res,
-                                   c.nsys, V, c.st),
+    const SpinorBuf& ro = rout ? *rout : r;
+    if ((rc = hcheck(blas_residual(c.vp, vec_ref(rhs, V), vec_ref(r, V), vec_ref(ro, V), c.sc.partials, c.sc.res,
+                                   c.nsys, V, c.st, ro.prec),
                      "residual")))
         return rc;
     if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, 2 * c.nsys * sizeof(double), hipMemcpyDeviceToHost, c.st),
@@ -650,9 +649,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
         // without x_in the FP64 iterate starts as zeros
         bool x_zero = true;
         if (so->x_in) {
-            if ((rc = hcheck(blas_gs(P_F64, vec_ref(xx, V), 0, 0, vec_ref(xx, V), nullptr, 0, 2, vec_ref(xx, V),
-                                     nullptr, c.sc.partials, c.sc.res, 0, ns, V, st),
-                             "norm")))
+            if ((rc = hcheck(blas_norm2(P_F64, vec_ref(xx, V), c.sc.partials, c.sc.res, ns, V, st), "norm")))
                 return rc;
             if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, ns * sizeof(double), hipMemcpyDeviceToHost, st),
                              "copy")))
@@ -689,16 +686,14 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
             int outer = 0;
             bool done = false;
             for (;;) {
-                // FP64 residual of the current iterate (b itself for a zero start: then the
-                // inner solve's right-hand side is converted from b)
+                // FP64 residual of the current iterate, rounded once into the inner solve's FP32
+                // right-hand side (b itself for a zero start: then that is converted from b)
                 c.vp = P_F64;
                 c.op = op64;
                 c.op_compute = P_F64;
                 const bool r_is_b = x_zero && outer == 0;
                 if (r_is_b) {
-                    if ((rc = hcheck(blas_gs(P_F64, vec_ref(bb, V), 0, 0, vec_ref(bb, V), nullptr, 0, 2,
-                                             vec_ref(bb, V), nullptr, c.sc.partials, c.sc.res, 0, ns, V, st),
-                                     "norm")))
+                    if ((rc = hcheck(blas_norm2(P_F64, vec_ref(bb, V), c.sc.partials, c.sc.res, ns, V, st), "norm")))
                         return rc;
                     if ((rc = hcheck(hipMemcpyAsync(c.hstage, c.sc.res, ns * sizeof(double), hipMemcpyDeviceToHost,
                                                     st),
@@ -709,7 +704,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                         rn2[k] = bn2[k] = c.hstage[k];
                         if (!std::isfinite(rn2[k])) return fail(TM_ERR_NONFINITE, "non-finite residual of system %d", k);
                     }
-                } else if ((rc = residual(c, bb, xx, false, rr, rn2.data(), bn2.data()))) {
+                } else if ((rc = residual(c, bb, xx, false, rr, rn2.data(), bn2.data(), &r32))) {
                     return rc;
                 }
                 done = true;
@@ -734,7 +729,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                 }
                 if (done || stagnant || outer >= so->max_outer || maxit >= so->max_iters) break;
                 // inner FP32 solve of D c = r to inner_tol, then x += c
-                if ((rc = hcheck(launch_spinor_convert(g, r_is_b ? bb : rr, r32, st), "convert"))) return rc;
+                if (r_is_b && (rc = hcheck(launch_spinor_convert(g, bb, r32, st), "convert"))) return rc;
                 c.vp = P_F32;
                 c.op = op32;
                 c.op_compute = P_F32;
