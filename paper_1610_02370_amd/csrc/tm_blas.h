@@ -26,24 +26,29 @@ int blas_max_vec();
 // out[sys] = ||x_sys||^2 (FP64 or FP32 fields, no scales; the sum over sites in FP64)
 hipError_t blas_norm2(Prec p, const VecRef& x, double* partials, double* out, int nsys, long long V,
                       hipStream_t st);
-// Classical Gram-Schmidt with delayed reorthogonalisation, two sweeps over the basis per Arnoldi
-// step.  Basis vectors v_0..v_{nb-1} (orthonormal) at basis.data + i*vec_stride; u is the lagged
-// direction (projected once), w the new operator output; FP64 or FP32, no scales.
-// Dots: out[sys*(4 nb + 4) + ...] = (<v_i, u>, <v_i, w>)_i as complex pairs, then <u, u>, <u, w>
+// Classical Gram-Schmidt with delayed reorthogonalisation, two sweeps over the stored vectors per
+// Arnoldi step.  The stored vectors u_0..u_{nb-1} (at basis.data + i*vec_stride, FP64 or FP32, no
+// scales) are the once-projected directions; the orthonormal basis is V = U T^-1 with T upper
+// triangular, kept per system in `tri` by the coefficient kernel.  u is the newest direction
+// u_nb, w the new operator output.
+// Dots: out[sys*(4 nb + 4) + ...] = (<u_i, u>, <u_i, w>)_i as complex pairs, then <u, u>, <u, w>
 // (complex), <w, w>.
 hipError_t blas_dgs_dots(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, const VecRef& w,
                          double* partials, double* out, int nsys, long long V, hipStream_t st);
-// Coefficients of the update from those dots (coef: 4 nb + 4 values per system; rep: beta, h, s
-// per system, with beta = ||u - V V^H u||, h = <v_nb, w> for v_nb = (u - V V^H u) / beta, s the
-// scale of the next direction); nb = 0 means u is v_0 itself.  Systems with bit k of `off` set
-// get zero coefficients; beta = 0 flags u in the span of the basis.  nsys <= 64.
+// Coefficients of the update from those dots: coef (4 + 2 nb values per system), rep per system
+// (stride 4 + 4 blas_dgs_tri_stride()): beta = ||u - V V^H u||, h = <v_nb, w> for v_nb = (u - V
+// V^H u) / beta, s the scale of the next direction, then c = V^H u and a = V^H w as complex
+// pairs; writes column nb of T (tri: per system blas_dgs_tri_stride()^2 complex, column-major).
+// nb = 0 means u is v_0 itself (T_00 = 1).  Systems with bit k of `off` set get zero
+// coefficients; beta = 0 flags u in the span of the basis.  nsys <= 64.
 hipError_t blas_dgs_coef(const double* d, int nb, int nsys, unsigned long long off, double* coef, double* rep,
-                         hipStream_t st);
-// Update: u <- (u - V c) / beta when write_u (the finished basis vector v_nb), y <- s (w - V a -
-// h v_nb) (the next direction); out[sys] = (||u||^2 or 0, ||y||^2) of the stored values.
-hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, int write_u,
-                           const VecRef& w, const VecRef& y, const double* coef, double* partials, double* out,
-                           int nsys, long long V, hipStream_t st);
+                         double* tri, hipStream_t st);
+int blas_dgs_tri_stride();
+// Update: y <- s (w - V a - h v_nb), formed from u, w and the stored vectors; out[sys] = ||y||^2 of
+// the stored values.
+hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, const VecRef& w,
+                           const VecRef& y, const double* coef, double* partials, double* out, int nsys, long long V,
+                           hipStream_t st);
 // y = a[sys] x
 hipError_t blas_scale(Prec pi, Prec po, const VecRef& x, const double* a, const VecRef& y, int nsys, long long V,
                       hipStream_t st);

@@ -72,13 +72,16 @@ __global__ void __launch_bounds__(kThreads) k_norm2(VecRef x, double* partials, 
 }
 
 // Classical Gram-Schmidt with delayed reorthogonalisation: two sweeps over the
-// basis per Arnoldi step.  At step j the basis holds v_0..v_{j-1} (orthonormal)
-// and, in slot j, u: the previous step's new direction, projected once and
-// scaled to about unit norm.  w = D z_j.
+// stored vectors per Arnoldi step.  The slots hold u_0..u_j: u_0 = v_0, and each
+// later u_i the direction of step i - 1 projected once against v_0..v_{i-1} and
+// scaled to about unit norm.  The orthonormal basis is never stored: u_i =
+// sum_{k<i} T_ki v_k + T_ii v_i with T upper triangular (T_ii = beta_i), so
+// V = U T^-1, and T (per system, a few hundred numbers) carries every product
+// with V.  w = D z_j.
 //
-// Dots sweep over basis vectors [i0, i0 + n): per system 4 n values
-// (<v_i, u>, <v_i, w>) as complex pairs, and with `head` 4 more: <u, u>,
-// <u, w> (complex), <w, w>.
+// Dots sweep over stored vectors [i0, i0 + n): per system 4 n values
+// (<u_i, u>, <u_i, w>) as complex pairs, and with `head` 4 more: <u, u>,
+// <u, w> (complex), <w, w>, for u = u_j.
 template <class P, int NV>
 __global__ void __launch_bounds__(kThreads) k_dgs_dots(VecRef basis, size_t vec_stride, int i0, int n, VecRef u,
                                                        VecRef w, int head, double* partials, long long V) {
@@ -139,61 +142,103 @@ __global__ void __launch_bounds__(kThreads) k_dgs_dots(VecRef basis, size_t vec_
     reduce_out<4 * NV + 4>(acc, 4 * n + (head ? 4 : 0), lds, partials, sys, nblk);
 }
 
-// Coefficients of the update sweep, one thread per system, from the dots d
-// (ds values per system: the 4 nb dot values of v_0..v_{nb-1}, then <u, u>,
-// <u, w>, <w, w>).  With c_i = <v_i, u> and a_i = <v_i, w>:
-//   beta = sqrt(<u, u> - sum |c_i|^2)            (u - V c has no cancellation: u is already
-//                                                 orthogonal to V up to rounding)
-//   v_j  = (u - sum c_i v_i) / beta
-//   h    = <v_j, w> = (<u, w> - sum conj(c_i) a_i) / beta
-//   w'   = w - sum a_i v_i - h v_j = w - e u - sum (a_i - c_i e) v_i,   e = h / beta
-//   s    = 1 / sqrt(<w, w> - sum |a_i|^2 - |h|^2), the norm of w' by Pythagoras, floored at
-//          1e-6 <w, w> (only a scale for the next direction s w'; its exact norm is
-//          returned by the update sweep)
-// At the first step of a cycle (nb == 0) u is v_0 itself: beta = 1, v_j is not rewritten.
-// coef per system (cstride): [1/beta, s e (complex), s, (c_i / beta, s (a_i - c_i e)) complex
-// pairs]; rep per system: [beta, h (complex), s].  Frozen systems (bit set in `off`) and a
-// vanishing beta (u in the span of the basis: the previous column ends the Krylov space) get
-// zero coefficients and beta 0.
-__global__ void k_dgs_coef(const double* d, int ds, int nb, int nsys, unsigned long long off, double* coef,
-                           int cstride, double* rep) {
+// Coefficients of the update sweep, one thread per system, from the dots d (4 nb + 4 values
+// per system) and the triangular factor t of the system (column-major from the earlier
+// steps, kTri x kTri complex; column nb is written here).  In the basis V:
+//   c = V^H u_j = T^-H (U^H u_j),  a = V^H w = T^-H (U^H w)      (forward substitution)
+//   beta = sqrt(<u, u> - |c|^2)   (u_j is already orthogonal to V up to rounding, so this
+//                                   has no cancellation); v_j = (u_j - V c) / beta
+//   h = <v_j, w> = (<u, w> - c^H a) / beta,  e = h / beta
+//   w' = w - V a - h v_j = w - e u_j - V (a - c e) = w - e u_j - U g,  T g = a - c e
+//                                                                     (back substitution)
+//   s = 1 / sqrt(<w, w> - |a|^2 - |h|^2), the norm of w' by Pythagoras, floored at
+//       1e-6 <w, w> (only the scale of the next direction s w'; its exact norm is returned by
+//       the update sweep)
+// At the first step of a cycle (nb == 0) u_0 is v_0 itself: beta = 1.
+// coef per system (4 + 2 nb): [s, s e (complex), 0, (s g_i) complex]; rep per system
+// (4 + 4 kTri): [beta, h (complex), s, then (c_i, a_i) complex pairs].  Frozen systems (bit set
+// in `off`) and a vanishing beta (u_j in the span of the basis: the previous column ends the
+// Krylov space) get zero coefficients and beta 0.
+constexpr int kTri = kMaxVec;
+
+__global__ void k_dgs_coef(const double* d, int nb, int nsys, unsigned long long off, double* coef, double* rep,
+                           double* tri) {
     const int k = threadIdx.x;
     if (k >= nsys) return;
+    const int ds = 4 * nb + 4, cstride = 4 + 2 * nb, rstride = 4 + 4 * kTri;
     const double* dk = d + (size_t)k * ds;
     double* ck = coef + (size_t)k * cstride;
-    double* rk = rep + (size_t)k * 4;
-    for (int i = 0; i < 4 + 4 * nb; ++i) ck[i] = 0.0;
-    for (int i = 0; i < 4; ++i) rk[i] = 0.0;
+    double* rk = rep + (size_t)k * rstride;
+    double* tk = tri + (size_t)k * kTri * kTri * 2;  // T[i][j] at tk[(j * kTri + i) * 2]
+    for (int i = 0; i < cstride; ++i) ck[i] = 0.0;
+    for (int i = 0; i < 4 + 4 * nb; ++i) rk[i] = 0.0;
     if ((off >> k) & 1ull) return;
+    double cr[kTri], ci[kTri], ar[kTri], ai[kTri];
+    // forward substitution with T^H (lower triangular, real diagonal)
+    for (int i = 0; i < nb; ++i) {
+        double xr = dk[4 * i], xi = dk[4 * i + 1], yr = dk[4 * i + 2], yi = dk[4 * i + 3];
+        for (int q = 0; q < i; ++q) {
+            const double tr = tk[(i * kTri + q) * 2], ti = tk[(i * kTri + q) * 2 + 1];  // T[q][i]
+            // conj(T[q][i]) * c_q
+            xr -= tr * cr[q] + ti * ci[q];
+            xi -= tr * ci[q] - ti * cr[q];
+            yr -= tr * ar[q] + ti * ai[q];
+            yi -= tr * ai[q] - ti * ar[q];
+        }
+        const double tii = tk[(i * kTri + i) * 2];
+        cr[i] = xr / tii;
+        ci[i] = xi / tii;
+        ar[i] = yr / tii;
+        ai[i] = yi / tii;
+    }
     const double uu = dk[4 * nb], uwr = dk[4 * nb + 1], uwi = dk[4 * nb + 2], ww = dk[4 * nb + 3];
     double beta = 1.0, hr = uwr, hi = uwi;
     if (nb > 0) {
         double t = uu;
-        for (int i = 0; i < nb; ++i) t -= dk[4 * i] * dk[4 * i] + dk[4 * i + 1] * dk[4 * i + 1];
+        for (int i = 0; i < nb; ++i) t -= cr[i] * cr[i] + ci[i] * ci[i];
         if (!(uu > 0) || !(t > 1e-28 * uu)) return;
         beta = sqrt(t);
         for (int i = 0; i < nb; ++i) {
-            const double cr = dk[4 * i], ci = dk[4 * i + 1], ar = dk[4 * i + 2], ai = dk[4 * i + 3];
-            hr -= cr * ar + ci * ai;
-            hi -= cr * ai - ci * ar;
+            hr -= cr[i] * ar[i] + ci[i] * ai[i];
+            hi -= cr[i] * ai[i] - ci[i] * ar[i];
         }
         hr /= beta;
         hi /= beta;
     }
+    // column nb of T
+    for (int i = 0; i < nb; ++i) {
+        tk[(nb * kTri + i) * 2] = cr[i];
+        tk[(nb * kTri + i) * 2 + 1] = ci[i];
+    }
+    tk[(nb * kTri + nb) * 2] = beta;
+    tk[(nb * kTri + nb) * 2 + 1] = 0.0;
     const double er = hr / beta, ei = hi / beta;
     double est = ww - hr * hr - hi * hi;
-    for (int i = 0; i < nb; ++i) est -= dk[4 * i + 2] * dk[4 * i + 2] + dk[4 * i + 3] * dk[4 * i + 3];
+    for (int i = 0; i < nb; ++i) est -= ar[i] * ar[i] + ai[i] * ai[i];
     const double s = ww > 0 ? 1.0 / sqrt(fmax(est, 1e-6 * ww)) : 0.0;
-    ck[0] = nb > 0 ? 1.0 / beta : 0.0;
+    // back substitution T g = a - c e, in place over (ar, ai)
+    for (int i = nb - 1; i >= 0; --i) {
+        double gr = ar[i] - (cr[i] * er - ci[i] * ei), gi = ai[i] - (cr[i] * ei + ci[i] * er);
+        for (int q = i + 1; q < nb; ++q) {
+            const double tr = tk[(q * kTri + i) * 2], ti = tk[(q * kTri + i) * 2 + 1];  // T[i][q]
+            gr -= tr * ar[q] - ti * ai[q];
+            gi -= tr * ai[q] + ti * ar[q];
+        }
+        const double tii = tk[(i * kTri + i) * 2];
+        // keep a_i for the report before it is overwritten by g_i
+        rk[4 + 4 * i + 2] = ar[i];
+        rk[4 + 4 * i + 3] = ai[i];
+        ar[i] = gr / tii;
+        ai[i] = gi / tii;
+    }
+    ck[0] = s;
     ck[1] = s * er;
     ck[2] = s * ei;
-    ck[3] = s;
     for (int i = 0; i < nb; ++i) {
-        const double cr = dk[4 * i], ci = dk[4 * i + 1], ar = dk[4 * i + 2], ai = dk[4 * i + 3];
-        ck[4 + 4 * i] = cr / beta;
-        ck[4 + 4 * i + 1] = ci / beta;
-        ck[4 + 4 * i + 2] = s * (ar - (cr * er - ci * ei));
-        ck[4 + 4 * i + 3] = s * (ai - (cr * ei + ci * er));
+        ck[4 + 2 * i] = s * ar[i];
+        ck[4 + 2 * i + 1] = s * ai[i];
+        rk[4 + 4 * i] = cr[i];
+        rk[4 + 4 * i + 1] = ci[i];
     }
     rk[0] = beta;
     rk[1] = hr;
@@ -201,64 +246,47 @@ __global__ void k_dgs_coef(const double* d, int ds, int nb, int nsys, unsigned l
     rk[3] = s;
 }
 
-// Update sweep with the coefficients of k_dgs_coef (per system at coef + sys * cstride):
-//   t = u / beta - sum_i (c_i / beta) v_i      written over u when write_u; ||t||^2
-//   y = s w - (s e) u - sum_i s (a_i - c_i e) v_i   written to y;           ||y||^2
-// (2 values per system: ||t||^2, ||y||^2; the first is 0 without write_u).
+// Update sweep with the coefficients of k_dgs_coef (per system at coef + sys * (4 + 2 nb)):
+//   y = s w - (s e) u_j - sum_i (s g_i) u_i   written to y; out = ||y||^2 of the stored values
 template <class P, int NV>
 __global__ void __launch_bounds__(kThreads) k_dgs_update(VecRef basis, size_t vec_stride, int nb, VecRef u,
-                                                         int write_u, VecRef w, VecRef y,
-                                                         const double* __restrict__ coef, int cstride,
+                                                         VecRef w, VecRef y, const double* __restrict__ coef,
                                                          double* partials, long long V) {
     typedef typename std::conditional<std::is_same<P, double>::value, double, float>::type R;
     __shared__ double lds[(kThreads / 64) * 2 * kMaxVec];
     const int sys = blockIdx.y;
     const int nblk = gridDim.x;
-    const double* cf = coef + (size_t)sys * cstride;
-    const R bu = (R)cf[0], sw = (R)cf[3];
+    const double* cf = coef + (size_t)sys * (4 + 2 * nb);
+    const R sw = (R)cf[0];
     const cplx<R> ew = cmk((R)cf[1], (R)cf[2]);
     const char* b0 = static_cast<const char*>(basis.data) + (size_t)sys * basis.sys_stride;
-    char* u0 = static_cast<char*>(u.data) + (size_t)sys * u.sys_stride;
+    const char* u0 = static_cast<const char*>(u.data) + (size_t)sys * u.sys_stride;
     const char* w0 = static_cast<const char*>(w.data) + (size_t)sys * w.sys_stride;
     char* y0 = static_cast<char*>(y.data) + (size_t)sys * y.sys_stride;
-    double acc[2] = {0, 0};
+    double acc[1] = {0};
     for (long long s = (long long)blockIdx.x * kThreads + threadIdx.x; s < V; s += (long long)nblk * kThreads) {
-        Spinor<R> tv, yv;
-        load_spinor<R, P>(u0, nullptr, V, s, tv);
+        Spinor<R> uv, yv;
+        load_spinor<R, P>(u0, nullptr, V, s, uv);
         load_spinor<R, P>(w0, nullptr, V, s, yv);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            yv.v[k] = sw * yv.v[k] - ew * tv.v[k];
-            tv.v[k] = bu * tv.v[k];
-        }
+        for (int k = 0; k < 12; ++k) yv.v[k] = sw * yv.v[k] - ew * uv.v[k];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             if (i < nb) {
                 Spinor<R> v;
                 load_spinor<R, P>(b0 + i * vec_stride, nullptr, V, s, v);
-                const cplx<R> pv = cmk((R)cf[4 + 4 * i], (R)cf[4 + 4 * i + 1]);
-                const cplx<R> qw = cmk((R)cf[4 + 4 * i + 2], (R)cf[4 + 4 * i + 3]);
+                const cplx<R> qw = cmk((R)cf[4 + 2 * i], (R)cf[4 + 2 * i + 1]);
 #pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    tv.v[k] = tv.v[k] - pv * v.v[k];
-                    yv.v[k] = yv.v[k] - qw * v.v[k];
-                }
+                for (int k = 0; k < 12; ++k) yv.v[k] = yv.v[k] - qw * v.v[k];
             }
-        }
-        if (write_u) {
-            store_spinor<R, P>(u0, nullptr, V, s, tv);
-            R n2 = 0;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) n2 += tv.v[k].re * tv.v[k].re + tv.v[k].im * tv.v[k].im;
-            acc[0] += (double)n2;
         }
         store_spinor<R, P>(y0, nullptr, V, s, yv);
         R n2 = 0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) n2 += yv.v[k].re * yv.v[k].re + yv.v[k].im * yv.v[k].im;
-        acc[1] += (double)n2;
+        acc[0] += (double)n2;
     }
-    reduce_out<2>(acc, 2, lds, partials, sys, nblk);
+    reduce_out<1>(acc, 1, lds, partials, sys, nblk);
 }
 
 // out[sys*stride + off + i] = sum over blocks of value sys*n + i (fixed order).
@@ -460,26 +488,27 @@ hipError_t blas_dgs_dots(Prec p, const VecRef& basis, size_t vec_stride, int nb,
 }
 
 hipError_t blas_dgs_coef(const double* d, int nb, int nsys, unsigned long long off, double* coef, double* rep,
-                         hipStream_t st) {
-    if (nb < 0 || nb > kMaxVec - 1 || nsys > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dgs_coef, dim3(1), dim3(64), 0, st, d, 4 * nb + 4, nb, nsys, off, coef, 4 * nb + 4, rep);
+                         double* tri, hipStream_t st) {
+    if (nb < 0 || nb > kTri - 1 || nsys > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dgs_coef, dim3(1), dim3(64), 0, st, d, nb, nsys, off, coef, rep, tri);
     return hipGetLastError();
 }
 
-hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, int write_u,
-                           const VecRef& w, const VecRef& y, const double* coef, double* partials, double* out,
-                           int nsys, long long V, hipStream_t st) {
+int blas_dgs_tri_stride() { return kTri; }
+
+hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int nb, const VecRef& u, const VecRef& w,
+                           const VecRef& y, const double* coef, double* partials, double* out, int nsys, long long V,
+                           hipStream_t st) {
     if (nb < 0 || nb > kMaxVec - 1 || (p != P_F64 && p != P_F32)) return hipErrorInvalidValue;
     const int nblk = blas_blocks(V);
     dim3 grid(nblk, nsys);
-    const int cs = 4 * nb + 4;
-#define TM_DGS_LAUNCH(NVT)                                                                                       \
-    if (p == P_F32)                                                                                             \
-        hipLaunchKernelGGL((k_dgs_update<float, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nb, u,  \
-                           write_u, w, y, coef, cs, partials, V);                                               \
-    else                                                                                                        \
+#define TM_DGS_LAUNCH(NVT)                                                                                     \
+    if (p == P_F32)                                                                                            \
+        hipLaunchKernelGGL((k_dgs_update<float, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nb, u, \
+                           w, y, coef, partials, V);                                                           \
+    else                                                                                                       \
         hipLaunchKernelGGL((k_dgs_update<double, NVT>), grid, dim3(kThreads), 0, st, basis, vec_stride, nb, u, \
-                           write_u, w, y, coef, cs, partials, V)
+                           w, y, coef, partials, V)
     if (nb <= 4) {
         TM_DGS_LAUNCH(4);
     } else if (nb <= 8) {
@@ -492,7 +521,7 @@ hipError_t blas_dgs_update(Prec p, const VecRef& basis, size_t vec_stride, int n
 #undef TM_DGS_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(2 * nsys), dim3(kThreads), 0, st, partials, nblk, 2 * nsys, out, 0);
+    hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(kThreads), 0, st, partials, nblk, nsys, out, 0);
     return hipGetLastError();
 }
 

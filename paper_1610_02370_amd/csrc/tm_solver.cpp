@@ -67,8 +67,9 @@ struct Scratch {
     double* res;       // [nsys][2]
     double* dots;      // [nsys][4 kMaxVec] Gram-Schmidt dots
     double* coef;      // [nsys][4 kMaxVec] update coefficients
-    double* rep;       // [nsys][4] beta, h, s
-    double* nrm2;      // [nsys][2] norms of the update sweep
+    double* rep;       // [nsys][4 + 4 kMaxVec] beta, h, s, V^H u, V^H w
+    double* nrm2;      // [nsys] norm of the update sweep's output
+    double* tri;       // [nsys][kMaxVec][kMaxVec] complex: U = V T
     double* partials;  // [nsys * 2 * kMaxVec][blocks]
 };
 
@@ -100,7 +101,8 @@ struct Ctx {
 
 int hcheck(hipError_t e, const char* where) { return e == hipSuccess ? TM_OK : hip_fail(e, where); }
 
-// Krylov storage: basis V (m+1 vectors at vp), Z (m at sp), w (vp), vS (sp, when sp != vp).
+// Krylov storage: the m+1 once-projected directions u_i (at vp; the orthonormal basis is
+// V = U T^-1, T kept by the Gram-Schmidt kernels), Z (m at sp), w (vp), vS (sp, when sp != vp).
 struct Krylov {
     int m;
     char* V;
@@ -291,10 +293,12 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             c.sap_cycles += c.n_cycles;
             c.sap_sys_cycles += (long long)c.n_cycles * ns;
             if ((rc = run_dirac(c.g, *c.op, zj, K.w, c.mu, ns, c.op_compute, c.st))) return rc;
-            // classical Gram-Schmidt with delayed reorthogonalisation: one sweep for the dots of
-            // v_0..v_{j-1} with u_j and w (and <u,u>, <u,w>, <w,w>), then one sweep that finishes
-            // v_j = (u_j - V V^H u_j) / beta and writes u_{j+1} = s (w - V_j V_j^H w), projected
-            // once; its second projection is the first part of the next step
+            // classical Gram-Schmidt with delayed reorthogonalisation: one sweep for the dots of the
+            // stored directions u_0..u_{j-1} with u_j and w (and <u,u>, <u,w>, <w,w>), a small
+            // kernel that takes them to the orthonormal basis V = U T^-1 and finishes v_j =
+            // (u_j - V V^H u_j) / beta implicitly (column j of T), then one sweep that writes
+            // u_{j+1} = s (w - V_j V_j^H w), projected once; its second projection is the first part
+            // of the next step.  V itself is never stored.
             const VecRef basis = vec_ref(K.Vb(c, 0), V), wr = vec_ref(K.w, V), ur = vec_ref(uj, V);
             const SpinorBuf un = K.Vb(c, j + 1);
             unsigned long long off = 0;
@@ -303,22 +307,20 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             if ((rc = hcheck(blas_dgs_dots(c.vp, basis, K.vstride, j, ur, wr, c.sc.partials, c.sc.dots, ns, V, c.st),
                              "gs")))
                 return rc;
-            if ((rc = hcheck(blas_dgs_coef(c.sc.dots, j, ns, off, c.sc.coef, c.sc.rep, c.st), "gs"))) return rc;
-            if ((rc = hcheck(blas_dgs_update(c.vp, basis, K.vstride, j, ur, j > 0, wr, vec_ref(un, V), c.sc.coef,
+            if ((rc = hcheck(blas_dgs_coef(c.sc.dots, j, ns, off, c.sc.coef, c.sc.rep, c.sc.tri, c.st), "gs")))
+                return rc;
+            if ((rc = hcheck(blas_dgs_update(c.vp, basis, K.vstride, j, ur, wr, vec_ref(un, V), c.sc.coef,
                                              c.sc.partials, c.sc.nrm2, ns, V, c.st),
                              "gs")))
                 return rc;
-            const int ds = 4 * j + 4;
-            const size_t nd = (size_t)ns * ds;
-            double* st_d = c.hstage;
-            double* st_rep = st_d + nd;
-            double* st_n = st_rep + 4 * (size_t)ns;
-            if ((rc = hcheck(hipMemcpyAsync(st_d, c.sc.dots, nd * sizeof(double), hipMemcpyDeviceToHost, c.st), "copy")))
-                return rc;
-            if ((rc = hcheck(hipMemcpyAsync(st_rep, c.sc.rep, 4 * ns * sizeof(double), hipMemcpyDeviceToHost, c.st),
+            const size_t rstride = 4 + 4 * (size_t)blas_dgs_tri_stride();
+            double* st_rep = c.hstage;
+            double* st_n = st_rep + rstride * ns;
+            if ((rc = hcheck(hipMemcpyAsync(st_rep, c.sc.rep, rstride * ns * sizeof(double), hipMemcpyDeviceToHost,
+                                            c.st),
                              "copy")))
                 return rc;
-            if ((rc = hcheck(hipMemcpyAsync(st_n, c.sc.nrm2, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, c.st),
+            if ((rc = hcheck(hipMemcpyAsync(st_n, c.sc.nrm2, ns * sizeof(double), hipMemcpyDeviceToHost, c.st),
                              "copy")))
                 return rc;
             if ((rc = hcheck(hipStreamSynchronize(c.st), "arnoldi step"))) return rc;
@@ -327,25 +329,22 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             ++steps;
             // a non-finite Hessenberg entry (an overflow in the preconditioner
             // or the operator) would otherwise read as a breakdown
-            for (size_t i = 0; i < nd + 6 * (size_t)ns; ++i)
-                if (!std::isfinite(c.hstage[i]))
-                    return fail(TM_ERR_NONFINITE, "non-finite value in the Arnoldi step %d (preconditioned vector)",
-                                steps);
-            bool all_frozen = true, rescale = false;
-            std::vector<double> fix(ns, 1.0);
+            for (int k = 0; k < ns; ++k)
+                for (size_t i = 0; i < 4 + 4 * (size_t)j; ++i)
+                    if (!std::isfinite(st_rep[k * rstride + i]) || !std::isfinite(st_n[k]))
+                        return fail(TM_ERR_NONFINITE, "non-finite value in the Arnoldi step %d (preconditioned vector)",
+                                    steps);
+            bool all_frozen = true;
             for (int k = 0; k < ns; ++k) {
                 if (frozen[k]) continue;
-                const double* dk = st_d + (size_t)k * ds;
-                const double* rk = st_rep + 4 * (size_t)k;
-                const double* nk = st_n + 2 * (size_t)k;
+                const double* rk = st_rep + rstride * k;  // beta, h, s, then (c_i, a_i) in the basis V
                 zc* Hk = &Hraw[(size_t)k * (m + 1) * m];
                 zc* gk = &gv[(size_t)k * (m + 1)];
-                double f = 1.0;  // ||v_j|| as written
                 if (j > 0) {
                     // finish column j-1: w_{j-1} = V h + u_j / s_{j-1} with u_j = V c + beta v_j
                     const double beta = rk[0], sj = sprev[k];
                     gk[j - 1] = gsave[k];  // undo the provisional rotation of column j-1
-                    for (int i = 0; i < j; ++i) Hk[i * m + j - 1] += zc(dk[4 * i], dk[4 * i + 1]) / sj;
+                    for (int i = 0; i < j; ++i) Hk[i * m + j - 1] += zc(rk[4 + 4 * i], rk[4 + 4 * i + 1]) / sj;
                     if (beta == 0.0) {
                         // u_j lies in the span of v_0..v_{j-1}: column j-1 closes the Krylov space
                         Hk[j * m + j - 1] = 0.0;
@@ -354,24 +353,16 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                         frozen[k] = 1;
                         continue;
                     }
-                    // v_j = (u_j - V c) / beta with beta by Pythagoras; when that norm was off
-                    // (cancellation), v_j is rescaled to unit norm
-                    const double nv = std::sqrt(std::max(0.0, nk[0]));
-                    if (nv > 0 && std::fabs(nv - 1.0) > 1e-4) {
-                        f = nv;
-                        fix[k] = 1.0 / nv;
-                        rescale = true;
-                    }
-                    Hk[j * m + j - 1] = beta * f / sj;
+                    Hk[j * m + j - 1] = beta / sj;
                     commit(k, j - 1);
                 }
                 ++out.iters[k];
                 // provisional column j (its second projection comes with the next step):
                 // w_j = V_{j-1} a + h v_j + u_{j+1} / s
-                for (int i = 0; i < j; ++i) Hk[i * m + j] = zc(dk[4 * i + 2], dk[4 * i + 3]);
-                Hk[j * m + j] = zc(rk[1], rk[2]) * f;
+                for (int i = 0; i < j; ++i) Hk[i * m + j] = zc(rk[4 + 4 * i + 2], rk[4 + 4 * i + 3]);
+                Hk[j * m + j] = zc(rk[1], rk[2]);
                 const double s = rk[3];
-                const double hn = s > 0 ? std::sqrt(std::max(0.0, nk[1])) / s : 0.0;
+                const double hn = s > 0 ? std::sqrt(std::max(0.0, st_n[k])) / s : 0.0;
                 Hk[(j + 1) * m + j] = hn;
                 sprev[k] = s;
                 gsave[k] = gk[j];
@@ -393,13 +384,6 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                 std::fprintf(stderr, "[tm] %s step %d: max residual estimate %.3e, %d of %d systems active, sap %.3f s\n",
                              c.vp == P_F64 ? "fgmres" : "inner fgmres", steps, worst, active, ns, c.t_sap);
                 std::fflush(stderr);
-            }
-            if (rescale && !all_frozen) {
-                for (int k = 0; k < ns; ++k) c.hinv[k] = fix[k];
-                if ((rc = hcheck(hipMemcpyAsync(c.sc.inv, c.hinv, ns * sizeof(double), hipMemcpyHostToDevice, c.st),
-                                 "copy")))
-                    return rc;
-                if ((rc = hcheck(blas_scale(c.vp, c.vp, ur, c.sc.inv, ur, ns, V, c.st), "scale"))) return rc;
             }
             if (all_frozen) break;
         }
@@ -473,7 +457,9 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
 int carve_scratch(Ctx& c) {
     const int nblk = blas_blocks(c.g.V);
     const size_t nvals = (size_t)c.nsys * 2 * blas_max_vec();
-    const size_t doubles = 3 * c.nsys + nvals + 2 * c.nsys + 4 * nvals + 6 * c.nsys + nvals * nblk + 64;
+    const size_t nrep = (size_t)c.nsys * (4 + 4 * blas_max_vec());
+    const size_t ntri = (size_t)c.nsys * blas_max_vec() * blas_max_vec() * 2;
+    const size_t doubles = 5 * c.nsys + 5 * nvals + nrep + c.nsys + ntri + nvals * nblk + 64;
     hipError_t e = c.ds->red.ensure(doubles * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "solver scratch");
     double* p = (double*)c.ds->red.ptr;
@@ -483,10 +469,11 @@ int carve_scratch(Ctx& c) {
     c.sc.res = p; p += 2 * c.nsys;
     c.sc.dots = p; p += 2 * nvals;
     c.sc.coef = p; p += 2 * nvals;
-    c.sc.rep = p; p += 4 * c.nsys;
-    c.sc.nrm2 = p; p += 2 * c.nsys;
+    c.sc.rep = p; p += (size_t)c.nsys * (4 + 4 * blas_max_vec());
+    c.sc.nrm2 = p; p += c.nsys;
+    c.sc.tri = p; p += (size_t)c.nsys * blas_max_vec() * blas_max_vec() * 2;
     c.sc.partials = p;
-    const size_t stage = 2 * nvals + 8 * c.nsys + 32, hinv = c.nsys + 32, hy = nvals + 32;
+    const size_t stage = nrep + c.nsys + 32, hinv = c.nsys + 32, hy = nvals + 32;
     e = c.host.ensure(stage + hinv + hy);
     if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
     c.hstage = c.host.p;
