@@ -6,8 +6,10 @@
 // matrix, Givens rotations and Krylov dimension.  A system whose residual
 // estimate reaches the tolerance is frozen: its next basis vectors are zero,
 // so batched kernels carry it at no effect.  Orthogonalisation is classical
-// Gram-Schmidt applied twice, fused into three passes over the basis; the
-// host reads one Hessenberg column per step and solves the small
+// Gram-Schmidt with delayed reorthogonalisation in two sweeps over the stored
+// directions per step, the orthonormal basis kept implicit through a small
+// triangular factor; the host reads one Hessenberg column per step (the
+// previous one finished, the current one provisional) and solves the small
 // least-squares problems.
 #include <hip/hip_runtime.h>
 
