@@ -348,7 +348,9 @@ static int prepare_eo(const Geo& g, const GaugeDev& G, const double* mu, int nsy
 }
 
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,
-            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st, bool eo) {
+            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st, bool eo, void* w_out) {
+    if (w_out && !sap_fills_w(g, b.prec, G.link_prec, G.clover_prec, eo))
+        return fail(TM_ERR_PREC, "D x from the half-sweep needs the 4^4 FP32 kernel with FP32 storage");
     SapArgs a;
     a.eo = eo ? 1 : 0;
     a.eo_adj = 0;
@@ -377,6 +379,7 @@ int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf
             // still zero, and before the first sweep the halo is zero too
             a.own_zero = (x_zero && cyc == 0) ? 1 : 0;
             a.halo_zero = (x_zero && cyc == 0 && colour == 0) ? 1 : 0;
+            a.w_out = (cyc == n_cycles - 1 && colour == 1) ? w_out : nullptr;
             hipError_t h = launch_sap_half(a, b.prec, G.link_prec, G.clover_prec, cp, st);
             if (h == hipErrorInvalidConfiguration)
                 return fail(TM_ERR_BLOCKS, "block of %d sites needs more LDS than the device has at this precision",
@@ -401,6 +404,26 @@ int run_dirac(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const Spinor
     hipError_t h = launch_dirac(a, in.prec, out.prec, G.link_prec, G.clover_prec, compute, st);
     if (h == hipErrorInvalidValue) return fail(TM_ERR_PREC, "unsupported precision combination for the operator");
     if (h != hipSuccess) return hip_fail(h, "dirac");
+    return TM_OK;
+}
+
+int run_dirac_colour(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu,
+                     int nsys, int colour, hipStream_t st) {
+    if (colour < 0 || colour > 1) return fail(TM_ERR_ARG, "colour must be 0 or 1");
+    DiracArgs a;
+    a.g = g;
+    a.links = G.links;
+    a.clover = G.clover;
+    a.in = in.data;
+    a.in_scale = in.scale;
+    a.out = out.data;
+    a.out_scale = out.scale;
+    a.nsys = nsys;
+    a.colour = colour;
+    for (int k = 0; k < kMaxSys; ++k) a.mu[k] = mu[k];
+    hipError_t h = launch_dirac_44(a, in.prec, out.prec, G.link_prec, G.clover_prec, st);
+    if (h == hipErrorNotSupported) return fail(TM_ERR_PREC, "the operator on one colour needs the 4^4 FP32 tiles");
+    if (h != hipSuccess) return hip_fail(h, "dirac on one colour");
     return TM_OK;
 }
 

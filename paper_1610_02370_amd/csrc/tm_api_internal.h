@@ -76,10 +76,16 @@ int prepare_site_inverses(const Geo& g, const GaugeDev& G, const double* mu, int
 int fit_group(DeviceState* ds, int nsys, int group, size_t per_sys, size_t fixed, size_t reusable = 0);
 // n_cycles red-black SAP cycles; eo selects even-odd preconditioned block
 // solves (site inverses built on first use for each |mu| and kept with G).
+// With w_out (only where sap_fills_w holds), the last half-sweep also writes
+// D x on its blocks (colour 1) to w_out; run_dirac_colour(..., 0) completes it.
 int run_sap(const Geo& g, const GaugeDev& G, const SpinorBuf& b, const SpinorBuf& x, const double* mu, int nsys,
-            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st, bool eo = false);
+            int n_cycles, int mr_iters, bool x_zero, int sys_tile, hipStream_t st, bool eo = false,
+            void* w_out = nullptr);
 int run_dirac(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu, int nsys,
               Prec compute, hipStream_t st);
+// out = D in on the 4^4 blocks of one colour only (FP32 tiled operator; other blocks untouched).
+int run_dirac_colour(const Geo& g, const GaugeDev& G, const SpinorBuf& in, const SpinorBuf& out, const double* mu,
+                     int nsys, int colour, hipStream_t st);
 
 // Device address of the current device's fixed scratch array of the no-allocation entry point
 // (tm_noalloc.hip), looked up once per device; out may be NULL (set-up only).

@@ -65,6 +65,7 @@ struct DiracArgs {
     void* out;
     float* out_scale;
     int nsys;
+    int colour = -1;     // -1: every 4^4 tile; 0 / 1: the blocks of that colour only (tiled operator)
     double mu[kMaxSys];
 };
 
@@ -83,6 +84,8 @@ struct SapArgs {
     int own_zero;        // 1: x is zero on this colour's blocks (skip reading it)
     int halo_zero;       // 1: x is zero on the other colour's blocks too (then r = b)
     int eo;              // 1: even-odd preconditioned block solves
+    void* w_out = nullptr;  // set (4^4 FP32 kernel, FP32 storage): D x on the swept blocks, written as
+                            // b minus the final block residual, [nsys] fields like x
     unsigned long long eo_adj;            // bit k: system k uses the adjoint inverses (mu_k < 0)
     const void* eo_inv[kMaxEoMu];         // inverse sets by |mu|
     unsigned char eo_sel[kMaxSys];        // system -> inverse set
@@ -155,6 +158,9 @@ hipError_t launch_dirac_44(const DiracArgs& a, Prec in_p, Prec out_p, Prec link_
 hipError_t launch_sap_half(const SapArgs& a, Prec spinor_p, Prec link_p, Prec clover_p, Prec compute,
                            hipStream_t st);
 bool sap_supported(Prec spinor_p, Prec link_p, Prec clover_p, Prec compute);
+// True when a half-sweep with these storage/link/clover precisions runs the 4^4 FP32 kernel with
+// FP32 storage, whose w_out output is then available.
+bool sap_fills_w(const Geo& g, Prec sp, Prec lp, Prec cp, bool eo);
 size_t sap_lds_bytes(int Vb, Prec compute);
 
 }  // namespace tmsap

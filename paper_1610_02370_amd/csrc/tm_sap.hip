@@ -1258,6 +1258,17 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
             }
         }
         store_spinor<float, S>(xx, xsc, g.V, s, e);
+        if constexpr (std::is_same<S, float>::value) {
+            if (a.w_out) {
+                // D x on the block, with x as just stored: the block's residual after the MR steps
+                // is b - D x there (the other colour's x is unchanged), so D x = b - rho
+                Spinor<float> t;
+                load_spinor<float, S>(bb, bsc, g.V, s, t);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) t.v[i] = t.v[i] - rho.v[i];
+                store_spinor<float, S>(reinterpret_cast<char*>(a.w_out) + sys * stride, nullptr, g.V, s, t);
+            }
+        }
     }
 }
 
@@ -1277,7 +1288,10 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int l = threadIdx.x;
 
     int B[4];
-    {
+    if (a.colour >= 0) {
+        // the blocks of one colour, ordered as the half-sweep orders them
+        s44_block(g, a.colour, xcd_swizzle(blockIdx.x, gridDim.x), B);
+    } else {
         long long t = xcd_swizzle(blockIdx.x, gridDim.x);  // block index, lexicographic over the block grid
         B[3] = (int)(t % g.nb[3]);
         t /= g.nb[3];
@@ -1338,7 +1352,8 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
 template <class Si, class So, class G, class C>
 hipError_t run_dirac_44(const DiracArgs& a, hipStream_t st) {
     const long long nblocks = (long long)a.g.nb[0] * a.g.nb[1] * a.g.nb[2] * a.g.nb[3];
-    hipLaunchKernelGGL((k_dirac_44<Si, So, G, C>), dim3((unsigned)nblocks), dim3(kV2), 0, st, a);
+    const long long n = a.colour >= 0 ? nblocks / 2 : nblocks;
+    hipLaunchKernelGGL((k_dirac_44<Si, So, G, C>), dim3((unsigned)n), dim3(kV2), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1409,6 +1424,11 @@ size_t sap_lds_bytes(int Vb, Prec compute) {
     const int nt = (Vb + 63) & ~63;
     const size_t rb = compute == P_F64 ? 8 : 4;
     return (24 * (size_t)nt + 4 * 16) * rb;
+}
+
+bool sap_fills_w(const Geo& g, Prec sp, Prec lp, Prec cp, bool eo) {
+    const bool is44 = g.lb[0] == 4 && g.lb[1] == 4 && g.lb[2] == 4 && g.lb[3] == 4;
+    return is44 && !eo && sp == P_F32 && lp == P_F32 && cp == P_F32 && !sap_v1_forced() && !sap_v2_forced();
 }
 
 bool sap_supported(Prec sp, Prec lp, Prec cp, Prec r) {

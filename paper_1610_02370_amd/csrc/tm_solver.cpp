@@ -284,17 +284,28 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
                 if ((rc = hcheck(launch_spinor_convert(c.g, uj, K.vS, c.st), "convert"))) return rc;
                 src = K.vS;
             }
-            // z_j = SAP(u_j) from a zero guess; w = D z_j
+            // z_j = SAP(u_j) from a zero guess; w = D z_j.  When the smoother and the operator
+            // share the FP32 gauge copy and z_j is stored in FP32, the last half-sweep gives D z_j on
+            // its own blocks (b minus the blocks' final residual), so the operator runs on the
+            // other colour's blocks only.
+            const bool w_from_sap = !c.mg && c.sap == c.op && c.op_compute == P_F32 && K.w.prec == P_F32 &&
+                                    zj.prec == P_F32 &&
+                                    sap_fills_w(c.g, src.prec, c.sap->link_prec, c.sap->clover_prec, c.eo);
             if ((rc = hcheck(hipEventRecord(c.ev[0], c.st), "event"))) return rc;
             if (c.mg)
                 rc = mg_apply(c.mg, c.ds, src, zj, c.mu, ns, c.st);
             else
-                rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, c.sys_tile, c.st, c.eo);
+                rc = run_sap(c.g, *c.sap, src, zj, c.mu, ns, c.n_cycles, c.mr_iters, true, c.sys_tile, c.st, c.eo,
+                             w_from_sap ? K.w.data : nullptr);
             if (rc) return rc;
             if ((rc = hcheck(hipEventRecord(c.ev[1], c.st), "event"))) return rc;
             c.sap_cycles += c.n_cycles;
             c.sap_sys_cycles += (long long)c.n_cycles * ns;
-            if ((rc = run_dirac(c.g, *c.op, zj, K.w, c.mu, ns, c.op_compute, c.st))) return rc;
+            if (w_from_sap)
+                rc = run_dirac_colour(c.g, *c.op, zj, K.w, c.mu, ns, 0, c.st);
+            else
+                rc = run_dirac(c.g, *c.op, zj, K.w, c.mu, ns, c.op_compute, c.st);
+            if (rc) return rc;
             // classical Gram-Schmidt with delayed reorthogonalisation: one sweep for the dots of the
             // stored directions u_0..u_{j-1} with u_j and w (and <u,u>, <u,w>, <w,w>), a small
             // kernel that takes them to the orthonormal basis V = U T^-1 and finishes v_j =
