@@ -195,10 +195,10 @@ struct CoreResult {
 // the estimates): for inner solves whose caller computes the true residual
 // next.  With x_acc (FP64, same systems), a solve from zero that ends that way
 // in its first cycle adds its solution to *x_acc instead of writing x
-// (out.accumulated).
+// (out.accumulated; with x_acc_zero, *x_acc is taken as zero and overwritten).
 int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, bool x_zero, const double* tol,
                 int max_iters, CoreResult& out, unsigned long long skip = 0, bool trust_estimate = false,
-                const SpinorBuf* x_acc = nullptr) {
+                const SpinorBuf* x_acc = nullptr, bool x_acc_zero = false) {
     const long long V = c.g.V;
     const int ns = c.nsys, m = K.m;
     int rc;
@@ -437,7 +437,7 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
             out.accumulated = x_acc && x_zero && by_estimate;
             if (out.accumulated) {
                 if ((rc = hcheck(blas_xupdate(P_F64, c.sp, vec_ref(*x_acc, V), vec_ref(z0, V), K.zstride,
-                                              zscale_stride, jdone, c.sc.y, 0, ns, V, c.st),
+                                              zscale_stride, jdone, c.sc.y, x_acc_zero, ns, V, c.st),
                                  "x update")))
                     return rc;
             } else if ((rc = hcheck(blas_xupdate(c.vp, c.sp, vec_ref(x, V), vec_ref(z0, V), K.zstride, zscale_stride,
@@ -459,10 +459,14 @@ int fgmres_core(Ctx& c, Krylov& K, const SpinorBuf& rhs, const SpinorBuf& x, boo
     }
     if (x_zero) {
         // no cycle ran: the solution is zero
-        if (x_acc)
+        if (x_acc && !x_acc_zero)
             out.accumulated = true;
-        else if ((rc = hcheck(blas_zero(x.data, internal_bytes(c.g, ns, c.vp), c.st), "zero")))
+        else if ((rc = hcheck(blas_zero((x_acc ? *x_acc : x).data, internal_bytes(c.g, ns, x_acc ? P_F64 : c.vp),
+                                        c.st),
+                              "zero")))
             return rc;
+        else if (x_acc)
+            out.accumulated = true;
     }
     return TM_OK;
 }
@@ -656,9 +660,9 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                 return rc;
             if ((rc = hcheck(hipStreamSynchronize(st), "norm"))) return rc;
             for (int k = 0; k < ns; ++k) x_zero &= c.hstage[k] == 0.0;
-        } else if ((rc = hcheck(blas_zero(xx.data, internal_bytes(g, ns, P_F64), st), "zero"))) {
-            return rc;
         }
+        // without x_in the FP64 iterate is not written until the solve writes it (a zero start
+        // never reads it; the first correction overwrites it)
 
         CoreResult res;
         if (!dc) {
@@ -685,6 +689,7 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
             std::vector<int> iters(ns, 0);
             int outer = 0;
             bool done = false;
+            bool xx_zero = x_zero;  // the FP64 iterate is the zero start (possibly not yet written)
             for (;;) {
                 // FP64 residual of the current iterate, rounded once into the inner solve's FP32
                 // right-hand side (b itself for a zero start: then that is converted from b)
@@ -756,15 +761,21 @@ int tm_fgmres_solve(const tm_geom* geom, const void* U, const void* b, void* x, 
                     std::fflush(stderr);
                 }
                 if ((rc = fgmres_core(c, K, r32, c32, true, itol.data(), so->max_iters - maxit, res, skip, true,
-                                      &xx)))
+                                      &xx, xx_zero)))
                     return rc;
                 for (int k = 0; k < ns; ++k) iters[k] += res.iters[k];
-                if (!res.accumulated &&
-                    (rc = hcheck(blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st),
-                                 "accumulate")))
-                    return rc;
+                if (!res.accumulated) {
+                    // x += c, or x = c while x is still the zero start
+                    const hipError_t h = xx_zero
+                                             ? blas_scale(P_F32, P_F64, vec_ref(c32, V), c.sc.ones, vec_ref(xx, V), ns, V, st)
+                                             : blas_accumulate(P_F64, P_F32, vec_ref(xx, V), vec_ref(c32, V), ns, V, st);
+                    if ((rc = hcheck(h, "accumulate"))) return rc;
+                }
+                xx_zero = false;
                 ++outer;
             }
+            if (xx_zero && (rc = hcheck(blas_zero(xx.data, internal_bytes(g, ns, P_F64), st), "zero")))
+                return rc;  // no correction was made: the solution is the zero start
             for (int k = 0; k < ns; ++k) {
                 const bool ok = rep.true_rel_res[g0 + k] <= tol;
                 rep.converged += ok;
