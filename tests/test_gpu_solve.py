@@ -88,6 +88,52 @@ def test_long_cycles_against_dense_lu(cfg_4444, storage):
         assert np.linalg.norm(xg[k].ravel() - ref) / np.linalg.norm(ref) < 1e-8
 
 
+def test_w_from_smoother_matches_full_operator(tmp_path):
+    # FP32 storage, 4^4 blocks: the Arnoldi step takes D z from the smoother's last half-sweep on
+    # one colour and runs the operator on the other.  The same solve in a process that selects the
+    # general-shape FP32 kernel (TM_SAP_KERNEL=v2) forms D z with the operator everywhere.  The two
+    # differ only in FP32 rounding: the same iterations up to one step where an estimate sits at a
+    # tolerance, both solutions within 1e-10 by the oracle, and so within 2e-10 ||b|| / |mu| of each
+    # other (sigma_min >= |mu|)
+    import os
+    import subprocess
+    import sys
+
+    dims, kappa, mu, csw = (8, 8, 8, 8), 0.1632, 0.003, 1.5
+    U = synth.gauge_field(dims, 0.5, seed=2)
+    b = synth.point_sources(dims, [(0, 0), (1, 2)])
+    mus = [mu, -mu]
+    kw = dict(storage="f32", form="defect_correction", restart=8, n_cycles=3, mr_iters=4, block_dims=(4, 4, 4, 4))
+    announce("solve with D z from the smoother against the full operator (child process, v2 kernel)")
+    x = dev(np.zeros_like(b))
+    rc, rep = tm.tm_fgmres_solve(dims, dev(U), dev(b), x, kappa, mus, csw, TOL, **kw)
+    assert rc == 0, rep
+    np.savez(tmp_path / "in.npz", U=U, b=b)
+    child = f"""
+import sys, numpy as np, torch
+sys.path.insert(0, {os.path.dirname(os.path.dirname(os.path.abspath(__file__)))!r})
+import paper_1610_02370_amd as tm
+d = np.load({str(tmp_path / "in.npz")!r})
+x = torch.zeros(d["b"].shape, dtype=torch.complex128, device="cuda")
+rc, rep = tm.tm_fgmres_solve({dims!r}, torch.from_numpy(d["U"]).cuda(), torch.from_numpy(d["b"]).cuda(), x,
+                             {kappa!r}, {mus!r}, {csw!r}, {TOL!r}, **{kw!r})
+np.savez({str(tmp_path / "out.npz")!r}, x=x.cpu().numpy(), rc=rc, iters=rep["iters"], outer=rep["outer"])
+"""
+    env = dict(os.environ, TM_SAP_KERNEL="v2")
+    r = subprocess.run([sys.executable, "-c", child], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    o = np.load(tmp_path / "out.npz")
+    assert int(o["rc"]) == 0
+    assert abs(rep["iters"] - int(o["iters"])) <= 1 and abs(rep["outer"] - int(o["outer"])) <= 1, \
+        (rep, o["iters"], o["outer"])
+    xg = host(x)
+    op = oracle.Operator(dims, U, oracle.kappa_to_m(kappa), mu, csw)
+    check_solutions(op, dims, b, xg, mus, TOL, "8^4 D z from the smoother", "f32")
+    check_solutions(op, dims, b, o["x"], mus, TOL, "8^4 D z from the operator", "f32")
+    for k in range(2):
+        assert np.linalg.norm(xg[k] - o["x"][k]) <= 2 * TOL * RES_SLACK * np.linalg.norm(b[k]) / mu
+
+
 @pytest.fixture(scope="module")
 def cfg_8888():
     dims, eps, kappa, mu, csw = (8, 8, 8, 8), 0.5, 0.1632, 0.003, 1.5
