@@ -75,6 +75,30 @@ __device__ constexpr R min_normal() {
     return sizeof(R) == 8 ? (R)2.2250738585072014e-308 : (R)1.17549435e-38f;
 }
 
+// The minimal-residual step's local sums <q, rho> and <q, q> (section 2.5's block
+// solver), added one product at a time so that each product is one fused
+// multiply-add (a sum of two products added in one step costs a third instruction).
+template <class R>
+__device__ inline void mr_dots(const Spinor<R>& q, const Spinor<R>& rho, R& qr_re, R& qr_im, R& qq) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        qr_re = qr_re + q.v[i].re * rho.v[i].re;
+        qr_re = qr_re + q.v[i].im * rho.v[i].im;
+        qr_im = qr_im + q.v[i].re * rho.v[i].im;
+        qr_im = qr_im - q.v[i].im * rho.v[i].re;
+        qq = qq + q.v[i].re * q.v[i].re;
+        qq = qq + q.v[i].im * q.v[i].im;
+    }
+}
+
+// rho -= alpha q as two fused multiply-adds per real component.
+template <class R>
+__device__ inline void mr_residual_update(cplx<R> alpha, const Spinor<R>& q, Spinor<R>& rho) {
+    const cplx<R> na = cmk(-alpha.re, -alpha.im);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) rho.v[i] = cmad(na, q.v[i], rho.v[i]);
+}
+
 // Sum of three values over the workgroup; every thread gets the result.
 template <class R>
 __device__ inline void block_sum3(R* red, R& a, R& b, R& c) {
@@ -373,21 +397,14 @@ __global__ void __launch_bounds__(MAXT) k_sap_half(SapArgs a) {
                 // q = (A + twist) rho - 1/2 (in-block hops of rho)
                 clover_apply(A, mu_tw, rho, q);
                 gen_block_hops_add<G, R, LC>(a, t, sh, nt, l, (R)-0.5, q, lk);
-#pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
-                    qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
-                    qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
-                }
+                mr_dots(q, rho, qr_re, qr_im, qq);
             }
             block_sum3(red, qr_re, qr_im, qq);
             if (active && qq >= min_normal<R>()) {
                 const cplx<R> alpha = cmk(qr_re / qq, qr_im / qq);
 #pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    xv.v[i] = cmad(alpha, rho.v[i], xv.v[i]);
-                    rho.v[i] = rho.v[i] - alpha * q.v[i];
-                }
+                for (int i = 0; i < 12; ++i) xv.v[i] = cmad(alpha, rho.v[i], xv.v[i]);
+                mr_residual_update(alpha, q, rho);
             }
         }
 
@@ -478,21 +495,15 @@ __global__ void __launch_bounds__(MAXT) k_sap_half_eo(SapArgs a) {
                 gen_block_hops<G, R>(a, t, sh, nt, l, acc);
                 clover_apply(A, mu_tw, rho, q);
 #pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    q.v[i] = q.v[i] + (R)0.5 * acc.v[i];
-                    qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
-                    qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
-                    qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
-                }
+                for (int i = 0; i < 12; ++i) q.v[i] = q.v[i] + (R)0.5 * acc.v[i];
+                mr_dots(q, rho, qr_re, qr_im, qq);
             }
             block_sum3(red, qr_re, qr_im, qq);
             if (odd && qq >= min_normal<R>()) {
                 const cplx<R> alpha = cmk(qr_re / qq, qr_im / qq);
 #pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    e.v[i] = cmad(alpha, rho.v[i], e.v[i]);
-                    rho.v[i] = rho.v[i] - alpha * q.v[i];
-                }
+                for (int i = 0; i < 12; ++i) e.v[i] = cmad(alpha, rho.v[i], e.v[i]);
+                mr_residual_update(alpha, q, rho);
             }
         }
 
@@ -924,12 +935,7 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
                 for (int i = 0; i < 12; ++i) q.v[i] = cmk(0.f, 0.f);
                 v2_pull(sm, l, fin, bin, str, Uo, q);
                 clover_acc(A, -2.f * mu_tw, rho, q);  // q = -2 D_BB rho
-#pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
-                    qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
-                    qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
-                }
+                mr_dots(q, rho, qr_re, qr_im, qq);
             }
             block_sum3(sm.red, qr_re, qr_im, qq);
             if (active && qq >= min_normal<float>()) {
@@ -938,10 +944,8 @@ __global__ void __launch_bounds__(kV2) k_sap_half_v2(SapArgs a) {
                 const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
                 const cplx<float> beta = cmk(-2.f * alpha.re, -2.f * alpha.im);
 #pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    e.v[i] = cmad(beta, rho.v[i], e.v[i]);
-                    rho.v[i] = rho.v[i] - alpha * q.v[i];
-                }
+                for (int i = 0; i < 12; ++i) e.v[i] = cmad(beta, rho.v[i], e.v[i]);
+                mr_residual_update(alpha, q, rho);
             }
         }
         if (active) store_spinor<float, S>(xx, xsc, g.V, s, e);
@@ -1035,7 +1039,7 @@ __device__ __attribute__((always_inline)) inline void s44_stencil(V2Shared& sm, 
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
+    for (int i = 0; i < 12; ++i) acc.v[i] = cmk(-0.f, -0.f);  // -0 + t = t: the first hop is stored
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         __builtin_amdgcn_sched_barrier(0);
@@ -1181,7 +1185,7 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
             __syncthreads();
             Spinor<float> acc;
 #pragma unroll
-            for (int i = 0; i < 12; ++i) acc.v[i] = cmk(0.f, 0.f);
+            for (int i = 0; i < 12; ++i) acc.v[i] = cmk(-0.f, -0.f);  // -0 + t = t: the first hop is stored
 #pragma unroll
             for (int mu = 0; mu < 4; ++mu) {
                 __builtin_amdgcn_sched_barrier(0);
@@ -1235,26 +1239,20 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
             __syncthreads();
             Spinor<float> q;
             float qr_re = 0.f, qr_im = 0.f, qq = 0.f;
+            // -0 start: adding a term to -0 returns the term, so the first hop is stored, not added
 #pragma unroll
-            for (int i = 0; i < 12; ++i) q.v[i] = cmk(0.f, 0.f);
+            for (int i = 0; i < 12; ++i) q.v[i] = cmk(-0.f, -0.f);
             v2_pull(sm, l, fin, bin, str, Uo, q);
             clover_acc(A, -2.f * mu_tw, rho, q);
-#pragma unroll
-            for (int i = 0; i < 12; ++i) {
-                qr_re += q.v[i].re * rho.v[i].re + q.v[i].im * rho.v[i].im;
-                qr_im += q.v[i].re * rho.v[i].im - q.v[i].im * rho.v[i].re;
-                qq += q.v[i].re * q.v[i].re + q.v[i].im * q.v[i].im;
-            }
+            mr_dots(q, rho, qr_re, qr_im, qq);
             block_sum3_w4(sm.red, qr_re, qr_im, qq);
             if (qq >= min_normal<float>()) {
                 const float inv = __builtin_amdgcn_rcpf(qq);
                 const cplx<float> alpha = cmk(qr_re * inv, qr_im * inv);
                 const cplx<float> beta = cmk(-2.f * alpha.re, -2.f * alpha.im);
 #pragma unroll
-                for (int i = 0; i < 12; ++i) {
-                    e.v[i] = cmad(beta, rho.v[i], e.v[i]);
-                    rho.v[i] = rho.v[i] - alpha * q.v[i];
-                }
+                for (int i = 0; i < 12; ++i) e.v[i] = cmad(beta, rho.v[i], e.v[i]);
+                mr_residual_update(alpha, q, rho);
             }
         }
         store_spinor<float, S>(xx, xsc, g.V, s, e);
