@@ -1173,7 +1173,7 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
                 Link<float> Ldn;  // U_mu(site below the lower face), mu = wmu
                 load_spinor<float, S>(xx, xsc, g.V, dn_site, hd);
                 load_link<float, G>(a.links, g.V, dn_site, wmu, Ldn);
-                v2_push(sm, l, true, fin, Uo, e);
+                if (own) v2_push(sm, l, true, fin, Uo, e);
                 if (dn_wrap) apply_bc(g, wmu, -1, hd);
                 switch (wax) {
                     case 0: s44_stage_backward<0>(Ldn, hd, 1.f, hb, top); break;
@@ -1188,17 +1188,20 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int i = 0; i < 12; ++i) acc.v[i] = cmk(-0.f, -0.f);  // -0 + t = t: the first hop is stored
 #pragma unroll
             for (int mu = 0; mu < 4; ++mu) {
+                // with x zero on the block (own_zero) only the halo terms remain: no in-block hops
                 __builtin_amdgcn_sched_barrier(0);
-                if (fin[mu]) {
+                if (own && fin[mu]) {
                     Half<float> h, gg;
                     project_forward_lds(sm.xs, mu, l + str[mu], h);
                     su3_mul(Uo[mu], h, gg);
                     forward_accumulate(mu, gg, acc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                Half<float> gg;
-                v2_get_half(sm.gb, mu, bcol[mu], gg);
-                backward_accumulate(mu, gg, acc);
+                if (own || !bin[mu]) {
+                    Half<float> gg;
+                    v2_get_half(sm.gb, mu, bcol[mu], gg);
+                    backward_accumulate(mu, gg, acc);
+                }
             }
             __syncthreads();
             // ---- pass 2: the upper-face halo, staged in xs
