@@ -1186,21 +1186,30 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
             Spinor<float> acc;
 #pragma unroll
             for (int i = 0; i < 12; ++i) acc.v[i] = cmk(-0.f, -0.f);  // -0 + t = t: the first hop is stored
+            if (own) {
 #pragma unroll
-            for (int mu = 0; mu < 4; ++mu) {
-                // with x zero on the block (own_zero) only the halo terms remain: no in-block hops
-                __builtin_amdgcn_sched_barrier(0);
-                if (own && fin[mu]) {
-                    Half<float> h, gg;
-                    project_forward_lds(sm.xs, mu, l + str[mu], h);
-                    su3_mul(Uo[mu], h, gg);
-                    forward_accumulate(mu, gg, acc);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                if (own || !bin[mu]) {
+                for (int mu = 0; mu < 4; ++mu) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (fin[mu]) {
+                        Half<float> h, gg;
+                        project_forward_lds(sm.xs, mu, l + str[mu], h);
+                        su3_mul(Uo[mu], h, gg);
+                        forward_accumulate(mu, gg, acc);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                     Half<float> gg;
                     v2_get_half(sm.gb, mu, bcol[mu], gg);
                     backward_accumulate(mu, gg, acc);
+                }
+            } else {
+                // x zero on the block (own_zero): only the lower-face halo products, no in-block hops
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu) {
+                    if (bcol[mu] > l) {  // bcol above l: a lower-face site, whose slot holds the halo
+                        Half<float> gg;
+                        v2_get_half(sm.gb, mu, bcol[mu], gg);
+                        backward_accumulate(mu, gg, acc);
+                    }
                 }
             }
             __syncthreads();
@@ -1258,16 +1267,21 @@ __global__ void __launch_bounds__(kV2) __attribute__((amdgpu_waves_per_eu(2, 2))
                 mr_residual_update(alpha, q, rho);
             }
         }
-        store_spinor<float, S>(xx, xsc, g.V, s, e);
+        // the site index again from an index the compiler cannot see through: held across the
+        // MR steps it would be spilled and reloaded once per system
+        int lo = l;
+        asm volatile("" : "+v"(lo));
+        const long long so = blk * 256 + lo;
+        store_spinor<float, S>(xx, xsc, g.V, so, e);
         if constexpr (std::is_same<S, float>::value) {
             if (a.w_out) {
                 // D x on the block, with x as just stored: the block's residual after the MR steps
                 // is b - D x there (the other colour's x is unchanged), so D x = b - rho
                 Spinor<float> t;
-                load_spinor<float, S>(bb, bsc, g.V, s, t);
+                load_spinor<float, S>(bb, bsc, g.V, so, t);
 #pragma unroll
                 for (int i = 0; i < 12; ++i) t.v[i] = t.v[i] - rho.v[i];
-                store_spinor<float, S>(reinterpret_cast<char*>(a.w_out) + sys * stride, nullptr, g.V, s, t);
+                store_spinor<float, S>(reinterpret_cast<char*>(a.w_out) + sys * stride, nullptr, g.V, so, t);
             }
         }
     }
