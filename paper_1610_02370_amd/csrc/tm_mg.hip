@@ -192,8 +192,11 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(MgArgs m, const void* __rest
 #pragma unroll
                 for (int q = 0; q < 12; ++q) {
                     const int h = q < 6 ? 0 : 2;
-                    d[h] += p.v[q].re * xv[k].v[q].re + p.v[q].im * xv[k].v[q].im;
-                    d[h + 1] += p.v[q].re * xv[k].v[q].im - p.v[q].im * xv[k].v[q].re;
+                    // one product per statement: each becomes one fused multiply-add
+                    d[h] = d[h] + p.v[q].re * xv[k].v[q].re;
+                    d[h] = d[h] + p.v[q].im * xv[k].v[q].im;
+                    d[h + 1] = d[h + 1] + p.v[q].re * xv[k].v[q].im;
+                    d[h + 1] = d[h + 1] - p.v[q].im * xv[k].v[q].re;
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[(ii * S + k) * 4 + e] = d[e];
@@ -432,10 +435,15 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarse_apply(Geo g, int nv, con
             for (int k = 0; k < kCoarseSys; ++k) {
                 if (k < ns) {
                     const float2 xv = xs[k * n2];
-                    acc0[k].x += mv.x * xv.x - mv.y * xv.y;
-                    acc0[k].y += mv.x * xv.y + mv.y * xv.x;
-                    acc1[k].x += mv.z * xv.x - mv.w * xv.y;
-                    acc1[k].y += mv.z * xv.y + mv.w * xv.x;
+                    // one product per statement: each becomes one fused multiply-add
+                    acc0[k].x = acc0[k].x + mv.x * xv.x;
+                    acc0[k].x = acc0[k].x - mv.y * xv.y;
+                    acc0[k].y = acc0[k].y + mv.x * xv.y;
+                    acc0[k].y = acc0[k].y + mv.y * xv.x;
+                    acc1[k].x = acc1[k].x + mv.z * xv.x;
+                    acc1[k].x = acc1[k].x - mv.w * xv.y;
+                    acc1[k].y = acc1[k].y + mv.z * xv.y;
+                    acc1[k].y = acc1[k].y + mv.w * xv.x;
                 }
             }
         }
@@ -590,8 +598,10 @@ __global__ void __launch_bounds__(64) k_mg_block_mul(BlockMulArgs a) {
 #pragma unroll
                     for (int k = 0; k < kBlockMulSys; ++k) {
                         const float2 v = xs[k][b];
-                        acc[k].x += m.x * v.x - m.y * v.y;
-                        acc[k].y += m.x * v.y + m.y * v.x;
+                        acc[k].x = acc[k].x + m.x * v.x;  // one fused multiply-add per product
+                        acc[k].x = acc[k].x - m.y * v.y;
+                        acc[k].y = acc[k].y + m.x * v.y;
+                        acc[k].y = acc[k].y + m.y * v.x;
                     }
                 }
 #pragma unroll
