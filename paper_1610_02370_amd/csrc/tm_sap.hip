@@ -75,7 +75,7 @@ __device__ constexpr R min_normal() {
     return sizeof(R) == 8 ? (R)2.2250738585072014e-308 : (R)1.17549435e-38f;
 }
 
-// The minimal-residual step's local sums <q, rho> and <q, q> (section 2.5's block
+// The minimal-residual step's local sums <q, rho> and <q, q> (section 2.4's block
 // solver), added one product at a time so that each product is one fused
 // multiply-add (a sum of two products added in one step costs a third instruction).
 template <class R>
