@@ -5,7 +5,7 @@
 // The paper fixes 4^4 blocks (Table 1) for its machine; on another chip the
 // best shape depends on the on-chip memory per workgroup and on how many
 // blocks fill the device, so it is measured.  Only throughput is measured:
-// the block shape also changes the preconditioner (section 2.5), so a solve
+// the block shape also changes the preconditioner (section 2.4), so a solve
 // with a tuned shape can take a different number of iterations.
 #include <hip/hip_runtime.h>
 
