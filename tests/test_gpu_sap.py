@@ -2,7 +2,7 @@
 
 Both sides run the same red-black sweeps (colour 0 first) with MR block solves
 on the same seeded inputs and initial guess.  Each result is checked norm-wise
-and per site against the error model of gpu_util (f64 1e-11, f32 1e-5,
+and per site against the error model of gpu_util (f64 1e-13, f32 2e-6,
 f16 2e-3, bf16 1.5e-2).
 """
 import numpy as np

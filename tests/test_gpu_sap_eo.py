@@ -5,7 +5,7 @@ D_oo - D_oe D_ee^-1 D_eo, sites split by the parity of t+z+y+x), MR runs on
 the reduced system and the even half is recovered.  The HIP path and the FP64
 oracle run the same red-black sweeps on the same seeded inputs; each result is
 checked norm-wise and per site against the smoother's error model of gpu_util
-(f64 1e-11, f32 1e-5, f16 2e-3, bf16 1.5e-2).
+(f64 1e-13, f32 2e-6, f16 2e-3, bf16 1.5e-2).
 """
 import numpy as np
 import pytest
